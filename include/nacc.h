@@ -1,0 +1,290 @@
+/*
+ * nacc.h -- C ABI of the MI355X (gfx950) library for occupancy-grid ray
+ * marching and packed differentiable volume rendering, after NerfAcc
+ * (Li, Tancik, Kanazawa, arXiv 2210.04847).
+ *
+ * The calls follow the paper's two-step statement of the problem (Sec. 2):
+ * ray marching emits ragged samples, then differentiable rendering
+ * accumulates them along each ray.  Between the two the caller evaluates its
+ * own radiance field (Sec. 3: sigma_fn / rgb_sigma_fn); callbacks never cross
+ * this boundary.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers to contiguous memory owned by
+ *     the caller, unless stated otherwise.  The library allocates nothing in
+ *     these calls and keeps no pointer after returning.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued asynchronously on it; nothing blocks the host unless
+ *     stated.
+ *   - Arguments are validated on the host before anything is launched.  A
+ *     call returns NACC_OK (0) or a negative status; it never aborts or
+ *     throws.  nacc_last_error() returns a message for the calling thread's
+ *     most recent failure.
+ *   - Ray and sample counts are int64; ray_indices and packed_info entries are
+ *     int32, so a call whose sample total would exceed 2^31-1 is rejected
+ *     (NACC_ECAPACITY).
+ *   - Floating point is IEEE FP32.  Marching follows the FP32 lattice
+ *     contract written out below, so its sample sets are reproducible
+ *     bit for bit on any IEEE machine.
+ *
+ * Packed sample layout (Sec. 3, the ragged outputs of ray_marching):
+ *   packed_info  int32[n_rays][2]: (first sample index, sample count) of
+ *                each ray; rays are stored consecutively in ray order.
+ *   ray_indices  int32[n_samples]: the ray of each sample.
+ *   t_starts, t_ends  float[n_samples]: the sample interval along the ray;
+ *                within a ray the intervals are in increasing t and adjacent
+ *                candidates share endpoints bit for bit.
+ *   sigmas       float[n_samples]: post-activation density.
+ *   rgbs         float[n_samples][3]: post-activation colour.
+ *
+ * FP32 lattice contract (our reading of Sec. 2.1; the paper states the
+ * method, not the formulae):
+ *   clip   per axis i with d_i != 0: ta = (lo_i - o_i) / d_i,
+ *          tb = (hi_i - o_i) / d_i, tmin_i = min(ta, tb),
+ *          tmax_i = max(ta, tb); an axis with d_i == 0 imposes nothing when
+ *          lo_i <= o_i <= hi_i and otherwise the ray misses.
+ *          t_near = max(max_i tmin_i, near_plane),
+ *          t_far = min(min_i tmax_i, far_plane); hit iff t_near < t_far.
+ *   steps  uniform (cone == 0): t_k = t_near + (float)k * dt.
+ *          cone (cone > 0): t_0 = t_near,
+ *          t_{k+1} = t_k + min(max(t_k * cone, dt), dt_max).
+ *          Candidate k exists while t_k < t_far and k < 2^24 (cone: also
+ *          while t_{k+1} > t_k).  Its interval is [t_k, t_{k+1}], not
+ *          clamped to t_far.
+ *   point  t_m = (t_k + t_{k+1}) * 0.5f, x_i = o_i + d_i * t_m.
+ *   cell   u_i = (x_i - lo_i) * s_i, s_i = fl32(res / (hi_i - lo_i)) (FP64
+ *          quotient rounded once); j_i = floor(min(max(u_i, 0), res - 1));
+ *          cell = (j_0 * res + j_1) * res + j_2 (x-major, C order);
+ *          occupied iff bit (cell & 31) of word bits[cell >> 5] is set.
+ *   Each operation above is one correctly rounded FP32 operation, with no
+ *   fused multiply-add.
+ */
+#ifndef NACC_H
+#define NACC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    NACC_OK = 0,
+    NACC_EINVAL = -1,    /* a null pointer, a negative size, a bad mode */
+    NACC_ESHAPE = -2,    /* sizes inconsistent with each other */
+    NACC_ECAPACITY = -3, /* an output would not fit its buffer or int32 */
+    NACC_EHIP = -4,      /* the HIP runtime reported an error */
+    NACC_ENOTSUP = -5    /* a valid request this build does not support */
+};
+
+/* Grid lookup modes. */
+enum {
+    NACC_LOOKUP_AABB = 0,     /* grid over the box [lo, hi]; the box is also
+                                 the clip box */
+    NACC_LOOKUP_CASCADE = 1,  /* n_grids nested grids over [-b,b]^3 * 2^l
+                                 (multi-scale grids, Sec. 2.1 footnote); the
+                                 clip box is the largest one */
+    NACC_LOOKUP_CONTRACT = 2  /* scene contraction x -> (2 - 1/|x|) x/|x|
+                                 for |x| > 1 before the lookup (Sec. 2.1,
+                                 "Scene Contraction"); no clip box */
+};
+
+/*
+ * Occupancy grid description (Sec. 2.1, "Pruning Empty and Occluded
+ * Regions": a binary grid cached and updated during training).
+ * The bit array has n_grids * res^3 bits, grid g occupying words
+ * [g * res^3 / 32, (g+1) * res^3 / 32).
+ *   lo, hi   AABB and CONTRACT: the box the grid covers.  CASCADE: the
+ *            level-0 cube, lo = -b, hi = +b on every axis, b a power of two;
+ *            level l covers [-b 2^l, b 2^l]^3, and a point goes to the
+ *            smallest level that holds it (max_i |x_i| <= b 2^l), the last
+ *            level holding everything else.
+ *   res      cells per axis; res^3 must be a multiple of 32; res <= 1024.
+ *   n_grids  AABB/CONTRACT: grids selectable per ray by grid_id;
+ *            CASCADE: number of levels (1..16).
+ *   lookup   NACC_LOOKUP_*.
+ */
+typedef struct nacc_grid_desc {
+    float lo[3];
+    float hi[3];
+    int32_t res;
+    int32_t n_grids;
+    int32_t lookup;
+    int32_t reserved;
+} nacc_grid_desc;
+
+/*
+ * Marching parameters (Sec. 3, ray_marching's near_plane / far_plane and
+ * the render step size; cone stepping for large scenes).
+ *   near_plane, far_plane  the t range before the clip.
+ *   dt        uniform step (cone == 0) or the smallest cone step; > 0.
+ *   dt_max    largest cone step (ignored when cone == 0); >= dt.
+ *   cone      0 for uniform steps; > 0 scales the step with t.
+ *   max_per_ray  0 for no cap; otherwise each ray keeps only its first
+ *             max_per_ray samples.
+ */
+typedef struct nacc_march_params {
+    float near_plane;
+    float far_plane;
+    float dt;
+    float dt_max;
+    float cone;
+    int32_t max_per_ray;
+} nacc_march_params;
+
+/* Library version string; never NULL. */
+const char* nacc_version(void);
+
+/* Message of the calling thread's most recent failed call ("" if none). */
+const char* nacc_last_error(void);
+
+/* Name of a status code. */
+const char* nacc_status_str(int status);
+
+/* Bytes of device workspace nacc_march_count needs for n_rays rays (>= 0);
+ * -1 if n_rays < 0. */
+int64_t nacc_march_workspace_size(int64_t n_rays);
+
+/*
+ * Marching, pass 1 of 2: count the samples of every ray and lay them out
+ * (Sec. 2.1, "GPU Memory Efficiency": empty space is pruned while marching,
+ * so only the samples in occupied cells are ever stored).
+ *   rays_o, rays_d  float[n_rays][3]: origins and directions (normalised
+ *                   directions are expected but not required).
+ *   grid_id         int32[n_rays] grid of each ray, or NULL for grid 0
+ *                   (ignored for CASCADE).
+ *   grid_bits       uint32[n_grids * res^3 / 32], LSB-first bit order.
+ *   packed_info     out int32[n_rays][2]: (start, count) per ray.
+ *   total           out int64[1]: the sample total, on the device.
+ *   workspace       device scratch of nacc_march_workspace_size(n_rays)
+ *                   bytes; contents on entry are irrelevant.
+ * Errors: NACC_EINVAL / NACC_ESHAPE for bad arguments; NACC_EHIP if a launch
+ * fails.  A total above 2^31-1 is reported by nacc_march_fill.
+ */
+int nacc_march_count(const float* rays_o, const float* rays_d,
+                     const int32_t* grid_id, int64_t n_rays,
+                     const uint32_t* grid_bits, const nacc_grid_desc* grid,
+                     const nacc_march_params* params, int32_t* packed_info,
+                     int64_t* total, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
+/*
+ * Marching, pass 2 of 2: write the samples laid out by nacc_march_count
+ * (the same rays, grid and parameters, and its packed_info).
+ *   capacity        length of ray_indices / t_starts / t_ends.
+ *   ray_indices     out int32[capacity], t_starts / t_ends out float[capacity].
+ *   status          out int32[1] on the device: NACC_OK, or NACC_ECAPACITY
+ *                   when some sample fell at or beyond `capacity` (those
+ *                   samples are not written; the others are).  May be NULL.
+ */
+int nacc_march_fill(const float* rays_o, const float* rays_d,
+                    const int32_t* grid_id, int64_t n_rays,
+                    const uint32_t* grid_bits, const nacc_grid_desc* grid,
+                    const nacc_march_params* params,
+                    const int32_t* packed_info, int64_t capacity,
+                    int32_t* ray_indices, float* t_starts, float* t_ends,
+                    int32_t* status, void* stream);
+
+/*
+ * Rendering forward, Eq. 1 (Sec. 2.2): per ray
+ *   alpha_i = 1 - exp(-sigma_i delta_i), delta_i = t_end_i - t_start_i,
+ *   T_i = exp(-sum_{j<i} sigma_j delta_j), w_i = T_i alpha_i,
+ *   color = sum w_i rgb_i, opacity = sum w_i,
+ *   depth = sum w_i (t_start_i + t_end_i) / 2.
+ * Early termination (Sec. 2.1): with early_stop_eps > 0 the first sample
+ * with T_i < early_stop_eps and every later sample of the ray get w = 0.
+ *   color out float[n_rays][3]; opacity, depth out float[n_rays];
+ *   weights out float[n_samples] or NULL (zero past the cut).
+ * Only samples referenced by packed_info are read.
+ */
+int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays,
+                    const float* t_starts, const float* t_ends,
+                    const float* sigmas, const float* rgbs,
+                    float early_stop_eps, float* color, float* opacity,
+                    float* depth, float* weights, void* stream);
+
+/*
+ * Rendering backward (Sec. 2.2: all outputs of the radiance field receive
+ * gradients).  Inputs as nacc_render_fwd plus the upstream gradients
+ * g_color float[n_rays][3] and g_opacity, g_depth float[n_rays] (either may
+ * be NULL = zero).  With v_i = g_color . rgb_i + g_opacity + g_depth m_i:
+ *   g_rgbs_i   = w_i g_color
+ *   g_sigmas_i = delta_i (T_{i+1} v_i - sum_{k>i} w_k v_k)
+ * both zero at and past the early-termination cut, which is recomputed
+ * exactly as in the forward call.  Transmittance is recomputed, not stored.
+ *   g_sigmas out float[n_samples], g_rgbs out float[n_samples][3]; every
+ *   sample referenced by packed_info is written.
+ */
+int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays,
+                    const float* t_starts, const float* t_ends,
+                    const float* sigmas, const float* rgbs,
+                    float early_stop_eps, const float* g_color,
+                    const float* g_opacity, const float* g_depth,
+                    float* g_sigmas, float* g_rgbs, void* stream);
+
+/* Bytes of device workspace nacc_render_fwd_bwd_mse needs (>= 0). */
+int64_t nacc_render_mse_workspace_size(int64_t n_rays);
+
+/*
+ * Fused forward + mean-squared-error loss + backward (the training step of
+ * Sec. 3: loss = mse(color, target), then backward), in one pass per ray.
+ *   target   float[n_rays][3].
+ *   loss     out float[1] on the device: mean over n_rays * 3 values.
+ *   color, opacity, depth, g_sigmas, g_rgbs as in the calls above, with
+ *   g_color = 2 (color - target) / (3 n_rays), g_opacity = g_depth = 0.
+ *   workspace  device scratch of nacc_render_mse_workspace_size bytes.
+ */
+int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays,
+                            const float* t_starts, const float* t_ends,
+                            const float* sigmas, const float* rgbs,
+                            float early_stop_eps, const float* target,
+                            float* color, float* opacity, float* depth,
+                            float* g_sigmas, float* g_rgbs, float* loss,
+                            void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/*
+ * Occupancy-grid update (Sec. 2.1: the grid is cached and updated during
+ * training; the update rule is delegated by the paper to Instant-NGP and
+ * read here as: decay every cell, take the max with fresh density samples at
+ * random cells, threshold).  The state is float occ[n_cells].
+ */
+
+/* occ[c] = occ[c] * decay for every cell (FP32 multiply). */
+int nacc_grid_decay(float* occ, int64_t n_cells, float decay, void* stream);
+
+/*
+ * n random cells of update `step` with jittered positions inside them.
+ * Sample q draws Philox4x64-10 (Salmon et al., SC 2011) at
+ * counter (q, step, 0, 0), key (seed, 0) -> (r0, r1, r2, r3):
+ *   cell     = ((r0 >> 32) * n_cells) >> 32, n_cells = levels * res^3
+ *   jitter_i = (float)(r_{i+1} >> 40) * 2^-24
+ *   x_i      = (lo_i + ((float)j_i + jitter_i) * h_i) * 2^level,
+ *              h_i = fl32((hi_i - lo_i) / res), (j_0, j_1, j_2) the C-order
+ *              index of the cell within its level, level = cell / res^3.
+ * For AABB/CONTRACT grids pass levels = 1 (positions are then in the grid's
+ * own coordinates, i.e. contracted space for CONTRACT).
+ *   cells out int32[n]; positions out float[n][3].
+ */
+int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
+                           const nacc_grid_desc* grid, int32_t levels,
+                           int32_t* cells, float* positions, void* stream);
+
+/* occ[cells[q]] = max(occ[cells[q]], values[q]) for q < n; independent of
+ * the order of duplicate cells; NaN values are ignored. */
+int nacc_grid_update_max(float* occ, const int32_t* cells,
+                         const float* values, int64_t n, int64_t n_cells,
+                         void* stream);
+
+/* bits: bit c is set iff occ[c] > threshold (strict); n_cells % 32 == 0;
+ * bits is uint32[n_cells / 32], LSB first. */
+int nacc_grid_pack(const float* occ, int64_t n_cells, float threshold,
+                   uint32_t* bits, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NACC_H */

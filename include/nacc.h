@@ -154,7 +154,8 @@ int64_t nacc_march_workspace_size(int64_t n_rays);
  *   rays_o, rays_d  float[n_rays][3]: origins and directions (normalised
  *                   directions are expected but not required).
  *   grid_id         int32[n_rays] grid of each ray, or NULL for grid 0
- *                   (ignored for CASCADE).
+ *                   (ignored for CASCADE); a ray whose grid id is outside
+ *                   [0, n_grids) gets no samples.
  *   grid_bits       uint32[n_grids * res^3 / 32], LSB-first bit order.
  *   packed_info     out int32[n_rays][2]: (start, count) per ray.
  *   total           out int64[1]: the sample total, on the device.
@@ -197,10 +198,13 @@ int nacc_march_fill(const float* rays_o, const float* rays_d,
  * with T_i < early_stop_eps and every later sample of the ray get w = 0.
  *   color out float[n_rays][3]; opacity, depth out float[n_rays];
  *   weights out float[n_samples] or NULL (zero past the cut).
- * Only samples referenced by packed_info are read.
+ *   n_samples  length of the sample arrays (they may be NULL when it is 0).
+ * Only samples referenced by packed_info are read.  A ray whose range
+ * [start, start + count) does not lie inside [0, n_samples) is rendered as
+ * an empty ray (zeros), so malformed packed_info never reads out of bounds.
  */
 int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays,
-                    const float* t_starts, const float* t_ends,
+                    int64_t n_samples, const float* t_starts, const float* t_ends,
                     const float* sigmas, const float* rgbs,
                     float early_stop_eps, float* color, float* opacity,
                     float* depth, float* weights, void* stream);
@@ -218,7 +222,7 @@ int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays,
  *   sample referenced by packed_info is written.
  */
 int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays,
-                    const float* t_starts, const float* t_ends,
+                    int64_t n_samples, const float* t_starts, const float* t_ends,
                     const float* sigmas, const float* rgbs,
                     float early_stop_eps, const float* g_color,
                     const float* g_opacity, const float* g_depth,
@@ -237,7 +241,8 @@ int64_t nacc_render_mse_workspace_size(int64_t n_rays);
  *   workspace  device scratch of nacc_render_mse_workspace_size bytes.
  */
 int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays,
-                            const float* t_starts, const float* t_ends,
+                            int64_t n_samples, const float* t_starts,
+                            const float* t_ends,
                             const float* sigmas, const float* rgbs,
                             float early_stop_eps, const float* target,
                             float* color, float* opacity, float* depth,
@@ -261,12 +266,13 @@ int nacc_grid_decay(float* occ, int64_t n_cells, float decay, void* stream);
  * counter (q, step, 0, 0), key (seed, 0) -> (r0, r1, r2, r3):
  *   cell     = ((r0 >> 32) * n_cells) >> 32, n_cells = levels * res^3
  *   jitter_i = (float)(r_{i+1} >> 40) * 2^-24
- *   x_i      = (lo_i + ((float)j_i + jitter_i) * h_i) * 2^level,
+ *   x_i      = lo_i + ((float)j_i + jitter_i) * h_i,
  *              h_i = fl32((hi_i - lo_i) / res), (j_0, j_1, j_2) the C-order
- *              index of the cell within its level, level = cell / res^3.
- * For AABB/CONTRACT grids pass levels = 1 (positions are then in the grid's
- * own coordinates, i.e. contracted space for CONTRACT).
- *   cells out int32[n]; positions out float[n][3].
+ *              index of the cell within its grid, grid = cell / res^3.
+ * CASCADE grids: `levels` is the number of levels and x is then scaled by
+ * 2^grid (exact).  Otherwise `levels` counts independent grids over the same
+ * box (grid = cell / res^3) and x is left in the box.
+ *   cells out int32[n] (global cell index); positions out float[n][3].
  */
 int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
                            const nacc_grid_desc* grid, int32_t levels,

@@ -1,0 +1,61 @@
+/*
+ * nacc_synth.h -- a synthetic radiance field for tests and benchmarks.
+ *
+ * NOT part of the method.  NerfAcc is field-agnostic: the user's radiance
+ * field is evaluated between marching and rendering (Sec. 3, sigma_fn /
+ * rgb_sigma_fn).  This analytic field stands in for that user field so the
+ * library can be exercised end to end without trained weights:
+ *   sigma(x) = sum_b peak_b * exp(-|x - c_b|^2 / (2 std_b^2))
+ *   rgb(x)   = 1 / (1 + exp(-(W x + bias)))          (W row-major 3x3)
+ * Sample positions are the FP32 midpoints x = o + d * ((t_start + t_end) * 0.5f)
+ * (no fused multiply-add).  Accuracy: a few FP32 ulps of the exponent
+ * arguments (relative error of sigma and rgb below 1e-5).
+ *
+ * Conventions as in nacc.h: device pointers, caller-owned memory, stream as
+ * void*, status codes, nacc_last_error() for messages.
+ */
+#ifndef NACC_SYNTH_H
+#define NACC_SYNTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Bytes of the prepared coefficient table for n_sets * n_blobs blobs. */
+int64_t nacc_synth_table_size(int32_t n_blobs, int32_t n_sets);
+
+/*
+ * Prepares the coefficient table (device memory of nacc_synth_table_size
+ * bytes) from the blob parameters:
+ *   centres float[n_sets][n_blobs][3] (one centre set per frame),
+ *   stds, peaks float[n_blobs], w float[3][3], bias float[3].
+ */
+int nacc_synth_prepare(const float* centres, const float* stds, const float* peaks, const float* w,
+                       const float* bias, int32_t n_blobs, int32_t n_sets, void* table, void* stream);
+
+/*
+ * sigma and rgb at the midpoints of packed samples.
+ *   n_rays    rays in rays_o / rays_d; samples naming another ray get 0.
+ *   ray_set   int32[n_rays] centre set of each ray, or NULL for set 0.
+ *   n_samples number of samples (or an upper bound when n_samples_dev is
+ *             given: then only the first *n_samples_dev are evaluated).
+ *   sigmas    out float[n_samples]; rgbs out float[n_samples][3] (nullable).
+ */
+int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets, const float* rays_o,
+                             const float* rays_d, int64_t n_rays, const int32_t* ray_set,
+                             const int32_t* ray_indices,
+                             const float* t_starts, const float* t_ends, int64_t n_samples,
+                             const int64_t* n_samples_dev, float* sigmas, float* rgbs, void* stream);
+
+/* sigma (and rgb, nullable) at points float[n][3]; point_set nullable. */
+int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, const float* points,
+                            const int32_t* point_set, int64_t n, float* sigmas, float* rgbs, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NACC_SYNTH_H */

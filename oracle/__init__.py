@@ -71,7 +71,7 @@ def _load():
     lib.oracle_philox4x64_10.argtypes = [_P, _P, _P]
     lib.oracle_grid_sample_cells.restype = None
     lib.oracle_grid_sample_cells.argtypes = [_U64, _U64, _I64, _I32, _I32,
-                                             _P, _P, _P]
+                                             _I32, _P, _P, _P]
     lib.oracle_grid_decay.restype = None
     lib.oracle_grid_decay.argtypes = [_P, _I64, _F]
     lib.oracle_grid_update_max.restype = None
@@ -227,13 +227,14 @@ def philox4x64_10(counter, key):
     return out
 
 
-def grid_sample_cells(seed, step, n, res, box, levels=1):
-    """Random cells and jittered positions of update `step`."""
+def grid_sample_cells(seed, step, n, res, box, levels=1, cascade=False):
+    """Random cells and jittered positions of update `step` (positions scaled
+    by 2^level for cascaded grids)."""
     lib = _load()
     bx = _c(box, np.float32).ravel()
     cells = np.zeros(n, np.int32)
     pos = np.zeros((n, 3), np.float32)
-    lib.oracle_grid_sample_cells(seed, step, n, res, levels, _ptr(bx),
+    lib.oracle_grid_sample_cells(seed, step, n, res, levels, int(cascade), _ptr(bx),
                                  _ptr(cells), _ptr(pos))
     return cells, pos
 

@@ -183,8 +183,10 @@ int64_t oracle_march(const float* rays_o, const float* rays_d,
         int64_t grid = (grid_id != NULL && lookup != 1) ? grid_id[r] : 0;
         int32_t count = 0;
         float t_near, t_far;
-        if (clip_ray(o, d, clip_lo, clip_hi, near_plane, far_plane, &t_near,
-                     &t_far)) {
+        /* a ray naming a grid that does not exist is a miss */
+        int valid_grid = grid >= 0 && grid < n_grids;
+        if (valid_grid && clip_ray(o, d, clip_lo, clip_hi, near_plane, far_plane,
+                                   &t_near, &t_far)) {
             float t0 = t_near;
             for (int64_t k = 0; k < ORACLE_MAX_CANDIDATES; ++k) {
                 float t1;
@@ -401,7 +403,8 @@ void oracle_philox4x64_10(const uint64_t* counter, const uint64_t* key,
  * h_i = fl32((hi_i - lo_i) / res) and (j_0, j_1, j_2) is the C-order cell.
  */
 void oracle_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
-                              int32_t res, int32_t levels, const float* box,
+                              int32_t res, int32_t levels, int32_t cascade,
+                              const float* box,
                               int32_t* cells, float* positions) {
     int64_t per_grid = (int64_t)res * res * res;
     uint64_t n_cells = (uint64_t)per_grid * (uint64_t)levels;
@@ -415,7 +418,7 @@ void oracle_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
         oracle_philox4x64_10(ctr, key, rnd);
         uint64_t cell = ((rnd[0] >> 32) * n_cells) >> 32;
         cells[q] = (int32_t)cell;
-        int64_t level = (int64_t)cell / per_grid;
+        int64_t level = cascade ? (int64_t)cell / per_grid : 0;
         int64_t local = (int64_t)cell % per_grid;
         int64_t j[3] = {local / ((int64_t)res * res), (local / res) % res, local % res};
         for (int i = 0; i < 3; ++i) {

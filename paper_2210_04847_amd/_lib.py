@@ -1,0 +1,329 @@
+"""ctypes binding of the gfx950 library (libnacc.so): argument marshalling only.
+
+Every call takes torch tensors that live on the GPU, checks dtype, device and
+contiguity, and passes raw pointers plus torch's current HIP stream to the C
+ABI declared in include/nacc.h and include/nacc_synth.h.  No arithmetic of the
+method happens here.  If the library has not been built, importing this module
+raises ImportError: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads torch's HIP runtime first; libnacc.so then binds to it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnacc.so")
+
+NACC_OK, NACC_EINVAL, NACC_ESHAPE, NACC_ECAPACITY, NACC_EHIP, NACC_ENOTSUP = 0, -1, -2, -3, -4, -5
+LOOKUP_AABB, LOOKUP_CASCADE, LOOKUP_CONTRACT = 0, 1, 2
+
+
+class NaccError(RuntimeError):
+    """A call into libnacc.so returned a non-zero status."""
+
+    def __init__(self, name, status, message):
+        super().__init__(f"{name}: {status_name(status)} ({status}): {message}")
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3),
+                ("res", ctypes.c_int32), ("n_grids", ctypes.c_int32),
+                ("lookup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MarchParams(ctypes.Structure):
+    _fields_ = [("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float),
+                ("dt", ctypes.c_float), ("dt_max", ctypes.c_float),
+                ("cone", ctypes.c_float), ("max_per_ray", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_U64 = ctypes.c_uint64
+_F = ctypes.c_float
+_SZ = ctypes.c_size_t
+_INT = ctypes.c_int
+
+_SIGNATURES = {
+    "nacc_version": (ctypes.c_char_p, []),
+    "nacc_last_error": (ctypes.c_char_p, []),
+    "nacc_status_str": (ctypes.c_char_p, [_INT]),
+    "nacc_march_workspace_size": (_I64, [_I64]),
+    "nacc_march_count": (_INT, [_P, _P, _P, _I64, _P, ctypes.POINTER(GridDesc),
+                                ctypes.POINTER(MarchParams), _P, _P, _P, _SZ, _P]),
+    "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, ctypes.POINTER(GridDesc),
+                               ctypes.POINTER(MarchParams), _P, _I64, _P, _P, _P, _P, _P]),
+    "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P]),
+    "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
+    "nacc_render_mse_workspace_size": (_I64, [_I64]),
+    "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P,
+                                       _P, _P, _P, _P, _SZ, _P]),
+    "nacc_grid_decay": (_INT, [_P, _I64, _F, _P]),
+    "nacc_grid_sample_cells": (_INT, [_U64, _U64, _I64, ctypes.POINTER(GridDesc), _I32,
+                                      _P, _P, _P]),
+    "nacc_grid_update_max": (_INT, [_P, _P, _P, _I64, _I64, _P]),
+    "nacc_grid_pack": (_INT, [_P, _I64, _F, _P, _P]),
+    "nacc_synth_table_size": (_I64, [_I32, _I32]),
+    "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _P, _P]),
+    "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
+                                        _P, _P, _P, _P]),
+    "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P]),
+}
+
+# Symbols declared in include/nacc.h and include/nacc_synth.h.
+EXPORTED = tuple(_SIGNATURES)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2210_04847_amd.build` "
+            "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_name(status: int) -> str:
+    return lib.nacc_status_str(status).decode()
+
+
+def version() -> str:
+    return lib.nacc_version().decode()
+
+
+def _check(name, status):
+    if status != NACC_OK:
+        raise NaccError(name, status, lib.nacc_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a tensor (None -> NULL)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, name, numel=None):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
+def grid_desc(lo, hi, res, n_grids=1, lookup=LOOKUP_AABB) -> GridDesc:
+    d = GridDesc()
+    for i in range(3):
+        d.lo[i] = float(lo[i])
+        d.hi[i] = float(hi[i])
+    d.res, d.n_grids, d.lookup, d.reserved = int(res), int(n_grids), int(lookup), 0
+    return d
+
+
+def march_params(near_plane, far_plane, dt, dt_max=1e10, cone=0.0, max_per_ray=0) -> MarchParams:
+    p = MarchParams()
+    p.near_plane, p.far_plane, p.dt = float(near_plane), float(far_plane), float(dt)
+    p.dt_max, p.cone, p.max_per_ray = float(dt_max), float(cone), int(max_per_ray)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers, one per C entry point (same names without the prefix).
+# ---------------------------------------------------------------------------
+
+def march_workspace_size(n_rays: int) -> int:
+    return int(lib.nacc_march_workspace_size(n_rays))
+
+
+def _grid_words(desc):
+    return desc.n_grids * desc.res ** 3 // 32
+
+
+def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, total,
+                workspace, stream=None):
+    n = rays_o.shape[0]
+    _need(rays_o, torch.float32, "rays_o", 3 * n)
+    _need(rays_d, torch.float32, "rays_d", 3 * n)
+    _need(grid_id, torch.int32, "grid_id", n)
+    _need(grid_bits, torch.int32, "grid_bits", _grid_words(desc))
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(total, torch.int64, "total", 1)
+    _need(workspace, torch.uint8, "workspace")
+    _check("nacc_march_count", lib.nacc_march_count(
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), ctypes.byref(desc),
+        ctypes.byref(params), _ptr(packed_info), _ptr(total), _ptr(workspace),
+        workspace.numel() if workspace is not None else 0, _stream(stream)))
+
+
+def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ray_indices,
+               t_starts, t_ends, status=None, stream=None):
+    n = rays_o.shape[0]
+    cap = ray_indices.numel()
+    _need(rays_o, torch.float32, "rays_o", 3 * n)
+    _need(rays_d, torch.float32, "rays_d", 3 * n)
+    _need(grid_id, torch.int32, "grid_id", n)
+    _need(grid_bits, torch.int32, "grid_bits", _grid_words(desc))
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(ray_indices, torch.int32, "ray_indices")
+    _need(t_starts, torch.float32, "t_starts", cap)
+    _need(t_ends, torch.float32, "t_ends", cap)
+    _need(status, torch.int32, "status", 1)
+    _check("nacc_march_fill", lib.nacc_march_fill(
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), ctypes.byref(desc),
+        ctypes.byref(params), _ptr(packed_info), cap, _ptr(ray_indices), _ptr(t_starts),
+        _ptr(t_ends), _ptr(status), _stream(stream)))
+
+
+def _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs):
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(t_starts, torch.float32, "t_starts")
+    _need(t_ends, torch.float32, "t_ends", e)
+    _need(sigmas, torch.float32, "sigmas", e)
+    _need(rgbs, torch.float32, "rgbs", 3 * e)
+    return n, e
+
+
+def render_fwd(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity,
+               depth, weights=None, stream=None):
+    n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
+    _need(color, torch.float32, "color", 3 * n)
+    _need(opacity, torch.float32, "opacity", n)
+    _need(depth, torch.float32, "depth", n)
+    _need(weights, torch.float32, "weights", e)
+    _check("nacc_render_fwd", lib.nacc_render_fwd(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
+        float(early_stop_eps), _ptr(color), _ptr(opacity), _ptr(depth), _ptr(weights),
+        _stream(stream)))
+
+
+def render_bwd(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, g_color,
+               g_opacity, g_depth, g_sigmas, g_rgbs, stream=None):
+    n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
+    _need(g_color, torch.float32, "g_color", 3 * n)
+    _need(g_opacity, torch.float32, "g_opacity", n)
+    _need(g_depth, torch.float32, "g_depth", n)
+    _need(g_sigmas, torch.float32, "g_sigmas", e)
+    _need(g_rgbs, torch.float32, "g_rgbs", 3 * e)
+    _check("nacc_render_bwd", lib.nacc_render_bwd(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
+        float(early_stop_eps), _ptr(g_color), _ptr(g_opacity), _ptr(g_depth), _ptr(g_sigmas),
+        _ptr(g_rgbs), _stream(stream)))
+
+
+def render_mse_workspace_size(n_rays: int) -> int:
+    return int(lib.nacc_render_mse_workspace_size(n_rays))
+
+
+def render_fwd_bwd_mse(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                       color, opacity, depth, g_sigmas, g_rgbs, loss, workspace, stream=None):
+    n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
+    _need(target, torch.float32, "target", 3 * n)
+    _need(color, torch.float32, "color", 3 * n)
+    _need(opacity, torch.float32, "opacity", n)
+    _need(depth, torch.float32, "depth", n)
+    _need(g_sigmas, torch.float32, "g_sigmas", e)
+    _need(g_rgbs, torch.float32, "g_rgbs", 3 * e)
+    _need(loss, torch.float32, "loss", 1)
+    _need(workspace, torch.uint8, "workspace")
+    _check("nacc_render_fwd_bwd_mse", lib.nacc_render_fwd_bwd_mse(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
+        float(early_stop_eps), _ptr(target), _ptr(color), _ptr(opacity), _ptr(depth),
+        _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss), _ptr(workspace), workspace.numel(),
+        _stream(stream)))
+
+
+def grid_decay(occ, decay, stream=None):
+    _need(occ, torch.float32, "occ")
+    _check("nacc_grid_decay", lib.nacc_grid_decay(_ptr(occ), occ.numel(), float(decay),
+                                                  _stream(stream)))
+
+
+def grid_sample_cells(seed, step, n, desc, levels, cells, positions, stream=None):
+    _need(cells, torch.int32, "cells", n)
+    _need(positions, torch.float32, "positions", 3 * n)
+    _check("nacc_grid_sample_cells", lib.nacc_grid_sample_cells(
+        int(seed), int(step), int(n), ctypes.byref(desc), int(levels), _ptr(cells),
+        _ptr(positions), _stream(stream)))
+
+
+def grid_update_max(occ, cells, values, stream=None):
+    n = cells.numel()
+    _need(occ, torch.float32, "occ")
+    _need(cells, torch.int32, "cells")
+    _need(values, torch.float32, "values", n)
+    _check("nacc_grid_update_max", lib.nacc_grid_update_max(
+        _ptr(occ), _ptr(cells), _ptr(values), n, occ.numel(), _stream(stream)))
+
+
+def grid_pack(occ, threshold, bits, stream=None):
+    _need(occ, torch.float32, "occ")
+    _need(bits, torch.int32, "bits", occ.numel() // 32)
+    _check("nacc_grid_pack", lib.nacc_grid_pack(_ptr(occ), occ.numel(), float(threshold),
+                                                _ptr(bits), _stream(stream)))
+
+
+def synth_table_size(n_blobs, n_sets) -> int:
+    return int(lib.nacc_synth_table_size(n_blobs, n_sets))
+
+
+def synth_prepare(centres, stds, peaks, w, bias, table, stream=None):
+    n_sets, n_blobs = centres.shape[0], centres.shape[1]
+    for t, nm in ((centres, "centres"), (stds, "stds"), (peaks, "peaks"), (w, "w"), (bias, "bias"),
+                  (table, "table")):
+        _need(t, torch.float32, nm)
+    _check("nacc_synth_prepare", lib.nacc_synth_prepare(
+        _ptr(centres), _ptr(stds), _ptr(peaks), _ptr(w), _ptr(bias), n_blobs, n_sets,
+        _ptr(table), _stream(stream)))
+
+
+def synth_field_samples(table, n_blobs, n_sets, rays_o, rays_d, ray_set, ray_indices, t_starts,
+                        t_ends, sigmas, rgbs=None, n_samples_dev=None, stream=None):
+    n = ray_indices.numel()
+    _need(table, torch.float32, "table")
+    _need(ray_indices, torch.int32, "ray_indices")
+    _need(ray_set, torch.int32, "ray_set", rays_o.numel() // 3)
+    _need(sigmas, torch.float32, "sigmas", n)
+    _need(rgbs, torch.float32, "rgbs", 3 * n)
+    _need(n_samples_dev, torch.int64, "n_samples_dev", 1)
+    _need(rays_o, torch.float32, "rays_o")
+    _need(rays_d, torch.float32, "rays_d", rays_o.numel())
+    _check("nacc_synth_field_samples", lib.nacc_synth_field_samples(
+        _ptr(table), n_blobs, n_sets, _ptr(rays_o), _ptr(rays_d), rays_o.numel() // 3,
+        _ptr(ray_set), _ptr(ray_indices),
+        _ptr(t_starts), _ptr(t_ends), n, _ptr(n_samples_dev), _ptr(sigmas), _ptr(rgbs),
+        _stream(stream)))
+
+
+def synth_field_points(table, n_blobs, n_sets, points, point_set, sigmas, rgbs=None, stream=None):
+    n = points.shape[0]
+    _need(table, torch.float32, "table")
+    _need(points, torch.float32, "points", 3 * n)
+    _need(point_set, torch.int32, "point_set", n)
+    _need(sigmas, torch.float32, "sigmas", n)
+    _need(rgbs, torch.float32, "rgbs", 3 * n)
+    _check("nacc_synth_field_points", lib.nacc_synth_field_points(
+        _ptr(table), n_blobs, n_sets, _ptr(points), _ptr(point_set), n, _ptr(sigmas), _ptr(rgbs),
+        _stream(stream)))

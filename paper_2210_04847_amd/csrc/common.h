@@ -1,0 +1,136 @@
+// Internal helpers of the gfx950 library: error reporting, launch checks and
+// wave64 cross-lane primitives built on DPP (data-parallel primitives).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nacc.h"
+
+namespace nacc {
+
+// Records a message for nacc_last_error() and returns `status`.
+int set_error(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// Clears the calling thread's message.
+void clear_error();
+// Converts a pending launch error into NACC_EHIP.
+int check_launch(const char* what);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Per-axis scale fl32(res / (hi - lo)): the quotient in FP64, rounded once.
+inline float axis_scale(int res, float lo, float hi) {
+    return static_cast<float>(static_cast<double>(res) /
+                              (static_cast<double>(hi) - static_cast<double>(lo)));
+}
+
+constexpr int kWave = 64;
+
+}  // namespace nacc
+
+#define NACC_REQUIRE(cond, status, ...)                    \
+    do {                                                   \
+        if (!(cond)) return ::nacc::set_error(status, __VA_ARGS__); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device side.  Every helper below must be called with all 64 lanes active
+// (wave-uniform control flow): DPP reads the registers of neighbouring lanes.
+// ---------------------------------------------------------------------------
+namespace nacc {
+namespace dev {
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ int bits_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform(T v);
+
+template <>
+__device__ __forceinline__ int uniform<int>(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <>
+__device__ __forceinline__ float uniform<float>(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+__device__ __forceinline__ float read_lane(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffu), lane);
+    uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int read_lane(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+// DPP move with 0 written into lanes whose source is out of range or masked.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp(double v) {
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffu), CTRL, ROW_MASK, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
+
+// DPP controls (GFX9 encoding).
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+
+// Inclusive prefix sum across the 64 lanes: Hillis-Steele within each row of
+// 16 lanes, then the row totals are carried by two row broadcasts.  The
+// association order is fixed, so results are deterministic.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T x) {
+    x = x + dpp<kRowShr1>(x);
+    x = x + dpp<kRowShr2>(x);
+    x = x + dpp<kRowShr4>(x);
+    x = x + dpp<kRowShr8>(x);
+    x = x + dpp<kRowBcast15, 0xa>(x);
+    x = x + dpp<kRowBcast31, 0xc>(x);
+    return x;
+}
+
+// The value of the lane below (0 in lane 0).
+template <typename T>
+__device__ __forceinline__ T shift_up_one(T x) {
+    return dpp<kWaveShr1>(x);
+}
+
+// Sum over the 64 lanes, returned in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+    return read_lane(wave_inclusive_sum(x), 63);
+}
+
+}  // namespace dev
+}  // namespace nacc

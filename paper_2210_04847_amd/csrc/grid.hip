@@ -1,0 +1,192 @@
+// Occupancy-grid update on gfx950 (NerfAcc, Sec. 2.1: a binary grid cached
+// and updated during training).  The update rule is delegated by the paper to
+// Instant-NGP; it is read here as: decay every cell, take the maximum with
+// fresh density samples at random jittered cell positions, threshold.
+//
+//   decay        occ[c] *= decay                       (streaming, float4)
+//   sample_cells Philox4x64-10 per sample -> cell, jittered position
+//   update_max   atomic max on the FP32 bit patterns (order-independent)
+//   pack         one ballot per wavefront -> two 32-bit words of bits
+#include <cmath>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using namespace nacc;
+using namespace nacc::dev;
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void decay_kernel(float* __restrict__ occ, int64_t n, float decay) {
+    const int64_t n4 = n / 4;
+    float4* occ4 = reinterpret_cast<float4*>(occ);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n4; i += stride) {
+        float4 v = occ4[i];
+        v.x = v.x * decay;
+        v.y = v.y * decay;
+        v.z = v.z * decay;
+        v.w = v.w * decay;
+        occ4[i] = v;
+    }
+    for (int64_t i = 4 * n4 + static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+        occ[i] = occ[i] * decay;
+    }
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 64x64 -> 128-bit products with the published multipliers, keys bumped by
+// the published Weyl constants between rounds.
+struct U64x4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                               uint64_t k1) {
+    constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
+    constexpr uint64_t kMul1 = 0xCA5A826395121157ull;
+    constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull;
+    constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t lo0 = kMul0 * c0, hi0 = __umul64hi(kMul0, c0);
+        const uint64_t lo1 = kMul1 * c2, hi1 = __umul64hi(kMul1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    return U64x4{{c0, c1, c2, c3}};
+}
+
+__global__ __launch_bounds__(kThreads) void sample_cells_kernel(uint64_t seed, uint64_t step, int64_t n, int res,
+                                                                 uint64_t n_cells, float lo0, float lo1, float lo2,
+                                                                 float h0, float h1, float h2, int cascade,
+                                                                 int32_t* __restrict__ cells,
+                                                                 float* __restrict__ positions) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (q >= n) return;
+    const U64x4 r = philox4x64_10(static_cast<uint64_t>(q), step, 0, 0, seed, 0);
+    const uint64_t cell = ((r.v[0] >> 32) * n_cells) >> 32;
+    cells[q] = static_cast<int32_t>(cell);
+    const uint64_t per_grid = static_cast<uint64_t>(res) * res * res;
+    const int level = cascade ? static_cast<int>(cell / per_grid) : 0;
+    const uint64_t local = cell % per_grid;
+    const int j0 = static_cast<int>(local / (static_cast<uint64_t>(res) * res));
+    const int j1 = static_cast<int>((local / res) % res);
+    const int j2 = static_cast<int>(local % res);
+    const float jit0 = static_cast<float>(r.v[1] >> 40) * 0x1p-24f;
+    const float jit1 = static_cast<float>(r.v[2] >> 40) * 0x1p-24f;
+    const float jit2 = static_cast<float>(r.v[3] >> 40) * 0x1p-24f;
+    positions[3 * q] = ldexpf(lo0 + (static_cast<float>(j0) + jit0) * h0, level);
+    positions[3 * q + 1] = ldexpf(lo1 + (static_cast<float>(j1) + jit1) * h1, level);
+    positions[3 * q + 2] = ldexpf(lo2 + (static_cast<float>(j2) + jit2) * h2, level);
+}
+
+// max on FP32 through integer atomics: non-negative floats order like their
+// signed bit patterns, negative floats order in reverse of their unsigned
+// bit patterns, and every non-negative pattern is below every negative one
+// as unsigned.  NaN values are skipped.
+__global__ __launch_bounds__(kThreads) void update_max_kernel(float* __restrict__ occ,
+                                                               const int32_t* __restrict__ cells,
+                                                               const float* __restrict__ values, int64_t n,
+                                                               int64_t n_cells) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (q >= n) return;
+    const int32_t c = cells[q];
+    const float v = values[q];
+    if (c < 0 || c >= n_cells || v != v) return;
+    if (!signbit(v)) {
+        atomicMax(reinterpret_cast<int*>(occ) + c, __float_as_int(v));
+    } else {
+        atomicMin(reinterpret_cast<unsigned int*>(occ) + c, __float_as_uint(v));
+    }
+}
+
+// One lane per cell; the wave's ballot is bits [64 w, 64 w + 64).
+__global__ __launch_bounds__(kThreads) void pack_kernel(const float* __restrict__ occ, int64_t n_cells,
+                                                         float threshold, uint32_t* __restrict__ bits) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    const bool set = i < n_cells && occ[i] > threshold;
+    const uint64_t m = ballot(set);
+    const int lane = lane_id();
+    const int64_t word = (i - lane) / 32;
+    if (lane == 0 && word < n_cells / 32) bits[word] = static_cast<uint32_t>(m);
+    if (lane == 32 && word + 1 < n_cells / 32) bits[word + 1] = static_cast<uint32_t>(m >> 32);
+}
+
+unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+extern "C" {
+
+int nacc_grid_decay(float* occ, int64_t n_cells, float decay, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_cells >= 0, NACC_EINVAL, "n_cells < 0");
+    NACC_REQUIRE(n_cells == 0 || occ != nullptr, NACC_EINVAL, "occ must be non-NULL");
+    NACC_REQUIRE(reinterpret_cast<uintptr_t>(occ) % 16 == 0, NACC_EINVAL, "occ must be 16-byte aligned");
+    if (n_cells == 0) return NACC_OK;
+    const int64_t work = (n_cells + 3) / 4;
+    const unsigned nb = static_cast<unsigned>(std::min<int64_t>(blocks_for(work), 8192));
+    hipLaunchKernelGGL(decay_kernel, dim3(nb), dim3(kThreads), 0, as_stream(stream), occ, n_cells, decay);
+    return check_launch("grid decay");
+}
+
+int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n, const nacc_grid_desc* grid, int32_t levels,
+                           int32_t* cells, float* positions, void* stream) {
+    clear_error();
+    NACC_REQUIRE(grid != nullptr, NACC_EINVAL, "grid must be non-NULL");
+    NACC_REQUIRE(n >= 0 && n <= INT32_MAX, NACC_EINVAL, "n = %lld out of [0, 2^31-1]", static_cast<long long>(n));
+    NACC_REQUIRE(n == 0 || (cells != nullptr && positions != nullptr), NACC_EINVAL, "outputs must be non-NULL");
+    NACC_REQUIRE(grid->res >= 1 && grid->res <= 1024, NACC_EINVAL, "grid res = %d out of [1, 1024]", grid->res);
+    NACC_REQUIRE(levels >= 1 && levels <= 16, NACC_EINVAL, "levels = %d out of [1, 16]", levels);
+    const uint64_t n_cells = static_cast<uint64_t>(grid->res) * grid->res * grid->res * levels;
+    NACC_REQUIRE(n_cells <= static_cast<uint64_t>(INT32_MAX), NACC_ESHAPE, "too many cells for int32 indices");
+    for (int i = 0; i < 3; ++i) {
+        NACC_REQUIRE(std::isfinite(grid->lo[i]) && std::isfinite(grid->hi[i]) && grid->lo[i] < grid->hi[i],
+                     NACC_EINVAL, "grid box axis %d is empty or not finite", i);
+    }
+    if (n == 0) return NACC_OK;
+    float h[3];
+    for (int i = 0; i < 3; ++i) {
+        h[i] = static_cast<float>((static_cast<double>(grid->hi[i]) - static_cast<double>(grid->lo[i])) /
+                                  static_cast<double>(grid->res));
+    }
+    hipLaunchKernelGGL(sample_cells_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, as_stream(stream), seed, step,
+                       n, grid->res, n_cells, grid->lo[0], grid->lo[1], grid->lo[2], h[0], h[1], h[2],
+                       grid->lookup == NACC_LOOKUP_CASCADE ? 1 : 0, cells, positions);
+    return check_launch("grid sample cells");
+}
+
+int nacc_grid_update_max(float* occ, const int32_t* cells, const float* values, int64_t n, int64_t n_cells,
+                         void* stream) {
+    clear_error();
+    NACC_REQUIRE(n >= 0 && n_cells >= 0, NACC_EINVAL, "negative size");
+    NACC_REQUIRE(n == 0 || (occ != nullptr && cells != nullptr && values != nullptr), NACC_EINVAL,
+                 "arguments must be non-NULL");
+    if (n == 0) return NACC_OK;
+    hipLaunchKernelGGL(update_max_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, as_stream(stream), occ, cells,
+                       values, n, n_cells);
+    return check_launch("grid update max");
+}
+
+int nacc_grid_pack(const float* occ, int64_t n_cells, float threshold, uint32_t* bits, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_cells >= 0 && n_cells % 32 == 0, NACC_ESHAPE, "n_cells = %lld must be a multiple of 32",
+                 static_cast<long long>(n_cells));
+    NACC_REQUIRE(n_cells == 0 || (occ != nullptr && bits != nullptr), NACC_EINVAL, "arguments must be non-NULL");
+    if (n_cells == 0) return NACC_OK;
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(n_cells)), dim3(kThreads), 0, as_stream(stream), occ, n_cells,
+                       threshold, bits);
+    return check_launch("grid pack");
+}
+
+}  // extern "C"

@@ -1,0 +1,565 @@
+// Occupancy-grid ray marching on gfx950 (NerfAcc, Sec. 2.1 "Ray Marching",
+// "Pruning Empty and Occluded Regions", "GPU Memory Efficiency").
+//
+// Samples are the lattice intervals of each ray whose midpoint lies in an
+// occupied cell.  Empty space is pruned while marching, so the ragged output
+// is produced by three steps:
+//   count  every ray's sample count, plus one partial sum per workgroup;
+//   scan   exclusive scan of the workgroup sums, then of the counts inside
+//          each workgroup -> packed_info (start, count) and the total;
+//   fill   the same traversal again, writing each sample at its offset.
+//
+// Uniform steps: one wavefront per ray, the 64 lanes test 64 consecutive
+// lattice candidates at once, so the 64 grid-word loads of an iteration are
+// independent (they overlap in flight instead of forming a dependent chain)
+// and the 256 KiB bit grid stays resident in the XCD's L2.  A ballot of the
+// occupied lanes gives the count (popcount) and, in the fill pass, each
+// lane's output slot (mbcnt), so the writes of a wave are contiguous.
+//
+// Cone steps: the lattice is a recurrence in t, so one lane walks one ray.
+//
+// All lattice arithmetic follows the FP32 contract in nacc.h: this file is
+// compiled with -ffp-contract=off and `fp contract(off)`, and uses only
+// correctly rounded + - * / sqrt, min/max, ldexp and float->int truncation of
+// non-negative values.
+#include <cmath>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using namespace nacc;
+using namespace nacc::dev;
+
+constexpr int kRaysPerBlock = 64;     // rays per workgroup in count/fill/scan
+constexpr int kUniformThreads = 256;  // 4 waves, 16 rays each
+constexpr int kMaxCandidates = 1 << 24;
+
+struct GridK {
+    float lo[3];
+    float s[3];        // fl32(res / (hi - lo))
+    float top;         // (float)(res - 1)
+    float base;        // cascade: half-extent of level 0
+    int res;
+    int n_grids;
+    uint32_t words;    // 32-bit words per grid
+};
+
+struct ClipK {
+    float lo[3];
+    float hi[3];
+};
+
+struct StepK {
+    float near_plane, far_plane, dt, dt_max, cone;
+    int max_per_ray;
+};
+
+// Ray against the clip box (FP32 slab test of the contract).
+__device__ __forceinline__ bool clip_ray(const float o[3], const float d[3], const ClipK& c,
+                                         float near_plane, float far_plane, float& t_near,
+                                         float& t_far) {
+    float t_enter = -INFINITY, t_exit = INFINITY;
+    bool miss = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] != 0.0f) {
+            float ta = (c.lo[i] - o[i]) / d[i];
+            float tb = (c.hi[i] - o[i]) / d[i];
+            t_enter = fmaxf(t_enter, fminf(ta, tb));
+            t_exit = fminf(t_exit, fmaxf(ta, tb));
+        } else if (!(o[i] >= c.lo[i] && o[i] <= c.hi[i])) {
+            miss = true;
+        }
+    }
+    t_near = fmaxf(t_enter, near_plane);
+    t_far = fminf(t_exit, far_plane);
+    return !miss && t_near < t_far;
+}
+
+// Occupancy bit of point x.  `word0` is the first word of the ray's grid
+// (box / contraction lookups); the cascade picks its level itself.
+template <int LOOKUP>
+__device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint32_t word0,
+                                         const GridK& g, float x0, float x1, float x2) {
+    if (LOOKUP == NACC_LOOKUP_CASCADE) {
+        // level = number of level boxes the point lies outside of, i.e. the
+        // smallest l with max|x_i| <= b 2^l, clamped to the last level.
+        float m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
+        int level = 0;
+        for (int l = 0; l < g.n_grids - 1; ++l) level += (m > ldexpf(g.base, l)) ? 1 : 0;
+        x0 = ldexpf(x0, -level);
+        x1 = ldexpf(x1, -level);
+        x2 = ldexpf(x2, -level);
+        word0 = static_cast<uint32_t>(level) * g.words;
+    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
+        float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
+        if (n > 1.0f) {
+            float f = (2.0f - 1.0f / n) / n;
+            x0 = x0 * f;
+            x1 = x1 * f;
+            x2 = x2 * f;
+        }
+    }
+    float u0 = fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top);
+    float u1 = fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top);
+    float u2 = fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top);
+    uint32_t res = static_cast<uint32_t>(g.res);
+    uint32_t cell = (static_cast<uint32_t>(static_cast<int>(u0)) * res +
+                     static_cast<uint32_t>(static_cast<int>(u1))) * res +
+                    static_cast<uint32_t>(static_cast<int>(u2));
+    uint32_t word = bits[word0 + (cell >> 5)];
+    return ((word >> (cell & 31u)) & 1u) != 0u;
+}
+
+// First word of the ray's grid, or false for an invalid grid id (the ray is
+// then treated as a miss).
+template <int LOOKUP>
+__device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id, int64_t r,
+                                            const GridK& g, uint32_t& word0) {
+    word0 = 0;
+    if (LOOKUP != NACC_LOOKUP_CASCADE && grid_id != nullptr) {
+        int gid = grid_id[r];
+        if (gid < 0 || gid >= g.n_grids) return false;
+        word0 = static_cast<uint32_t>(gid) * g.words;
+    }
+    return true;
+}
+
+// One ray, uniform steps, whole wave.  Returns the ray's sample count (the
+// same value in every lane).  FILL writes samples [0, limit) at `start`.
+template <int LOOKUP, bool FILL>
+__device__ __forceinline__ int march_ray_uniform(
+    int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const GridK& g,
+    const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    bool& overflow) {
+    const int lane = lane_id();
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    uint32_t word0;
+    if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
+    float t_near, t_far;
+    if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    int count = 0;
+    for (int k0 = 0; k0 < kMaxCandidates; k0 += kWave) {
+        const int k = k0 + lane;
+        const float t0 = t_near + static_cast<float>(k) * p.dt;
+        const bool live = t0 < t_far;
+        if (ballot(live) == 0) break;  // t_k is non-decreasing in k
+        const float t1 = t_near + static_cast<float>(k + 1) * p.dt;
+        const float tm = (t0 + t1) * 0.5f;
+        bool hit = false;
+        if (live) hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm,
+                                         o[2] + d[2] * tm);
+        const uint64_t m = ballot(hit);
+        if (FILL && hit) {
+            const int idx = count + bits_below(m);
+            if (idx < limit) {
+                const int64_t pos = start + idx;
+                if (pos >= 0 && pos < capacity) {
+                    ray_indices[pos] = static_cast<int32_t>(r);
+                    t_starts[pos] = t0;
+                    t_ends[pos] = t1;
+                } else {
+                    overflow = true;
+                }
+            }
+        }
+        count += __popcll(m);
+        if (p.max_per_ray > 0 && count >= p.max_per_ray) {
+            count = p.max_per_ray;
+            break;
+        }
+        if (FILL && count >= limit) break;
+    }
+    return count;
+}
+
+template <int LOOKUP>
+__global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
+    GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
+    int64_t* __restrict__ block_sums) {
+    __shared__ int64_t wave_total[kUniformThreads / kWave];
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    int64_t total = 0;
+    bool unused = false;
+    for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
+        const int64_t r = first + i;
+        if (r >= n_rays) break;
+        const int n = march_ray_uniform<LOOKUP, false>(r, rays_o, rays_d, grid_id, bits, g, c, p,
+                                                       0, 0, 0, nullptr, nullptr, nullptr, unused);
+        if (lane_id() == 0) packed_info[2 * r + 1] = n;
+        total += n;
+    }
+    if (lane_id() == 0) wave_total[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int w = 0; w < kUniformThreads / kWave; ++w) s += wave_total[w];
+        block_sums[blockIdx.x] = s;
+    }
+}
+
+template <int LOOKUP>
+__global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
+    GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    int32_t* __restrict__ status) {
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    bool overflow = false;
+    for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
+        const int64_t r = first + i;
+        if (r >= n_rays) break;
+        const int64_t start = packed_info[2 * r];
+        const int limit = uniform<int>(packed_info[2 * r + 1]);
+        if (limit == 0) continue;
+        march_ray_uniform<LOOKUP, true>(r, rays_o, rays_d, grid_id, bits, g, c, p, start, limit,
+                                        capacity, ray_indices, t_starts, t_ends, overflow);
+    }
+    if (overflow && status != nullptr) *status = NACC_ECAPACITY;
+}
+
+// One ray per lane, cone steps (the lattice is a recurrence in t).
+template <int LOOKUP, bool FILL>
+__device__ __forceinline__ int march_ray_cone(
+    int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const GridK& g,
+    const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    bool& overflow) {
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    uint32_t word0;
+    if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
+    float t_near, t_far;
+    if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    int count = 0;
+    float t0 = t_near;
+    for (int k = 0; k < kMaxCandidates; ++k) {
+        if (!(t0 < t_far)) break;
+        const float step = fminf(fmaxf(t0 * p.cone, p.dt), p.dt_max);
+        const float t1 = t0 + step;
+        if (!(t1 > t0)) break;
+        const float tm = (t0 + t1) * 0.5f;
+        if (occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm,
+                             o[2] + d[2] * tm)) {
+            if (p.max_per_ray > 0 && count >= p.max_per_ray) break;
+            if (FILL) {
+                if (count >= limit) break;
+                const int64_t pos = start + count;
+                if (pos >= 0 && pos < capacity) {
+                    ray_indices[pos] = static_cast<int32_t>(r);
+                    t_starts[pos] = t0;
+                    t_ends[pos] = t1;
+                } else {
+                    overflow = true;
+                }
+            }
+            ++count;
+        }
+        t0 = t1;
+    }
+    return count;
+}
+
+template <int LOOKUP>
+__global__ __launch_bounds__(kRaysPerBlock) void count_cone_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
+    GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
+    int64_t* __restrict__ block_sums) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    bool unused = false;
+    int n = 0;
+    if (r < n_rays) {
+        n = march_ray_cone<LOOKUP, false>(r, rays_o, rays_d, grid_id, bits, g, c, p, 0, 0, 0,
+                                          nullptr, nullptr, nullptr, unused);
+        packed_info[2 * r + 1] = n;
+    }
+    const int s = wave_sum(n);  // <= 64 * 2^24 fits int32
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s;
+}
+
+template <int LOOKUP>
+__global__ __launch_bounds__(kRaysPerBlock) void fill_cone_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
+    GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    int32_t* __restrict__ status) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    if (r >= n_rays) return;
+    const int limit = packed_info[2 * r + 1];
+    if (limit == 0) return;
+    bool overflow = false;
+    march_ray_cone<LOOKUP, true>(r, rays_o, rays_d, grid_id, bits, g, c, p, packed_info[2 * r],
+                                 limit, capacity, ray_indices, t_starts, t_ends, overflow);
+    if (overflow && status != nullptr) *status = NACC_ECAPACITY;
+}
+
+// Exclusive scan of the per-workgroup sums, in place, by one workgroup:
+// each thread sums a contiguous run, the 1024 run totals are scanned in LDS,
+// then each thread rewrites its run as exclusive offsets.  Integer, exact.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(
+    int64_t* __restrict__ sums, int64_t nb, int64_t* __restrict__ total) {
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t a = min(nb, static_cast<int64_t>(t) * per);
+    const int64_t b = min(nb, a + per);
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += sums[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t v = sums[i];
+        sums[i] = run;
+        run += v;
+    }
+    if (t == kScanThreads - 1) *total = part[t];
+}
+
+// packed_info[r].start = offset of r's workgroup + exclusive scan of the
+// counts inside it (one wave = the workgroup's 64 rays).  Starts that do
+// not fit int32 saturate; the fill pass then reports NACC_ECAPACITY.
+__global__ __launch_bounds__(kRaysPerBlock) void finalize_starts_kernel(
+    const int64_t* __restrict__ block_offsets, int64_t n_rays, int32_t* __restrict__ packed_info) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    const int n = r < n_rays ? packed_info[2 * r + 1] : 0;
+    const int incl = wave_inclusive_sum(n);
+    const int64_t start = block_offsets[blockIdx.x] + (incl - n);
+    if (r < n_rays) packed_info[2 * r] = static_cast<int32_t>(min(start, static_cast<int64_t>(INT32_MAX)));
+}
+
+__global__ void set_status_kernel(int32_t* status, int32_t value) { *status = value; }
+
+// --------------------------------------------------------------------------
+// Host side: validation and launch.
+// --------------------------------------------------------------------------
+
+int64_t num_blocks(int64_t n_rays) { return (n_rays + kRaysPerBlock - 1) / kRaysPerBlock; }
+
+int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uint32_t* bits,
+             const nacc_grid_desc* grid, const nacc_march_params* params) {
+    NACC_REQUIRE(grid != nullptr && params != nullptr, NACC_EINVAL, "grid and params must be non-NULL");
+    NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_rays));
+    NACC_REQUIRE(n_rays == 0 || (rays_o != nullptr && rays_d != nullptr && bits != nullptr),
+                 NACC_EINVAL, "rays_o, rays_d and grid_bits must be non-NULL");
+    const int res = grid->res;
+    NACC_REQUIRE(res >= 1 && res <= 1024, NACC_EINVAL, "grid res = %d out of [1, 1024]", res);
+    const int64_t cells = static_cast<int64_t>(res) * res * res;
+    NACC_REQUIRE(cells % 32 == 0, NACC_ESHAPE, "res^3 = %lld is not a multiple of 32",
+                 static_cast<long long>(cells));
+    NACC_REQUIRE(grid->lookup >= 0 && grid->lookup <= 2, NACC_EINVAL, "unknown lookup mode %d", grid->lookup);
+    NACC_REQUIRE(grid->n_grids >= 1, NACC_EINVAL, "n_grids = %d < 1", grid->n_grids);
+    NACC_REQUIRE(static_cast<int64_t>(grid->n_grids) * (cells / 32) <= UINT32_MAX, NACC_ESHAPE,
+                 "grid array exceeds 2^32 words");
+    for (int i = 0; i < 3; ++i) {
+        NACC_REQUIRE(std::isfinite(grid->lo[i]) && std::isfinite(grid->hi[i]) && grid->lo[i] < grid->hi[i],
+                     NACC_EINVAL, "grid box axis %d is empty or not finite", i);
+    }
+    if (grid->lookup == NACC_LOOKUP_CASCADE) {
+        NACC_REQUIRE(grid->n_grids <= 16, NACC_EINVAL, "cascade levels = %d > 16", grid->n_grids);
+        int e = 0;
+        const float b = grid->hi[0];
+        NACC_REQUIRE(std::frexp(b, &e) == 0.5f, NACC_EINVAL, "cascade half-extent %g is not a power of two", b);
+        for (int i = 0; i < 3; ++i) {
+            NACC_REQUIRE(grid->hi[i] == b && grid->lo[i] == -b, NACC_EINVAL,
+                         "cascade level-0 box must be [-b, b]^3");
+        }
+    }
+    const nacc_march_params& p = *params;
+    NACC_REQUIRE(std::isfinite(p.dt) && p.dt > 0.0f, NACC_EINVAL, "dt = %g must be finite and > 0", p.dt);
+    NACC_REQUIRE(std::isfinite(p.cone) && p.cone >= 0.0f, NACC_EINVAL, "cone = %g must be finite and >= 0",
+                 p.cone);
+    NACC_REQUIRE(p.cone == 0.0f || p.dt_max >= p.dt, NACC_EINVAL, "dt_max = %g < dt = %g", p.dt_max, p.dt);
+    NACC_REQUIRE(!std::isnan(p.near_plane) && !std::isnan(p.far_plane), NACC_EINVAL, "near/far is NaN");
+    NACC_REQUIRE(p.max_per_ray >= 0, NACC_EINVAL, "max_per_ray = %d < 0", p.max_per_ray);
+    return NACC_OK;
+}
+
+void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params, GridK& g, ClipK& c,
+                    StepK& p) {
+    for (int i = 0; i < 3; ++i) {
+        g.lo[i] = grid.lo[i];
+        g.s[i] = axis_scale(grid.res, grid.lo[i], grid.hi[i]);
+        c.lo[i] = grid.lo[i];
+        c.hi[i] = grid.hi[i];
+        if (grid.lookup == NACC_LOOKUP_CASCADE) {
+            c.lo[i] = std::ldexp(grid.lo[i], grid.n_grids - 1);
+            c.hi[i] = std::ldexp(grid.hi[i], grid.n_grids - 1);
+        } else if (grid.lookup == NACC_LOOKUP_CONTRACT) {
+            c.lo[i] = -INFINITY;
+            c.hi[i] = INFINITY;
+        }
+    }
+    g.top = static_cast<float>(grid.res - 1);
+    g.base = grid.hi[0];
+    g.res = grid.res;
+    g.n_grids = grid.n_grids;
+    g.words = static_cast<uint32_t>(static_cast<int64_t>(grid.res) * grid.res * grid.res / 32);
+    p.near_plane = params.near_plane;
+    p.far_plane = params.far_plane;
+    p.dt = params.dt;
+    p.dt_max = params.dt_max;
+    p.cone = params.cone;
+    p.max_per_ray = params.max_per_ray;
+}
+
+template <int LOOKUP>
+void launch_count(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
+                  int64_t n, const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p,
+                  int32_t* packed, int64_t* sums) {
+    if (cone) {
+        hipLaunchKernelGGL(count_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                           bits, g, c, p, packed, sums);
+    } else {
+        hipLaunchKernelGGL(count_uniform_kernel<LOOKUP>, dim3(nb), dim3(kUniformThreads), 0, s, o, d, gid,
+                           n, bits, g, c, p, packed, sums);
+    }
+}
+
+template <int LOOKUP>
+void launch_fill(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
+                 int64_t n, const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p,
+                 const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
+                 int32_t* status) {
+    if (cone) {
+        hipLaunchKernelGGL(fill_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, bits,
+                           g, c, p, packed, capacity, ri, ts, te, status);
+    } else {
+        hipLaunchKernelGGL(fill_uniform_kernel<LOOKUP>, dim3(nb), dim3(kUniformThreads), 0, s, o, d, gid, n,
+                           bits, g, c, p, packed, capacity, ri, ts, te, status);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t nacc_march_workspace_size(int64_t n_rays) {
+    if (n_rays < 0) return -1;
+    return ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+}
+
+int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
+                     const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
+                     int32_t* packed_info, int64_t* total, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+    clear_error();
+    int st = validate(rays_o, rays_d, n_rays, grid_bits, grid, params);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(total != nullptr, NACC_EINVAL, "total must be non-NULL");
+    NACC_REQUIRE(n_rays == 0 || packed_info != nullptr, NACC_EINVAL, "packed_info must be non-NULL");
+    const int64_t need = nacc_march_workspace_size(n_rays);
+    NACC_REQUIRE(need == 0 || workspace != nullptr, NACC_EINVAL, "workspace must be non-NULL");
+    NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE,
+                 "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(need));
+    GridK g;
+    ClipK c;
+    StepK p;
+    make_constants(*grid, *params, g, c, p);
+    hipStream_t s = as_stream(stream);
+    const int64_t nb = num_blocks(n_rays);
+    int64_t* sums = static_cast<int64_t*>(workspace);
+    const bool cone = params->cone > 0.0f;
+    if (nb > 0) {
+        switch (grid->lookup) {
+            case NACC_LOOKUP_AABB:
+                launch_count<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                                               packed_info, sums);
+                break;
+            case NACC_LOOKUP_CASCADE:
+                launch_count<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                                                  p, packed_info, sums);
+                break;
+            default:
+                launch_count<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
+                                                   c, p, packed_info, sums);
+                break;
+        }
+        st = check_launch("march count");
+        if (st != NACC_OK) return st;
+    }
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
+    st = check_launch("march scan");
+    if (st != NACC_OK) return st;
+    if (nb > 0) {
+        hipLaunchKernelGGL(finalize_starts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, sums, n_rays,
+                           packed_info);
+        st = check_launch("march starts");
+    }
+    return st;
+}
+
+int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
+                    const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
+                    const int32_t* packed_info, int64_t capacity, int32_t* ray_indices, float* t_starts,
+                    float* t_ends, int32_t* status, void* stream) {
+    clear_error();
+    int st = validate(rays_o, rays_d, n_rays, grid_bits, grid, params);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(capacity >= 0 && capacity <= INT32_MAX, NACC_ECAPACITY,
+                 "capacity = %lld out of [0, 2^31-1]", static_cast<long long>(capacity));
+    NACC_REQUIRE(n_rays == 0 || packed_info != nullptr, NACC_EINVAL, "packed_info must be non-NULL");
+    NACC_REQUIRE(capacity == 0 || (ray_indices != nullptr && t_starts != nullptr && t_ends != nullptr),
+                 NACC_EINVAL, "sample outputs must be non-NULL");
+    GridK g;
+    ClipK c;
+    StepK p;
+    make_constants(*grid, *params, g, c, p);
+    hipStream_t s = as_stream(stream);
+    if (status != nullptr) {
+        hipLaunchKernelGGL(set_status_kernel, dim3(1), dim3(1), 0, s, status, static_cast<int32_t>(NACC_OK));
+        st = check_launch("march status");
+        if (st != NACC_OK) return st;
+    }
+    const int64_t nb = num_blocks(n_rays);
+    if (nb == 0) return NACC_OK;
+    const bool cone = params->cone > 0.0f;
+    switch (grid->lookup) {
+        case NACC_LOOKUP_AABB:
+            launch_fill<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                                          packed_info, capacity, ray_indices, t_starts, t_ends, status);
+            break;
+        case NACC_LOOKUP_CASCADE:
+            launch_fill<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                                             packed_info, capacity, ray_indices, t_starts, t_ends, status);
+            break;
+        default:
+            launch_fill<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                                              packed_info, capacity, ray_indices, t_starts, t_ends, status);
+            break;
+    }
+    return check_launch("march fill");
+}
+
+}  // extern "C"

@@ -1,0 +1,450 @@
+// Packed differentiable volume rendering on gfx950 (NerfAcc, Eq. 1 and
+// Sec. 2.2 "Differentiable Rendering"; early termination from Sec. 2.1).
+//
+// One wavefront per ray.  The ray's samples are read in chunks of 64, one per
+// lane, with coalesced loads of the packed arrays.  Inside a chunk the
+// exclusive transmittance comes from a DPP prefix sum of tau = sigma * delta
+// over the 64 lanes; the running prefix across chunks is carried in FP64.
+// The same routine (chunk_transmittance) produces T in the forward, the
+// backward and the fused kernels, so all three place the early-termination
+// cut on the same sample.
+//
+// Backward: g_sigma_i = delta_i (T_{i+1} v_i - S_i), S_i = sum_{k>i} w_k v_k.
+// S_i is formed as (FP64 total) - (FP64 inclusive prefix): in FP64 this
+// difference keeps full FP32 accuracy even where T is ~1e-4 and S_i is tiny,
+// which the FP32 total-minus-prefix form would not.
+#include <cmath>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using namespace nacc;
+using namespace nacc::dev;
+
+constexpr int kRenderThreads = 256;  // 4 waves
+constexpr int kRaysPerRenderBlock = kRenderThreads / kWave;
+
+struct Sample {
+    float t0, t1, sigma, r, g, b;
+};
+
+__device__ __forceinline__ Sample load_sample(bool valid, int64_t s, const float* __restrict__ ts,
+                                              const float* __restrict__ te, const float* __restrict__ sig,
+                                              const float* __restrict__ rgb) {
+    Sample x{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (valid) {
+        x.t0 = ts[s];
+        x.t1 = te[s];
+        x.sigma = sig[s];
+        x.r = rgb[3 * s];
+        x.g = rgb[3 * s + 1];
+        x.b = rgb[3 * s + 2];
+    }
+    return x;
+}
+
+// T at the start and the end of each lane's sample, given the FP64 prefix
+// of tau before the chunk.  Returns the inclusive chunk prefix in `incl`.
+struct Trans {
+    float tau;    // sigma * delta
+    float incl;   // inclusive prefix of tau inside the chunk
+    float t_in;   // T_i  = exp(-(carry + exclusive prefix))
+};
+
+__device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double carry) {
+    Trans t;
+    t.tau = x.sigma * (x.t1 - x.t0);
+    t.incl = wave_inclusive_sum(t.tau);
+    const float excl = shift_up_one(t.incl);
+    t.t_in = expf(-static_cast<float>(carry + static_cast<double>(excl)));
+    return t;
+}
+
+__device__ __forceinline__ float t_out(const Trans& t, double carry) {
+    return expf(-static_cast<float>(carry + static_cast<double>(t.incl)));
+}
+
+// Number of leading lanes kept in this chunk: the first valid lane with
+// T < eps and every lane after it are cut (64 = no cut here).
+__device__ __forceinline__ int chunk_keep(bool valid, float t_in, float eps) {
+    if (!(eps > 0.0f)) return kWave;
+    const uint64_t m = ballot(valid && t_in < eps);
+    return m == 0 ? kWave : static_cast<int>(__builtin_ctzll(m));
+}
+
+// The ray's sample range from packed_info; a range that does not lie inside
+// [0, n_samples) is treated as an empty ray, so no access leaves the arrays.
+__device__ __forceinline__ void ray_range(const int32_t* __restrict__ packed_info, int64_t r, int64_t n_samples,
+                                          int64_t& start, int& n) {
+    const int s0 = uniform<int>(packed_info[2 * r]);
+    const int c0 = uniform<int>(packed_info[2 * r + 1]);
+    const bool ok = s0 >= 0 && c0 >= 0 && static_cast<int64_t>(s0) + c0 <= n_samples;
+    start = ok ? s0 : 0;
+    n = ok ? c0 : 0;
+}
+
+template <bool WEIGHTS>
+__global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
+    const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
+    const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
+    float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth,
+    float* __restrict__ weights) {
+    const int lane = lane_id();
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock +
+                      uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    if (r >= n_rays) return;
+    int64_t start;
+    int n;
+    ray_range(packed_info, r, n_samples, start, n);
+    double carry = 0.0;
+    float acc_r = 0.0f, acc_g = 0.0f, acc_b = 0.0f, acc_a = 0.0f, acc_d = 0.0f;
+    int c = 0;
+    for (; c < n; c += kWave) {
+        const int i = c + lane;
+        const bool valid = i < n;
+        const int64_t s = start + i;
+        const Sample x = load_sample(valid, s, ts, te, sig, rgb);
+        const Trans t = chunk_transmittance(x, carry);
+        const int keep_n = chunk_keep(valid, t.t_in, eps);
+        const bool keep = valid && lane < keep_n;
+        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        acc_r += w * x.r;
+        acc_g += w * x.g;
+        acc_b += w * x.b;
+        acc_a += w;
+        acc_d += w * ((x.t0 + x.t1) * 0.5f);
+        if (WEIGHTS && valid) weights[s] = w;
+        carry += static_cast<double>(read_lane(t.incl, 63));
+        if (keep_n < kWave) {
+            c += kWave;
+            break;
+        }
+    }
+    if (WEIGHTS) {
+        for (; c < n; c += kWave) {
+            if (c + lane < n) weights[start + c + lane] = 0.0f;
+        }
+    }
+    acc_r = wave_sum(acc_r);
+    acc_g = wave_sum(acc_g);
+    acc_b = wave_sum(acc_b);
+    acc_a = wave_sum(acc_a);
+    acc_d = wave_sum(acc_d);
+    if (lane == 0) {
+        color[3 * r] = acc_r;
+        color[3 * r + 1] = acc_g;
+        color[3 * r + 2] = acc_b;
+        opacity[r] = acc_a;
+        depth[r] = acc_d;
+    }
+}
+
+// Upstream gradient of one ray: v_i = gc . rgb_i + ga + gd * m_i.
+struct RayGrad {
+    float gr, gg, gb, ga, gd;
+};
+
+// In FP64, so that the total and the prefixes of w v in the two passes are
+// sums of the same terms to FP64 rounding.
+__device__ __forceinline__ double vdot(const RayGrad& q, const Sample& x) {
+    const double m = static_cast<double>((x.t0 + x.t1) * 0.5f);
+    return static_cast<double>(q.gr) * x.r + static_cast<double>(q.gg) * x.g + static_cast<double>(q.gb) * x.b +
+           static_cast<double>(q.ga) + static_cast<double>(q.gd) * m;
+}
+
+// Pass A of the backward: the cut (samples kept) and sum_{k<cut} w_k v_k.
+__device__ __forceinline__ void backward_pass_a(int64_t start, int n, const float* __restrict__ ts,
+                                                const float* __restrict__ te, const float* __restrict__ sig,
+                                                const float* __restrict__ rgb, float eps, const RayGrad& q,
+                                                int& kept, double& total) {
+    const int lane = lane_id();
+    double carry = 0.0;
+    double acc = 0.0;
+    kept = n;
+    for (int c = 0; c < n; c += kWave) {
+        const int i = c + lane;
+        const bool valid = i < n;
+        const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
+        const Trans t = chunk_transmittance(x, carry);
+        const int keep_n = chunk_keep(valid, t.t_in, eps);
+        const bool keep = valid && lane < keep_n;
+        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        acc += static_cast<double>(w) * vdot(q, x);
+        carry += static_cast<double>(read_lane(t.incl, 63));
+        if (keep_n < kWave) {
+            kept = c + keep_n;
+            break;
+        }
+    }
+    total = wave_sum(acc);
+}
+
+// Pass B: recompute T and w chunk by chunk, form the FP64 suffix sums and
+// write both gradients (zeros from the cut on).
+__device__ __forceinline__ void backward_pass_b(int64_t start, int n, int kept, double total,
+                                                const float* __restrict__ ts, const float* __restrict__ te,
+                                                const float* __restrict__ sig, const float* __restrict__ rgb,
+                                                const RayGrad& q, float* __restrict__ g_sigmas,
+                                                float* __restrict__ g_rgbs) {
+    const int lane = lane_id();
+    double carry = 0.0;     // prefix of tau
+    double carry_wv = 0.0;  // prefix of w v
+    int c = 0;
+    for (; c < kept; c += kWave) {
+        const int i = c + lane;
+        const bool valid = i < n;
+        const int64_t s = start + i;
+        const Sample x = load_sample(valid && i < kept, s, ts, te, sig, rgb);
+        const Trans t = chunk_transmittance(x, carry);
+        const bool keep = i < kept;
+        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        const double v = vdot(q, x);
+        const double wv = static_cast<double>(w) * v;
+        const double incl_wv = wave_inclusive_sum(wv) + carry_wv;
+        if (valid) {
+            float gs = 0.0f, gr = 0.0f, gg = 0.0f, gb = 0.0f;
+            if (keep) {
+                const double suffix = total - incl_wv;
+                const double dtau = static_cast<double>(t_out(t, carry)) * v - suffix;
+                gs = static_cast<float>(static_cast<double>(x.t1 - x.t0) * dtau);
+                gr = w * q.gr;
+                gg = w * q.gg;
+                gb = w * q.gb;
+            }
+            g_sigmas[s] = gs;
+            g_rgbs[3 * s] = gr;
+            g_rgbs[3 * s + 1] = gg;
+            g_rgbs[3 * s + 2] = gb;
+        }
+        carry += static_cast<double>(read_lane(t.incl, 63));
+        carry_wv = read_lane(incl_wv, 63);
+    }
+    // chunks entirely past the cut: zeros, no loads
+    for (; c < n; c += kWave) {
+        const int i = c + lane;
+        if (i < n) {
+            const int64_t s = start + i;
+            g_sigmas[s] = 0.0f;
+            g_rgbs[3 * s] = 0.0f;
+            g_rgbs[3 * s + 1] = 0.0f;
+            g_rgbs[3 * s + 2] = 0.0f;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
+    const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
+    const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
+    const float* __restrict__ g_color, const float* __restrict__ g_opacity, const float* __restrict__ g_depth,
+    float* __restrict__ g_sigmas, float* __restrict__ g_rgbs) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock +
+                      uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    if (r >= n_rays) return;
+    int64_t start;
+    int n;
+    ray_range(packed_info, r, n_samples, start, n);
+    if (n == 0) return;
+    RayGrad q;
+    q.gr = uniform<float>(g_color[3 * r]);
+    q.gg = uniform<float>(g_color[3 * r + 1]);
+    q.gb = uniform<float>(g_color[3 * r + 2]);
+    q.ga = g_opacity != nullptr ? uniform<float>(g_opacity[r]) : 0.0f;
+    q.gd = g_depth != nullptr ? uniform<float>(g_depth[r]) : 0.0f;
+    int kept;
+    double total;
+    backward_pass_a(start, n, ts, te, sig, rgb, eps, q, kept, total);
+    backward_pass_b(start, n, kept, total, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
+}
+
+// Fused forward + MSE + backward.  Pass A is the forward with the colour
+// accumulated in FP64, which also gives sum_k w_k v_k = g_C . C exactly
+// enough for the suffix sums of pass B (v_k = g_C . rgb_k here).
+__global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
+    const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
+    const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
+    const float* __restrict__ target, float inv_count2, float* __restrict__ color, float* __restrict__ opacity,
+    float* __restrict__ depth, float* __restrict__ g_sigmas, float* __restrict__ g_rgbs,
+    double* __restrict__ loss_partial) {
+    __shared__ double wave_loss[kRaysPerRenderBlock];
+    const int lane = lane_id();
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave;
+    double ray_loss = 0.0;
+    if (r < n_rays) {
+        int64_t start;
+        int n;
+        ray_range(packed_info, r, n_samples, start, n);
+        double carry = 0.0;
+        double acc_r = 0.0, acc_g = 0.0, acc_b = 0.0;
+        float acc_a = 0.0f, acc_d = 0.0f;
+        int kept = n;
+        for (int c = 0; c < n; c += kWave) {
+            const int i = c + lane;
+            const bool valid = i < n;
+            const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
+            const Trans t = chunk_transmittance(x, carry);
+            const int keep_n = chunk_keep(valid, t.t_in, eps);
+            const bool keep = valid && lane < keep_n;
+            const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+            acc_r += static_cast<double>(w) * x.r;
+            acc_g += static_cast<double>(w) * x.g;
+            acc_b += static_cast<double>(w) * x.b;
+            acc_a += w;
+            acc_d += w * ((x.t0 + x.t1) * 0.5f);
+            carry += static_cast<double>(read_lane(t.incl, 63));
+            if (keep_n < kWave) {
+                kept = c + keep_n;
+                break;
+            }
+        }
+        acc_r = wave_sum(acc_r);
+        acc_g = wave_sum(acc_g);
+        acc_b = wave_sum(acc_b);
+        acc_a = wave_sum(acc_a);
+        acc_d = wave_sum(acc_d);
+        const float cr = static_cast<float>(acc_r), cg = static_cast<float>(acc_g),
+                    cb = static_cast<float>(acc_b);
+        const float er = cr - target[3 * r], eg = cg - target[3 * r + 1], eb = cb - target[3 * r + 2];
+        RayGrad q;
+        q.gr = uniform<float>(er * inv_count2);
+        q.gg = uniform<float>(eg * inv_count2);
+        q.gb = uniform<float>(eb * inv_count2);
+        q.ga = 0.0f;
+        q.gd = 0.0f;
+        ray_loss = static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
+        if (lane == 0) {
+            color[3 * r] = cr;
+            color[3 * r + 1] = cg;
+            color[3 * r + 2] = cb;
+            opacity[r] = acc_a;
+            depth[r] = acc_d;
+        }
+        if (n > 0) {
+            const double total = static_cast<double>(q.gr) * acc_r + static_cast<double>(q.gg) * acc_g +
+                                 static_cast<double>(q.gb) * acc_b;
+            backward_pass_b(start, n, kept, total, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
+        }
+    }
+    if (lane == 0) wave_loss[wave] = ray_loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kRaysPerRenderBlock; ++w) s += wave_loss[w];
+        loss_partial[blockIdx.x] = s;
+    }
+}
+
+// loss = (sum of the partials, in a fixed order) / (3 n_rays).
+constexpr int kLossThreads = 1024;
+
+__global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const double* __restrict__ partial, int64_t nb,
+                                                                   double inv_count, float* __restrict__ loss) {
+    __shared__ double part[kLossThreads];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += kLossThreads) s += partial[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kLossThreads / 2; off > 0; off >>= 1) {
+        if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = static_cast<float>(part[0] * inv_count);
+}
+
+int64_t render_blocks(int64_t n_rays) { return (n_rays + kRaysPerRenderBlock - 1) / kRaysPerRenderBlock; }
+
+int validate_render(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* ts,
+                    const float* te, const float* sig, const float* rgb, float eps) {
+    NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_rays));
+    NACC_REQUIRE(n_samples >= 0 && n_samples <= INT32_MAX, NACC_EINVAL, "n_samples = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_samples));
+    NACC_REQUIRE(n_rays == 0 || packed_info != nullptr, NACC_EINVAL, "packed_info must be non-NULL");
+    NACC_REQUIRE(n_samples == 0 || (ts != nullptr && te != nullptr && sig != nullptr && rgb != nullptr),
+                 NACC_EINVAL, "sample inputs must be non-NULL");
+    NACC_REQUIRE(!std::isnan(eps) && eps >= 0.0f && eps < 1.0f, NACC_EINVAL, "early_stop_eps = %g out of [0, 1)",
+                 eps);
+    return NACC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                    const float* t_ends,
+                    const float* sigmas, const float* rgbs, float early_stop_eps, float* color, float* opacity,
+                    float* depth, float* weights, void* stream) {
+    clear_error();
+    int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(n_rays == 0 || (color != nullptr && opacity != nullptr && depth != nullptr), NACC_EINVAL,
+                 "color, opacity and depth must be non-NULL");
+    if (n_rays == 0) return NACC_OK;
+    hipStream_t s = as_stream(stream);
+    const dim3 grid(static_cast<unsigned>(render_blocks(n_rays)));
+    if (weights != nullptr) {
+        hipLaunchKernelGGL(render_fwd_kernel<true>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
+                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights);
+    } else {
+        hipLaunchKernelGGL(render_fwd_kernel<false>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
+                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights);
+    }
+    return check_launch("render fwd");
+}
+
+int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                    const float* t_ends,
+                    const float* sigmas, const float* rgbs, float early_stop_eps, const float* g_color,
+                    const float* g_opacity, const float* g_depth, float* g_sigmas, float* g_rgbs, void* stream) {
+    clear_error();
+    int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(n_rays == 0 || (g_color != nullptr && g_sigmas != nullptr && g_rgbs != nullptr), NACC_EINVAL,
+                 "g_color, g_sigmas and g_rgbs must be non-NULL");
+    if (n_rays == 0) return NACC_OK;
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(render_bwd_kernel, dim3(static_cast<unsigned>(render_blocks(n_rays))),
+                       dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs,
+                       early_stop_eps, g_color, g_opacity, g_depth, g_sigmas, g_rgbs);
+    return check_launch("render bwd");
+}
+
+int64_t nacc_render_mse_workspace_size(int64_t n_rays) {
+    if (n_rays < 0) return -1;
+    return ((render_blocks(n_rays) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
+}
+
+int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                            const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
+                            const float* target, float* color, float* opacity, float* depth, float* g_sigmas,
+                            float* g_rgbs, float* loss, void* workspace, size_t workspace_bytes, void* stream) {
+    clear_error();
+    int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(n_rays > 0, NACC_EINVAL, "the mean squared error needs n_rays > 0");
+    NACC_REQUIRE(target != nullptr && color != nullptr && opacity != nullptr && depth != nullptr &&
+                     g_sigmas != nullptr && g_rgbs != nullptr && loss != nullptr && workspace != nullptr,
+                 NACC_EINVAL, "outputs, target and workspace must be non-NULL");
+    const int64_t need = nacc_render_mse_workspace_size(n_rays);
+    NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE, "workspace of %zu bytes, need %lld",
+                 workspace_bytes, static_cast<long long>(need));
+    hipStream_t s = as_stream(stream);
+    const int64_t nb = render_blocks(n_rays);
+    const double count = 3.0 * static_cast<double>(n_rays);
+    const float inv_count2 = static_cast<float>(2.0 / count);
+    double* partial = static_cast<double*>(workspace);
+    hipLaunchKernelGGL(render_mse_kernel, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s,
+                       packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                       inv_count2,
+                       color, opacity, depth, g_sigmas, g_rgbs, partial);
+    st = check_launch("render fwd+bwd+mse");
+    if (st != NACC_OK) return st;
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, partial, nb, 1.0 / count, loss);
+    return check_launch("render loss");
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// Synthetic Gaussian-blob radiance field (test and benchmark input only; it
+// stands in for the user's field of Sec. 3 and is not part of the method).
+//
+// The coefficient table holds, per blob, (c_x, c_y, c_z, k, peak) with
+// k = -log2(e) / (2 std^2), so each blob costs one exp2 on the hardware
+// transcendental unit; the 9 + 3 colour coefficients follow the blobs.
+#include <cmath>
+
+#include "common.h"
+#include "nacc_synth.h"
+
+namespace {
+
+using namespace nacc;
+
+constexpr int kThreads = 256;
+constexpr int kBlobStride = 5;
+constexpr float kLog2e = 1.4426950408889634f;
+
+int64_t table_floats(int32_t n_blobs, int32_t n_sets) {
+    return static_cast<int64_t>(n_sets) * n_blobs * kBlobStride + 12;
+}
+
+__global__ void prepare_kernel(const float* __restrict__ centres, const float* __restrict__ stds,
+                               const float* __restrict__ peaks, const float* __restrict__ w,
+                               const float* __restrict__ bias, int32_t n_blobs, int32_t n_sets,
+                               float* __restrict__ table) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nb = static_cast<int64_t>(n_sets) * n_blobs;
+    if (i < nb) {
+        const int b = static_cast<int>(i % n_blobs);
+        const float s = stds[b];
+        float* e = table + kBlobStride * i;
+        e[0] = centres[3 * i];
+        e[1] = centres[3 * i + 1];
+        e[2] = centres[3 * i + 2];
+        e[3] = -kLog2e / (2.0f * s * s);
+        e[4] = peaks[b];
+    } else if (i < nb + 12) {
+        const int j = static_cast<int>(i - nb);
+        table[kBlobStride * nb + j] = j < 9 ? w[j] : bias[j - 9];
+    }
+}
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ void eval_field(const float* __restrict__ table, int n_blobs, int set, float x0, float x1,
+                                           float x2, float& sigma) {
+    const float* blob = table + static_cast<int64_t>(set) * n_blobs * kBlobStride;
+    float acc = 0.0f;
+    for (int b = 0; b < n_blobs; ++b) {
+        const float dx = x0 - blob[kBlobStride * b];
+        const float dy = x1 - blob[kBlobStride * b + 1];
+        const float dz = x2 - blob[kBlobStride * b + 2];
+        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        acc = fmaf(blob[kBlobStride * b + 4], exp2_fast(d2 * blob[kBlobStride * b + 3]), acc);
+    }
+    sigma = acc;
+}
+
+__device__ __forceinline__ void eval_rgb(const float* __restrict__ cc, float x0, float x1, float x2, float& r,
+                                         float& g, float& b) {
+    const float z0 = fmaf(cc[0], x0, fmaf(cc[1], x1, fmaf(cc[2], x2, cc[9])));
+    const float z1 = fmaf(cc[3], x0, fmaf(cc[4], x1, fmaf(cc[5], x2, cc[10])));
+    const float z2 = fmaf(cc[6], x0, fmaf(cc[7], x1, fmaf(cc[8], x2, cc[11])));
+    r = 1.0f / (1.0f + exp2_fast(-z0 * kLog2e));
+    g = 1.0f / (1.0f + exp2_fast(-z1 * kLog2e));
+    b = 1.0f / (1.0f + exp2_fast(-z2 * kLog2e));
+}
+
+// Sample midpoint, FP32, no contraction (matches the positions of the tests).
+__device__ __forceinline__ float midpoint_coord(float o, float d, float t0, float t1) {
+#pragma clang fp contract(off)
+    const float tm = (t0 + t1) * 0.5f;
+    return o + d * tm;
+}
+
+__global__ __launch_bounds__(kThreads) void field_samples_kernel(
+    const float* __restrict__ table, int n_blobs, int n_sets, const float* __restrict__ rays_o,
+    const float* __restrict__ rays_d, int64_t n_rays, const int32_t* __restrict__ ray_set,
+    const int32_t* __restrict__ ray_indices,
+    const float* __restrict__ ts, const float* __restrict__ te, int64_t n_cap, const int64_t* __restrict__ n_dev,
+    float* __restrict__ sigmas, float* __restrict__ rgbs) {
+    const int64_t n = n_dev != nullptr ? min(n_cap, *n_dev) : n_cap;
+    const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    for (int64_t s = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; s < n; s += stride) {
+        const int64_t r = ray_indices[s];
+        if (r < 0 || r >= n_rays) {
+            sigmas[s] = 0.0f;
+            if (rgbs != nullptr) rgbs[3 * s] = rgbs[3 * s + 1] = rgbs[3 * s + 2] = 0.0f;
+            continue;
+        }
+        const float t0 = ts[s], t1 = te[s];
+        const float x0 = midpoint_coord(rays_o[3 * r], rays_d[3 * r], t0, t1);
+        const float x1 = midpoint_coord(rays_o[3 * r + 1], rays_d[3 * r + 1], t0, t1);
+        const float x2 = midpoint_coord(rays_o[3 * r + 2], rays_d[3 * r + 2], t0, t1);
+        int set = ray_set != nullptr ? ray_set[r] : 0;
+        set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        float sigma;
+        eval_field(table, n_blobs, set, x0, x1, x2, sigma);
+        sigmas[s] = sigma;
+        if (rgbs != nullptr) {
+            float cr, cg, cb;
+            eval_rgb(cc, x0, x1, x2, cr, cg, cb);
+            rgbs[3 * s] = cr;
+            rgbs[3 * s + 1] = cg;
+            rgbs[3 * s + 2] = cb;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __restrict__ table, int n_blobs,
+                                                                 int n_sets, const float* __restrict__ points,
+                                                                 const int32_t* __restrict__ point_set, int64_t n,
+                                                                 float* __restrict__ sigmas,
+                                                                 float* __restrict__ rgbs) {
+    const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; q < n; q += stride) {
+        const float x0 = points[3 * q], x1 = points[3 * q + 1], x2 = points[3 * q + 2];
+        int set = point_set != nullptr ? point_set[q] : 0;
+        set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        float sigma;
+        eval_field(table, n_blobs, set, x0, x1, x2, sigma);
+        sigmas[q] = sigma;
+        if (rgbs != nullptr) {
+            float cr, cg, cb;
+            eval_rgb(cc, x0, x1, x2, cr, cg, cb);
+            rgbs[3 * q] = cr;
+            rgbs[3 * q + 1] = cg;
+            rgbs[3 * q + 2] = cb;
+        }
+    }
+}
+
+unsigned field_blocks(int64_t n) {
+    const int64_t want = (n + kThreads - 1) / kThreads;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16)));
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t nacc_synth_table_size(int32_t n_blobs, int32_t n_sets) {
+    if (n_blobs < 1 || n_sets < 1) return -1;
+    return table_floats(n_blobs, n_sets) * static_cast<int64_t>(sizeof(float));
+}
+
+int nacc_synth_prepare(const float* centres, const float* stds, const float* peaks, const float* w, const float* bias,
+                       int32_t n_blobs, int32_t n_sets, void* table, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_blobs >= 1 && n_sets >= 1, NACC_EINVAL, "n_blobs and n_sets must be >= 1");
+    NACC_REQUIRE(centres && stds && peaks && w && bias && table, NACC_EINVAL, "arguments must be non-NULL");
+    const int64_t total = static_cast<int64_t>(n_sets) * n_blobs + 12;
+    hipLaunchKernelGGL(prepare_kernel, dim3(static_cast<unsigned>((total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, as_stream(stream), centres, stds, peaks, w, bias, n_blobs, n_sets,
+                       static_cast<float*>(table));
+    return check_launch("synth prepare");
+}
+
+int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets, const float* rays_o,
+                             const float* rays_d, int64_t n_rays, const int32_t* ray_set,
+                             const int32_t* ray_indices,
+                             const float* t_starts, const float* t_ends, int64_t n_samples,
+                             const int64_t* n_samples_dev, float* sigmas, float* rgbs, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_blobs >= 1 && n_sets >= 1, NACC_EINVAL, "n_blobs and n_sets must be >= 1");
+    NACC_REQUIRE(n_samples >= 0, NACC_EINVAL, "n_samples < 0");
+    NACC_REQUIRE(n_samples == 0 || (table && rays_o && rays_d && ray_indices && t_starts && t_ends && sigmas),
+                 NACC_EINVAL, "arguments must be non-NULL");
+    if (n_samples == 0) return NACC_OK;
+    hipLaunchKernelGGL(field_samples_kernel, dim3(field_blocks(n_samples)), dim3(kThreads), 0, as_stream(stream),
+                       static_cast<const float*>(table), n_blobs, n_sets, rays_o, rays_d, n_rays, ray_set,
+                       ray_indices,
+                       t_starts, t_ends, n_samples, n_samples_dev, sigmas, rgbs);
+    return check_launch("synth field samples");
+}
+
+int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, const float* points,
+                            const int32_t* point_set, int64_t n, float* sigmas, float* rgbs, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_blobs >= 1 && n_sets >= 1, NACC_EINVAL, "n_blobs and n_sets must be >= 1");
+    NACC_REQUIRE(n >= 0, NACC_EINVAL, "n < 0");
+    NACC_REQUIRE(n == 0 || (table && points && sigmas), NACC_EINVAL, "arguments must be non-NULL");
+    if (n == 0) return NACC_OK;
+    hipLaunchKernelGGL(field_points_kernel, dim3(field_blocks(n)), dim3(kThreads), 0, as_stream(stream),
+                       static_cast<const float*>(table), n_blobs, n_sets, points, point_set, n, sigmas, rgbs);
+    return check_launch("synth field points");
+}
+
+}  // extern "C"

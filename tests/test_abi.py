@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the headers declare, carries gfx950 code, and rejects bad
+arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nacc.h", "nacc_synth.h")]
+
+
+def declared_symbols():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(nacc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_headers_declare_the_binding():
+    from paper_2210_04847_amd import _lib
+    assert set(declared_symbols()) == set(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2210_04847_amd import _lib
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(raw, s)]
+    assert not missing, missing
+
+
+def test_library_holds_gfx950_code():
+    from paper_2210_04847_amd import _lib
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_status_strings_and_version():
+    from paper_2210_04847_amd import _lib
+    assert _lib.version().startswith("nacc")
+    assert _lib.status_name(_lib.NACC_ECAPACITY) == "NACC_ECAPACITY"
+    assert _lib.status_name(12345) == "NACC_UNKNOWN"
+
+
+def _march_count_raw(lib, n_rays, desc, params, ws_bytes=1 << 20):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    return lib.nacc_march_count(fake, fake, None, n_rays, fake, ctypes.byref(desc),
+                                ctypes.byref(params), fake, fake, fake, ws_bytes, None)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("res", 0), ("res", 2000), ("lookup", 7), ("n_grids", 0), ("res", 3),
+])
+def test_bad_grid_rejected_on_host(field, value):
+    from paper_2210_04847_amd import _lib
+    desc = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
+    setattr(desc, field, value)
+    params = _lib.march_params(0.0, 10.0, 0.01)
+    st = _march_count_raw(_lib.lib, 10, desc, params)
+    assert st in (_lib.NACC_EINVAL, _lib.NACC_ESHAPE)
+    assert _lib.lib.nacc_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [dict(dt=0.0), dict(dt=float("nan")), dict(cone=-1.0),
+                                dict(cone=0.01, dt_max=0.001), dict(max_per_ray=-2),
+                                dict(near_plane=float("nan"))])
+def test_bad_params_rejected_on_host(kw):
+    from paper_2210_04847_amd import _lib
+    desc = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
+    args = dict(near_plane=0.0, far_plane=10.0, dt=0.01, dt_max=1e10, cone=0.0, max_per_ray=0)
+    args.update(kw)
+    params = _lib.march_params(**args)
+    assert _march_count_raw(_lib.lib, 10, desc, params) == _lib.NACC_EINVAL
+
+
+def test_bad_cascade_box_rejected():
+    from paper_2210_04847_amd import _lib
+    desc = _lib.grid_desc((-1.5, -1.5, -1.5), (1.5, 1.5, 1.5), 8, 4, _lib.LOOKUP_CASCADE)
+    params = _lib.march_params(0.0, 10.0, 0.01)
+    assert _march_count_raw(_lib.lib, 10, desc, params) == _lib.NACC_EINVAL
+
+
+def test_small_workspace_and_bad_sizes_rejected():
+    from paper_2210_04847_amd import _lib
+    desc = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
+    params = _lib.march_params(0.0, 10.0, 0.01)
+    assert _march_count_raw(_lib.lib, 100000, desc, params, ws_bytes=8) == _lib.NACC_ESHAPE
+    assert _march_count_raw(_lib.lib, -1, desc, params) == _lib.NACC_EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    lib = _lib.lib
+    assert lib.nacc_render_fwd(fake, 10, 5, fake, fake, fake, fake, 1.5, fake, fake, fake, None,
+                               None) == _lib.NACC_EINVAL
+    assert lib.nacc_render_fwd(fake, 10, 5, None, fake, fake, fake, 0.0, fake, fake, fake, None,
+                               None) == _lib.NACC_EINVAL
+    assert lib.nacc_grid_pack(fake, 33, 0.5, fake, None) == _lib.NACC_ESHAPE
+    assert lib.nacc_render_fwd_bwd_mse(fake, 0, 0, None, None, None, None, 0.0, fake, fake, fake,
+                                       fake, fake, fake, fake, fake, 1 << 20,
+                                       None) == _lib.NACC_EINVAL
+    assert lib.nacc_march_workspace_size(-5) == -1
+    assert lib.nacc_march_workspace_size(64) >= 8
+
+
+def test_zero_rays_launch_nothing_but_need_total():
+    from paper_2210_04847_amd import _lib
+    desc = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
+    params = _lib.march_params(0.0, 10.0, 0.01)
+    fake = ctypes.c_void_p(0x1000)
+    st = _lib.lib.nacc_march_count(fake, fake, None, 0, fake, ctypes.byref(desc),
+                                   ctypes.byref(params), None, None, None, 0, None)
+    assert st == _lib.NACC_EINVAL  # total is required even for zero rays

@@ -1,0 +1,184 @@
+"""GPU parity of rendering forward, backward and the fused forward + MSE +
+backward against the FP64 oracle, on identical FP32 inputs drawn by the
+seeded generators (tolerances derived in tests/parity.py)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import assert_bit_exact, check_backward, check_forward
+
+pytestmark = pytest.mark.gpu
+
+
+def _nacc():
+    import paper_2210_04847_amd as nacc
+    return nacc
+
+
+def _cuda(*arrays):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+CASES = {
+    # name: (n_rays, seed, mean_count, max_count, sigma_max)
+    "short": (500, 1, 20, 120, 60.0),
+    "ragged": (700, 2, 90, 300, 40.0),      # up to 5 chunks of 64 per ray
+    "dense": (300, 3, 150, 400, 300.0),     # opaque: many early cuts
+    "long": (40, 4, 1500, 3000, 2.0),       # ~25-50 chunks per ray, carries
+}
+
+
+def _inputs(case):
+    n, seed, mean, mx, smax = CASES[case]
+    return synth.ragged_render_inputs(n, seed, mean_count=mean, max_count=mx, sigma_max=smax)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_forward(case, eps):
+    lib = _nacc()._lib
+    packed, ts, te, sg, cl = _inputs(case)
+    n = packed.shape[0]
+    p_d, ts_d, te_d, sg_d, cl_d = _cuda(packed, ts, te, sg, cl)
+    color = torch.empty((n, 3), device="cuda")
+    opacity = torch.empty(n, device="cuda")
+    depth = torch.empty(n, device="cuda")
+    weights = torch.empty(ts.size, device="cuda")
+    lib.render_fwd(p_d, ts_d, te_d, sg_d, cl_d, eps, color, opacity, depth, weights)
+    torch.cuda.synchronize()
+    got = dict(color=color.cpu().numpy(), opacity=opacity.cpu().numpy(), depth=depth.cpu().numpy())
+    _, amb = check_forward(got, packed, ts, te, sg, cl, eps, weights.cpu().numpy())
+    assert amb.mean() < 0.05
+    # weights-free variant gives the same outputs bit for bit
+    c2 = torch.empty_like(color)
+    o2 = torch.empty_like(opacity)
+    d2 = torch.empty_like(depth)
+    lib.render_fwd(p_d, ts_d, te_d, sg_d, cl_d, eps, c2, o2, d2, None)
+    assert_bit_exact(c2.cpu().numpy(), got["color"], "color without weights")
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_backward(case, eps):
+    lib = _nacc()._lib
+    packed, ts, te, sg, cl = _inputs(case)
+    n = packed.shape[0]
+    g = np.random.default_rng(17)
+    gc = g.standard_normal((n, 3)).astype(np.float32)
+    ga = g.standard_normal(n).astype(np.float32)
+    gd = g.standard_normal(n).astype(np.float32)
+    p_d, ts_d, te_d, sg_d, cl_d, gc_d, ga_d, gd_d = _cuda(packed, ts, te, sg, cl, gc, ga, gd)
+    g_sig = torch.full((ts.size,), np.nan, device="cuda")
+    g_rgb = torch.full((ts.size, 3), np.nan, device="cuda")
+    lib.render_bwd(p_d, ts_d, te_d, sg_d, cl_d, eps, gc_d, ga_d, gd_d, g_sig, g_rgb)
+    torch.cuda.synchronize()
+    check_backward(g_sig.cpu().numpy(), g_rgb.cpu().numpy(), packed, ts, te, sg, cl,
+                   gc.astype(np.float64), ga.astype(np.float64), gd.astype(np.float64), eps)
+    # colour-only upstream gradient with NULL opacity / depth gradients
+    lib.render_bwd(p_d, ts_d, te_d, sg_d, cl_d, eps, gc_d, None, None, g_sig, g_rgb)
+    torch.cuda.synchronize()
+    check_backward(g_sig.cpu().numpy(), g_rgb.cpu().numpy(), packed, ts, te, sg, cl,
+                   gc.astype(np.float64), None, None, eps)
+
+
+@pytest.mark.parametrize("case", ["short", "ragged", "dense"])
+def test_fused_mse(case):
+    lib = _nacc()._lib
+    packed, ts, te, sg, cl = _inputs(case)
+    n = packed.shape[0]
+    eps = 1e-4
+    tgt = synth.targets(n, 23)
+    p_d, ts_d, te_d, sg_d, cl_d, tg_d = _cuda(packed, ts, te, sg, cl, tgt)
+    color = torch.empty((n, 3), device="cuda")
+    opacity = torch.empty(n, device="cuda")
+    depth = torch.empty(n, device="cuda")
+    g_sig = torch.full((ts.size,), np.nan, device="cuda")
+    g_rgb = torch.full((ts.size, 3), np.nan, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    ws = torch.empty(lib.render_mse_workspace_size(n), dtype=torch.uint8, device="cuda")
+    lib.render_fwd_bwd_mse(p_d, ts_d, te_d, sg_d, cl_d, eps, tg_d, color, opacity, depth,
+                           g_sig, g_rgb, loss, ws)
+    torch.cuda.synchronize()
+    got = dict(color=color.cpu().numpy(), opacity=opacity.cpu().numpy(), depth=depth.cpu().numpy())
+    ref, _ = check_forward(got, packed, ts, te, sg, cl, eps)
+    want_loss, g_color = oracle.mse_loss_and_grad(ref["color"], tgt)
+    assert abs(float(loss.item()) - want_loss) <= 1e-5 * want_loss
+    # the loss gradient depends on the rendered colour; its FP32 rendering
+    # error (<= 1e-5 |C|) propagates into both gradients
+    dg = 2.0 / (3 * n) * 1e-5 * np.abs(ref["color"]).max(1)
+    prop = oracle.render_bwd(packed, ts, te, sg, cl, np.repeat(dg[:, None], 3, 1), eps=eps)
+    ray_of = np.repeat(np.arange(n), packed[:, 1])
+    extra_rgb = (ref["weights"] * dg[ray_of])[:, None]
+    check_backward(g_sig.cpu().numpy(), g_rgb.cpu().numpy(), packed, ts, te, sg, cl, g_color,
+                   None, None, eps, extra_scale=prop["scale"], extra_rgb=extra_rgb)
+
+
+def test_autograd_function_matches_kernels():
+    nacc = _nacc()
+    packed, ts, te, sg, cl = _inputs("ragged")
+    n = packed.shape[0]
+    p_d, ts_d, te_d = _cuda(packed, ts, te)
+    sig = torch.from_numpy(sg).cuda().requires_grad_(True)
+    rgb = torch.from_numpy(cl).cuda().requires_grad_(True)
+    color, opacity, depth = nacc.rendering(p_d, ts_d.reshape(-1, 1), te_d.reshape(-1, 1),
+                                           sig.reshape(-1, 1), rgb, early_stop_eps=1e-4)
+    g = np.random.default_rng(5)
+    gc = g.standard_normal((n, 3)).astype(np.float32)
+    gd = g.standard_normal((n, 1)).astype(np.float32)
+    loss = (color * torch.from_numpy(gc).cuda()).sum() + (depth * torch.from_numpy(gd).cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    check_forward(dict(color=color.detach().cpu().numpy(), opacity=opacity.detach().cpu().numpy(),
+                       depth=depth.detach().cpu().numpy()), packed, ts, te, sg, cl, 1e-4)
+    check_backward(sig.grad.cpu().numpy(), rgb.grad.cpu().numpy(), packed, ts, te, sg, cl,
+                   gc.astype(np.float64), None, gd.ravel().astype(np.float64), 1e-4)
+
+
+def test_rendering_with_callback():
+    nacc = _nacc()
+    packed, ts, te, sg, cl = _inputs("short")
+    p_d, ts_d, te_d, sg_d, cl_d = _cuda(packed, ts, te, sg, cl)
+    ri = torch.from_numpy(np.repeat(np.arange(packed.shape[0]), packed[:, 1]).astype(np.int32)).cuda()
+
+    def rgb_sigma_fn(t0, t1, ray_indices):
+        assert ray_indices is ri
+        return cl_d, sg_d.reshape(-1, 1)
+
+    color, opacity, depth = nacc.rendering(rgb_sigma_fn, p_d, ts_d, te_d, ray_indices=ri,
+                                           early_stop_eps=0.0)
+    check_forward(dict(color=color.detach().cpu().numpy(), opacity=opacity.detach().cpu().numpy(),
+                       depth=depth.detach().cpu().numpy()), packed, ts, te, sg, cl, 0.0)
+
+
+def test_empty_rays_and_zero_rays():
+    lib = _nacc()._lib
+    packed = np.zeros((10, 2), np.int32)
+    z = np.zeros(0, np.float32)
+    p_d, ts_d, te_d, sg_d = _cuda(packed, z, z, z)
+    cl_d = torch.zeros((0, 3), device="cuda")
+    color = torch.full((10, 3), np.nan, device="cuda")
+    opacity = torch.full((10,), np.nan, device="cuda")
+    depth = torch.full((10,), np.nan, device="cuda")
+    lib.render_fwd(p_d, ts_d, te_d, sg_d, cl_d, 1e-4, color, opacity, depth)
+    torch.cuda.synchronize()
+    assert torch.all(color == 0) and torch.all(opacity == 0) and torch.all(depth == 0)
+    e = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    lib.render_fwd(e, ts_d, te_d, sg_d, cl_d, 1e-4, color[:0], opacity[:0], depth[:0])
+
+
+def test_render_deterministic():
+    lib = _nacc()._lib
+    packed, ts, te, sg, cl = _inputs("ragged")
+    n = packed.shape[0]
+    p_d, ts_d, te_d, sg_d, cl_d = _cuda(packed, ts, te, sg, cl)
+    outs = []
+    for _ in range(2):
+        g_sig = torch.empty(ts.size, device="cuda")
+        g_rgb = torch.empty((ts.size, 3), device="cuda")
+        gc = torch.ones((n, 3), device="cuda")
+        lib.render_bwd(p_d, ts_d, te_d, sg_d, cl_d, 1e-4, gc, None, None, g_sig, g_rgb)
+        outs.append((g_sig.cpu().numpy(), g_rgb.cpu().numpy()))
+    assert_bit_exact(outs[0][0], outs[1][0], "g_sigmas repeat")
+    assert_bit_exact(outs[0][1], outs[1][1], "g_rgbs repeat")

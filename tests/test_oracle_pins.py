@@ -501,7 +501,7 @@ def test_sample_cells_inside_and_uniform():
 def test_sample_cells_cascade_levels():
     res, levels = 8, 4
     base = np.array([-1, -1, -1, 1, 1, 1], np.float32)
-    cells, pos = oracle.grid_sample_cells(5, 0, 50000, res, base, levels)
+    cells, pos = oracle.grid_sample_cells(5, 0, 50000, res, base, levels, cascade=True)
     lvl = cells // res ** 3
     assert set(np.unique(lvl)) == {0, 1, 2, 3}
     m = np.abs(pos).max(1)

@@ -198,6 +198,7 @@ int nacc_march_fill(const float* rays_o, const float* rays_d,
  * with T_i < early_stop_eps and every later sample of the ray get w = 0.
  *   color out float[n_rays][3]; opacity, depth out float[n_rays];
  *   weights out float[n_samples] or NULL (zero past the cut).
+ *   kept    out int32[n_rays] or NULL: samples before the cut per ray.
  *   n_samples  length of the sample arrays (they may be NULL when it is 0).
  * Only samples referenced by packed_info are read.  A ray whose range
  * [start, start + count) does not lie inside [0, n_samples) is rendered as
@@ -207,7 +208,8 @@ int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays,
                     int64_t n_samples, const float* t_starts, const float* t_ends,
                     const float* sigmas, const float* rgbs,
                     float early_stop_eps, float* color, float* opacity,
-                    float* depth, float* weights, void* stream);
+                    float* depth, float* weights, int32_t* kept,
+                    void* stream);
 
 /*
  * Rendering backward (Sec. 2.2: all outputs of the radiance field receive

@@ -57,7 +57,7 @@ _SIGNATURES = {
                                 ctypes.POINTER(MarchParams), _P, _P, _P, _SZ, _P]),
     "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, ctypes.POINTER(GridDesc),
                                ctypes.POINTER(MarchParams), _P, _I64, _P, _P, _P, _P, _P]),
-    "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P]),
+    "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_mse_workspace_size": (_I64, [_I64]),
     "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P,
@@ -207,16 +207,17 @@ def _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs):
 
 
 def render_fwd(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity,
-               depth, weights=None, stream=None):
+               depth, weights=None, kept=None, stream=None):
     n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
     _need(color, torch.float32, "color", 3 * n)
     _need(opacity, torch.float32, "opacity", n)
     _need(depth, torch.float32, "depth", n)
     _need(weights, torch.float32, "weights", e)
+    _need(kept, torch.int32, "kept", n)
     _check("nacc_render_fwd", lib.nacc_render_fwd(
         _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
         float(early_stop_eps), _ptr(color), _ptr(opacity), _ptr(depth), _ptr(weights),
-        _stream(stream)))
+        _ptr(kept), _stream(stream)))
 
 
 def render_bwd(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, g_color,

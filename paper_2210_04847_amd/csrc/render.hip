@@ -10,9 +10,10 @@
 // cut on the same sample.
 //
 // Backward: g_sigma_i = delta_i (T_{i+1} v_i - S_i), S_i = sum_{k>i} w_k v_k.
-// S_i is formed as (FP64 total) - (FP64 inclusive prefix): in FP64 this
-// difference keeps full FP32 accuracy even where T is ~1e-4 and S_i is tiny,
-// which the FP32 total-minus-prefix form would not.
+// S_i is a true suffix sum, accumulated in FP64 from the end of the ray
+// (chunks in reverse, lanes in reverse sample order), so it stays accurate
+// relative to its own terms however small T gets; a total-minus-prefix form
+// would lose every digit once T falls below the rounding of the total.
 #include <cmath>
 
 #include "common.h"
@@ -46,8 +47,8 @@ __device__ __forceinline__ Sample load_sample(bool valid, int64_t s, const float
     return x;
 }
 
-// T at the start and the end of each lane's sample, given the FP64 prefix
-// of tau before the chunk.  Returns the inclusive chunk prefix in `incl`.
+// T at the start of each lane's sample, given the FP64 prefix of tau before
+// the chunk, and the inclusive chunk prefix of tau.
 struct Trans {
     float tau;    // sigma * delta
     float incl;   // inclusive prefix of tau inside the chunk
@@ -61,10 +62,6 @@ __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double car
     const float excl = shift_up_one(t.incl);
     t.t_in = expf(-static_cast<float>(carry + static_cast<double>(excl)));
     return t;
-}
-
-__device__ __forceinline__ float t_out(const Trans& t, double carry) {
-    return expf(-static_cast<float>(carry + static_cast<double>(t.incl)));
 }
 
 // Number of leading lanes kept in this chunk: the first valid lane with
@@ -91,7 +88,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
     float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth,
-    float* __restrict__ weights) {
+    float* __restrict__ weights, int32_t* __restrict__ kept) {
     const int lane = lane_id();
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock +
                       uniform<int>(static_cast<int>(threadIdx.x) / kWave);
@@ -102,6 +99,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
     double carry = 0.0;
     float acc_r = 0.0f, acc_g = 0.0f, acc_b = 0.0f, acc_a = 0.0f, acc_d = 0.0f;
     int c = 0;
+    int n_kept = n;
     for (; c < n; c += kWave) {
         const int i = c + lane;
         const bool valid = i < n;
@@ -119,6 +117,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         if (WEIGHTS && valid) weights[s] = w;
         carry += static_cast<double>(read_lane(t.incl, 63));
         if (keep_n < kWave) {
+            n_kept = c + keep_n;
             c += kWave;
             break;
         }
@@ -139,6 +138,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         color[3 * r + 2] = acc_b;
         opacity[r] = acc_a;
         depth[r] = acc_d;
+        if (kept != nullptr) kept[r] = n_kept;
     }
 }
 
@@ -147,83 +147,95 @@ struct RayGrad {
     float gr, gg, gb, ga, gd;
 };
 
-// In FP64, so that the total and the prefixes of w v in the two passes are
-// sums of the same terms to FP64 rounding.
+// v_i in FP64; the products w_i v_i are summed in FP64 for the suffix sums.
 __device__ __forceinline__ double vdot(const RayGrad& q, const Sample& x) {
     const double m = static_cast<double>((x.t0 + x.t1) * 0.5f);
     return static_cast<double>(q.gr) * x.r + static_cast<double>(q.gg) * x.g + static_cast<double>(q.gb) * x.b +
            static_cast<double>(q.ga) + static_cast<double>(q.gd) * m;
 }
 
-// Pass A of the backward: the cut (samples kept) and sum_{k<cut} w_k v_k.
+// Pass A of the backward: the cut (number of samples kept) and the FP64
+// prefix of tau at the start of the chunk holding the last kept sample.  T is
+// formed exactly as in the forward kernel, so the cut is the same sample.
 __device__ __forceinline__ void backward_pass_a(int64_t start, int n, const float* __restrict__ ts,
                                                 const float* __restrict__ te, const float* __restrict__ sig,
-                                                const float* __restrict__ rgb, float eps, const RayGrad& q,
-                                                int& kept, double& total) {
+                                                const float* __restrict__ rgb, float eps, int& kept,
+                                                double& prefix_hi) {
     const int lane = lane_id();
-    double carry = 0.0;
-    double acc = 0.0;
+    double carry = 0.0, carry_prev = 0.0;
     kept = n;
+    prefix_hi = 0.0;
     for (int c = 0; c < n; c += kWave) {
         const int i = c + lane;
         const bool valid = i < n;
         const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
-        const bool keep = valid && lane < keep_n;
-        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
-        acc += static_cast<double>(w) * vdot(q, x);
-        carry += static_cast<double>(read_lane(t.incl, 63));
         if (keep_n < kWave) {
             kept = c + keep_n;
-            break;
+            prefix_hi = keep_n > 0 ? carry : carry_prev;
+            return;
         }
+        carry_prev = carry;
+        carry += static_cast<double>(read_lane(t.incl, 63));
+        prefix_hi = carry_prev;
     }
-    total = wave_sum(acc);
 }
 
-// Pass B: recompute T and w chunk by chunk, form the FP64 suffix sums and
-// write both gradients (zeros from the cut on).
-__device__ __forceinline__ void backward_pass_b(int64_t start, int n, int kept, double total,
+// Pass B: the kept samples chunk by chunk from the last to the first, lanes
+// in reverse sample order (lane L holds sample c + 63 - L), so that a
+// forward DPP scan over the lanes is a suffix scan over the samples.
+//   suffix of tau inside the chunk -> T_i, T_{i+1} from the chunk's FP64 end
+//   prefix; suffix of w v (FP64) -> S_i = sum_{k>i} w_k v_k accumulated from
+//   the end of the ray, accurate relative to the terms it sums even where T
+//   is far below 1e-4.
+// Samples from the cut on get zero gradients.
+__device__ __forceinline__ void backward_pass_b(int64_t start, int n, int kept, double prefix_hi,
                                                 const float* __restrict__ ts, const float* __restrict__ te,
                                                 const float* __restrict__ sig, const float* __restrict__ rgb,
                                                 const RayGrad& q, float* __restrict__ g_sigmas,
                                                 float* __restrict__ g_rgbs) {
     const int lane = lane_id();
-    double carry = 0.0;     // prefix of tau
-    double carry_wv = 0.0;  // prefix of w v
-    int c = 0;
-    for (; c < kept; c += kWave) {
-        const int i = c + lane;
-        const bool valid = i < n;
-        const int64_t s = start + i;
-        const Sample x = load_sample(valid && i < kept, s, ts, te, sig, rgb);
-        const Trans t = chunk_transmittance(x, carry);
-        const bool keep = i < kept;
-        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
-        const double v = vdot(q, x);
-        const double wv = static_cast<double>(w) * v;
-        const double incl_wv = wave_inclusive_sum(wv) + carry_wv;
-        if (valid) {
-            float gs = 0.0f, gr = 0.0f, gg = 0.0f, gb = 0.0f;
+    if (kept > 0) {
+        const int c_hi = ((kept - 1) / kWave) * kWave;
+        double end_next = 0.0;   // tau prefix at the end of the next lower chunk
+        double suffix_wv = 0.0;  // sum of w v over the chunks above
+        for (int c = c_hi; c >= 0; c -= kWave) {
+            const int i = c + (kWave - 1) - lane;
+            const bool keep = i < kept;
+            const int64_t s = start + i;
+            const Sample x = load_sample(keep, s, ts, te, sig, rgb);
+            const float tau = x.sigma * (x.t1 - x.t0);
+            const float incl = wave_inclusive_sum(tau);  // sum over samples >= i in the chunk
+            const float excl = shift_up_one(incl);       // sum over samples >  i in the chunk
+            const float chunk_tau = read_lane(incl, 63);
+            const double p_end = c == c_hi ? prefix_hi + static_cast<double>(chunk_tau) : end_next;
+            const float t_in = expf(-static_cast<float>(p_end - static_cast<double>(incl)));
+            const float t_next = expf(-static_cast<float>(p_end - static_cast<double>(excl)));
+            const float w = keep ? t_in * -expm1f(-tau) : 0.0f;
+            const double v = vdot(q, x);
+            const double wv = static_cast<double>(w) * v;
+            const double incl_wv = wave_inclusive_sum(wv);
+            const double suffix = suffix_wv + shift_up_one(incl_wv);
             if (keep) {
-                const double suffix = total - incl_wv;
-                const double dtau = static_cast<double>(t_out(t, carry)) * v - suffix;
-                gs = static_cast<float>(static_cast<double>(x.t1 - x.t0) * dtau);
-                gr = w * q.gr;
-                gg = w * q.gg;
-                gb = w * q.gb;
+                const double dtau = static_cast<double>(t_next) * v - suffix;
+                g_sigmas[s] = static_cast<float>(static_cast<double>(x.t1 - x.t0) * dtau);
+                g_rgbs[3 * s] = w * q.gr;
+                g_rgbs[3 * s + 1] = w * q.gg;
+                g_rgbs[3 * s + 2] = w * q.gb;
+            } else if (i < n) {
+                g_sigmas[s] = 0.0f;
+                g_rgbs[3 * s] = 0.0f;
+                g_rgbs[3 * s + 1] = 0.0f;
+                g_rgbs[3 * s + 2] = 0.0f;
             }
-            g_sigmas[s] = gs;
-            g_rgbs[3 * s] = gr;
-            g_rgbs[3 * s + 1] = gg;
-            g_rgbs[3 * s + 2] = gb;
+            suffix_wv += read_lane(incl_wv, 63);
+            end_next = p_end - static_cast<double>(chunk_tau);
         }
-        carry += static_cast<double>(read_lane(t.incl, 63));
-        carry_wv = read_lane(incl_wv, 63);
     }
     // chunks entirely past the cut: zeros, no loads
-    for (; c < n; c += kWave) {
+    const int first_zero = kept > 0 ? ((kept - 1) / kWave + 1) * kWave : 0;
+    for (int c = first_zero; c < n; c += kWave) {
         const int i = c + lane;
         if (i < n) {
             const int64_t s = start + i;
@@ -254,9 +266,9 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
     q.ga = g_opacity != nullptr ? uniform<float>(g_opacity[r]) : 0.0f;
     q.gd = g_depth != nullptr ? uniform<float>(g_depth[r]) : 0.0f;
     int kept;
-    double total;
-    backward_pass_a(start, n, ts, te, sig, rgb, eps, q, kept, total);
-    backward_pass_b(start, n, kept, total, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
+    double prefix_hi;
+    backward_pass_a(start, n, ts, te, sig, rgb, eps, kept, prefix_hi);
+    backward_pass_b(start, n, kept, prefix_hi, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
 }
 
 // Fused forward + MSE + backward.  Pass A is the forward with the colour
@@ -271,13 +283,13 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     __shared__ double wave_loss[kRaysPerRenderBlock];
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave;
-    double ray_loss = 0.0;
-    if (r < n_rays) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
+    double wave_total = 0.0;
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave; r < n_rays; r += stride) {
         int64_t start;
         int n;
         ray_range(packed_info, r, n_samples, start, n);
-        double carry = 0.0;
+        double carry = 0.0, carry_prev = 0.0, prefix_hi = 0.0;
         double acc_r = 0.0, acc_g = 0.0, acc_b = 0.0;
         float acc_a = 0.0f, acc_d = 0.0f;
         int kept = n;
@@ -294,11 +306,14 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
             acc_b += static_cast<double>(w) * x.b;
             acc_a += w;
             acc_d += w * ((x.t0 + x.t1) * 0.5f);
-            carry += static_cast<double>(read_lane(t.incl, 63));
             if (keep_n < kWave) {
                 kept = c + keep_n;
+                prefix_hi = keep_n > 0 ? carry : carry_prev;
                 break;
             }
+            carry_prev = carry;
+            carry += static_cast<double>(read_lane(t.incl, 63));
+            prefix_hi = carry_prev;
         }
         acc_r = wave_sum(acc_r);
         acc_g = wave_sum(acc_g);
@@ -314,7 +329,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
         q.gb = uniform<float>(eb * inv_count2);
         q.ga = 0.0f;
         q.gd = 0.0f;
-        ray_loss = static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
+        wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
         if (lane == 0) {
             color[3 * r] = cr;
             color[3 * r + 1] = cg;
@@ -322,13 +337,9 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
             opacity[r] = acc_a;
             depth[r] = acc_d;
         }
-        if (n > 0) {
-            const double total = static_cast<double>(q.gr) * acc_r + static_cast<double>(q.gg) * acc_g +
-                                 static_cast<double>(q.gb) * acc_b;
-            backward_pass_b(start, n, kept, total, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
-        }
+        if (n > 0) backward_pass_b(start, n, kept, prefix_hi, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
     }
-    if (lane == 0) wave_loss[wave] = ray_loss;
+    if (lane == 0) wave_loss[wave] = wave_total;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
@@ -356,6 +367,12 @@ __global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const double*
 
 int64_t render_blocks(int64_t n_rays) { return (n_rays + kRaysPerRenderBlock - 1) / kRaysPerRenderBlock; }
 
+// The fused kernel walks the rays grid-stride with at most this many
+// workgroups (16 per CU), so its loss needs few partial sums.
+constexpr int64_t kMaxMseBlocks = 4096;
+
+int64_t mse_blocks(int64_t n_rays) { return std::max<int64_t>(1, std::min(render_blocks(n_rays), kMaxMseBlocks)); }
+
 int validate_render(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* ts,
                     const float* te, const float* sig, const float* rgb, float eps) {
     NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
@@ -375,9 +392,8 @@ int validate_render(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
 extern "C" {
 
 int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
-                    const float* t_ends,
-                    const float* sigmas, const float* rgbs, float early_stop_eps, float* color, float* opacity,
-                    float* depth, float* weights, void* stream) {
+                    const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps, float* color,
+                    float* opacity, float* depth, float* weights, int32_t* kept, void* stream) {
     clear_error();
     int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
     if (st != NACC_OK) return st;
@@ -388,10 +404,12 @@ int nacc_render_fwd(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
     const dim3 grid(static_cast<unsigned>(render_blocks(n_rays)));
     if (weights != nullptr) {
         hipLaunchKernelGGL(render_fwd_kernel<true>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
-                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights);
+                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights,
+                           kept);
     } else {
         hipLaunchKernelGGL(render_fwd_kernel<false>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
-                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights);
+                           n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, color, opacity, depth, weights,
+                           kept);
     }
     return check_launch("render fwd");
 }
@@ -415,7 +433,7 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
 
 int64_t nacc_render_mse_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
-    return ((render_blocks(n_rays) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
+    return ((mse_blocks(n_rays) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
 }
 
 int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
@@ -433,7 +451,7 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
     NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE, "workspace of %zu bytes, need %lld",
                  workspace_bytes, static_cast<long long>(need));
     hipStream_t s = as_stream(stream);
-    const int64_t nb = render_blocks(n_rays);
+    const int64_t nb = mse_blocks(n_rays);
     const double count = 3.0 * static_cast<double>(n_rays);
     const float inv_count2 = static_cast<float>(2.0 / count);
     double* partial = static_cast<double*>(workspace);

@@ -99,8 +99,9 @@ def check_forward(got, packed, t_starts, t_ends, sigmas, rgbs, eps, weights_got=
 
 def check_backward(g_sig, g_rgb, packed, t_starts, t_ends, sigmas, rgbs, g_color, g_opacity,
                    g_depth, eps, extra_scale=None, extra_rgb=None):
-    """Compares GPU gradients with the oracle's; extra_scale / extra_rgb add
-    propagated uncertainty (fused loss)."""
+    """Compares GPU gradients with the oracle's.  extra_scale / extra_rgb are
+    absolute bounds of error propagated from an input the kernel computes
+    itself (the fused loss gradient, from its own FP32 colour)."""
     ref = oracle.render_bwd(packed, t_starts, t_ends, sigmas, rgbs, g_color, g_opacity, g_depth,
                             eps)
     amb = ambiguous_rays(packed, t_starts, t_ends, sigmas, eps)
@@ -111,8 +112,9 @@ def check_backward(g_sig, g_rgb, packed, t_starts, t_ends, sigmas, rgbs, g_color
                                   g_depth, eps * (1 + f * CUT_BAND)) for f in (-1.5, 1.5)]
 
     def within(r):
-        sc = r["scale"] + (0 if extra_scale is None else extra_scale)
-        ok_s = _close(np.asarray(g_sig, np.float64), r["g_sigmas"], GRAD_RTOL, sc, 1e-20)
+        # extra_scale is an absolute bound of propagated input error
+        floor = 1e-20 + (0 if extra_scale is None else extra_scale)
+        ok_s = _close(np.asarray(g_sig, np.float64), r["g_sigmas"], GRAD_RTOL, r["scale"], floor)
         ex = 0 if extra_rgb is None else extra_rgb
         ok_c = (np.abs(np.asarray(g_rgb, np.float64).reshape(-1, 3) - r["g_rgbs"])
                 <= GRAD_RTOL * np.abs(r["g_rgbs"]) + ex + 1e-20).all(1)

@@ -92,9 +92,9 @@ def test_small_workspace_and_bad_sizes_rejected():
     fake = ctypes.c_void_p(0x1000)
     lib = _lib.lib
     assert lib.nacc_render_fwd(fake, 10, 5, fake, fake, fake, fake, 1.5, fake, fake, fake, None,
-                               None) == _lib.NACC_EINVAL
+                               None, None) == _lib.NACC_EINVAL
     assert lib.nacc_render_fwd(fake, 10, 5, None, fake, fake, fake, 0.0, fake, fake, fake, None,
-                               None) == _lib.NACC_EINVAL
+                               None, None) == _lib.NACC_EINVAL
     assert lib.nacc_grid_pack(fake, 33, 0.5, fake, None) == _lib.NACC_ESHAPE
     assert lib.nacc_render_fwd_bwd_mse(fake, 0, 0, None, None, None, None, 0.0, fake, fake, fake,
                                        fake, fake, fake, fake, fake, 1 << 20,

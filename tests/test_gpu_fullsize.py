@@ -1,0 +1,97 @@
+"""Parity at the full training size (262,144 rays, 128^3 grid, 32 blobs) in
+the launch configuration the benchmark times, on sampled outputs the oracle
+computes ray by ray."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import assert_bit_exact, check_backward, check_forward
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def step():
+    import bench
+    import paper_2210_04847_amd as nacc
+    w = synth.WORKLOADS["train_262k"]
+    inp = synth.workload_inputs(w)
+    st = bench.TrainStep(w, inp, torch, nacc)
+    st.march_count()
+    st.march_fill()
+    st.field_eval()
+    torch.cuda.synchronize()
+    return w, inp, st
+
+
+def _sample_rays(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def test_fullsize_march_sampled_rays(step):
+    w, inp, st = step
+    assert int(st.status.item()) == 0
+    packed = st.packed.cpu().numpy()
+    total = int(st.total.item())
+    assert packed[:, 1].sum() == total and packed[-1, 0] + packed[-1, 1] == total
+    assert np.array_equal(packed[1:, 0], np.cumsum(packed[:-1, 1]))
+    rays = _sample_rays(w.n_rays, 3000, 41)
+    mask = oracle.grid_threshold(inp["occ"], 0.01)
+    p_o, ri_o, ts_o, te_o = oracle.march(inp["rays_o"][rays], inp["rays_d"][rays], mask, w.res,
+                                         np.asarray(w.box, np.float32), w.near, w.far, w.dt)
+    assert_bit_exact(packed[rays, 1], p_o[:, 1], "sampled counts")
+    idx = np.concatenate([np.arange(packed[r, 0], packed[r, 0] + packed[r, 1]) for r in rays])
+    ri = st.ray_indices[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert_bit_exact(ri, rays[ri_o], "sampled ray indices")
+    assert_bit_exact(st.t_starts[torch.from_numpy(idx).cuda()].cpu().numpy(), ts_o, "t_starts")
+    assert_bit_exact(st.t_ends[torch.from_numpy(idx).cuda()].cpu().numpy(), te_o, "t_ends")
+
+
+def test_fullsize_field_sampled(step):
+    w, inp, st = step
+    total = int(st.total.item())
+    idx = np.sort(np.random.default_rng(42).choice(total, 20000, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    ri = st.ray_indices[it].cpu().numpy()
+    pos = oracle.sample_positions(inp["rays_o"], inp["rays_d"], ri,
+                                  st.t_starts[it].cpu().numpy(), st.t_ends[it].cpu().numpy())
+    s_o, c_o = oracle.blob_field(inp["scene"], pos)
+    assert np.all(np.abs(st.sigmas[it].cpu().numpy() - s_o) <= 2e-5 * s_o + 1e-30)
+    assert np.all(np.abs(st.rgbs[it].cpu().numpy() - c_o) <= 1e-5 * c_o)
+
+
+def test_fullsize_fused_render_sampled(step):
+    """The fused kernel at full size on density / colour values drawn by the
+    generator for every marched sample; sampled rays checked against the
+    oracle with the strict render and gradient tolerances."""
+    w, inp, st = step
+    total = int(st.total.item())
+    g = np.random.Generator(np.random.PCG64(77))
+    sig = np.where(g.random(total) < 0.3, 0.0, g.uniform(0, 50, total)).astype(np.float32)
+    rgb = g.random((total, 3)).astype(np.float32)
+    st.sigmas[:total].copy_(torch.from_numpy(sig))
+    st.rgbs[:total].copy_(torch.from_numpy(rgb))
+    st.render()
+    torch.cuda.synchronize()
+    packed = st.packed.cpu().numpy()
+    rays = _sample_rays(w.n_rays, 2000, 43)
+    sub = packed[rays].copy()
+    idx = np.concatenate([np.arange(p[0], p[0] + p[1]) for p in sub]).astype(np.int64)
+    sub[:, 0] = np.concatenate([[0], np.cumsum(sub[:-1, 1])])
+    it = torch.from_numpy(idx).cuda()
+    ts = st.t_starts[it].cpu().numpy()
+    te = st.t_ends[it].cpu().numpy()
+    got = dict(color=st.color.cpu().numpy()[rays], opacity=st.opacity.cpu().numpy()[rays],
+               depth=st.depth.cpu().numpy()[rays])
+    ref, _ = check_forward(got, sub, ts, te, sig[idx], rgb[idx], w.early_stop_eps)
+    tgt = inp["targets"][rays].astype(np.float64)
+    g_color = 2.0 * (ref["color"] - tgt) / (3 * w.n_rays)
+    dg = 2.0 / (3 * w.n_rays) * 1e-5 * np.abs(ref["color"]).max(1)
+    prop = oracle.render_bwd(sub, ts, te, sig[idx], rgb[idx], np.repeat(dg[:, None], 3, 1),
+                             eps=w.early_stop_eps)
+    ray_of = np.repeat(np.arange(len(rays)), sub[:, 1])
+    check_backward(st.g_sigmas[it].cpu().numpy(), st.g_rgbs[it].cpu().numpy(), sub, ts, te,
+                   sig[idx], rgb[idx], g_color, None, None, w.early_stop_eps,
+                   extra_scale=prop["scale"], extra_rgb=(ref["weights"] * dg[ray_of])[:, None])

@@ -1,0 +1,144 @@
+"""GPU parity of the occupancy-grid update against the oracle: Philox cell
+draws and positions, decay, max-update and bit packing bit for bit; a whole
+update with the field within the field's tolerance; checkpoint / resume."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import assert_bit_exact
+
+pytestmark = pytest.mark.gpu
+
+BOX = np.array(synth.BOX_1_5, np.float32)
+
+
+def _lib():
+    import paper_2210_04847_amd as nacc
+    return nacc._lib
+
+
+def _pack_mask(mask):
+    """LSB-first 32-bit words of a 0/1 mask (numpy's packbits, little order)."""
+    return np.packbits(mask.astype(np.uint8), bitorder="little").view("<u4").view(np.int32)
+
+
+@pytest.mark.parametrize("res,levels,cascade,box", [
+    (128, 1, False, BOX),
+    (32, 4, True, np.array([-1, -1, -1, 1, 1, 1], np.float32)),
+    (16, 5, False, BOX),
+])
+def test_sample_cells(res, levels, cascade, box):
+    lib = _lib()
+    n = 200003
+    lk = lib.LOOKUP_CASCADE if cascade else lib.LOOKUP_AABB
+    desc = lib.grid_desc(box[:3], box[3:], res, levels, lk)
+    cells = torch.empty(n, dtype=torch.int32, device="cuda")
+    pos = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    for step in (0, 7):
+        lib.grid_sample_cells(4001, step, n, desc, levels, cells, pos)
+        torch.cuda.synchronize()
+        c_o, p_o = oracle.grid_sample_cells(4001, step, n, res, box, levels, cascade)
+        assert_bit_exact(cells.cpu().numpy(), c_o, "cells")
+        assert_bit_exact(pos.cpu().numpy(), p_o, "positions")
+
+
+def test_decay_update_pack():
+    lib = _lib()
+    g = np.random.default_rng(31)
+    n_cells = 128 ** 3
+    occ0 = (g.random(n_cells) * 0.03).astype(np.float32)
+    occ = torch.from_numpy(occ0).cuda()
+    lib.grid_decay(occ, 0.95)
+    want = oracle.grid_decay(occ0, 0.95)
+    # odd sizes exercise the scalar tail of the vectorised decay
+    tail = torch.from_numpy(occ0[:1000003].copy()).cuda()
+    lib.grid_decay(tail, 0.95)
+    torch.cuda.synchronize()
+    assert_bit_exact(occ.cpu().numpy(), want, "decay")
+    assert_bit_exact(tail.cpu().numpy(), want[:1000003], "decay tail")
+    cells = g.integers(0, n_cells, 300000).astype(np.int32)
+    cells[:5000] = cells[5000:10000]  # duplicates
+    vals = (g.random(300000) * 0.05).astype(np.float32)
+    vals[::97] = np.nan
+    lib.grid_update_max(occ, torch.from_numpy(cells).cuda(), torch.from_numpy(vals).cuda())
+    torch.cuda.synchronize()
+    want = oracle.grid_update_max(want, cells, vals)
+    assert_bit_exact(occ.cpu().numpy(), want, "update max")
+    bits = torch.empty(n_cells // 32, dtype=torch.int32, device="cuda")
+    lib.grid_pack(occ, 0.01, bits)
+    torch.cuda.synchronize()
+    assert_bit_exact(bits.cpu().numpy(), _pack_mask(oracle.grid_threshold(want, 0.01)), "pack")
+    # a size that is a multiple of 32 but not of 64 (last wave half full)
+    small = torch.from_numpy(want[:96].copy()).cuda()
+    sb = torch.empty(3, dtype=torch.int32, device="cuda")
+    lib.grid_pack(small, 0.01, sb)
+    torch.cuda.synchronize()
+    assert_bit_exact(sb.cpu().numpy(), _pack_mask(oracle.grid_threshold(want[:96], 0.01)), "pack 96")
+
+
+def _field_and_grid(res=64):
+    import paper_2210_04847_amd as nacc
+    scene = synth.blob_scene(32, 1001)
+    occ = synth.initial_occupancy(scene, res, synth.BOX_1_5)
+    grid = nacc.OccupancyGrid(synth.BOX_1_5, res)
+    grid.set_occupancy(torch.from_numpy(occ).cuda(), 0.01)
+    field = nacc.BlobField(scene)
+    return scene, occ, grid, field
+
+
+def test_update_with_field():
+    scene, occ, grid, field = _field_and_grid()
+    n = 1 << 16
+    grid.update(lambda p: field.points(p), decay=0.95, threshold=0.01, n_samples=n, seed=4001)
+    torch.cuda.synchronize()
+    cells, pos = oracle.grid_sample_cells(4001, 0, n, 64, BOX)
+    sig = oracle.blob_field(scene, pos, want_rgb=False)
+    want = oracle.grid_update_max(oracle.grid_decay(occ, 0.95), cells, sig.astype(np.float32))
+    got = grid.occ.cpu().numpy()
+    # the field is FP32 (relative error below 2e-5): occupancy agrees within it
+    assert np.all(np.abs(got - want) <= 2e-5 * np.abs(want) + 1e-30)
+    bits = grid.bits.cpu().numpy()
+    want_bits = _pack_mask(oracle.grid_threshold(want, 0.01))
+    differ = np.flatnonzero(bits != want_bits)
+    near = np.abs(want - 0.01) <= 2e-5 * 0.01
+    for wi in differ:  # only cells at the threshold may flip
+        cells_in = np.arange(32 * wi, 32 * wi + 32)
+        diff_bits = (bits[wi] ^ want_bits[wi]) & 0xFFFFFFFF
+        flipped = cells_in[[(diff_bits >> b) & 1 == 1 for b in range(32)]]
+        assert near[flipped].all()
+
+
+def test_checkpoint_resume_bit_identical():
+    _, _, grid_a, field = _field_and_grid(32)
+    _, _, grid_b, _ = _field_and_grid(32)
+    fn = lambda p: field.points(p)
+    for _ in range(4):
+        grid_a.update(fn, n_samples=4096, seed=9)
+    for _ in range(2):
+        grid_b.update(fn, n_samples=4096, seed=9)
+    state = {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in grid_b.state_dict().items()}
+    import io
+    buf = io.BytesIO()
+    torch.save(state, buf)
+    buf.seek(0)
+    loaded = torch.load(buf, weights_only=True)
+    _, _, grid_c, _ = _field_and_grid(32)
+    grid_c.load_state_dict({k: (v.cuda() if torch.is_tensor(v) else v) for k, v in loaded.items()})
+    for _ in range(2):
+        grid_c.update(fn, n_samples=4096, seed=9)
+    torch.cuda.synchronize()
+    assert_bit_exact(grid_c.occ.cpu().numpy(), grid_a.occ.cpu().numpy(), "occ after resume")
+    assert_bit_exact(grid_c.bits.cpu().numpy(), grid_a.bits.cpu().numpy(), "bits after resume")
+
+
+def test_field_matches_oracle_field():
+    import paper_2210_04847_amd as nacc
+    scene = synth.blob_scene(32, 1001)
+    field = nacc.BlobField(scene)
+    pts = np.random.default_rng(3).uniform(-1.6, 1.6, (100000, 3)).astype(np.float32)
+    sig, rgb = field.points(torch.from_numpy(pts).cuda(), want_rgb=True)
+    s_o, c_o = oracle.blob_field(scene, pts)
+    assert np.all(np.abs(sig.cpu().numpy() - s_o) <= 2e-5 * s_o + 1e-30)
+    assert np.all(np.abs(rgb.cpu().numpy() - c_o) <= 1e-5 * c_o)

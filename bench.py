@@ -88,12 +88,12 @@ class TrainStep:
     # phases ------------------------------------------------------------
     def march_count(self):
         self.lib.march_count(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
-                             self.params, self.packed, self.total, self.ws)
+                             self.params, self.packed, self.total, self.ws, self.grid.mip)
 
     def march_fill(self):
         self.lib.march_fill(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
                             self.params, self.packed, self.ray_indices, self.t_starts, self.t_ends,
-                            self.status)
+                            self.status, self.grid.mip)
 
     def field_eval(self):
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
@@ -117,6 +117,7 @@ class TrainStep:
                                self.ema_pos, None, self.ema_sigma)
         lib.grid_update_max(g.occ, self.ema_cells, self.ema_sigma)
         lib.grid_pack(g.occ, THRESHOLD, g.bits)
+        lib.grid_build_mip(g.bits, g.desc, g.mip)
         self.updates += 1
 
     PHASES = ("march_count", "march_fill", "field", "render", "grid_update")

@@ -157,6 +157,12 @@ int64_t nacc_march_workspace_size(int64_t n_rays);
  *                   (ignored for CASCADE); a ray whose grid id is outside
  *                   [0, n_grids) gets no samples.
  *   grid_bits       uint32[n_grids * res^3 / 32], LSB-first bit order.
+ *   grid_mip        the skip grid built from grid_bits by
+ *                   nacc_grid_build_mip, or NULL.  It only lets the kernels
+ *                   skip candidates that lie in empty cells, so results are
+ *                   identical with and without it; it must be rebuilt
+ *                   whenever grid_bits changes.  Used for uniform steps
+ *                   with the box lookup and res % 4 == 0, ignored otherwise.
  *   packed_info     out int32[n_rays][2]: (start, count) per ray.
  *   total           out int64[1]: the sample total, on the device.
  *   workspace       device scratch of nacc_march_workspace_size(n_rays)
@@ -166,7 +172,8 @@ int64_t nacc_march_workspace_size(int64_t n_rays);
  */
 int nacc_march_count(const float* rays_o, const float* rays_d,
                      const int32_t* grid_id, int64_t n_rays,
-                     const uint32_t* grid_bits, const nacc_grid_desc* grid,
+                     const uint32_t* grid_bits, const uint32_t* grid_mip,
+                     const nacc_grid_desc* grid,
                      const nacc_march_params* params, int32_t* packed_info,
                      int64_t* total, void* workspace, size_t workspace_bytes,
                      void* stream);
@@ -182,7 +189,8 @@ int nacc_march_count(const float* rays_o, const float* rays_d,
  */
 int nacc_march_fill(const float* rays_o, const float* rays_d,
                     const int32_t* grid_id, int64_t n_rays,
-                    const uint32_t* grid_bits, const nacc_grid_desc* grid,
+                    const uint32_t* grid_bits, const uint32_t* grid_mip,
+                    const nacc_grid_desc* grid,
                     const nacc_march_params* params,
                     const int32_t* packed_info, int64_t capacity,
                     int32_t* ray_indices, float* t_starts, float* t_ends,
@@ -285,6 +293,22 @@ int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
 int nacc_grid_update_max(float* occ, const int32_t* cells,
                          const float* values, int64_t n, int64_t n_cells,
                          void* stream);
+
+/* Words of the skip grid of `grid` (n_grids grids), 0 if res % 4 != 0. */
+int64_t nacc_grid_mip_words(const nacc_grid_desc* grid);
+
+/*
+ * Builds the skip grid used by the marching calls to pass over empty space
+ * (Sec. 2.1, "Pruning Empty and Occluded Regions"): per grid, h = ceil(
+ * (res/4)^3 / 32) words with one bit per coarse cell of 4x4x4 fine cells
+ * (C order, LSB first), set iff some occupied fine cell lies in the coarse
+ * cell or in one of its 26 neighbours (dilated by one coarse cell), followed
+ * by h words of the undilated coarse bits.
+ *   bits  uint32[n_grids * res^3 / 32]; mip out uint32[nacc_grid_mip_words].
+ * NACC_ENOTSUP unless res % 4 == 0.
+ */
+int nacc_grid_build_mip(const uint32_t* bits, const nacc_grid_desc* grid,
+                        uint32_t* mip, void* stream);
 
 /* bits: bit c is set iff occ[c] > threshold (strict); n_cells % 32 == 0;
  * bits is uint32[n_cells / 32], LSB first. */

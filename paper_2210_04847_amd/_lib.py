@@ -53,9 +53,9 @@ _SIGNATURES = {
     "nacc_last_error": (ctypes.c_char_p, []),
     "nacc_status_str": (ctypes.c_char_p, [_INT]),
     "nacc_march_workspace_size": (_I64, [_I64]),
-    "nacc_march_count": (_INT, [_P, _P, _P, _I64, _P, ctypes.POINTER(GridDesc),
+    "nacc_march_count": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
                                 ctypes.POINTER(MarchParams), _P, _P, _P, _SZ, _P]),
-    "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, ctypes.POINTER(GridDesc),
+    "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
                                ctypes.POINTER(MarchParams), _P, _I64, _P, _P, _P, _P, _P]),
     "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
@@ -67,6 +67,8 @@ _SIGNATURES = {
                                       _P, _P, _P]),
     "nacc_grid_update_max": (_INT, [_P, _P, _P, _I64, _I64, _P]),
     "nacc_grid_pack": (_INT, [_P, _I64, _F, _P, _P]),
+    "nacc_grid_mip_words": (_I64, [ctypes.POINTER(GridDesc)]),
+    "nacc_grid_build_mip": (_INT, [_P, ctypes.POINTER(GridDesc), _P, _P]),
     "nacc_synth_table_size": (_I64, [_I32, _I32]),
     "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _P, _P]),
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
@@ -161,7 +163,7 @@ def _grid_words(desc):
 
 
 def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, total,
-                workspace, stream=None):
+                workspace, grid_mip=None, stream=None):
     n = rays_o.shape[0]
     _need(rays_o, torch.float32, "rays_o", 3 * n)
     _need(rays_d, torch.float32, "rays_d", 3 * n)
@@ -170,14 +172,16 @@ def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, t
     _need(packed_info, torch.int32, "packed_info", 2 * n)
     _need(total, torch.int64, "total", 1)
     _need(workspace, torch.uint8, "workspace")
+    _need(grid_mip, torch.int32, "grid_mip", grid_mip_words(desc))
     _check("nacc_march_count", lib.nacc_march_count(
-        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), ctypes.byref(desc),
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_mip),
+        ctypes.byref(desc),
         ctypes.byref(params), _ptr(packed_info), _ptr(total), _ptr(workspace),
         workspace.numel() if workspace is not None else 0, _stream(stream)))
 
 
 def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ray_indices,
-               t_starts, t_ends, status=None, stream=None):
+               t_starts, t_ends, status=None, grid_mip=None, stream=None):
     n = rays_o.shape[0]
     cap = ray_indices.numel()
     _need(rays_o, torch.float32, "rays_o", 3 * n)
@@ -189,8 +193,10 @@ def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ra
     _need(t_starts, torch.float32, "t_starts", cap)
     _need(t_ends, torch.float32, "t_ends", cap)
     _need(status, torch.int32, "status", 1)
+    _need(grid_mip, torch.int32, "grid_mip", grid_mip_words(desc))
     _check("nacc_march_fill", lib.nacc_march_fill(
-        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), ctypes.byref(desc),
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_mip),
+        ctypes.byref(desc),
         ctypes.byref(params), _ptr(packed_info), cap, _ptr(ray_indices), _ptr(t_starts),
         _ptr(t_ends), _ptr(status), _stream(stream)))
 
@@ -277,6 +283,17 @@ def grid_update_max(occ, cells, values, stream=None):
     _need(values, torch.float32, "values", n)
     _check("nacc_grid_update_max", lib.nacc_grid_update_max(
         _ptr(occ), _ptr(cells), _ptr(values), n, occ.numel(), _stream(stream)))
+
+
+def grid_mip_words(desc) -> int:
+    return int(lib.nacc_grid_mip_words(ctypes.byref(desc)))
+
+
+def grid_build_mip(bits, desc, mip, stream=None):
+    _need(bits, torch.int32, "bits", _grid_words(desc))
+    _need(mip, torch.int32, "mip", grid_mip_words(desc))
+    _check("nacc_grid_build_mip", lib.nacc_grid_build_mip(_ptr(bits), ctypes.byref(desc), _ptr(mip),
+                                                          _stream(stream)))
 
 
 def grid_pack(occ, threshold, bits, stream=None):

@@ -49,7 +49,15 @@ class OccupancyGrid:
         self.bits = torch.zeros(self.cells // 32, dtype=torch.int32, device=dev)
         self.desc = _lib.grid_desc(self.box[:3], self.box[3:], self.res, self.n_grids,
                                    self.lookup)
+        # skip grid for passing over empty space (box lookup, res % 4 == 0)
+        mw = _lib.grid_mip_words(self.desc) if self.lookup == _lib.LOOKUP_AABB else 0
+        self.mip = torch.zeros(mw, dtype=torch.int32, device=dev) if mw > 0 else None
         self.updates = 0
+
+    def _repack(self, threshold):
+        _lib.grid_pack(self.occ, threshold, self.bits)
+        if self.mip is not None:
+            _lib.grid_build_mip(self.bits, self.desc, self.mip)
 
     def set_occupancy(self, occ, threshold=0.01):
         """Replaces the density state and repacks the bits (occ > threshold)."""
@@ -57,7 +65,7 @@ class OccupancyGrid:
         if occ.numel() != self.cells:
             raise ValueError(f"expected {self.cells} values, got {occ.numel()}")
         self.occ.copy_(occ)
-        _lib.grid_pack(self.occ, threshold, self.bits)
+        self._repack(threshold)
 
     def update(self, sigma_fn, decay=0.95, threshold=0.01, n_samples=1 << 18, seed=0):
         """One update: decay all cells, max with sigma_fn at n random jittered
@@ -76,7 +84,7 @@ class OccupancyGrid:
             sig = sigma_fn(pos, torch.div(cells, self.res ** 3, rounding_mode="floor"))
         sig = torch.as_tensor(sig, dtype=torch.float32, device=dev).reshape(-1).contiguous()
         _lib.grid_update_max(self.occ, cells, sig)
-        _lib.grid_pack(self.occ, threshold, self.bits)
+        self._repack(threshold)
         self.updates += 1
 
     def state_dict(self):
@@ -87,16 +95,19 @@ class OccupancyGrid:
     def load_state_dict(self, state):
         self.occ.copy_(state["occ"])
         self.bits.copy_(state["bits"])
+        if self.mip is not None:
+            _lib.grid_build_mip(self.bits, self.desc, self.mip)
         self.updates = int(state["updates"])
 
 
 def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=1e10,
                  render_step_size=STEP_1024, cone_angle=0.0, dt_max=1e10, max_per_ray=0,
-                 grid_id=None):
+                 grid_id=None, skip_empty=True):
     """Marches the rays through the occupancy grid (Sec. 2.1) and returns the
     packed samples (Sec. 3): packed_info [R, 2] int32 (start, count),
     ray_indices [E] int32, t_starts [E], t_ends [E] float32.  One device-to-host
-    copy of the total sizes the outputs exactly."""
+    copy of the total sizes the outputs exactly.  skip_empty uses the grid's
+    skip grid (same samples, less work)."""
     rays_o = rays_o.reshape(-1, 3).contiguous()
     rays_d = rays_d.reshape(-1, 3).contiguous()
     n = rays_o.shape[0]
@@ -107,7 +118,8 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
     total = torch.empty(1, dtype=torch.int64, device=dev)
     ws = torch.empty(max(_lib.march_workspace_size(n), 1), dtype=torch.uint8, device=dev)
     gid = None if grid_id is None else grid_id.to(torch.int32).contiguous()
-    _lib.march_count(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, total, ws)
+    mip = grid.mip if skip_empty else None
+    _lib.march_count(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, total, ws, mip)
     e = int(total.item())
     if e > 2 ** 31 - 1:
         raise _lib.NaccError("ray_marching", _lib.NACC_ECAPACITY,
@@ -116,7 +128,7 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
     t_starts = torch.empty(e, dtype=torch.float32, device=dev)
     t_ends = torch.empty(e, dtype=torch.float32, device=dev)
     _lib.march_fill(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, ray_indices,
-                    t_starts, t_ends)
+                    t_starts, t_ends, None, mip)
     return packed, ray_indices, t_starts, t_ends
 
 

@@ -45,6 +45,8 @@ struct GridK {
     int res;
     int n_grids;
     uint32_t words;    // 32-bit words per grid
+    int coarse;        // coarse cells per axis of the skip grid (res / 4)
+    uint32_t mip_words;  // 32-bit words per grid of the skip grid (dilated half first)
 };
 
 struct ClipK {
@@ -114,6 +116,47 @@ __device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint
     return ((word >> (cell & 31u)) & 1u) != 0u;
 }
 
+// Fine cell indices (j_0, j_1, j_2) of point x under the box lookup.
+__device__ __forceinline__ void cell_indices(const GridK& g, float x0, float x1, float x2, uint32_t& j0, uint32_t& j1,
+                                             uint32_t& j2) {
+    j0 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top)));
+    j1 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top)));
+    j2 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top)));
+}
+
+// Bit of the dilated skip grid at the coarse cell holding fine cell j: it is
+// clear only if every fine cell within one coarse cell (4 fine cells) of
+// it, in every direction, is empty.
+__device__ __forceinline__ bool skip_bit(const uint32_t* __restrict__ mip, uint32_t mip0, const GridK& g,
+                                         uint32_t j0, uint32_t j1, uint32_t j2) {
+    const uint32_t c = static_cast<uint32_t>(g.coarse);
+    const uint32_t cell = ((j0 >> 2) * c + (j1 >> 2)) * c + (j2 >> 2);
+    return ((mip[mip0 + (cell >> 5)] >> (cell & 31u)) & 1u) != 0u;
+}
+
+// Largest group size G in {64, 32, 16, 8} such that the midpoints of any
+// two candidates at most G/2 steps apart fall in fine cells at most 4 apart
+// on every axis (bound on |u_k - u_t| below 3.9, with a generous allowance
+// for FP32 rounding of t, x and u), so that one test point per group plus
+// the one-coarse-cell dilation covers every candidate of the group.
+// 0: no grouping for this ray.
+__device__ __forceinline__ int group_size(const GridK& g, const float o[3], const float d[3], float t_near,
+                                          float t_far, float dt) {
+    const float tmax = fmaxf(fabsf(t_near), fabsf(t_far));
+    float slope = 0.0f, slack = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float sd = g.s[i] * fabsf(d[i]);
+        slope = fmaxf(slope, sd * dt);
+        slack = fmaxf(slack, g.s[i] * (fabsf(o[i]) + fabsf(g.lo[i]) + 2.0f * fabsf(d[i]) * tmax));
+    }
+    slack = (slack + static_cast<float>(g.res)) * 0x1p-16f;
+    for (int G = 64; G >= 8; G >>= 1) {
+        if (slope * static_cast<float>(G / 2) + slack <= 3.9f) return G;
+    }
+    return 0;
+}
+
 // First word of the ray's grid, or false for an invalid grid id (the ray is
 // then treated as a miss).
 template <int LOOKUP>
@@ -130,11 +173,19 @@ __device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id,
 
 // One ray, uniform steps, whole wave.  Returns the ray's sample count (the
 // same value in every lane).  FILL writes samples [0, limit) at `start`.
-template <int LOOKUP, bool FILL>
+//
+// With a skip grid (MIP, box lookup only), candidates are grouped G at a
+// time; one test point per group (its middle candidate, computed with the
+// same contract formulae) is looked up in the dilated skip grid, 64 groups
+// per wave.  A chunk of 64 candidates whose groups are all clear is skipped
+// without touching its candidates, and lanes in clear groups skip their
+// fine lookup: their cells are empty by construction, so the sample set is
+// exactly the one of the plain traversal.
+template <int LOOKUP, bool FILL, bool MIP>
 __device__ __forceinline__ int march_ray_uniform(
     int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const GridK& g,
-    const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ mip,
+    const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     bool& overflow) {
     const int lane = lane_id();
@@ -148,8 +199,45 @@ __device__ __forceinline__ int march_ray_uniform(
     if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
     float t_near, t_far;
     if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    const uint32_t mip0 = MIP ? (word0 / g.words) * g.mip_words : 0u;
+    int G = MIP ? uniform<int>(group_size(g, o, d, t_near, t_far, p.dt)) : 0;
+    uint64_t live_groups = ~0ull;  // groups [window * 64, window * 64 + 64) as bits
+    uint64_t live_chunks = ~0ull;  // chunks of the window as bits
+    int window_chunk = -(1 << 30);  // first chunk of the current window
     int count = 0;
     for (int k0 = 0; k0 < kMaxCandidates; k0 += kWave) {
+        const int chunk = k0 / kWave;
+        bool lane_live = true;
+        if (MIP && G > 0) {
+            if (chunk >= window_chunk + G && k0 + kWave * G > kMaxCandidates) {
+                // test points past 2^24 would not be exact lattice points:
+                // plain traversal from here on
+                G = 0;
+            }
+        }
+        if (MIP && G > 0) {
+            if (chunk >= window_chunk + G) {
+                // new window: 64 groups of G candidates = G chunks
+                window_chunk = chunk;
+                const int kt = k0 + lane * G + G / 2;
+                const float a0 = t_near + static_cast<float>(kt) * p.dt;
+                const float a1 = t_near + static_cast<float>(kt + 1) * p.dt;
+                const float am = (a0 + a1) * 0.5f;
+                uint32_t j0, j1, j2;
+                cell_indices(g, o[0] + d[0] * am, o[1] + d[1] * am, o[2] + d[2] * am, j0, j1, j2);
+                live_groups = ballot(skip_bit(mip, mip0, g, j0, j1, j2));
+                const int per_chunk = kWave / G;  // groups per chunk: 1, 2, 4 or 8
+                const uint64_t group_mask = (1ull << per_chunk) - 1ull;
+                live_chunks = ballot(lane < G && ((live_groups >> (lane * per_chunk)) & group_mask) != 0ull);
+            }
+            const int rel = chunk - window_chunk;
+            if (((live_chunks >> rel) & 1ull) == 0ull) {
+                // every candidate of this chunk lies in empty cells
+                if (!(t_near + static_cast<float>(k0) * p.dt < t_far)) break;
+                continue;
+            }
+            lane_live = ((live_groups >> ((rel * kWave + lane) / G)) & 1ull) != 0ull;
+        }
         const int k = k0 + lane;
         const float t0 = t_near + static_cast<float>(k) * p.dt;
         const bool live = t0 < t_far;
@@ -157,8 +245,9 @@ __device__ __forceinline__ int march_ray_uniform(
         const float t1 = t_near + static_cast<float>(k + 1) * p.dt;
         const float tm = (t0 + t1) * 0.5f;
         bool hit = false;
-        if (live) hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm,
-                                         o[2] + d[2] * tm);
+        if (live && lane_live) {
+            hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+        }
         const uint64_t m = ballot(hit);
         if (FILL && hit) {
             const int idx = count + bits_below(m);
@@ -183,11 +272,11 @@ __device__ __forceinline__ int march_ray_uniform(
     return count;
 }
 
-template <int LOOKUP>
+template <int LOOKUP, bool MIP>
 __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
+    const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
     int64_t* __restrict__ block_sums) {
     __shared__ int64_t wave_total[kUniformThreads / kWave];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
@@ -197,8 +286,8 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
-        const int n = march_ray_uniform<LOOKUP, false>(r, rays_o, rays_d, grid_id, bits, g, c, p,
-                                                       0, 0, 0, nullptr, nullptr, nullptr, unused);
+        const int n = march_ray_uniform<LOOKUP, false, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p,
+                                                            0, 0, 0, nullptr, nullptr, nullptr, unused);
         if (lane_id() == 0) packed_info[2 * r + 1] = n;
         total += n;
     }
@@ -211,11 +300,12 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     }
 }
 
-template <int LOOKUP>
+template <int LOOKUP, bool MIP>
 __global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info, int64_t capacity,
+    const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
+    int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     int32_t* __restrict__ status) {
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
@@ -227,8 +317,8 @@ __global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
         const int64_t start = packed_info[2 * r];
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
-        march_ray_uniform<LOOKUP, true>(r, rays_o, rays_d, grid_id, bits, g, c, p, start, limit,
-                                        capacity, ray_indices, t_starts, t_ends, overflow);
+        march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit,
+                                             capacity, ray_indices, t_starts, t_ends, overflow);
     }
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
@@ -426,6 +516,8 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     g.res = grid.res;
     g.n_grids = grid.n_grids;
     g.words = static_cast<uint32_t>(static_cast<int64_t>(grid.res) * grid.res * grid.res / 32);
+    g.coarse = grid.res / 4;
+    g.mip_words = static_cast<uint32_t>(nacc_grid_mip_words(&grid) / std::max(grid.n_grids, 1));
     p.near_plane = params.near_plane;
     p.far_plane = params.far_plane;
     p.dt = params.dt;
@@ -436,29 +528,42 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
 
 template <int LOOKUP>
 void launch_count(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                  int64_t n, const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p,
-                  int32_t* packed, int64_t* sums) {
+                  int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
+                  const StepK& p, int32_t* packed, int64_t* sums) {
     if (cone) {
         hipLaunchKernelGGL(count_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
                            bits, g, c, p, packed, sums);
+    } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
+        hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
+                           gid, n, bits, mip, g, c, p, packed, sums);
     } else {
-        hipLaunchKernelGGL(count_uniform_kernel<LOOKUP>, dim3(nb), dim3(kUniformThreads), 0, s, o, d, gid,
-                           n, bits, g, c, p, packed, sums);
+        hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
+                           gid, n, bits, mip, g, c, p, packed, sums);
     }
 }
 
 template <int LOOKUP>
 void launch_fill(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                 int64_t n, const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p,
-                 const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
+                 int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
+                 const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
                  int32_t* status) {
     if (cone) {
         hipLaunchKernelGGL(fill_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, bits,
                            g, c, p, packed, capacity, ri, ts, te, status);
+    } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
+        hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
+                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status);
     } else {
-        hipLaunchKernelGGL(fill_uniform_kernel<LOOKUP>, dim3(nb), dim3(kUniformThreads), 0, s, o, d, gid, n,
-                           bits, g, c, p, packed, capacity, ri, ts, te, status);
+        hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
+                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status);
     }
+}
+
+// The skip grid is used by uniform steps with the box lookup and needs
+// res % 4 == 0; anything else marches without it.
+const uint32_t* usable_mip(const uint32_t* mip, const nacc_grid_desc& grid, const nacc_march_params& p) {
+    if (mip == nullptr || grid.lookup != NACC_LOOKUP_AABB || p.cone != 0.0f || grid.res % 4 != 0) return nullptr;
+    return mip;
 }
 
 }  // namespace
@@ -471,7 +576,8 @@ int64_t nacc_march_workspace_size(int64_t n_rays) {
 }
 
 int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                     const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
+                     const uint32_t* grid_bits, const uint32_t* grid_mip, const nacc_grid_desc* grid,
+                     const nacc_march_params* params,
                      int32_t* packed_info, int64_t* total, void* workspace, size_t workspace_bytes,
                      void* stream) {
     clear_error();
@@ -491,18 +597,19 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
     const int64_t nb = num_blocks(n_rays);
     int64_t* sums = static_cast<int64_t*>(workspace);
     const bool cone = params->cone > 0.0f;
+    const uint32_t* mip = usable_mip(grid_mip, *grid, *params);
     if (nb > 0) {
         switch (grid->lookup) {
             case NACC_LOOKUP_AABB:
-                launch_count<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                launch_count<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
                                                packed_info, sums);
                 break;
             case NACC_LOOKUP_CASCADE:
-                launch_count<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                launch_count<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c,
                                                   p, packed_info, sums);
                 break;
             default:
-                launch_count<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
+                launch_count<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g,
                                                    c, p, packed_info, sums);
                 break;
         }
@@ -521,7 +628,8 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
 }
 
 int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                    const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
+                    const uint32_t* grid_bits, const uint32_t* grid_mip, const nacc_grid_desc* grid,
+                    const nacc_march_params* params,
                     const int32_t* packed_info, int64_t capacity, int32_t* ray_indices, float* t_starts,
                     float* t_ends, int32_t* status, void* stream) {
     clear_error();
@@ -545,17 +653,18 @@ int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* gri
     const int64_t nb = num_blocks(n_rays);
     if (nb == 0) return NACC_OK;
     const bool cone = params->cone > 0.0f;
+    const uint32_t* mip = usable_mip(grid_mip, *grid, *params);
     switch (grid->lookup) {
         case NACC_LOOKUP_AABB:
-            launch_fill<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+            launch_fill<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
                                           packed_info, capacity, ray_indices, t_starts, t_ends, status);
             break;
         case NACC_LOOKUP_CASCADE:
-            launch_fill<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+            launch_fill<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
                                              packed_info, capacity, ray_indices, t_starts, t_ends, status);
             break;
         default:
-            launch_fill<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+            launch_fill<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
                                               packed_info, capacity, ray_indices, t_starts, t_ends, status);
             break;
     }

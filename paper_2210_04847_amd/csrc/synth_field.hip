@@ -48,6 +48,7 @@ __device__ __forceinline__ void eval_field(const float* __restrict__ table, int 
                                            float x2, float& sigma) {
     const float* blob = table + static_cast<int64_t>(set) * n_blobs * kBlobStride;
     float acc = 0.0f;
+#pragma unroll 4
     for (int b = 0; b < n_blobs; ++b) {
         const float dx = x0 - blob[kBlobStride * b];
         const float dy = x1 - blob[kBlobStride * b + 1];
@@ -75,6 +76,9 @@ __device__ __forceinline__ float midpoint_coord(float o, float d, float t0, floa
     return o + d * tm;
 }
 
+// With a single centre set (PER_SET false) every lane reads the same blob
+// parameters, which the compiler then fetches with scalar loads.
+template <bool PER_SET>
 __global__ __launch_bounds__(kThreads) void field_samples_kernel(
     const float* __restrict__ table, int n_blobs, int n_sets, const float* __restrict__ rays_o,
     const float* __restrict__ rays_d, int64_t n_rays, const int32_t* __restrict__ ray_set,
@@ -95,8 +99,11 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
         const float x0 = midpoint_coord(rays_o[3 * r], rays_d[3 * r], t0, t1);
         const float x1 = midpoint_coord(rays_o[3 * r + 1], rays_d[3 * r + 1], t0, t1);
         const float x2 = midpoint_coord(rays_o[3 * r + 2], rays_d[3 * r + 2], t0, t1);
-        int set = ray_set != nullptr ? ray_set[r] : 0;
-        set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        int set = 0;
+        if (PER_SET) {
+            set = ray_set[r];
+            set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        }
         float sigma;
         eval_field(table, n_blobs, set, x0, x1, x2, sigma);
         sigmas[s] = sigma;
@@ -110,6 +117,7 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
     }
 }
 
+template <bool PER_SET>
 __global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __restrict__ table, int n_blobs,
                                                                  int n_sets, const float* __restrict__ points,
                                                                  const int32_t* __restrict__ point_set, int64_t n,
@@ -119,8 +127,11 @@ __global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __r
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; q < n; q += stride) {
         const float x0 = points[3 * q], x1 = points[3 * q + 1], x2 = points[3 * q + 2];
-        int set = point_set != nullptr ? point_set[q] : 0;
-        set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        int set = 0;
+        if (PER_SET) {
+            set = point_set[q];
+            set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+        }
         float sigma;
         eval_field(table, n_blobs, set, x0, x1, x2, sigma);
         sigmas[q] = sigma;
@@ -171,7 +182,8 @@ int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets,
     NACC_REQUIRE(n_samples == 0 || (table && rays_o && rays_d && ray_indices && t_starts && t_ends && sigmas),
                  NACC_EINVAL, "arguments must be non-NULL");
     if (n_samples == 0) return NACC_OK;
-    hipLaunchKernelGGL(field_samples_kernel, dim3(field_blocks(n_samples)), dim3(kThreads), 0, as_stream(stream),
+    auto kernel = ray_set != nullptr ? field_samples_kernel<true> : field_samples_kernel<false>;
+    hipLaunchKernelGGL(kernel, dim3(field_blocks(n_samples)), dim3(kThreads), 0, as_stream(stream),
                        static_cast<const float*>(table), n_blobs, n_sets, rays_o, rays_d, n_rays, ray_set,
                        ray_indices,
                        t_starts, t_ends, n_samples, n_samples_dev, sigmas, rgbs);
@@ -185,7 +197,8 @@ int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, 
     NACC_REQUIRE(n >= 0, NACC_EINVAL, "n < 0");
     NACC_REQUIRE(n == 0 || (table && points && sigmas), NACC_EINVAL, "arguments must be non-NULL");
     if (n == 0) return NACC_OK;
-    hipLaunchKernelGGL(field_points_kernel, dim3(field_blocks(n)), dim3(kThreads), 0, as_stream(stream),
+    auto kernel = point_set != nullptr ? field_points_kernel<true> : field_points_kernel<false>;
+    hipLaunchKernelGGL(kernel, dim3(field_blocks(n)), dim3(kThreads), 0, as_stream(stream),
                        static_cast<const float*>(table), n_blobs, n_sets, points, point_set, n, sigmas, rgbs);
     return check_launch("synth field points");
 }

@@ -47,7 +47,7 @@ def test_status_strings_and_version():
 
 def _march_count_raw(lib, n_rays, desc, params, ws_bytes=1 << 20):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
-    return lib.nacc_march_count(fake, fake, None, n_rays, fake, ctypes.byref(desc),
+    return lib.nacc_march_count(fake, fake, None, n_rays, fake, None, ctypes.byref(desc),
                                 ctypes.byref(params), fake, fake, fake, ws_bytes, None)
 
 
@@ -108,6 +108,6 @@ def test_zero_rays_launch_nothing_but_need_total():
     desc = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
     params = _lib.march_params(0.0, 10.0, 0.01)
     fake = ctypes.c_void_p(0x1000)
-    st = _lib.lib.nacc_march_count(fake, fake, None, 0, fake, ctypes.byref(desc),
+    st = _lib.lib.nacc_march_count(fake, fake, None, 0, fake, None, ctypes.byref(desc),
                                    ctypes.byref(params), None, None, None, 0, None)
     assert st == _lib.NACC_EINVAL  # total is required even for zero rays

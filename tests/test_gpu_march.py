@@ -19,7 +19,7 @@ def _nacc():
 
 
 def gpu_march(o, d, mask, res, box, near, far, dt, dt_max=1e10, cone=0.0, lookup=0, n_grids=1,
-              grid_id=None, max_per_ray=0):
+              grid_id=None, max_per_ray=0, skip_empty=True):
     """Packs the 0/1 mask with the library's pack kernel, marches, returns
     numpy arrays (packed, ray_indices, t_starts, t_ends)."""
     nacc = _nacc()
@@ -28,16 +28,19 @@ def gpu_march(o, d, mask, res, box, near, far, dt, dt_max=1e10, cone=0.0, lookup
     grid.set_occupancy(torch.from_numpy(mask.astype(np.float32)).cuda(), 0.5)
     gid = None if grid_id is None else torch.from_numpy(grid_id.astype(np.int32)).cuda()
     p, ri, ts, te = nacc.ray_marching(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(),
-                                      grid, near, far, dt, cone, dt_max, max_per_ray, gid)
+                                      grid, near, far, dt, cone, dt_max, max_per_ray, gid,
+                                      skip_empty)
     torch.cuda.synchronize()
     return p.cpu().numpy(), ri.cpu().numpy(), ts.cpu().numpy(), te.cpu().numpy()
 
 
 def compare(o, d, mask, res, box, near, far, dt, **kw):
-    got = gpu_march(o, d, mask, res, box, near, far, dt, **kw)
+    """Both traversals (with and without the skip grid) against the oracle."""
     want = oracle.march(o, d, mask, res, box, near, far, dt, **kw)
-    for g, w, name in zip(got, want, ("packed_info", "ray_indices", "t_starts", "t_ends")):
-        assert_bit_exact(g, w, name)
+    for skip in (False, True):
+        got = gpu_march(o, d, mask, res, box, near, far, dt, skip_empty=skip, **kw)
+        for g, w, name in zip(got, want, ("packed_info", "ray_indices", "t_starts", "t_ends")):
+            assert_bit_exact(g, w, f"{name} (skip grid {skip})")
     return want
 
 
@@ -50,7 +53,8 @@ def test_plain_workload_4096_rays():
     assert p[:, 1].max() > 64 and (p[:, 1] == 0).any()
 
 
-@pytest.mark.parametrize("res,p_occ,seed", [(4, 0.4, 1), (8, 0.3, 2), (16, 0.2, 3), (32, 0.5, 4)])
+@pytest.mark.parametrize("res,p_occ,seed", [(4, 0.4, 1), (8, 0.3, 2), (16, 0.2, 3), (32, 0.5, 4),
+                                            (32, 0.02, 5), (64, 0.005, 6)])
 def test_tiny_random_grids(res, p_occ, seed):
     mask = synth.random_mask(res ** 3, p_occ, seed)
     o, d = synth.rays_toward_origin(1000, 100 + seed)
@@ -81,6 +85,40 @@ def test_empty_full_and_no_rays():
     compare(o, d, np.ones(8 ** 3, np.uint8), 8, BOX, 0.0, 1e10, 0.01)
     compare(o[:0], d[:0], np.ones(8 ** 3, np.uint8), 8, BOX, 0.0, 1e10, 0.01)
     compare(o[:1], d[:1], np.ones(8 ** 3, np.uint8), 8, BOX, 0.0, 1e10, 0.01)
+
+
+@pytest.mark.parametrize("scale,dt", [(1.0, 0.0051), (3.0, 0.0051), (0.3, 0.0051), (1.0, 0.03),
+                                      (1.0, 0.2)])
+def test_skip_grid_group_sizes(scale, dt):
+    # unnormalised directions and coarse steps change the group size per
+    # ray (down to no grouping at all); the samples must not change
+    w = synth.WORKLOADS["train_262k"]
+    scene = synth.blob_scene(32, 1001)
+    occ = synth.initial_occupancy(scene, 64, synth.BOX_1_5)
+    mask = oracle.grid_threshold(occ, 0.01)
+    o, d = synth.rays_toward_origin(1500, 50)
+    compare(o, (d * np.float32(scale)).astype(np.float32), mask, 64, BOX, 0.0, 1e10, dt)
+
+
+def test_skip_grid_contents():
+    import paper_2210_04847_amd as nacc
+    from scipy.ndimage import maximum_filter
+    res = 32
+    mask = synth.random_mask(2 * res ** 3, 0.002, 51)
+    grid = nacc.OccupancyGrid(BOX, res, n_grids=2)
+    grid.set_occupancy(torch.from_numpy(mask.astype(np.float32)).cuda(), 0.5)
+    torch.cuda.synchronize()
+    mip = grid.mip.cpu().numpy().view(np.uint32)
+    c = res // 4
+    half = (c ** 3 + 31) // 32
+    for gi in range(2):
+        m = mask[gi * res ** 3:(gi + 1) * res ** 3].reshape(c, 4, c, 4, c, 4)
+        coarse = m.max(axis=(1, 3, 5))
+        dil = maximum_filter(coarse, size=3, mode="constant", cval=0)
+        for arr, off in ((dil, 0), (coarse, half)):
+            words = np.packbits(arr.ravel().astype(np.uint8), bitorder="little")
+            words = np.pad(words, (0, 4 * half - words.size)).view("<u4")
+            assert np.array_equal(mip[gi * 2 * half + off: gi * 2 * half + off + half], words)
 
 
 def test_long_rays_many_chunks():

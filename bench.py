@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="train_262k", choices=["train_262k", "plain_fwd_4k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-grid", choices=["on", "off"], default="off",
+                    help="march with the dilated coarse skip grid")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
     return ap.parse_args()
 
@@ -47,7 +49,7 @@ class TrainStep:
     """Buffers and launches of one training step (everything on torch's
     current stream)."""
 
-    def __init__(self, w, inp, torch, nacc):
+    def __init__(self, w, inp, torch, nacc, skip_grid=False):
         self.torch, self.nacc, self.lib = torch, nacc, nacc._lib
         dev = torch.device("cuda")
         t = lambda a: torch.from_numpy(a).to(dev)
@@ -65,7 +67,8 @@ class TrainStep:
         self.params = self.lib.march_params(w.near, w.far, w.dt)
         self.packed = torch.empty((n, 2), dtype=i32, device=dev)
         self.total = torch.empty(1, dtype=torch.int64, device=dev)
-        self.ws = torch.empty(self.lib.march_workspace_size(n), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(self.lib.march_workspace_size(n, self.grid.desc, self.params),
+                              dtype=torch.uint8, device=dev)
         self.ray_indices = torch.empty(cap, dtype=i32, device=dev)
         self.t_starts = torch.empty(cap, dtype=f32, device=dev)
         self.t_ends = torch.empty(cap, dtype=f32, device=dev)
@@ -84,16 +87,17 @@ class TrainStep:
         self.ema_sigma = torch.empty(EMA_CELLS, dtype=f32, device=dev)
         self.updates = 0
         self.seed = 4000 + w.seed_base
+        self.mip = self.grid.mip if skip_grid else None
 
     # phases ------------------------------------------------------------
     def march_count(self):
         self.lib.march_count(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
-                             self.params, self.packed, self.total, self.ws, self.grid.mip)
+                             self.params, self.packed, self.total, self.ws, self.mip)
 
     def march_fill(self):
         self.lib.march_fill(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
                             self.params, self.packed, self.ray_indices, self.t_starts, self.t_ends,
-                            self.status, self.grid.mip)
+                            self.status, self.mip, self.ws)
 
     def field_eval(self):
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
@@ -201,7 +205,7 @@ def main():
     t_gen = time.perf_counter()
     inp = synth.workload_inputs(w)
     print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    st = TrainStep(w, inp, torch, nacc)
+    st = TrainStep(w, inp, torch, nacc, skip_grid=args.skip_grid == "on")
     torch.cuda.synchronize()
 
     steps, warmup = args.steps, args.warmup
@@ -273,7 +277,7 @@ def main():
         "config": {"workload": w.name, "rays": w.n_rays, "grid": f"{w.res}^3 bit-packed",
                    "blobs": w.n_blobs, "dt": w.dt, "early_stop_eps": w.early_stop_eps,
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
-                   "form": "plain", "parallelism": "single GPU"},
+                   "form": "plain", "skip_grid": args.skip_grid, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": None},

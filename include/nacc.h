@@ -143,9 +143,14 @@ const char* nacc_last_error(void);
 /* Name of a status code. */
 const char* nacc_status_str(int status);
 
-/* Bytes of device workspace nacc_march_count needs for n_rays rays (>= 0);
- * -1 if n_rays < 0. */
-int64_t nacc_march_workspace_size(int64_t n_rays);
+/* Bytes of device workspace the marching calls need for n_rays rays with
+ * this grid and these parameters (>= 0); -1 for invalid arguments.  The
+ * workspace holds the scan's partial sums and, for uniform steps, one 64-bit
+ * occupancy mask per ray and chunk of 64 candidates (enough chunks for the
+ * longest chord of the clip box), which let nacc_march_fill write the
+ * samples without traversing the grid again. */
+int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid,
+                                  const nacc_march_params* params);
 
 /*
  * Marching, pass 1 of 2: count the samples of every ray and lay them out
@@ -165,8 +170,9 @@ int64_t nacc_march_workspace_size(int64_t n_rays);
  *                   with the box lookup and res % 4 == 0, ignored otherwise.
  *   packed_info     out int32[n_rays][2]: (start, count) per ray.
  *   total           out int64[1]: the sample total, on the device.
- *   workspace       device scratch of nacc_march_workspace_size(n_rays)
- *                   bytes; contents on entry are irrelevant.
+ *   workspace       device scratch of nacc_march_workspace_size bytes;
+ *                   contents on entry are irrelevant; pass the same buffer,
+ *                   unmodified, to nacc_march_fill.
  * Errors: NACC_EINVAL / NACC_ESHAPE for bad arguments; NACC_EHIP if a launch
  * fails.  A total above 2^31-1 is reported by nacc_march_fill.
  */
@@ -180,7 +186,8 @@ int nacc_march_count(const float* rays_o, const float* rays_d,
 
 /*
  * Marching, pass 2 of 2: write the samples laid out by nacc_march_count
- * (the same rays, grid and parameters, and its packed_info).
+ * (the same rays, grid and parameters, its packed_info and its workspace;
+ * workspace may be NULL, the grid is then traversed again).
  *   capacity        length of ray_indices / t_starts / t_ends.
  *   ray_indices     out int32[capacity], t_starts / t_ends out float[capacity].
  *   status          out int32[1] on the device: NACC_OK, or NACC_ECAPACITY
@@ -192,7 +199,8 @@ int nacc_march_fill(const float* rays_o, const float* rays_d,
                     const uint32_t* grid_bits, const uint32_t* grid_mip,
                     const nacc_grid_desc* grid,
                     const nacc_march_params* params,
-                    const int32_t* packed_info, int64_t capacity,
+                    const int32_t* packed_info, const void* workspace,
+                    size_t workspace_bytes, int64_t capacity,
                     int32_t* ray_indices, float* t_starts, float* t_ends,
                     int32_t* status, void* stream);
 

@@ -52,11 +52,11 @@ _SIGNATURES = {
     "nacc_version": (ctypes.c_char_p, []),
     "nacc_last_error": (ctypes.c_char_p, []),
     "nacc_status_str": (ctypes.c_char_p, [_INT]),
-    "nacc_march_workspace_size": (_I64, [_I64]),
+    "nacc_march_workspace_size": (_I64, [_I64, ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams)]),
     "nacc_march_count": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
                                 ctypes.POINTER(MarchParams), _P, _P, _P, _SZ, _P]),
     "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
-                               ctypes.POINTER(MarchParams), _P, _I64, _P, _P, _P, _P, _P]),
+                               ctypes.POINTER(MarchParams), _P, _P, _SZ, _I64, _P, _P, _P, _P, _P]),
     "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_mse_workspace_size": (_I64, [_I64]),
@@ -154,8 +154,11 @@ def march_params(near_plane, far_plane, dt, dt_max=1e10, cone=0.0, max_per_ray=0
 # Thin wrappers, one per C entry point (same names without the prefix).
 # ---------------------------------------------------------------------------
 
-def march_workspace_size(n_rays: int) -> int:
-    return int(lib.nacc_march_workspace_size(n_rays))
+def march_workspace_size(n_rays: int, desc, params) -> int:
+    n = int(lib.nacc_march_workspace_size(n_rays, ctypes.byref(desc), ctypes.byref(params)))
+    if n < 0:
+        raise NaccError("nacc_march_workspace_size", NACC_EINVAL, lib.nacc_last_error().decode())
+    return n
 
 
 def _grid_words(desc):
@@ -181,7 +184,7 @@ def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, t
 
 
 def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ray_indices,
-               t_starts, t_ends, status=None, grid_mip=None, stream=None):
+               t_starts, t_ends, status=None, grid_mip=None, workspace=None, stream=None):
     n = rays_o.shape[0]
     cap = ray_indices.numel()
     _need(rays_o, torch.float32, "rays_o", 3 * n)
@@ -194,11 +197,12 @@ def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ra
     _need(t_ends, torch.float32, "t_ends", cap)
     _need(status, torch.int32, "status", 1)
     _need(grid_mip, torch.int32, "grid_mip", grid_mip_words(desc))
+    _need(workspace, torch.uint8, "workspace")
     _check("nacc_march_fill", lib.nacc_march_fill(
         _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_mip),
-        ctypes.byref(desc),
-        ctypes.byref(params), _ptr(packed_info), cap, _ptr(ray_indices), _ptr(t_starts),
-        _ptr(t_ends), _ptr(status), _stream(stream)))
+        ctypes.byref(desc), ctypes.byref(params), _ptr(packed_info), _ptr(workspace),
+        workspace.numel() if workspace is not None else 0, cap, _ptr(ray_indices),
+        _ptr(t_starts), _ptr(t_ends), _ptr(status), _stream(stream)))
 
 
 def _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs):

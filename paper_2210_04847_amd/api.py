@@ -102,12 +102,13 @@ class OccupancyGrid:
 
 def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=1e10,
                  render_step_size=STEP_1024, cone_angle=0.0, dt_max=1e10, max_per_ray=0,
-                 grid_id=None, skip_empty=True):
+                 grid_id=None, skip_empty=True, replay_masks=True):
     """Marches the rays through the occupancy grid (Sec. 2.1) and returns the
     packed samples (Sec. 3): packed_info [R, 2] int32 (start, count),
     ray_indices [E] int32, t_starts [E], t_ends [E] float32.  One device-to-host
     copy of the total sizes the outputs exactly.  skip_empty uses the grid's
-    skip grid (same samples, less work)."""
+    skip grid and replay_masks lets the fill pass reuse the count pass's
+    occupancy masks (same samples either way, less work)."""
     rays_o = rays_o.reshape(-1, 3).contiguous()
     rays_d = rays_d.reshape(-1, 3).contiguous()
     n = rays_o.shape[0]
@@ -116,7 +117,8 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
                                max_per_ray)
     packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
     total = torch.empty(1, dtype=torch.int64, device=dev)
-    ws = torch.empty(max(_lib.march_workspace_size(n), 1), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(_lib.march_workspace_size(n, grid.desc, params), 1), dtype=torch.uint8,
+                     device=dev)
     gid = None if grid_id is None else grid_id.to(torch.int32).contiguous()
     mip = grid.mip if skip_empty else None
     _lib.march_count(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, total, ws, mip)
@@ -128,7 +130,7 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
     t_starts = torch.empty(e, dtype=torch.float32, device=dev)
     t_ends = torch.empty(e, dtype=torch.float32, device=dev)
     _lib.march_fill(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, ray_indices,
-                    t_starts, t_ends, None, mip)
+                    t_starts, t_ends, None, mip, ws if replay_masks else None)
     return packed, ray_indices, t_starts, t_ends
 
 

@@ -104,7 +104,8 @@ __device__ __forceinline__ double dpp(double v) {
 
 // DPP controls (GFX9 encoding).
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138, kWaveShl1 = 0x130;
 
 // Inclusive prefix sum across the 64 lanes: Hillis-Steele within each row of
 // 16 lanes, then the row totals are carried by two row broadcasts.  The
@@ -124,6 +125,30 @@ __device__ __forceinline__ T wave_inclusive_sum(T x) {
 template <typename T>
 __device__ __forceinline__ T shift_up_one(T x) {
     return dpp<kWaveShr1>(x);
+}
+
+// The value of the lane above (0 in lane 63).
+template <typename T>
+__device__ __forceinline__ T shift_down_one(T x) {
+    return dpp<kWaveShl1>(x);
+}
+
+// Inclusive suffix sum across the 64 lanes (lane i gets the sum over lanes
+// i..63): Hillis-Steele within each row of 16 lanes towards lower lanes,
+// then each row adds the totals of the rows above it.  Fixed association.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_suffix(T x) {
+    x = x + dpp<kRowShl1>(x);
+    x = x + dpp<kRowShl2>(x);
+    x = x + dpp<kRowShl4>(x);
+    x = x + dpp<kRowShl8>(x);
+    const T r1 = read_lane(x, 16), r2 = read_lane(x, 32), r3 = read_lane(x, 48);
+    const T above2 = r3;
+    const T above1 = r2 + r3;
+    const T above0 = r1 + above1;
+    const int row = lane_id() >> 4;
+    const T add = row == 0 ? above0 : (row == 1 ? above1 : (row == 2 ? above2 : T(0)));
+    return x + add;
 }
 
 // Sum over the 64 lanes, returned in every lane.

@@ -187,7 +187,8 @@ __device__ __forceinline__ int march_ray_uniform(
     const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ mip,
     const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    bool& overflow) {
+    bool& overflow, uint64_t* __restrict__ masks = nullptr, int n_masks = 0, int first_chunk = 0,
+    int count0 = 0) {
     const int lane = lane_id();
     float o[3], d[3];
 #pragma unroll
@@ -204,8 +205,8 @@ __device__ __forceinline__ int march_ray_uniform(
     uint64_t live_groups = ~0ull;  // groups [window * 64, window * 64 + 64) as bits
     uint64_t live_chunks = ~0ull;  // chunks of the window as bits
     int window_chunk = -(1 << 30);  // first chunk of the current window
-    int count = 0;
-    for (int k0 = 0; k0 < kMaxCandidates; k0 += kWave) {
+    int count = count0;
+    for (int k0 = first_chunk * kWave; k0 < kMaxCandidates; k0 += kWave) {
         const int chunk = k0 / kWave;
         bool lane_live = true;
         if (MIP && G > 0) {
@@ -234,6 +235,7 @@ __device__ __forceinline__ int march_ray_uniform(
             if (((live_chunks >> rel) & 1ull) == 0ull) {
                 // every candidate of this chunk lies in empty cells
                 if (!(t_near + static_cast<float>(k0) * p.dt < t_far)) break;
+                if (!FILL && chunk < n_masks && lane == 0) masks[chunk] = 0ull;
                 continue;
             }
             lane_live = ((live_groups >> ((rel * kWave + lane) / G)) & 1ull) != 0ull;
@@ -249,6 +251,7 @@ __device__ __forceinline__ int march_ray_uniform(
             hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
         }
         const uint64_t m = ballot(hit);
+        if (!FILL && chunk < n_masks && lane == 0) masks[chunk] = m;
         if (FILL && hit) {
             const int idx = count + bits_below(m);
             if (idx < limit) {
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
-    int64_t* __restrict__ block_sums) {
+    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
     __shared__ int64_t wave_total[kUniformThreads / kWave];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
@@ -286,8 +289,9 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
-        const int n = march_ray_uniform<LOOKUP, false, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p,
-                                                            0, 0, 0, nullptr, nullptr, nullptr, unused);
+        const int n = march_ray_uniform<LOOKUP, false, MIP>(
+            r, rays_o, rays_d, grid_id, bits, mip, g, c, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
+            masks != nullptr ? masks + r * n_masks : nullptr, masks != nullptr ? n_masks : 0);
         if (lane_id() == 0) packed_info[2 * r + 1] = n;
         total += n;
     }
@@ -300,14 +304,60 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     }
 }
 
+// Writes the samples of one ray from the per-chunk occupancy masks stored by
+// the count pass (the first n_masks chunks), so the grid is not traversed a
+// second time; a ray whose samples continue past those chunks is traversed
+// from there on.
+template <int LOOKUP, bool MIP>
+__device__ __forceinline__ void fill_ray_from_masks(
+    int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ mip,
+    const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow,
+    const uint64_t* __restrict__ masks, int n_masks) {
+    const int lane = lane_id();
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    float t_near, t_far;
+    clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far);
+    int written = 0;
+    int j = 0;
+    for (; j < n_masks && written < limit; ++j) {
+        const uint64_t m = masks[j];
+        if (m == 0ull) continue;
+        if ((m >> lane) & 1ull) {
+            const int idx = written + bits_below(m);
+            if (idx < limit) {
+                const int k = j * kWave + lane;
+                const int64_t pos = start + idx;
+                if (pos >= 0 && pos < capacity) {
+                    ray_indices[pos] = static_cast<int32_t>(r);
+                    t_starts[pos] = t_near + static_cast<float>(k) * p.dt;
+                    t_ends[pos] = t_near + static_cast<float>(k + 1) * p.dt;
+                } else {
+                    overflow = true;
+                }
+            }
+        }
+        written += __popcll(m);
+    }
+    if (written < limit) {
+        march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit, capacity,
+                                             ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks, written);
+    }
+}
+
 template <int LOOKUP, bool MIP>
 __global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
-    int64_t capacity,
-    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    int32_t* __restrict__ status) {
+    int64_t capacity, int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
     bool overflow = false;
@@ -317,8 +367,13 @@ __global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
         const int64_t start = packed_info[2 * r];
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
-        march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit,
-                                             capacity, ray_indices, t_starts, t_ends, overflow);
+        if (masks != nullptr) {
+            fill_ray_from_masks<LOOKUP, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit, capacity,
+                                             ray_indices, t_starts, t_ends, overflow, masks + r * n_masks, n_masks);
+        } else {
+            march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit,
+                                                 capacity, ray_indices, t_starts, t_ends, overflow);
+        }
     }
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
@@ -456,6 +511,44 @@ __global__ void set_status_kernel(int32_t* status, int32_t value) { *status = va
 
 int64_t num_blocks(int64_t n_rays) { return (n_rays + kRaysPerBlock - 1) / kRaysPerBlock; }
 
+constexpr int kMaxMaskChunks = 32;
+
+// Workspace of the marching calls: the per-workgroup sums of the scan, then
+// (uniform steps only) n_masks 64-bit occupancy masks per ray, one per chunk
+// of 64 candidates, written by the count pass and replayed by the fill pass.
+// n_masks covers the longest chord of the clip box (or far - near) in steps.
+struct Layout {
+    int64_t sums_bytes;
+    int n_masks;
+    int64_t bytes;
+};
+
+Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_march_params& p) {
+    Layout l;
+    l.sums_bytes = ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+    l.n_masks = 0;
+    if (p.cone == 0.0f && p.dt > 0.0f) {
+        double span = static_cast<double>(p.far_plane) - static_cast<double>(p.near_plane);
+        if (grid.lookup != NACC_LOOKUP_CONTRACT) {
+            const double scale = grid.lookup == NACC_LOOKUP_CASCADE ? std::ldexp(1.0, grid.n_grids - 1) : 1.0;
+            double d2 = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const double e = (static_cast<double>(grid.hi[i]) - static_cast<double>(grid.lo[i])) * scale;
+                d2 += e * e;
+            }
+            span = std::min(span, std::sqrt(d2));
+        }
+        if (std::isfinite(span) && span > 0.0) {
+            const double chunks = std::ceil((span / p.dt + 2.0) / kWave);
+            l.n_masks = static_cast<int>(std::min<double>(chunks, kMaxMaskChunks));
+        } else if (!std::isfinite(span)) {
+            l.n_masks = kMaxMaskChunks;
+        }
+    }
+    l.bytes = l.sums_bytes + n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t));
+    return l;
+}
+
 int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uint32_t* bits,
              const nacc_grid_desc* grid, const nacc_march_params* params) {
     NACC_REQUIRE(grid != nullptr && params != nullptr, NACC_EINVAL, "grid and params must be non-NULL");
@@ -529,16 +622,16 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
 template <int LOOKUP>
 void launch_count(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
                   int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
-                  const StepK& p, int32_t* packed, int64_t* sums) {
+                  const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
     if (cone) {
         hipLaunchKernelGGL(count_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
                            bits, g, c, p, packed, sums);
     } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
         hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, sums);
+                           gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
     } else {
         hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, sums);
+                           gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
     }
 }
 
@@ -546,16 +639,16 @@ template <int LOOKUP>
 void launch_fill(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
                  int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
                  const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
-                 int32_t* status) {
+                 int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
         hipLaunchKernelGGL(fill_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, bits,
                            g, c, p, packed, capacity, ri, ts, te, status);
     } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
         hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status);
+                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
     } else {
         hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status);
+                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
     }
 }
 
@@ -570,9 +663,11 @@ const uint32_t* usable_mip(const uint32_t* mip, const nacc_grid_desc& grid, cons
 
 extern "C" {
 
-int64_t nacc_march_workspace_size(int64_t n_rays) {
-    if (n_rays < 0) return -1;
-    return ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid, const nacc_march_params* params) {
+    clear_error();
+    if (n_rays < 0 || grid == nullptr || params == nullptr) return -1;
+    if (validate(nullptr, nullptr, 0, nullptr, grid, params) != NACC_OK) return -1;
+    return workspace_layout(n_rays, *grid, *params).bytes;
 }
 
 int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
@@ -585,10 +680,13 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
     if (st != NACC_OK) return st;
     NACC_REQUIRE(total != nullptr, NACC_EINVAL, "total must be non-NULL");
     NACC_REQUIRE(n_rays == 0 || packed_info != nullptr, NACC_EINVAL, "packed_info must be non-NULL");
-    const int64_t need = nacc_march_workspace_size(n_rays);
+    const Layout lay = workspace_layout(n_rays, *grid, *params);
+    const int64_t need = lay.bytes;
     NACC_REQUIRE(need == 0 || workspace != nullptr, NACC_EINVAL, "workspace must be non-NULL");
     NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE,
                  "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(need));
+    uint64_t* masks = lay.n_masks > 0 ? reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + lay.sums_bytes)
+                                      : nullptr;
     GridK g;
     ClipK c;
     StepK p;
@@ -602,15 +700,15 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
         switch (grid->lookup) {
             case NACC_LOOKUP_AABB:
                 launch_count<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                               packed_info, sums);
+                                               packed_info, sums, masks, lay.n_masks);
                 break;
             case NACC_LOOKUP_CASCADE:
                 launch_count<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c,
-                                                  p, packed_info, sums);
+                                                  p, packed_info, sums, masks, lay.n_masks);
                 break;
             default:
                 launch_count<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g,
-                                                   c, p, packed_info, sums);
+                                                   c, p, packed_info, sums, masks, lay.n_masks);
                 break;
         }
         st = check_launch("march count");
@@ -630,8 +728,8 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
 int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
                     const uint32_t* grid_bits, const uint32_t* grid_mip, const nacc_grid_desc* grid,
                     const nacc_march_params* params,
-                    const int32_t* packed_info, int64_t capacity, int32_t* ray_indices, float* t_starts,
-                    float* t_ends, int32_t* status, void* stream) {
+                    const int32_t* packed_info, const void* workspace, size_t workspace_bytes, int64_t capacity,
+                    int32_t* ray_indices, float* t_starts, float* t_ends, int32_t* status, void* stream) {
     clear_error();
     int st = validate(rays_o, rays_d, n_rays, grid_bits, grid, params);
     if (st != NACC_OK) return st;
@@ -654,18 +752,25 @@ int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* gri
     if (nb == 0) return NACC_OK;
     const bool cone = params->cone > 0.0f;
     const uint32_t* mip = usable_mip(grid_mip, *grid, *params);
+    const Layout lay = workspace_layout(n_rays, *grid, *params);
+    NACC_REQUIRE(workspace == nullptr || static_cast<int64_t>(workspace_bytes) >= lay.bytes, NACC_ESHAPE,
+                 "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(lay.bytes));
+    const uint64_t* masks =
+        workspace != nullptr && lay.n_masks > 0
+            ? reinterpret_cast<const uint64_t*>(static_cast<const char*>(workspace) + lay.sums_bytes)
+            : nullptr;
     switch (grid->lookup) {
         case NACC_LOOKUP_AABB:
             launch_fill<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                          packed_info, capacity, ray_indices, t_starts, t_ends, status);
+                                          packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
             break;
         case NACC_LOOKUP_CASCADE:
             launch_fill<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                             packed_info, capacity, ray_indices, t_starts, t_ends, status);
+                                             packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
             break;
         default:
             launch_fill<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                              packed_info, capacity, ray_indices, t_starts, t_ends, status);
+                                              packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
             break;
     }
     return check_launch("march fill");

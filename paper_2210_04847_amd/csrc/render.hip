@@ -10,10 +10,13 @@
 // cut on the same sample.
 //
 // Backward: g_sigma_i = delta_i (T_{i+1} v_i - S_i), S_i = sum_{k>i} w_k v_k.
-// S_i is a true suffix sum, accumulated in FP64 from the end of the ray
-// (chunks in reverse, lanes in reverse sample order), so it stays accurate
-// relative to its own terms however small T gets; a total-minus-prefix form
-// would lose every digit once T falls below the rounding of the total.
+// S_i is a true suffix sum, accumulated from the end of the ray (chunks in
+// reverse, a DPP suffix scan inside each chunk), so it stays accurate
+// relative to its own terms however small T gets; a
+// total-minus-prefix form would lose every digit once T falls below the
+// rounding of the total.  The first chunks of each ray stay in registers
+// between the forward and the backward pass (no second read, no second
+// transmittance evaluation for them).
 #include <cmath>
 
 #include "common.h"
@@ -26,6 +29,7 @@ using namespace nacc;
 using namespace nacc::dev;
 
 constexpr int kRenderThreads = 256;  // 4 waves
+constexpr int kCachedChunks = 2;     // chunks of 64 samples kept in registers per ray
 constexpr int kRaysPerRenderBlock = kRenderThreads / kWave;
 
 struct Sample {
@@ -147,95 +151,135 @@ struct RayGrad {
     float gr, gg, gb, ga, gd;
 };
 
-// v_i in FP64; the products w_i v_i are summed in FP64 for the suffix sums.
-__device__ __forceinline__ double vdot(const RayGrad& q, const Sample& x) {
-    const double m = static_cast<double>((x.t0 + x.t1) * 0.5f);
-    return static_cast<double>(q.gr) * x.r + static_cast<double>(q.gg) * x.g + static_cast<double>(q.gb) * x.b +
-           static_cast<double>(q.ga) + static_cast<double>(q.gd) * m;
+__device__ __forceinline__ float vdot(const RayGrad& q, const Sample& x) {
+    return ((q.gr * x.r + q.gg * x.g) + q.gb * x.b) + (q.ga + q.gd * ((x.t0 + x.t1) * 0.5f));
 }
 
-// Pass A of the backward: the cut (number of samples kept) and the FP64
-// prefix of tau at the start of the chunk holding the last kept sample.  T is
-// formed exactly as in the forward kernel, so the cut is the same sample.
-__device__ __forceinline__ void backward_pass_a(int64_t start, int n, const float* __restrict__ ts,
-                                                const float* __restrict__ te, const float* __restrict__ sig,
-                                                const float* __restrict__ rgb, float eps, int& kept,
-                                                double& prefix_hi) {
+// Gradients of one chunk (lane i = sample c + i) given w_i and T_{i+1};
+// `above` is sum_k w_k v_k over the samples after the chunk.  Returns the
+// same sum over the samples from the chunk on.  S_i = above + (suffix of
+// w v inside the chunk past i): every partial sum is formed from the end of
+// the ray, so it is accurate relative to the terms it adds however small T
+// gets.  Lanes at or past the cut get zeros.
+__device__ __forceinline__ float chunk_grads(const RayGrad& q, const Sample& x, float w, float t_next, bool keep,
+                                             bool valid, int64_t s, float above, float* __restrict__ g_sigmas,
+                                             float* __restrict__ g_rgbs) {
+    const float v = vdot(q, x);
+    const float wv = keep ? w * v : 0.0f;
+    const float incl = wave_inclusive_suffix(wv);
+    const float suffix = above + shift_down_one(incl);
+    if (keep) {
+        g_sigmas[s] = (x.t1 - x.t0) * (t_next * v - suffix);
+        g_rgbs[3 * s] = w * q.gr;
+        g_rgbs[3 * s + 1] = w * q.gg;
+        g_rgbs[3 * s + 2] = w * q.gb;
+    } else if (valid) {
+        g_sigmas[s] = 0.0f;
+        g_rgbs[3 * s] = 0.0f;
+        g_rgbs[3 * s + 1] = 0.0f;
+        g_rgbs[3 * s + 2] = 0.0f;
+    }
+    return above + read_lane(incl, 0);
+}
+
+// Forward pass of one ray shared by the backward and the fused kernels.
+// The first K chunks are loaded up front and kept in registers together
+// with w_i and T_{i+1}; later chunks are streamed.  Produces the cut, the
+// FP64 tau prefix at the start of the chunk holding the last kept sample,
+// and (ACCUM) the rendered colour / opacity / depth.
+template <int K>
+struct RayCache {
+    Sample x[K];
+    float w[K];
+    float t_next[K];
+};
+
+template <int K, bool ACCUM>
+__device__ __forceinline__ void ray_forward(int64_t start, int n, const float* __restrict__ ts,
+                                            const float* __restrict__ te, const float* __restrict__ sig,
+                                            const float* __restrict__ rgb, float eps, RayCache<K>& cache, int& kept,
+                                            double& prefix_hi, float acc[3], float& acc_a, float& acc_d) {
     const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int i = c * kWave + lane;
+        cache.x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
+    }
     double carry = 0.0, carry_prev = 0.0;
     kept = n;
     prefix_hi = 0.0;
-    for (int c = 0; c < n; c += kWave) {
+    bool stopped = false;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        cache.w[c] = 0.0f;
+        cache.t_next[c] = 0.0f;
+        if (stopped || c * kWave >= n) continue;
+        const int i = c * kWave + lane;
+        const bool valid = i < n;
+        const Trans t = chunk_transmittance(cache.x[c], carry);
+        const int keep_n = chunk_keep(valid, t.t_in, eps);
+        const bool keep = valid && lane < keep_n;
+        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        cache.w[c] = w;
+        cache.t_next[c] = expf(-static_cast<float>(carry + static_cast<double>(t.incl)));
+        if (ACCUM) {
+            acc[0] += w * cache.x[c].r;
+            acc[1] += w * cache.x[c].g;
+            acc[2] += w * cache.x[c].b;
+            acc_a += w;
+            acc_d += w * ((cache.x[c].t0 + cache.x[c].t1) * 0.5f);
+        }
+        if (keep_n < kWave) {
+            kept = c * kWave + keep_n;
+            prefix_hi = keep_n > 0 ? carry : carry_prev;
+            stopped = true;
+        } else {
+            carry_prev = carry;
+            carry += static_cast<double>(read_lane(t.incl, 63));
+            prefix_hi = carry_prev;
+        }
+    }
+    for (int c = K * kWave; !stopped && c < n; c += kWave) {
         const int i = c + lane;
         const bool valid = i < n;
         const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
+        if (ACCUM) {
+            const bool keep = valid && lane < keep_n;
+            const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+            acc[0] += w * x.r;
+            acc[1] += w * x.g;
+            acc[2] += w * x.b;
+            acc_a += w;
+            acc_d += w * ((x.t0 + x.t1) * 0.5f);
+        }
         if (keep_n < kWave) {
             kept = c + keep_n;
             prefix_hi = keep_n > 0 ? carry : carry_prev;
-            return;
+            stopped = true;
+        } else {
+            carry_prev = carry;
+            carry += static_cast<double>(read_lane(t.incl, 63));
+            prefix_hi = carry_prev;
         }
-        carry_prev = carry;
-        carry += static_cast<double>(read_lane(t.incl, 63));
-        prefix_hi = carry_prev;
     }
 }
 
-// Pass B: the kept samples chunk by chunk from the last to the first, lanes
-// in reverse sample order (lane L holds sample c + 63 - L), so that a
-// forward DPP scan over the lanes is a suffix scan over the samples.
-//   suffix of tau inside the chunk -> T_i, T_{i+1} from the chunk's FP64 end
-//   prefix; suffix of w v (FP64) -> S_i = sum_{k>i} w_k v_k accumulated from
-//   the end of the ray, accurate relative to the terms it sums even where T
-//   is far below 1e-4.
-// Samples from the cut on get zero gradients.
-__device__ __forceinline__ void backward_pass_b(int64_t start, int n, int kept, double prefix_hi,
-                                                const float* __restrict__ ts, const float* __restrict__ te,
-                                                const float* __restrict__ sig, const float* __restrict__ rgb,
-                                                const RayGrad& q, float* __restrict__ g_sigmas,
-                                                float* __restrict__ g_rgbs) {
+// Backward pass of one ray: chunks from the last kept one down to the first.
+// Streamed chunks rebuild T from the FP64 prefix at their end (walked down
+// from prefix_hi); cached chunks reuse w and T_{i+1} from the forward pass.
+template <int K>
+__device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, double prefix_hi,
+                                             const float* __restrict__ ts, const float* __restrict__ te,
+                                             const float* __restrict__ sig, const float* __restrict__ rgb,
+                                             const RayCache<K>& cache, const RayGrad& q, float* __restrict__ g_sigmas,
+                                             float* __restrict__ g_rgbs) {
     const int lane = lane_id();
-    if (kept > 0) {
-        const int c_hi = ((kept - 1) / kWave) * kWave;
-        double end_next = 0.0;   // tau prefix at the end of the next lower chunk
-        double suffix_wv = 0.0;  // sum of w v over the chunks above
-        for (int c = c_hi; c >= 0; c -= kWave) {
-            const int i = c + (kWave - 1) - lane;
-            const bool keep = i < kept;
-            const int64_t s = start + i;
-            const Sample x = load_sample(keep, s, ts, te, sig, rgb);
-            const float tau = x.sigma * (x.t1 - x.t0);
-            const float incl = wave_inclusive_sum(tau);  // sum over samples >= i in the chunk
-            const float excl = shift_up_one(incl);       // sum over samples >  i in the chunk
-            const float chunk_tau = read_lane(incl, 63);
-            const double p_end = c == c_hi ? prefix_hi + static_cast<double>(chunk_tau) : end_next;
-            const float t_in = expf(-static_cast<float>(p_end - static_cast<double>(incl)));
-            const float t_next = expf(-static_cast<float>(p_end - static_cast<double>(excl)));
-            const float w = keep ? t_in * -expm1f(-tau) : 0.0f;
-            const double v = vdot(q, x);
-            const double wv = static_cast<double>(w) * v;
-            const double incl_wv = wave_inclusive_sum(wv);
-            const double suffix = suffix_wv + shift_up_one(incl_wv);
-            if (keep) {
-                const double dtau = static_cast<double>(t_next) * v - suffix;
-                g_sigmas[s] = static_cast<float>(static_cast<double>(x.t1 - x.t0) * dtau);
-                g_rgbs[3 * s] = w * q.gr;
-                g_rgbs[3 * s + 1] = w * q.gg;
-                g_rgbs[3 * s + 2] = w * q.gb;
-            } else if (i < n) {
-                g_sigmas[s] = 0.0f;
-                g_rgbs[3 * s] = 0.0f;
-                g_rgbs[3 * s + 1] = 0.0f;
-                g_rgbs[3 * s + 2] = 0.0f;
-            }
-            suffix_wv += read_lane(incl_wv, 63);
-            end_next = p_end - static_cast<double>(chunk_tau);
-        }
-    }
-    // chunks entirely past the cut: zeros, no loads
-    const int first_zero = kept > 0 ? ((kept - 1) / kWave + 1) * kWave : 0;
-    for (int c = first_zero; c < n; c += kWave) {
+    const int cached_end = K * kWave;
+    const int c_hi = kept > 0 ? ((kept - 1) / kWave) * kWave : -kWave;
+    // streamed chunks past the cut: zeros, no loads
+    for (int c = max(c_hi + kWave, cached_end); c < n; c += kWave) {
         const int i = c + lane;
         if (i < n) {
             const int64_t s = start + i;
@@ -245,8 +289,33 @@ __device__ __forceinline__ void backward_pass_b(int64_t start, int n, int kept, 
             g_rgbs[3 * s + 2] = 0.0f;
         }
     }
+    float above = 0.0f;
+    double p_end = 0.0;  // tau prefix at the end of the chunk being processed
+    for (int c = c_hi; c >= cached_end; c -= kWave) {
+        const int i = c + lane;
+        const bool keep = i < kept;
+        const int64_t s = start + i;
+        const Sample x = load_sample(keep, s, ts, te, sig, rgb);
+        const float tau = x.sigma * (x.t1 - x.t0);
+        const float incl = wave_inclusive_sum(tau);
+        const float chunk_tau = read_lane(incl, 63);
+        const double p_start = c == c_hi ? prefix_hi : p_end - static_cast<double>(chunk_tau);
+        const float t_in = expf(-static_cast<float>(p_start + static_cast<double>(shift_up_one(incl))));
+        const float t_next = expf(-static_cast<float>(p_start + static_cast<double>(incl)));
+        const float w = keep ? t_in * -expm1f(-tau) : 0.0f;
+        above = chunk_grads(q, x, w, t_next, keep, i < n, s, above, g_sigmas, g_rgbs);
+        p_end = p_start;
+    }
+#pragma unroll
+    for (int c = K - 1; c >= 0; --c) {
+        if (c * kWave >= n) continue;
+        const int i = c * kWave + lane;
+        above = chunk_grads(q, cache.x[c], cache.w[c], cache.t_next[c], i < kept, i < n, start + i, above, g_sigmas,
+                            g_rgbs);
+    }
 }
 
+template <int K>
 __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
@@ -265,15 +334,20 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
     q.gb = uniform<float>(g_color[3 * r + 2]);
     q.ga = g_opacity != nullptr ? uniform<float>(g_opacity[r]) : 0.0f;
     q.gd = g_depth != nullptr ? uniform<float>(g_depth[r]) : 0.0f;
+    RayCache<K> cache;
     int kept;
     double prefix_hi;
-    backward_pass_a(start, n, ts, te, sig, rgb, eps, kept, prefix_hi);
-    backward_pass_b(start, n, kept, prefix_hi, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    float acc_a = 0.0f, acc_d = 0.0f;
+    ray_forward<K, false>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d);
+    ray_backward<K>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
 }
 
-// Fused forward + MSE + backward.  Pass A is the forward with the colour
-// accumulated in FP64, which also gives sum_k w_k v_k = g_C . C exactly
-// enough for the suffix sums of pass B (v_k = g_C . rgb_k here).
+// Fused forward + MSE + backward.  The forward gives the colour, the loss
+// gradient g_C = 2 (C - target) / (3 n_rays) follows, then the backward runs
+// on the cached chunks.  Rays are walked grid-stride so the
+// loss needs one partial sum per workgroup.
+template <int K>
 __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
@@ -289,39 +363,17 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
         int64_t start;
         int n;
         ray_range(packed_info, r, n_samples, start, n);
-        double carry = 0.0, carry_prev = 0.0, prefix_hi = 0.0;
-        double acc_r = 0.0, acc_g = 0.0, acc_b = 0.0;
+        RayCache<K> cache;
+        int kept;
+        double prefix_hi;
+        float acc[3] = {0.0f, 0.0f, 0.0f};
         float acc_a = 0.0f, acc_d = 0.0f;
-        int kept = n;
-        for (int c = 0; c < n; c += kWave) {
-            const int i = c + lane;
-            const bool valid = i < n;
-            const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
-            const Trans t = chunk_transmittance(x, carry);
-            const int keep_n = chunk_keep(valid, t.t_in, eps);
-            const bool keep = valid && lane < keep_n;
-            const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
-            acc_r += static_cast<double>(w) * x.r;
-            acc_g += static_cast<double>(w) * x.g;
-            acc_b += static_cast<double>(w) * x.b;
-            acc_a += w;
-            acc_d += w * ((x.t0 + x.t1) * 0.5f);
-            if (keep_n < kWave) {
-                kept = c + keep_n;
-                prefix_hi = keep_n > 0 ? carry : carry_prev;
-                break;
-            }
-            carry_prev = carry;
-            carry += static_cast<double>(read_lane(t.incl, 63));
-            prefix_hi = carry_prev;
-        }
-        acc_r = wave_sum(acc_r);
-        acc_g = wave_sum(acc_g);
-        acc_b = wave_sum(acc_b);
+        ray_forward<K, true>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d);
+        const float cr = wave_sum(acc[0]);
+        const float cg = wave_sum(acc[1]);
+        const float cb = wave_sum(acc[2]);
         acc_a = wave_sum(acc_a);
         acc_d = wave_sum(acc_d);
-        const float cr = static_cast<float>(acc_r), cg = static_cast<float>(acc_g),
-                    cb = static_cast<float>(acc_b);
         const float er = cr - target[3 * r], eg = cg - target[3 * r + 1], eb = cb - target[3 * r + 2];
         RayGrad q;
         q.gr = uniform<float>(er * inv_count2);
@@ -337,7 +389,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
             opacity[r] = acc_a;
             depth[r] = acc_d;
         }
-        if (n > 0) backward_pass_b(start, n, kept, prefix_hi, ts, te, sig, rgb, q, g_sigmas, g_rgbs);
+        if (n > 0) ray_backward<K>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
     }
     if (lane == 0) wave_loss[wave] = wave_total;
     __syncthreads();
@@ -425,7 +477,7 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
                  "g_color, g_sigmas and g_rgbs must be non-NULL");
     if (n_rays == 0) return NACC_OK;
     hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(render_bwd_kernel, dim3(static_cast<unsigned>(render_blocks(n_rays))),
+    hipLaunchKernelGGL(render_bwd_kernel<kCachedChunks>, dim3(static_cast<unsigned>(render_blocks(n_rays))),
                        dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs,
                        early_stop_eps, g_color, g_opacity, g_depth, g_sigmas, g_rgbs);
     return check_launch("render bwd");
@@ -455,7 +507,7 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
     const double count = 3.0 * static_cast<double>(n_rays);
     const float inv_count2 = static_cast<float>(2.0 / count);
     double* partial = static_cast<double*>(workspace);
-    hipLaunchKernelGGL(render_mse_kernel, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s,
+    hipLaunchKernelGGL(render_mse_kernel<kCachedChunks>, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s,
                        packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
                        inv_count2,
                        color, opacity, depth, g_sigmas, g_rgbs, partial);

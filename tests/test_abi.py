@@ -99,8 +99,10 @@ def test_small_workspace_and_bad_sizes_rejected():
     assert lib.nacc_render_fwd_bwd_mse(fake, 0, 0, None, None, None, None, 0.0, fake, fake, fake,
                                        fake, fake, fake, fake, fake, 1 << 20,
                                        None) == _lib.NACC_EINVAL
-    assert lib.nacc_march_workspace_size(-5) == -1
-    assert lib.nacc_march_workspace_size(64) >= 8
+    assert lib.nacc_march_workspace_size(-5, ctypes.byref(desc), ctypes.byref(params)) == -1
+    assert lib.nacc_march_workspace_size(64, ctypes.byref(desc), ctypes.byref(params)) >= 8
+    bad = _lib.march_params(0.0, 10.0, -1.0)
+    assert lib.nacc_march_workspace_size(64, ctypes.byref(desc), ctypes.byref(bad)) == -1
 
 
 def test_zero_rays_launch_nothing_but_need_total():

@@ -19,7 +19,7 @@ def _nacc():
 
 
 def gpu_march(o, d, mask, res, box, near, far, dt, dt_max=1e10, cone=0.0, lookup=0, n_grids=1,
-              grid_id=None, max_per_ray=0, skip_empty=True):
+              grid_id=None, max_per_ray=0, skip_empty=True, replay_masks=True):
     """Packs the 0/1 mask with the library's pack kernel, marches, returns
     numpy arrays (packed, ray_indices, t_starts, t_ends)."""
     nacc = _nacc()
@@ -29,18 +29,19 @@ def gpu_march(o, d, mask, res, box, near, far, dt, dt_max=1e10, cone=0.0, lookup
     gid = None if grid_id is None else torch.from_numpy(grid_id.astype(np.int32)).cuda()
     p, ri, ts, te = nacc.ray_marching(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(),
                                       grid, near, far, dt, cone, dt_max, max_per_ray, gid,
-                                      skip_empty)
+                                      skip_empty, replay_masks)
     torch.cuda.synchronize()
     return p.cpu().numpy(), ri.cpu().numpy(), ts.cpu().numpy(), te.cpu().numpy()
 
 
 def compare(o, d, mask, res, box, near, far, dt, **kw):
-    """Both traversals (with and without the skip grid) against the oracle."""
+    """Every traversal variant (skip grid on/off, fill replaying the count
+    pass's masks or traversing again) against the oracle."""
     want = oracle.march(o, d, mask, res, box, near, far, dt, **kw)
-    for skip in (False, True):
-        got = gpu_march(o, d, mask, res, box, near, far, dt, skip_empty=skip, **kw)
+    for skip, replay in ((False, True), (True, True), (False, False)):
+        got = gpu_march(o, d, mask, res, box, near, far, dt, skip_empty=skip, replay_masks=replay, **kw)
         for g, w, name in zip(got, want, ("packed_info", "ray_indices", "t_starts", "t_ends")):
-            assert_bit_exact(g, w, f"{name} (skip grid {skip})")
+            assert_bit_exact(g, w, f"{name} (skip grid {skip}, replay {replay})")
     return want
 
 
@@ -182,7 +183,7 @@ def test_capacity_overflow_reported():
     params = lib.march_params(0.0, 1e10, 0.01)
     packed = torch.empty((64, 2), dtype=torch.int32, device="cuda")
     total = torch.empty(1, dtype=torch.int64, device="cuda")
-    ws = torch.empty(lib.march_workspace_size(64), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.march_workspace_size(64, grid.desc, params), dtype=torch.uint8, device="cuda")
     lib.march_count(ro, rd, None, grid.bits, grid.desc, params, packed, total, ws)
     e = int(total.item())
     cap = e // 2
@@ -190,7 +191,7 @@ def test_capacity_overflow_reported():
     ts = torch.zeros(cap, dtype=torch.float32, device="cuda")
     te = torch.zeros(cap, dtype=torch.float32, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    lib.march_fill(ro, rd, None, grid.bits, grid.desc, params, packed, ri, ts, te, status)
+    lib.march_fill(ro, rd, None, grid.bits, grid.desc, params, packed, ri, ts, te, status, None, ws)
     assert int(status.item()) == lib.NACC_ECAPACITY
     # the samples that fit are written and correct
     _, ri_o, ts_o, _ = oracle.march(o, d, mask.astype(np.uint8), 8, BOX, 0.0, 1e10, 0.01)

@@ -205,6 +205,7 @@ __device__ __forceinline__ int march_ray_uniform(
     uint64_t live_groups = ~0ull;  // groups [window * 64, window * 64 + 64) as bits
     uint64_t live_chunks = ~0ull;  // chunks of the window as bits
     int window_chunk = -(1 << 30);  // first chunk of the current window
+    uint64_t my_mask = 0ull;        // count pass: lane j keeps the ballot of chunk j
     int count = count0;
     for (int k0 = first_chunk * kWave; k0 < kMaxCandidates; k0 += kWave) {
         const int chunk = k0 / kWave;
@@ -235,7 +236,6 @@ __device__ __forceinline__ int march_ray_uniform(
             if (((live_chunks >> rel) & 1ull) == 0ull) {
                 // every candidate of this chunk lies in empty cells
                 if (!(t_near + static_cast<float>(k0) * p.dt < t_far)) break;
-                if (!FILL && chunk < n_masks && lane == 0) masks[chunk] = 0ull;
                 continue;
             }
             lane_live = ((live_groups >> ((rel * kWave + lane) / G)) & 1ull) != 0ull;
@@ -251,7 +251,7 @@ __device__ __forceinline__ int march_ray_uniform(
             hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
         }
         const uint64_t m = ballot(hit);
-        if (!FILL && chunk < n_masks && lane == 0) masks[chunk] = m;
+        if (!FILL && lane == chunk) my_mask = m;
         if (FILL && hit) {
             const int idx = count + bits_below(m);
             if (idx < limit) {
@@ -272,6 +272,7 @@ __device__ __forceinline__ int march_ray_uniform(
         }
         if (FILL && count >= limit) break;
     }
+    if (!FILL && lane < n_masks) masks[lane] = my_mask;
     return count;
 }
 
@@ -324,10 +325,13 @@ __device__ __forceinline__ void fill_ray_from_masks(
     }
     float t_near, t_far;
     clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far);
+    const uint64_t mine = lane < n_masks ? masks[lane] : 0ull;  // one load: lane j holds chunk j
     int written = 0;
-    int j = 0;
-    for (; j < n_masks && written < limit; ++j) {
-        const uint64_t m = masks[j];
+    for (int j = 0; j < n_masks && written < limit; ++j) {
+        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(
+                                __builtin_amdgcn_readlane(static_cast<int>(mine >> 32), j)))
+                            << 32) |
+                           static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mine), j));
         if (m == 0ull) continue;
         if ((m >> lane) & 1ull) {
             const int idx = written + bits_below(m);

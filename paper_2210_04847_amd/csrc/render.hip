@@ -44,19 +44,49 @@ __device__ __forceinline__ Sample load_sample(bool valid, int64_t s, const float
         x.t0 = ts[s];
         x.t1 = te[s];
         x.sigma = sig[s];
-        x.r = rgb[3 * s];
-        x.g = rgb[3 * s + 1];
-        x.b = rgb[3 * s + 2];
+        const float3 c = reinterpret_cast<const float3*>(rgb)[s];
+        x.r = c.x;
+        x.g = c.y;
+        x.b = c.z;
     }
     return x;
 }
 
-// T at the start of each lane's sample, given the FP64 prefix of tau before
-// the chunk, and the inclusive chunk prefix of tau.
+__device__ __forceinline__ void store_rgb(float* __restrict__ out, int64_t s, float r, float g, float b) {
+    reinterpret_cast<float3*>(out)[s] = make_float3(r, g, b);
+}
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// e^-x for x >= 0 on the hardware exp2 (relative error a few ulp).
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-x * kLog2e); }
+
+// alpha = 1 - e^-tau without cancellation: for tau <= 1/4 the alternating
+// series tau (1 - tau/2 (1 - tau/3 (... (1 - tau/6)))) (truncation below
+// tau^6 / 5040 < 5e-8 relative), above it 1 - e^-tau directly (e^-tau <=
+// 0.78, so the subtraction loses at most a few ulp).
+__device__ __forceinline__ float alpha_of(float tau) {
+    if (tau <= 0.25f) {
+        float p = 1.0f - tau * (1.0f / 6.0f);
+        p = 1.0f - tau * (1.0f / 5.0f) * p;
+        p = 1.0f - tau * 0.25f * p;
+        p = 1.0f - tau * (1.0f / 3.0f) * p;
+        p = 1.0f - tau * 0.5f * p;
+        return tau * p;
+    }
+    return 1.0f - exp_neg(tau);
+}
+
+// Transmittance of each lane's sample in a chunk, given the FP64 prefix of
+// tau before the chunk: T_i = e^-carry * e^-(exclusive chunk prefix).  The
+// chunk factor comes from the FP64 carry rounded once to FP32, the lane
+// factor from a short FP32 prefix inside the chunk; relative error about
+// (carry + chunk prefix) * log2(e) * 2^-24 plus a few ulp.
 struct Trans {
-    float tau;    // sigma * delta
-    float incl;   // inclusive prefix of tau inside the chunk
-    float t_in;   // T_i  = exp(-(carry + exclusive prefix))
+    float tau;     // sigma * delta
+    float incl;    // inclusive prefix of tau inside the chunk
+    float t_in;    // T_i
+    float t_next;  // T_{i+1}
 };
 
 __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double carry) {
@@ -64,7 +94,9 @@ __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double car
     t.tau = x.sigma * (x.t1 - x.t0);
     t.incl = wave_inclusive_sum(t.tau);
     const float excl = shift_up_one(t.incl);
-    t.t_in = expf(-static_cast<float>(carry + static_cast<double>(excl)));
+    const float t0 = uniform<float>(exp_neg(static_cast<float>(carry)));
+    t.t_in = t0 * exp_neg(excl);
+    t.t_next = t0 * exp_neg(t.incl);
     return t;
 }
 
@@ -112,7 +144,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
-        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         acc_r += w * x.r;
         acc_g += w * x.g;
         acc_b += w * x.b;
@@ -170,14 +202,10 @@ __device__ __forceinline__ float chunk_grads(const RayGrad& q, const Sample& x, 
     const float suffix = above + shift_down_one(incl);
     if (keep) {
         g_sigmas[s] = (x.t1 - x.t0) * (t_next * v - suffix);
-        g_rgbs[3 * s] = w * q.gr;
-        g_rgbs[3 * s + 1] = w * q.gg;
-        g_rgbs[3 * s + 2] = w * q.gb;
+        store_rgb(g_rgbs, s, w * q.gr, w * q.gg, w * q.gb);
     } else if (valid) {
         g_sigmas[s] = 0.0f;
-        g_rgbs[3 * s] = 0.0f;
-        g_rgbs[3 * s + 1] = 0.0f;
-        g_rgbs[3 * s + 2] = 0.0f;
+        store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
     }
     return above + read_lane(incl, 0);
 }
@@ -219,9 +247,9 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         const Trans t = chunk_transmittance(cache.x[c], carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
-        const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+        const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         cache.w[c] = w;
-        cache.t_next[c] = expf(-static_cast<float>(carry + static_cast<double>(t.incl)));
+        cache.t_next[c] = t.t_next;
         if (ACCUM) {
             acc[0] += w * cache.x[c].r;
             acc[1] += w * cache.x[c].g;
@@ -247,7 +275,7 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         if (ACCUM) {
             const bool keep = valid && lane < keep_n;
-            const float w = keep ? t.t_in * -expm1f(-t.tau) : 0.0f;
+            const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
             acc[0] += w * x.r;
             acc[1] += w * x.g;
             acc[2] += w * x.b;
@@ -284,9 +312,7 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
         if (i < n) {
             const int64_t s = start + i;
             g_sigmas[s] = 0.0f;
-            g_rgbs[3 * s] = 0.0f;
-            g_rgbs[3 * s + 1] = 0.0f;
-            g_rgbs[3 * s + 2] = 0.0f;
+            store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
         }
     }
     float above = 0.0f;
@@ -297,12 +323,11 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
         const int64_t s = start + i;
         const Sample x = load_sample(keep, s, ts, te, sig, rgb);
         const float tau = x.sigma * (x.t1 - x.t0);
-        const float incl = wave_inclusive_sum(tau);
-        const float chunk_tau = read_lane(incl, 63);
+        const float chunk_tau = wave_sum(tau);
         const double p_start = c == c_hi ? prefix_hi : p_end - static_cast<double>(chunk_tau);
-        const float t_in = expf(-static_cast<float>(p_start + static_cast<double>(shift_up_one(incl))));
-        const float t_next = expf(-static_cast<float>(p_start + static_cast<double>(incl)));
-        const float w = keep ? t_in * -expm1f(-tau) : 0.0f;
+        const Trans t = chunk_transmittance(x, p_start);
+        const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
+        const float t_next = t.t_next;
         above = chunk_grads(q, x, w, t_next, keep, i < n, s, above, g_sigmas, g_rgbs);
         p_end = p_start;
     }

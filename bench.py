@@ -1,14 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark of the marching + rendering training step on one MI355X.
+"""Benchmark of occupancy-grid ray marching + packed differentiable rendering
+on one MI355X.
 
-One step = march (count, scan, fill) -> synthetic field at the samples ->
-fused render forward + MSE + backward, plus the occupancy-grid update
-(decay, 2^18 random cells, field, max, pack) every 16 steps.  Inputs are
-synthetic, seeded and resident in HBM before the timed region; outputs are
-written into capacity-sized buffers, so no step waits on the host.
+Default workload (train_262k): one training step = march (count, scan, fill)
+-> synthetic field at the samples -> fused render forward + MSE + backward,
+plus the occupancy-grid update (decay, 2^18 random cells, field, max, pack)
+every 16 steps.  262,144 rays, 128^3 grid of 32 blobs.  Inputs are seeded,
+synthetic and resident in HBM before the timed region; outputs go to
+capacity-sized buffers, so no step waits on the host.  The step is captured
+in HIP graphs (one for a plain step, one for a step with the grid update)
+after the launch parameters are autotuned; per-phase times come from an
+eager pass with HIP events on the launch stream.
 
-Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
-the path runs on one GPU.
+--workload dynamic_64: 64 frames with their own grids (~262k rays, Poisson
+counts per frame); 64 per-frame plain calls (each sized by a host read of the
+sample total, like the paper's API) against one batched graph-captured step
+over all frames; their outputs are checked bit for bit.
+
+--workload plain_fwd_4k: 4,096 rays, 8 blobs, forward only, no early
+termination.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU).
 """
 from __future__ import annotations
 
@@ -37,32 +49,41 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--workload", default="train_262k", choices=["train_262k", "plain_fwd_4k"])
+    ap.add_argument("--workload", default="train_262k",
+                    choices=["train_262k", "plain_fwd_4k", "dynamic_64"])
+    ap.add_argument("--form", choices=["graph", "eager"], default="graph",
+                    help="time the step captured in HIP graphs, or launched eagerly")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rays", type=int, default=131072)
     ap.add_argument("--skip-grid", choices=["on", "off"], default="off",
                     help="march with the dilated coarse skip grid")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
-    ap.add_argument("--cpu-sample-rays", type=int, default=131072)
     return ap.parse_args()
 
 
-class TrainStep:
-    """Buffers and launches of one training step (everything on torch's
-    current stream)."""
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
-    def __init__(self, w, inp, torch, nacc, skip_grid=False):
+
+class Step:
+    """Buffers and launches of one step over the rays with grid(s) `grid`
+    (everything on torch's current stream).  grid_id (optional, per ray)
+    picks the grid and the field's centre set."""
+
+    def __init__(self, torch, nacc, w, rays_o, rays_d, targets, grid, field, grid_id=None,
+                 skip_grid=False, forward_only=False, loss_rays=0, seed=0):
         self.torch, self.nacc, self.lib = torch, nacc, nacc._lib
-        dev = torch.device("cuda")
-        t = lambda a: torch.from_numpy(a).to(dev)
+        dev = rays_o.device
         self.w = w
-        self.n = w.n_rays
-        self.rays_o, self.rays_d = t(inp["rays_o"]), t(inp["rays_d"])
-        self.target = t(inp["targets"])
-        self.grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
-        self.grid.set_occupancy(t(inp["occ"]), THRESHOLD)
-        self.field = nacc.BlobField(inp["scene"], device=dev)
+        self.n = rays_o.shape[0]
+        self.rays_o, self.rays_d, self.target = rays_o, rays_d, targets
+        self.grid, self.field = grid, field
+        self.grid_id = grid_id
+        self.forward_only = forward_only
+        self.loss_rays = loss_rays
         diag = math.sqrt(sum((w.box[3 + i] - w.box[i]) ** 2 for i in range(3)))
         self.capacity = self.n * (int(math.ceil(diag / w.dt)) + 2)
         n, cap = self.n, self.capacity
@@ -70,7 +91,7 @@ class TrainStep:
         self.params = self.lib.march_params(w.near, w.far, w.dt)
         self.packed = torch.empty((n, 2), dtype=i32, device=dev)
         self.total = torch.empty(1, dtype=torch.int64, device=dev)
-        self.ws = torch.empty(self.lib.march_workspace_size(n, self.grid.desc, self.params),
+        self.ws = torch.empty(max(self.lib.march_workspace_size(n, grid.desc, self.params), 1),
                               dtype=torch.uint8, device=dev)
         self.ray_indices = torch.empty(cap, dtype=i32, device=dev)
         self.t_starts = torch.empty(cap, dtype=f32, device=dev)
@@ -84,74 +105,92 @@ class TrainStep:
         self.opacity = torch.empty(n, dtype=f32, device=dev)
         self.depth = torch.empty(n, dtype=f32, device=dev)
         self.loss = torch.empty(1, dtype=f32, device=dev)
-        self.mse_ws = torch.empty(self.lib.render_mse_workspace_size(n), dtype=torch.uint8, device=dev)
+        self.mse_ws = torch.empty(max(self.lib.render_mse_workspace_size(n), 1), dtype=torch.uint8,
+                                  device=dev)
         self.ema_cells = torch.empty(EMA_CELLS, dtype=i32, device=dev)
         self.ema_pos = torch.empty((EMA_CELLS, 3), dtype=f32, device=dev)
         self.ema_sigma = torch.empty(EMA_CELLS, dtype=f32, device=dev)
-        self.updates = 0
-        self.seed = 4000 + w.seed_base
-        self.mip = self.grid.mip if skip_grid else None
+        self.updates = torch.zeros(1, dtype=torch.int64, device=dev)  # read by the kernel
+        self.seed = seed
+        self.mip = grid.mip if skip_grid else None
 
-    # phases ------------------------------------------------------------
     def march_count(self):
-        self.lib.march_count(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
+        self.lib.march_count(self.rays_o, self.rays_d, self.grid_id, self.grid.bits, self.grid.desc,
                              self.params, self.packed, self.total, self.ws, self.mip)
 
     def march_fill(self):
-        self.lib.march_fill(self.rays_o, self.rays_d, None, self.grid.bits, self.grid.desc,
+        self.lib.march_fill(self.rays_o, self.rays_d, self.grid_id, self.grid.bits, self.grid.desc,
                             self.params, self.packed, self.ray_indices, self.t_starts, self.t_ends,
                             self.status, self.mip, self.ws)
 
     def field_eval(self):
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
-                                     self.rays_o, self.rays_d, None, self.ray_indices,
+                                     self.rays_o, self.rays_d, self.grid_id, self.ray_indices,
                                      self.t_starts, self.t_ends, self.sigmas, self.rgbs,
                                      self.total)
 
     def render(self):
-        e = self.capacity
-        self.lib.render_fwd_bwd_mse(self.packed, self.t_starts[:e], self.t_ends[:e],
-                                    self.sigmas[:e], self.rgbs[:e], self.w.early_stop_eps,
-                                    self.target, self.color, self.opacity, self.depth,
-                                    self.g_sigmas, self.g_rgbs, self.loss, self.mse_ws)
+        if self.forward_only:
+            self.lib.render_fwd(self.packed, self.t_starts, self.t_ends, self.sigmas, self.rgbs,
+                                self.w.early_stop_eps, self.color, self.opacity, self.depth)
+        else:
+            self.lib.render_fwd_bwd_mse(self.packed, self.t_starts, self.t_ends, self.sigmas,
+                                        self.rgbs, self.w.early_stop_eps, self.target, self.color,
+                                        self.opacity, self.depth, self.g_sigmas, self.g_rgbs,
+                                        self.loss, self.mse_ws, self.loss_rays)
 
     def grid_update(self):
         lib, g = self.lib, self.grid
         lib.grid_decay(g.occ, EMA_DECAY)
-        lib.grid_sample_cells(self.seed, self.updates, EMA_CELLS, g.desc, 1, self.ema_cells,
-                              self.ema_pos)
+        lib.grid_sample_cells(self.seed, self.updates, EMA_CELLS, g.desc, g.n_grids,
+                              self.ema_cells, self.ema_pos)
         lib.synth_field_points(self.field.table, self.field.n_blobs, self.field.n_sets,
-                               self.ema_pos, None, self.ema_sigma)
+                               self.ema_pos, None, self.ema_sigma,
+                               point_cell=self.ema_cells if g.n_grids > 1 else None,
+                               cells_per_set=g.res ** 3)
         lib.grid_update_max(g.occ, self.ema_cells, self.ema_sigma)
         lib.grid_pack(g.occ, THRESHOLD, g.bits)
-        lib.grid_build_mip(g.bits, g.desc, g.mip)
-        self.updates += 1
+        if g.mip is not None:
+            lib.grid_build_mip(g.bits, g.desc, g.mip)
+        self.updates.add_(1)
 
     PHASES = ("march_count", "march_fill", "field", "render", "grid_update")
 
-    def step(self, k, events=None):
-        ev = events
-        if ev is not None:
-            ev[0].record()
-        self.march_count()
-        if ev is not None:
-            ev[1].record()
-        self.march_fill()
-        if ev is not None:
-            ev[2].record()
-        self.field_eval()
-        if ev is not None:
-            ev[3].record()
-        self.render()
-        if ev is not None:
-            ev[4].record()
-        if k % EMA_EVERY == 0:
+    def step(self, update=False, events=None):
+        fns = (self.march_count, self.march_fill, self.field_eval, self.render)
+        for j, fn in enumerate(fns):
+            if events is not None:
+                events[j].record()
+            fn()
+        if events is not None:
+            events[4].record()
+        if update:
             self.grid_update()
-        if ev is not None:
-            ev[5].record()
+        if events is not None:
+            events[5].record()
+
+    def outputs(self):
+        """Tensors a change of launch parameters must leave bit-identical."""
+        return (self.packed, self.ray_indices[:1 << 20], self.t_starts[:1 << 20], self.color,
+                self.g_sigmas[:1 << 20], self.g_rgbs[:1 << 18])
 
 
-def algorithmic_bytes(n_rays, e, v):
+def capture(torch, fn):
+    """fn captured in a HIP graph (warmed up on a side stream first)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def algorithmic_bytes(n_rays, e, v, forward_only=False):
     """Bytes each phase must move (reads of its inputs + writes of its
     outputs, each once), for one step with e samples of which v precede the
     early-termination cut."""
@@ -162,9 +201,10 @@ def algorithmic_bytes(n_rays, e, v):
         "march_fill": 32 * n_rays + 12 * e,
         # ray index + interval in (12 B), sigma + rgb out (16 B), rays once
         "field": 28 * e + 24 * n_rays,
-        # kept samples read once (24 B), gradients of every sample written
-        # (16 B), packed_info + target in, colour/opacity/depth out (40 B/ray)
-        "render": 24 * v + 16 * e + 40 * n_rays,
+        # forward: kept samples read once (24 B) + packed_info in, colour /
+        # opacity / depth out; fused: also gradients of every sample written
+        # (16 B) and the target read (40 B/ray in all)
+        "render": (24 * v + 28 * n_rays) if forward_only else (24 * v + 16 * e + 40 * n_rays),
     }
 
 
@@ -186,9 +226,9 @@ def recorded_traffic(kernel, source):
     return None
 
 
-def cpu_baseline(w, inp, n_sample):
+def cpu_baseline(w, inp, n_sample, forward_only=False):
     """The oracle, as it stands, on the first n_sample rays of the workload:
-    brute-force marching, FP64 field, FP64 forward + MSE + backward."""
+    brute-force marching, FP64 field, FP64 forward (+ MSE + backward)."""
     import numpy as np
 
     import oracle
@@ -201,32 +241,59 @@ def cpu_baseline(w, inp, n_sample):
     pos = oracle.sample_positions(o, d, ri, ts, te)
     sig, rgb = oracle.blob_field(inp["scene"], pos)
     fwd = oracle.render_fwd(packed, ts, te, sig, rgb, w.early_stop_eps)
-    _, g_color = oracle.mse_loss_and_grad(fwd["color"], inp["targets"][:n_sample])
-    oracle.render_bwd(packed, ts, te, sig, rgb, g_color, eps=w.early_stop_eps)
+    if not forward_only:
+        _, g_color = oracle.mse_loss_and_grad(fwd["color"], inp["targets"][:n_sample])
+        oracle.render_bwd(packed, ts, te, sig, rgb, g_color, eps=w.early_stop_eps)
     dt = time.perf_counter() - t0
+    what = "march+field+fwd" if forward_only else "march+field+fwd+bwd"
     return {"value": ri.size / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} of {w.n_rays} rays ({ri.size} samples), "
-                      f"march+field+fwd+bwd, one thread, {dt:.1f} s, host {platform.processor() or platform.machine()}"}
+            "sample": f"first {n_sample} of {inp['rays_o'].shape[0]} rays ({ri.size} samples), "
+                      f"{what}, one thread, {dt:.1f} s, host "
+                      f"{platform.processor() or platform.machine()}"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              "(rays shard across GPUs without communication except the grid update; see the "
-              "design notes)", file=sys.stderr)
-        sys.exit(2)
+def kept_fraction(st, e_last):
+    """Samples before the early-termination cut / all samples, from one
+    forward with per-ray kept counts (outside the timed region)."""
+    torch = st.torch
+    kept = torch.empty(st.n, dtype=torch.int32, device="cuda")
+    st.lib.render_fwd(st.packed, st.t_starts, st.t_ends, st.sigmas, st.rgbs, st.w.early_stop_eps,
+                      st.color, st.opacity, st.depth, None, kept)
+    return int(kept.sum().item()) / max(e_last, 1)
+
+
+def phase_timing(torch, st, steps, first_index, updates=True):
+    """Per-phase HIP-event times of `steps` eager steps (grid update every 16
+    steps, if `updates`)."""
     import numpy as np
-    import torch
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    upd = [updates and (first_index + k) % EMA_EVERY == 0 for k in range(steps)]
+    for k in range(steps):
+        st.step(update=upd[k], events=events[k])
+    torch.cuda.synchronize()
+    out = {p: [] for p in Step.PHASES}
+    for k in range(steps):
+        for j, p in enumerate(Step.PHASES):
+            if p == "grid_update" and not upd[k]:
+                continue
+            out[p].append(events[k][j].elapsed_time(events[k][j + 1]))
+    return {p: (float(np.mean(v)) if v else 0.0) for p, v in out.items()}
 
+
+def bench_train(args, torch, nacc):
     import synth
-    import paper_2210_04847_amd as nacc
-
     w = synth.WORKLOADS[args.workload]
+    forward_only = args.workload == "plain_fwd_4k"
     t_gen = time.perf_counter()
     inp = synth.workload_inputs(w)
-    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    st = TrainStep(w, inp, torch, nacc, skip_grid=args.skip_grid == "on")
+    log(f"inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
+    grid.set_occupancy(t(inp["occ"]), THRESHOLD)
+    field = nacc.BlobField(inp["scene"], device=dev)
+    st = Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid, field,
+              skip_grid=args.skip_grid == "on", forward_only=forward_only, seed=4000 + w.seed_base)
     torch.cuda.synchronize()
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18  # float32 elements
@@ -236,21 +303,38 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    tuned = None
+    if not args.no_autotune:
+        from paper_2210_04847_amd import autotune
+        cands = dict(autotune.CANDIDATES)
+        if forward_only:
+            cands = {"march_waves_per_group": cands["march_waves_per_group"]}
+        tuned, _ = autotune.autotune(lambda: st.step(), st.outputs, cands, log=log)
+        log(f"tuned: {tuned}")
     steps, warmup = args.steps, args.warmup
     for k in range(warmup):
-        st.step(k)
+        st.step(update=k % EMA_EVERY == 0)
     torch.cuda.synchronize()
-    print(f"# warmup done ({warmup} steps)", file=sys.stderr, flush=True)
+    log(f"warmup done ({warmup} steps)")
+
+    graphs = None
+    if args.form == "graph":
+        graphs = (capture(torch, lambda: st.step(update=False)),
+                  capture(torch, lambda: st.step(update=True)))
+        log("captured the step in HIP graphs")
 
     totals = torch.empty(steps, dtype=torch.int64, device="cuda")
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record()
     for k in range(steps):
-        st.step(warmup + k, events[k])
+        upd = (warmup + k) % EMA_EVERY == 0
+        if graphs is not None:
+            graphs[1 if upd else 0].replay()
+        else:
+            st.step(update=upd)
         totals[k:k + 1].copy_(st.total)
     stop.record()
     torch.cuda.synchronize()
@@ -258,39 +342,22 @@ def main():
     ms_total = start.elapsed_time(stop)
     if int(st.status.item()) != 0:
         raise RuntimeError("capacity overflow in the timed region")
-
     e_steps = totals.cpu().numpy()
     e_total = int(e_steps.sum())
-    phase_ms = {p: [] for p in TrainStep.PHASES}
-    for k in range(steps):
-        ev = events[k]
-        for j, p in enumerate(TrainStep.PHASES):
-            if p == "grid_update" and (warmup + k) % EMA_EVERY != 0:
-                continue
-            phase_ms[p].append(ev[j].elapsed_time(ev[j + 1]))
-    phase_avg = {p: (float(np.mean(v)) if v else 0.0) for p, v in phase_ms.items()}
-
-    # samples before the cut (V): one forward with the per-ray kept counts,
-    # outside the timed region, on the final step's samples
-    e_last = int(e_steps[-1])
-    kept = torch.empty(st.n, dtype=torch.int32, device="cuda")
-    nacc._lib.render_fwd(st.packed, st.t_starts[:e_last], st.t_ends[:e_last], st.sigmas[:e_last],
-                         st.rgbs[:e_last], w.early_stop_eps, st.color, st.opacity, st.depth,
-                         None, kept)
-    v_last = int(kept.sum().item())
-    v_frac = v_last / max(e_last, 1)
-
+    phase_avg = phase_timing(torch, st, min(steps, 32), warmup + steps)
     e_mean = e_total / steps
-    v_mean = e_mean * v_frac
-    alg = algorithmic_bytes(st.n, e_mean, v_mean)
-    # the dominant kernel of the path itself (the synthetic field stands in
-    # for the user's radiance field and is reported, not ranked)
+    v_frac = kept_fraction(st, int(e_steps[-1]))
+    alg = algorithmic_bytes(st.n, e_mean, e_mean * v_frac, forward_only)
+    # the dominant kernel of the path itself (the synthetic field stands in for
+    # the user's radiance field and is reported, not ranked)
     per_launch = {p: phase_avg[p] for p in alg if p != "field"}
     dominant = max(per_launch, key=per_launch.get)
     achieved = alg[dominant] / (phase_avg[dominant] * 1e-3)
     step_ms = ms_total / steps
     step_bytes = sum(alg.values())
-
+    traffic = None
+    if dominant == "render" and not forward_only:
+        traffic = recorded_traffic("render_mse_kernel", "paper_2210_04847_amd/csrc/render.hip")
     result = {
         "metric": METRIC,
         "value": e_total / (ms_total * 1e-3),
@@ -306,13 +373,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "rays": w.n_rays, "grid": f"{w.res}^3 bit-packed",
                    "blobs": w.n_blobs, "dt": w.dt, "early_stop_eps": w.early_stop_eps,
+                   "pass": "forward" if forward_only else "forward+mse+backward",
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
-                   "form": "plain", "skip_grid": args.skip_grid, "parallelism": "single GPU"},
+                   "form": args.form, "skip_grid": args.skip_grid, "tuning": tuned,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": (recorded_traffic("render_mse_kernel",
-                                                  "paper_2210_04847_amd/csrc/render.hip")
-                                 if dominant == "render" else None)},
+                     "traffic": traffic},
         "samples_per_step": e_mean,
         "kept_fraction": v_frac,
         "phase_ms": phase_avg,
@@ -324,8 +391,175 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(w, inp, min(args.cpu_sample_rays, w.n_rays))
+        log("timing the oracle on the host")
+        result["cpu_baseline"] = cpu_baseline(w, inp, min(args.cpu_sample_rays, w.n_rays),
+                                              forward_only)
+    return result
+
+
+def bench_dynamic(args, torch, nacc):
+    """Per-frame plain calls vs one batched graph-captured step."""
+    import numpy as np
+
+    import synth
+    w = synth.DYNAMIC_WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    inp = synth.dynamic_inputs(w)
+    log(f"inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    nf, res = w.n_frames, inp["res"]
+    grid = nacc.OccupancyGrid(w.box, res, n_grids=nf, device=dev)
+    grid.set_occupancy(t(inp["occ"]), THRESHOLD)
+    field = nacc.BlobField(inp["scene"], device=dev)
+    rays_o, rays_d = t(inp["rays_o"]), t(inp["rays_d"])
+    tgt, frame = t(inp["targets"]), t(inp["frame"])
+    n_total = rays_o.shape[0]
+    batched = Step(torch, nacc, w, rays_o, rays_d, tgt, grid, field, grid_id=frame,
+                   seed=4000 + w.seed_base)
+    lib = nacc._lib
+    words = res ** 3 // 32
+    starts = np.concatenate([[0], np.cumsum(inp["counts"])]).astype(np.int64)
+    desc1 = lib.grid_desc(w.box[:3], w.box[3:], res)
+    params = lib.march_params(w.near, w.far, w.dt)
+
+    def plain_frames(keep=None):
+        """One plain call sequence per frame: its rays, its grid (a view of the
+        frame's words), outputs sized exactly after a host read of the total,
+        gradients normalised by the whole batch (loss_rays)."""
+        for f in range(nf):
+            a, b = int(starts[f]), int(starts[f + 1])
+            n = b - a
+            if n == 0:
+                continue
+            o, d = rays_o[a:b], rays_d[a:b]
+            bits = grid.bits[f * words:(f + 1) * words]
+            packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
+            total = torch.empty(1, dtype=torch.int64, device=dev)
+            ws = torch.empty(lib.march_workspace_size(n, desc1, params), dtype=torch.uint8,
+                             device=dev)
+            lib.march_count(o, d, None, bits, desc1, params, packed, total, ws)
+            e = int(total.item())
+            ri = torch.empty(e, dtype=torch.int32, device=dev)
+            ts = torch.empty(e, dtype=torch.float32, device=dev)
+            te = torch.empty(e, dtype=torch.float32, device=dev)
+            lib.march_fill(o, d, None, bits, desc1, params, packed, ri, ts, te, None, None, ws)
+            sig = torch.empty(e, dtype=torch.float32, device=dev)
+            rgb = torch.empty((e, 3), dtype=torch.float32, device=dev)
+            lib.synth_field_samples(field.table, field.n_blobs, field.n_sets, o, d, frame[a:b], ri,
+                                    ts, te, sig, rgb)
+            color = torch.empty((n, 3), dtype=torch.float32, device=dev)
+            opac = torch.empty(n, dtype=torch.float32, device=dev)
+            dep = torch.empty(n, dtype=torch.float32, device=dev)
+            gs = torch.empty(e, dtype=torch.float32, device=dev)
+            gr = torch.empty((e, 3), dtype=torch.float32, device=dev)
+            loss = torch.empty(1, dtype=torch.float32, device=dev)
+            mws = torch.empty(lib.render_mse_workspace_size(n), dtype=torch.uint8, device=dev)
+            lib.render_fwd_bwd_mse(packed, ts, te, sig, rgb, w.early_stop_eps, tgt[a:b], color,
+                                   opac, dep, gs, gr, loss, mws, n_total)
+            if keep is not None:
+                keep.append((packed, ri + a, ts, color, gs, gr))
+
+    tuned = None
+    if not args.no_autotune:
+        from paper_2210_04847_amd import autotune
+        tuned, _ = autotune.autotune(lambda: batched.step(), batched.outputs, log=log)
+        log(f"tuned: {tuned}")
+    for _ in range(3):
+        batched.step()
+        plain_frames()
+    torch.cuda.synchronize()
+
+    # the batched step against the plain calls, bit for bit
+    kept = []
+    plain_frames(kept)
+    batched.step()
+    torch.cuda.synchronize()
+    e_b = int(batched.total.item())
+    cat = lambda j: torch.cat([k[j].reshape(-1) for k in kept])
+    bits32 = lambda x: x.contiguous().view(torch.int32)
+    same = {
+        "counts": bool(torch.equal(batched.packed[:, 1], cat(0).reshape(-1, 2)[:, 1])),
+        "ray_indices": bool(torch.equal(batched.ray_indices[:e_b], cat(1))),
+        "t_starts": bool(torch.equal(bits32(batched.t_starts[:e_b]), bits32(cat(2)))),
+        "color": bool(torch.equal(bits32(batched.color.reshape(-1)), bits32(cat(3)))),
+        "g_sigmas": bool(torch.equal(bits32(batched.g_sigmas[:e_b]), bits32(cat(4)))),
+        "g_rgbs": bool(torch.equal(bits32(batched.g_rgbs[:e_b].reshape(-1)), bits32(cat(5)))),
+    }
+    log(f"batched vs plain identical: {same}")
+
+    steps = args.steps
+    reps = max(steps // 8, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain_frames()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / reps
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        batched.step()
+    stop.record()
+    torch.cuda.synchronize()
+    eager_ms = start.elapsed_time(stop) / steps
+    g = capture(torch, lambda: batched.step())
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    graph_ms = start.elapsed_time(stop) / steps
+    phase_avg = phase_timing(torch, batched, min(steps, 16), 1, updates=False)
+    v_frac = kept_fraction(batched, e_b)
+    alg = algorithmic_bytes(n_total, e_b, e_b * v_frac)
+    achieved = alg["render"] / (phase_avg["render"] * 1e-3)
+    return {
+        "metric": METRIC,
+        "value": e_b / (graph_ms * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 3,
+        "ms_per_step": graph_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "frames": nf, "rays": n_total, "grid": f"{nf} x {res}^3",
+                   "blobs": w.n_blobs, "early_stop_eps": w.early_stop_eps,
+                   "pass": "forward+mse+backward", "form": "batched, one HIP graph per step",
+                   "tuning": tuned, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "render", "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": None},
+        "samples_per_step": e_b,
+        "batched_graph_ms": graph_ms,
+        "batched_eager_ms": eager_ms,
+        "plain_per_frame_ms": plain_ms,
+        "batched_over_plain": plain_ms / graph_ms,
+        "identical_outputs": same,
+        "phase_ms": phase_avg,
+        "cpu_baseline": None,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              "(rays shard across GPUs without communication except the grid update; see the "
+              "design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2210_04847_amd as nacc
+    if args.workload.startswith("dynamic"):
+        result = bench_dynamic(args, torch, nacc)
+    else:
+        result = bench_train(args, torch, nacc)
     print(json.dumps(result), flush=True)
 
 

@@ -137,6 +137,32 @@ typedef struct nacc_march_params {
 /* Library version string; never NULL. */
 const char* nacc_version(void);
 
+/*
+ * Launch parameters that change speed, never results: every setting
+ * produces bit-identical marching output and rendering results, since the
+ * per-ray arithmetic does not depend on them (rendering of rays longer than
+ * 64 chunks of 64 samples aside, whose backward may then differ in the last
+ * bits); the fused loss value is a sum in a different order.  Process-wide;
+ * set them before launching, not concurrently with launches.
+ *   march_waves_per_group  wavefronts sharing each group of 64 rays in the
+ *                          uniform-step marching kernels: 1, 2 or 4 (4).
+ *   render_cached_chunks   chunks of 64 samples per ray kept in registers
+ *                          between the forward and the backward pass: 1..4
+ *                          (4).
+ *   render_mse_max_blocks  workgroups of the fused loss kernel, 1..2^20
+ *                          (8192).
+ * Workspace sizes do not depend on these settings.
+ */
+typedef struct nacc_tuning {
+    int32_t march_waves_per_group;
+    int32_t render_cached_chunks;
+    int32_t render_mse_max_blocks;
+    int32_t reserved;
+} nacc_tuning;
+
+void nacc_get_tuning(nacc_tuning* out);
+int nacc_set_tuning(const nacc_tuning* tuning);
+
 /* Message of the calling thread's most recent failed call ("" if none). */
 const char* nacc_last_error(void);
 
@@ -246,16 +272,22 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays,
                     const float* g_opacity, const float* g_depth,
                     float* g_sigmas, float* g_rgbs, void* stream);
 
-/* Bytes of device workspace nacc_render_fwd_bwd_mse needs (>= 0). */
+/* Bytes of device workspace nacc_render_fwd_bwd_mse needs (>= 0; the same
+ * under every nacc_tuning, so a workspace stays valid after retuning). */
 int64_t nacc_render_mse_workspace_size(int64_t n_rays);
 
 /*
  * Fused forward + mean-squared-error loss + backward (the training step of
  * Sec. 3: loss = mse(color, target), then backward), in one pass per ray.
- *   target   float[n_rays][3].
- *   loss     out float[1] on the device: mean over n_rays * 3 values.
+ *   target     float[n_rays][3].
+ *   loss_rays  rays the mean is taken over (0 = n_rays; >= n_rays): a batch
+ *              split over several calls passes its total, so that the calls'
+ *              gradients equal those of one call over the whole batch and
+ *              their losses add up to its loss.
+ *   loss       out float[1] on the device: sum of squared errors of these
+ *              rays divided by 3 loss_rays.
  *   color, opacity, depth, g_sigmas, g_rgbs as in the calls above, with
- *   g_color = 2 (color - target) / (3 n_rays), g_opacity = g_depth = 0.
+ *   g_color = 2 (color - target) / (3 loss_rays), g_opacity = g_depth = 0.
  *   workspace  device scratch of nacc_render_mse_workspace_size bytes.
  */
 int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays,
@@ -263,6 +295,7 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays,
                             const float* t_ends,
                             const float* sigmas, const float* rgbs,
                             float early_stop_eps, const float* target,
+                            int64_t loss_rays,
                             float* color, float* opacity, float* depth,
                             float* g_sigmas, float* g_rgbs, float* loss,
                             void* workspace, size_t workspace_bytes,
@@ -287,12 +320,17 @@ int nacc_grid_decay(float* occ, int64_t n_cells, float decay, void* stream);
  *   x_i      = lo_i + ((float)j_i + jitter_i) * h_i,
  *              h_i = fl32((hi_i - lo_i) / res), (j_0, j_1, j_2) the C-order
  *              index of the cell within its grid, grid = cell / res^3.
- * CASCADE grids: `levels` is the number of levels and x is then scaled by
- * 2^grid (exact).  Otherwise `levels` counts independent grids over the same
- * box (grid = cell / res^3) and x is left in the box.
+ * CASCADE grids: `levels` (1..16) is the number of levels and x is then
+ * scaled by 2^grid (exact).  Otherwise `levels` (>= 1) counts independent
+ * grids over the same box (grid = cell / res^3) and x is left in the box.
+ * n_cells must fit int32 (NACC_ESHAPE otherwise).
+ *   step_dev  uint64[1] on the device, or NULL: when given, the update number
+ *             is read from it at run time (so that a captured graph can
+ *             replay updates with advancing numbers) and `step` is ignored.
  *   cells out int32[n] (global cell index); positions out float[n][3].
  */
-int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n,
+int nacc_grid_sample_cells(uint64_t seed, uint64_t step,
+                           const uint64_t* step_dev, int64_t n,
                            const nacc_grid_desc* grid, int32_t levels,
                            int32_t* cells, float* positions, void* stream);
 

@@ -50,9 +50,13 @@ int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets,
                              const float* t_starts, const float* t_ends, int64_t n_samples,
                              const int64_t* n_samples_dev, float* sigmas, float* rgbs, void* stream);
 
-/* sigma (and rgb, nullable) at points float[n][3]; point_set nullable. */
+/* sigma (and rgb, nullable) at points float[n][3].  The centre set of point
+ * q is point_set[q] if point_set is given, else point_cell[q] / cells_per_set
+ * if point_cell is given (cells drawn over several grids by
+ * nacc_grid_sample_cells), else 0. */
 int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, const float* points,
-                            const int32_t* point_set, int64_t n, float* sigmas, float* rgbs, void* stream);
+                            const int32_t* point_set, const int32_t* point_cell, int64_t cells_per_set,
+                            int64_t n, float* sigmas, float* rgbs, void* stream);
 
 #ifdef __cplusplus
 }

@@ -34,6 +34,11 @@ class GridDesc(ctypes.Structure):
                 ("lookup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("march_waves_per_group", ctypes.c_int32), ("render_cached_chunks", ctypes.c_int32),
+                ("render_mse_max_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class MarchParams(ctypes.Structure):
     _fields_ = [("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float),
                 ("dt", ctypes.c_float), ("dt_max", ctypes.c_float),
@@ -50,6 +55,8 @@ _INT = ctypes.c_int
 
 _SIGNATURES = {
     "nacc_version": (ctypes.c_char_p, []),
+    "nacc_get_tuning": (None, [ctypes.POINTER(Tuning)]),
+    "nacc_set_tuning": (_INT, [ctypes.POINTER(Tuning)]),
     "nacc_last_error": (ctypes.c_char_p, []),
     "nacc_status_str": (ctypes.c_char_p, [_INT]),
     "nacc_march_workspace_size": (_I64, [_I64, ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams)]),
@@ -60,10 +67,10 @@ _SIGNATURES = {
     "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_mse_workspace_size": (_I64, [_I64]),
-    "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P,
+    "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _I64, _P, _P, _P,
                                        _P, _P, _P, _P, _SZ, _P]),
     "nacc_grid_decay": (_INT, [_P, _I64, _F, _P]),
-    "nacc_grid_sample_cells": (_INT, [_U64, _U64, _I64, ctypes.POINTER(GridDesc), _I32,
+    "nacc_grid_sample_cells": (_INT, [_U64, _U64, _P, _I64, ctypes.POINTER(GridDesc), _I32,
                                       _P, _P, _P]),
     "nacc_grid_update_max": (_INT, [_P, _P, _P, _I64, _I64, _P]),
     "nacc_grid_pack": (_INT, [_P, _I64, _F, _P, _P]),
@@ -73,7 +80,7 @@ _SIGNATURES = {
     "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _P, _P]),
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
                                         _P, _P, _P, _P]),
-    "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P]),
+    "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P]),
 }
 
 # Symbols declared in include/nacc.h and include/nacc_synth.h.
@@ -102,6 +109,22 @@ def status_name(status: int) -> str:
 
 def version() -> str:
     return lib.nacc_version().decode()
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    lib.nacc_get_tuning(ctypes.byref(t))
+    return {name: getattr(t, name) for name, _ in Tuning._fields_ if name != "reserved"}
+
+
+def set_tuning(**kw) -> None:
+    """Changes launch parameters (never results); unspecified keys keep their
+    current values."""
+    cur = get_tuning()
+    cur.update(kw)
+    t = Tuning(cur["march_waves_per_group"], cur["render_cached_chunks"],
+               cur["render_mse_max_blocks"], 0)
+    _check("nacc_set_tuning", lib.nacc_set_tuning(ctypes.byref(t)))
 
 
 def _check(name, status):
@@ -249,7 +272,8 @@ def render_mse_workspace_size(n_rays: int) -> int:
 
 
 def render_fwd_bwd_mse(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
-                       color, opacity, depth, g_sigmas, g_rgbs, loss, workspace, stream=None):
+                       color, opacity, depth, g_sigmas, g_rgbs, loss, workspace, loss_rays=0,
+                       stream=None):
     n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
     _need(target, torch.float32, "target", 3 * n)
     _need(color, torch.float32, "color", 3 * n)
@@ -261,8 +285,8 @@ def render_fwd_bwd_mse(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_e
     _need(workspace, torch.uint8, "workspace")
     _check("nacc_render_fwd_bwd_mse", lib.nacc_render_fwd_bwd_mse(
         _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
-        float(early_stop_eps), _ptr(target), _ptr(color), _ptr(opacity), _ptr(depth),
-        _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss), _ptr(workspace), workspace.numel(),
+        float(early_stop_eps), _ptr(target), int(loss_rays), _ptr(color), _ptr(opacity),
+        _ptr(depth), _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss), _ptr(workspace), workspace.numel(),
         _stream(stream)))
 
 
@@ -272,12 +296,16 @@ def grid_decay(occ, decay, stream=None):
                                                   _stream(stream)))
 
 
-def grid_sample_cells(seed, step, n, desc, levels, cells, positions, stream=None):
+def grid_sample_cells(seed, step, n, desc, levels, cells, positions, step_dev=None, stream=None):
+    """step: the update number, or a one-element int64 GPU tensor holding it."""
+    if torch.is_tensor(step):
+        _need(step, torch.int64, "step", 1)
+        step, step_dev = 0, step
     _need(cells, torch.int32, "cells", n)
     _need(positions, torch.float32, "positions", 3 * n)
     _check("nacc_grid_sample_cells", lib.nacc_grid_sample_cells(
-        int(seed), int(step), int(n), ctypes.byref(desc), int(levels), _ptr(cells),
-        _ptr(positions), _stream(stream)))
+        int(seed), int(step), _ptr(step_dev), int(n), ctypes.byref(desc), int(levels),
+        _ptr(cells), _ptr(positions), _stream(stream)))
 
 
 def grid_update_max(occ, cells, values, stream=None):
@@ -339,13 +367,15 @@ def synth_field_samples(table, n_blobs, n_sets, rays_o, rays_d, ray_set, ray_ind
         _stream(stream)))
 
 
-def synth_field_points(table, n_blobs, n_sets, points, point_set, sigmas, rgbs=None, stream=None):
+def synth_field_points(table, n_blobs, n_sets, points, point_set, sigmas, rgbs=None,
+                       point_cell=None, cells_per_set=0, stream=None):
     n = points.shape[0]
     _need(table, torch.float32, "table")
     _need(points, torch.float32, "points", 3 * n)
     _need(point_set, torch.int32, "point_set", n)
+    _need(point_cell, torch.int32, "point_cell", n)
     _need(sigmas, torch.float32, "sigmas", n)
     _need(rgbs, torch.float32, "rgbs", 3 * n)
     _check("nacc_synth_field_points", lib.nacc_synth_field_points(
-        _ptr(table), n_blobs, n_sets, _ptr(points), _ptr(point_set), n, _ptr(sigmas), _ptr(rgbs),
-        _stream(stream)))
+        _ptr(table), n_blobs, n_sets, _ptr(points), _ptr(point_set), _ptr(point_cell),
+        int(cells_per_set), n, _ptr(sigmas), _ptr(rgbs), _stream(stream)))

@@ -237,6 +237,7 @@ class BlobField:
         dev = points.device
         sig = torch.empty(n, dtype=torch.float32, device=dev)
         rgb = torch.empty((n, 3), dtype=torch.float32, device=dev) if want_rgb else None
+        ps = None if point_set is None else point_set.to(torch.int32).contiguous()
         _lib.synth_field_points(self.table, self.n_blobs, self.n_sets, points.contiguous(),
-                                point_set, sig, rgb)
+                                ps, sig, rgb)
         return (sig, rgb) if want_rgb else sig

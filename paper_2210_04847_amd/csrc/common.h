@@ -16,6 +16,8 @@ int set_error(int status, const char* fmt, ...) __attribute__((format(printf, 2,
 void clear_error();
 // Converts a pending launch error into NACC_EHIP.
 int check_launch(const char* what);
+// Launch parameters picked by the caller or the autotuner (nacc_set_tuning).
+const nacc_tuning& tuning();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 

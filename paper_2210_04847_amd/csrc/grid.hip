@@ -66,14 +66,17 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
     return U64x4{{c0, c1, c2, c3}};
 }
 
-__global__ __launch_bounds__(kThreads) void sample_cells_kernel(uint64_t seed, uint64_t step, int64_t n, int res,
+__global__ __launch_bounds__(kThreads) void sample_cells_kernel(uint64_t seed, uint64_t step,
+                                                                 const uint64_t* __restrict__ step_dev, int64_t n,
+                                                                 int res,
                                                                  uint64_t n_cells, float lo0, float lo1, float lo2,
                                                                  float h0, float h1, float h2, int cascade,
                                                                  int32_t* __restrict__ cells,
                                                                  float* __restrict__ positions) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (q >= n) return;
-    const U64x4 r = philox4x64_10(static_cast<uint64_t>(q), step, 0, 0, seed, 0);
+    const uint64_t update = step_dev != nullptr ? *step_dev : step;
+    const U64x4 r = philox4x64_10(static_cast<uint64_t>(q), update, 0, 0, seed, 0);
     const uint64_t cell = ((r.v[0] >> 32) * n_cells) >> 32;
     cells[q] = static_cast<int32_t>(cell);
     const uint64_t per_grid = static_cast<uint64_t>(res) * res * res;
@@ -197,14 +200,17 @@ int nacc_grid_decay(float* occ, int64_t n_cells, float decay, void* stream) {
     return check_launch("grid decay");
 }
 
-int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n, const nacc_grid_desc* grid, int32_t levels,
-                           int32_t* cells, float* positions, void* stream) {
+int nacc_grid_sample_cells(uint64_t seed, uint64_t step, const uint64_t* step_dev, int64_t n,
+                           const nacc_grid_desc* grid, int32_t levels, int32_t* cells, float* positions,
+                           void* stream) {
     clear_error();
     NACC_REQUIRE(grid != nullptr, NACC_EINVAL, "grid must be non-NULL");
     NACC_REQUIRE(n >= 0 && n <= INT32_MAX, NACC_EINVAL, "n = %lld out of [0, 2^31-1]", static_cast<long long>(n));
     NACC_REQUIRE(n == 0 || (cells != nullptr && positions != nullptr), NACC_EINVAL, "outputs must be non-NULL");
     NACC_REQUIRE(grid->res >= 1 && grid->res <= 1024, NACC_EINVAL, "grid res = %d out of [1, 1024]", grid->res);
-    NACC_REQUIRE(levels >= 1 && levels <= 16, NACC_EINVAL, "levels = %d out of [1, 16]", levels);
+    const bool cascade = grid->lookup == NACC_LOOKUP_CASCADE;
+    NACC_REQUIRE(levels >= 1 && (!cascade || levels <= 16), NACC_EINVAL, "levels = %d out of [1, %s]", levels,
+                 cascade ? "16" : "2^31");
     const uint64_t n_cells = static_cast<uint64_t>(grid->res) * grid->res * grid->res * levels;
     NACC_REQUIRE(n_cells <= static_cast<uint64_t>(INT32_MAX), NACC_ESHAPE, "too many cells for int32 indices");
     for (int i = 0; i < 3; ++i) {
@@ -218,8 +224,8 @@ int nacc_grid_sample_cells(uint64_t seed, uint64_t step, int64_t n, const nacc_g
                                   static_cast<double>(grid->res));
     }
     hipLaunchKernelGGL(sample_cells_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, as_stream(stream), seed, step,
-                       n, grid->res, n_cells, grid->lo[0], grid->lo[1], grid->lo[2], h[0], h[1], h[2],
-                       grid->lookup == NACC_LOOKUP_CASCADE ? 1 : 0, cells, positions);
+                       step_dev, n, grid->res, n_cells, grid->lo[0], grid->lo[1], grid->lo[2], h[0], h[1], h[2],
+                       cascade ? 1 : 0, cells, positions);
     return check_launch("grid sample cells");
 }
 

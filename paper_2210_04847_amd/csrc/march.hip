@@ -34,7 +34,6 @@ using namespace nacc;
 using namespace nacc::dev;
 
 constexpr int kRaysPerBlock = 64;     // rays per workgroup in count/fill/scan
-constexpr int kUniformThreads = 256;  // 4 waves, 16 rays each
 constexpr int kMaxCandidates = 1 << 24;
 
 struct GridK {
@@ -276,18 +275,18 @@ __device__ __forceinline__ int march_ray_uniform(
     return count;
 }
 
-template <int LOOKUP, bool MIP>
-__global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
+template <int LOOKUP, bool MIP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
     int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
-    __shared__ int64_t wave_total[kUniformThreads / kWave];
+    __shared__ int64_t wave_total[WAVES];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
     int64_t total = 0;
     bool unused = false;
-    for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
+    for (int i = wave; i < kRaysPerBlock; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const int n = march_ray_uniform<LOOKUP, false, MIP>(
@@ -300,7 +299,7 @@ __global__ __launch_bounds__(kUniformThreads) void count_uniform_kernel(
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t s = 0;
-        for (int w = 0; w < kUniformThreads / kWave; ++w) s += wave_total[w];
+        for (int w = 0; w < WAVES; ++w) s += wave_total[w];
         block_sums[blockIdx.x] = s;
     }
 }
@@ -355,8 +354,8 @@ __device__ __forceinline__ void fill_ray_from_masks(
     }
 }
 
-template <int LOOKUP, bool MIP>
-__global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
+template <int LOOKUP, bool MIP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
@@ -365,7 +364,7 @@ __global__ __launch_bounds__(kUniformThreads) void fill_uniform_kernel(
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
     bool overflow = false;
-    for (int i = wave; i < kRaysPerBlock; i += kUniformThreads / kWave) {
+    for (int i = wave; i < kRaysPerBlock; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const int64_t start = packed_info[2 * r];
@@ -623,19 +622,49 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     p.max_per_ray = params.max_per_ray;
 }
 
+template <int LOOKUP, bool MIP, int WAVES>
+void launch_count_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
+                          const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c, const StepK& p,
+                          int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
+    hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, MIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
+                       bits, mip, g, c, p, packed, sums, masks, n_masks);
+}
+
+template <int LOOKUP, bool MIP, int WAVES>
+void launch_fill_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
+                         const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c, const StepK& p,
+                         const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te, int32_t* status,
+                         const uint64_t* masks, int n_masks) {
+    hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, MIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
+                       bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+}
+
+template <int LOOKUP, bool MIP, typename... A>
+void count_by_waves(int waves, A&&... a) {
+    if (waves == 1) launch_count_uniform<LOOKUP, MIP, 1>(a...);
+    else if (waves == 2) launch_count_uniform<LOOKUP, MIP, 2>(a...);
+    else launch_count_uniform<LOOKUP, MIP, 4>(a...);
+}
+
+template <int LOOKUP, bool MIP, typename... A>
+void fill_by_waves(int waves, A&&... a) {
+    if (waves == 1) launch_fill_uniform<LOOKUP, MIP, 1>(a...);
+    else if (waves == 2) launch_fill_uniform<LOOKUP, MIP, 2>(a...);
+    else launch_fill_uniform<LOOKUP, MIP, 4>(a...);
+}
+
 template <int LOOKUP>
 void launch_count(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
                   int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
                   const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
+    const int waves = tuning().march_waves_per_group;
     if (cone) {
         hipLaunchKernelGGL(count_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
                            bits, g, c, p, packed, sums);
     } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
-        hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
+        count_by_waves<LOOKUP, true>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
     } else {
-        hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
+        count_by_waves<LOOKUP, false>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
     }
 }
 
@@ -644,15 +673,16 @@ void launch_fill(bool cone, int64_t nb, hipStream_t s, const float* o, const flo
                  int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
                  const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
                  int32_t* status, const uint64_t* masks, int n_masks) {
+    const int waves = tuning().march_waves_per_group;
     if (cone) {
         hipLaunchKernelGGL(fill_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, bits,
                            g, c, p, packed, capacity, ri, ts, te, status);
     } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
-        hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, true>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+        fill_by_waves<LOOKUP, true>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te,
+                                    status, masks, n_masks);
     } else {
-        hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, false>), dim3(nb), dim3(kUniformThreads), 0, s, o, d,
-                           gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+        fill_by_waves<LOOKUP, false>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te,
+                                     status, masks, n_masks);
     }
 }
 

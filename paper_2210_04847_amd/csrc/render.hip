@@ -29,7 +29,6 @@ using namespace nacc;
 using namespace nacc::dev;
 
 constexpr int kRenderThreads = 256;  // 4 waves
-constexpr int kCachedChunks = 2;     // chunks of 64 samples kept in registers per ray
 constexpr int kRaysPerRenderBlock = kRenderThreads / kWave;
 
 struct Sample {
@@ -220,6 +219,7 @@ struct RayCache {
     Sample x[K];
     float w[K];
     float t_next[K];
+    double carries;  // lane j: FP64 tau prefix at the start of chunk j (j < 64)
 };
 
 template <int K, bool ACCUM>
@@ -236,12 +236,14 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
     double carry = 0.0, carry_prev = 0.0;
     kept = n;
     prefix_hi = 0.0;
+    cache.carries = 0.0;
     bool stopped = false;
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         cache.w[c] = 0.0f;
         cache.t_next[c] = 0.0f;
         if (stopped || c * kWave >= n) continue;
+        if (lane == c) cache.carries = carry;
         const int i = c * kWave + lane;
         const bool valid = i < n;
         const Trans t = chunk_transmittance(cache.x[c], carry);
@@ -268,6 +270,7 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         }
     }
     for (int c = K * kWave; !stopped && c < n; c += kWave) {
+        if (lane == c / kWave) cache.carries = carry;
         const int i = c + lane;
         const bool valid = i < n;
         const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
@@ -324,7 +327,11 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
         const Sample x = load_sample(keep, s, ts, te, sig, rgb);
         const float tau = x.sigma * (x.t1 - x.t0);
         const float chunk_tau = wave_sum(tau);
-        const double p_start = c == c_hi ? prefix_hi : p_end - static_cast<double>(chunk_tau);
+        // the forward pass's own carry (so T is bit for bit the forward T)
+        // for the first 64 chunks, else the prefix walked down from the end
+        const int chunk = c / kWave;
+        const double p_start = chunk < kWave ? read_lane(cache.carries, chunk)
+                                             : (c == c_hi ? prefix_hi : p_end - static_cast<double>(chunk_tau));
         const Trans t = chunk_transmittance(x, p_start);
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         const float t_next = t.t_next;
@@ -444,11 +451,44 @@ __global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const double*
 
 int64_t render_blocks(int64_t n_rays) { return (n_rays + kRaysPerRenderBlock - 1) / kRaysPerRenderBlock; }
 
-// The fused kernel walks the rays grid-stride with at most this many
-// workgroups (16 per CU), so its loss needs few partial sums.
-constexpr int64_t kMaxMseBlocks = 4096;
+// The fused kernel walks the rays grid-stride with at most
+// tuning().render_mse_max_blocks workgroups, so its loss needs few partial
+// sums.
+int64_t mse_blocks(int64_t n_rays) {
+    return std::max<int64_t>(1, std::min<int64_t>(render_blocks(n_rays), tuning().render_mse_max_blocks));
+}
 
-int64_t mse_blocks(int64_t n_rays) { return std::max<int64_t>(1, std::min(render_blocks(n_rays), kMaxMseBlocks)); }
+// Kernels instantiated for 1..4 register-cached chunks per ray.
+template <template <int> class F, typename... A>
+void dispatch_cached(int k, A&&... a) {
+    switch (k) {
+        case 1: F<1>::run(a...); break;
+        case 3: F<3>::run(a...); break;
+        case 4: F<4>::run(a...); break;
+        default: F<2>::run(a...); break;
+    }
+}
+
+template <int K>
+struct LaunchBwd {
+    static void run(dim3 grid, hipStream_t s, const int32_t* packed_info, int64_t n_rays, int64_t n_samples,
+                    const float* ts, const float* te, const float* sig, const float* rgb, float eps, const float* gc,
+                    const float* go, const float* gd, float* g_sig, float* g_rgb) {
+        hipLaunchKernelGGL(render_bwd_kernel<K>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, ts,
+                           te, sig, rgb, eps, gc, go, gd, g_sig, g_rgb);
+    }
+};
+
+template <int K>
+struct LaunchMse {
+    static void run(dim3 grid, hipStream_t s, const int32_t* packed_info, int64_t n_rays, int64_t n_samples,
+                    const float* ts, const float* te, const float* sig, const float* rgb, float eps, const float* target,
+                    float inv_count2, float* color, float* opacity, float* depth, float* g_sig, float* g_rgb,
+                    double* partial) {
+        hipLaunchKernelGGL(render_mse_kernel<K>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, ts,
+                           te, sig, rgb, eps, target, inv_count2, color, opacity, depth, g_sig, g_rgb, partial);
+    }
+};
 
 int validate_render(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* ts,
                     const float* te, const float* sig, const float* rgb, float eps) {
@@ -502,25 +542,31 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
                  "g_color, g_sigmas and g_rgbs must be non-NULL");
     if (n_rays == 0) return NACC_OK;
     hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(render_bwd_kernel<kCachedChunks>, dim3(static_cast<unsigned>(render_blocks(n_rays))),
-                       dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs,
-                       early_stop_eps, g_color, g_opacity, g_depth, g_sigmas, g_rgbs);
+    dispatch_cached<LaunchBwd>(tuning().render_cached_chunks, dim3(static_cast<unsigned>(render_blocks(n_rays))), s,
+                               packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, g_color,
+                               g_opacity, g_depth, g_sigmas, g_rgbs);
     return check_launch("render bwd");
 }
 
 int64_t nacc_render_mse_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
-    return ((mse_blocks(n_rays) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
+    // one partial per workgroup at any tuning (render_blocks bounds mse_blocks)
+    return ((std::max<int64_t>(1, render_blocks(n_rays)) * static_cast<int64_t>(sizeof(double)) + 255) / 256) *
+           256;
 }
 
 int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
                             const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
-                            const float* target, float* color, float* opacity, float* depth, float* g_sigmas,
-                            float* g_rgbs, float* loss, void* workspace, size_t workspace_bytes, void* stream) {
+                            const float* target, int64_t loss_rays, float* color, float* opacity, float* depth,
+                            float* g_sigmas, float* g_rgbs, float* loss, void* workspace, size_t workspace_bytes,
+                            void* stream) {
     clear_error();
     int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
     if (st != NACC_OK) return st;
     NACC_REQUIRE(n_rays > 0, NACC_EINVAL, "the mean squared error needs n_rays > 0");
+    if (loss_rays == 0) loss_rays = n_rays;
+    NACC_REQUIRE(loss_rays >= n_rays, NACC_EINVAL, "loss_rays = %lld < n_rays = %lld",
+                 static_cast<long long>(loss_rays), static_cast<long long>(n_rays));
     NACC_REQUIRE(target != nullptr && color != nullptr && opacity != nullptr && depth != nullptr &&
                      g_sigmas != nullptr && g_rgbs != nullptr && loss != nullptr && workspace != nullptr,
                  NACC_EINVAL, "outputs, target and workspace must be non-NULL");
@@ -529,13 +575,12 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
                  workspace_bytes, static_cast<long long>(need));
     hipStream_t s = as_stream(stream);
     const int64_t nb = mse_blocks(n_rays);
-    const double count = 3.0 * static_cast<double>(n_rays);
+    const double count = 3.0 * static_cast<double>(loss_rays);
     const float inv_count2 = static_cast<float>(2.0 / count);
     double* partial = static_cast<double*>(workspace);
-    hipLaunchKernelGGL(render_mse_kernel<kCachedChunks>, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s,
-                       packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
-                       inv_count2,
-                       color, opacity, depth, g_sigmas, g_rgbs, partial);
+    dispatch_cached<LaunchMse>(tuning().render_cached_chunks, dim3(static_cast<unsigned>(nb)), s, packed_info, n_rays,
+                               n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target, inv_count2, color,
+                               opacity, depth, g_sigmas, g_rgbs, partial);
     st = check_launch("render fwd+bwd+mse");
     if (st != NACC_OK) return st;
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, partial, nb, 1.0 / count, loss);

@@ -6,6 +6,7 @@
 
 namespace {
 thread_local char g_message[512] = "";
+nacc_tuning g_tuning = {4, 4, 8192, 0};
 }
 
 namespace nacc {
@@ -20,6 +21,8 @@ int set_error(int status, const char* fmt, ...) {
 
 void clear_error() { g_message[0] = '\0'; }
 
+const nacc_tuning& tuning() { return g_tuning; }
+
 int check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -33,6 +36,23 @@ int check_launch(const char* what) {
 extern "C" {
 
 const char* nacc_version(void) { return "nacc 0.1.0 (gfx950)"; }
+
+void nacc_get_tuning(nacc_tuning* out) {
+    if (out != nullptr) *out = g_tuning;
+}
+
+int nacc_set_tuning(const nacc_tuning* t) {
+    nacc::clear_error();
+    NACC_REQUIRE(t != nullptr, NACC_EINVAL, "tuning must be non-NULL");
+    NACC_REQUIRE(t->march_waves_per_group == 1 || t->march_waves_per_group == 2 || t->march_waves_per_group == 4,
+                 NACC_EINVAL, "march_waves_per_group = %d not in {1, 2, 4}", t->march_waves_per_group);
+    NACC_REQUIRE(t->render_cached_chunks >= 1 && t->render_cached_chunks <= 4, NACC_EINVAL,
+                 "render_cached_chunks = %d not in [1, 4]", t->render_cached_chunks);
+    NACC_REQUIRE(t->render_mse_max_blocks >= 1 && t->render_mse_max_blocks <= (1 << 20), NACC_EINVAL,
+                 "render_mse_max_blocks = %d not in [1, 2^20]", t->render_mse_max_blocks);
+    g_tuning = *t;
+    return NACC_OK;
+}
 
 const char* nacc_last_error(void) { return g_message; }
 

@@ -117,10 +117,14 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
     }
 }
 
+// Centre set per point: point_set[q], or point_cell[q] / cells_per_set when
+// the points were drawn as cells of several grids.
 template <bool PER_SET>
 __global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __restrict__ table, int n_blobs,
                                                                  int n_sets, const float* __restrict__ points,
-                                                                 const int32_t* __restrict__ point_set, int64_t n,
+                                                                 const int32_t* __restrict__ point_set,
+                                                                 const int32_t* __restrict__ point_cell,
+                                                                 int64_t cells_per_set, int64_t n,
                                                                  float* __restrict__ sigmas,
                                                                  float* __restrict__ rgbs) {
     const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __r
         const float x0 = points[3 * q], x1 = points[3 * q + 1], x2 = points[3 * q + 2];
         int set = 0;
         if (PER_SET) {
-            set = point_set[q];
+            set = point_set != nullptr ? point_set[q] : static_cast<int>(point_cell[q] / cells_per_set);
             set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
         }
         float sigma;
@@ -191,15 +195,19 @@ int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets,
 }
 
 int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, const float* points,
-                            const int32_t* point_set, int64_t n, float* sigmas, float* rgbs, void* stream) {
+                            const int32_t* point_set, const int32_t* point_cell, int64_t cells_per_set, int64_t n,
+                            float* sigmas, float* rgbs, void* stream) {
     clear_error();
     NACC_REQUIRE(n_blobs >= 1 && n_sets >= 1, NACC_EINVAL, "n_blobs and n_sets must be >= 1");
     NACC_REQUIRE(n >= 0, NACC_EINVAL, "n < 0");
     NACC_REQUIRE(n == 0 || (table && points && sigmas), NACC_EINVAL, "arguments must be non-NULL");
+    NACC_REQUIRE(point_cell == nullptr || cells_per_set > 0, NACC_EINVAL, "cells_per_set must be > 0");
     if (n == 0) return NACC_OK;
-    auto kernel = point_set != nullptr ? field_points_kernel<true> : field_points_kernel<false>;
+    const bool per_set = point_set != nullptr || point_cell != nullptr;
+    auto kernel = per_set ? field_points_kernel<true> : field_points_kernel<false>;
     hipLaunchKernelGGL(kernel, dim3(field_blocks(n)), dim3(kThreads), 0, as_stream(stream),
-                       static_cast<const float*>(table), n_blobs, n_sets, points, point_set, n, sigmas, rgbs);
+                       static_cast<const float*>(table), n_blobs, n_sets, points, point_set, point_cell,
+                       cells_per_set, n, sigmas, rgbs);
     return check_launch("synth field points");
 }
 

@@ -136,6 +136,37 @@ def initial_occupancy(scene: BlobScene, res: int, box, set_index: int = 0,
     return blob_density(scene, pts, set_index).astype(np.float32)
 
 
+def local_occupancy(scene: BlobScene, res: int, box, set_index: int = 0,
+                    reach: float = 7.0) -> np.ndarray:
+    """FP32 occupancy values of one centre set: each blob adds its density
+    at the cell centres within `reach` standard deviations of its centre
+    (per axis), evaluated separably as a product of three 1-D Gaussians in
+    FP64.  This is the input definition of the per-frame grids (the
+    contributions it leaves out are below 50 e^-24.5 ~ 1e-9)."""
+    lo = np.asarray(box[:3], np.float64)
+    hi = np.asarray(box[3:], np.float64)
+    h = (hi - lo) / res
+    occ = np.zeros((res, res, res), np.float64)
+    for b in range(scene.n_blobs):
+        c = scene.centres[set_index, b].astype(np.float64)
+        sd = float(scene.stds[b])
+        span = []
+        for i in range(3):
+            a = max(0, int(np.floor((c[i] - reach * sd - lo[i]) / h[i] - 0.5)))
+            e = min(res, int(np.ceil((c[i] + reach * sd - lo[i]) / h[i] + 0.5)))
+            span.append((a, e))
+        if any(a >= e for a, e in span):
+            continue
+        g = []
+        for i, (a, e) in enumerate(span):
+            x = lo[i] + (np.arange(a, e) + 0.5) * h[i]
+            g.append(np.exp(-((x - c[i]) ** 2) / (2.0 * sd * sd)))
+        blk = float(scene.peaks[b]) * g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :]
+        (a0, e0), (a1, e1), (a2, e2) = span
+        occ[a0:e0, a1:e1, a2:e2] += blk
+    return occ.astype(np.float32).ravel()
+
+
 def random_mask(n_cells: int, p: float, seed: int) -> np.ndarray:
     """uint8 0/1 occupancy mask with P(1) = p."""
     return (_rng(seed).random(n_cells) < p).astype(np.uint8)
@@ -207,6 +238,47 @@ WORKLOADS = {
     "train_262k": Workload("train_262k", 262144, 32, 128, BOX_1_5, STEP_1024,
                            1e-4, 0.0, 1e10, 1),
 }
+
+
+@dataclass
+class DynamicWorkload:
+    name: str
+    n_frames: int
+    mean_rays: float
+    n_blobs: int
+    res: int
+    box: tuple
+    dt: float
+    early_stop_eps: float
+    near: float
+    far: float
+    seed_base: int
+
+
+DYNAMIC_WORKLOADS = {
+    "dynamic_64": DynamicWorkload("dynamic_64", 64, 4096.0, 32, 128, BOX_1_5, STEP_1024, 1e-4,
+                                  0.0, 1e10, 3),
+}
+
+
+def dynamic_inputs(w: DynamicWorkload, n_frames: int | None = None, res: int | None = None,
+                   mean_rays: float | None = None):
+    """Rays (grouped by frame, frame f at time f / (F - 1)), their frame ids,
+    the moving blob scene, one occupancy grid per frame and loss targets.
+    Ray counts per frame ~ Poisson(mean_rays)."""
+    nf = w.n_frames if n_frames is None else n_frames
+    rs = w.res if res is None else res
+    mean = w.mean_rays if mean_rays is None else mean_rays
+    g = _rng(2000 + w.seed_base)
+    counts = g.poisson(mean, nf).astype(np.int64)
+    n = int(counts.sum())
+    o, d = rays_toward_origin(n, 2100 + w.seed_base)
+    frame = np.repeat(np.arange(nf), counts).astype(np.int32)
+    scene = moving_blob_scene(w.n_blobs, nf, 1000 + w.seed_base)
+    occ = np.concatenate([local_occupancy(scene, rs, w.box, f) for f in range(nf)])
+    tgt = targets(n, 3000 + w.seed_base)
+    return dict(rays_o=o, rays_d=d, frame=frame, counts=counts, scene=scene, occ=occ,
+                targets=tgt, res=rs)
 
 
 def workload_inputs(w: Workload, n_rays: int | None = None):

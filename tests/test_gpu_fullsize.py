@@ -18,7 +18,12 @@ def step():
     import paper_2210_04847_amd as nacc
     w = synth.WORKLOADS["train_262k"]
     inp = synth.workload_inputs(w)
-    st = bench.TrainStep(w, inp, torch, nacc)
+    t = lambda a: torch.from_numpy(a).cuda()
+    grid = nacc.OccupancyGrid(w.box, w.res)
+    grid.set_occupancy(t(inp["occ"]), 0.01)
+    field = nacc.BlobField(inp["scene"])
+    st = bench.Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid,
+                    field)
     st.march_count()
     st.march_fill()
     st.field_eval()

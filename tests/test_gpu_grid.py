@@ -28,6 +28,7 @@ def _pack_mask(mask):
     (128, 1, False, BOX),
     (32, 4, True, np.array([-1, -1, -1, 1, 1, 1], np.float32)),
     (16, 5, False, BOX),
+    (32, 64, False, BOX),  # one grid per frame of a 64-frame batch
 ])
 def test_sample_cells(res, levels, cascade, box):
     lib = _lib()

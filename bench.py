@@ -50,14 +50,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="train_262k",
-                    choices=["train_262k", "plain_fwd_4k", "dynamic_64"])
+                    choices=["train_262k", "plain_fwd_4k", "unbounded_262k", "dynamic_64",
+                             "images_8"])
     ap.add_argument("--form", choices=["graph", "eager"], default="graph",
                     help="time the step captured in HIP graphs, or launched eagerly")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
-    ap.add_argument("--skip-grid", choices=["on", "off"], default="off",
-                    help="march with the dilated coarse skip grid")
+    ap.add_argument("--skip-field", choices=["on", "off"], default="off",
+                    help="march with the grid's skip field (empty-space skipping; pays off on "
+                         "sparse scenes only)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
@@ -74,7 +76,7 @@ class Step:
     picks the grid and the field's centre set."""
 
     def __init__(self, torch, nacc, w, rays_o, rays_d, targets, grid, field, grid_id=None,
-                 skip_grid=False, forward_only=False, loss_rays=0, seed=0):
+                 skip_field=False, forward_only=False, loss_rays=0, seed=0):
         self.torch, self.nacc, self.lib = torch, nacc, nacc._lib
         dev = rays_o.device
         self.w = w
@@ -84,11 +86,12 @@ class Step:
         self.grid_id = grid_id
         self.forward_only = forward_only
         self.loss_rays = loss_rays
-        diag = math.sqrt(sum((w.box[3 + i] - w.box[i]) ** 2 for i in range(3)))
-        self.capacity = self.n * (int(math.ceil(diag / w.dt)) + 2)
+        self.params = self.lib.march_params(w.near, w.far, w.dt, getattr(w, "dt_max", 1e10),
+                                            getattr(w, "cone", 0.0))
+        # sample buffers no step can overflow, so no step reads the total back
+        self.capacity = self.n * self.lib.march_max_samples_per_ray(grid.desc, self.params)
         n, cap = self.n, self.capacity
         i32, f32 = torch.int32, torch.float32
-        self.params = self.lib.march_params(w.near, w.far, w.dt)
         self.packed = torch.empty((n, 2), dtype=i32, device=dev)
         self.total = torch.empty(1, dtype=torch.int64, device=dev)
         self.ws = torch.empty(max(self.lib.march_workspace_size(n, grid.desc, self.params), 1),
@@ -112,16 +115,16 @@ class Step:
         self.ema_sigma = torch.empty(EMA_CELLS, dtype=f32, device=dev)
         self.updates = torch.zeros(1, dtype=torch.int64, device=dev)  # read by the kernel
         self.seed = seed
-        self.mip = grid.mip if skip_grid else None
+        self.skip = grid.skip if skip_field else None
 
     def march_count(self):
         self.lib.march_count(self.rays_o, self.rays_d, self.grid_id, self.grid.bits, self.grid.desc,
-                             self.params, self.packed, self.total, self.ws, self.mip)
+                             self.params, self.packed, self.total, self.ws, self.skip)
 
     def march_fill(self):
         self.lib.march_fill(self.rays_o, self.rays_d, self.grid_id, self.grid.bits, self.grid.desc,
                             self.params, self.packed, self.ray_indices, self.t_starts, self.t_ends,
-                            self.status, self.mip, self.ws)
+                            self.status, self.skip, self.ws)
 
     def field_eval(self):
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
@@ -146,12 +149,12 @@ class Step:
                               self.ema_cells, self.ema_pos)
         lib.synth_field_points(self.field.table, self.field.n_blobs, self.field.n_sets,
                                self.ema_pos, None, self.ema_sigma,
-                               point_cell=self.ema_cells if g.n_grids > 1 else None,
+                               point_cell=self.ema_cells if self.field.n_sets > 1 else None,
                                cells_per_set=g.res ** 3)
         lib.grid_update_max(g.occ, self.ema_cells, self.ema_sigma)
         lib.grid_pack(g.occ, THRESHOLD, g.bits)
-        if g.mip is not None:
-            lib.grid_build_mip(g.bits, g.desc, g.mip)
+        if g.skip is not None:
+            lib.grid_build_skip(g.bits, g.desc, g.skip)
         self.updates.add_(1)
 
     PHASES = ("march_count", "march_fill", "field", "render", "grid_update")
@@ -235,9 +238,13 @@ def cpu_baseline(w, inp, n_sample, forward_only=False):
     o = inp["rays_o"][:n_sample]
     d = inp["rays_d"][:n_sample]
     mask = oracle.grid_threshold(inp["occ"], THRESHOLD)
+    cascades = getattr(w, "cascades", 1)
+    lookup = oracle.LOOKUP_CASCADE if cascades > 1 else oracle.LOOKUP_AABB
     t0 = time.perf_counter()
     packed, ri, ts, te = oracle.march(o, d, mask, w.res, np.asarray(w.box, np.float32), w.near,
-                                      w.far, w.dt)
+                                      w.far, w.dt, dt_max=getattr(w, "dt_max", 1e10),
+                                      cone=getattr(w, "cone", 0.0), lookup=lookup,
+                                      n_grids=cascades)
     pos = oracle.sample_positions(o, d, ri, ts, te)
     sig, rgb = oracle.blob_field(inp["scene"], pos)
     fwd = oracle.render_fwd(packed, ts, te, sig, rgb, w.early_stop_eps)
@@ -282,18 +289,22 @@ def phase_timing(torch, st, steps, first_index, updates=True):
 
 def bench_train(args, torch, nacc):
     import synth
-    w = synth.WORKLOADS[args.workload]
+    unbounded = args.workload in synth.UNBOUNDED_WORKLOADS
+    w = (synth.UNBOUNDED_WORKLOADS if unbounded else synth.WORKLOADS)[args.workload]
     forward_only = args.workload == "plain_fwd_4k"
     t_gen = time.perf_counter()
-    inp = synth.workload_inputs(w)
+    inp = synth.unbounded_inputs(w) if unbounded else synth.workload_inputs(w)
     log(f"inputs generated in {time.perf_counter() - t_gen:.1f} s")
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(a).to(dev)
-    grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
+    if unbounded:
+        grid = nacc.OccupancyGrid(w.box, w.res, n_grids=w.cascades, lookup="cascade", device=dev)
+    else:
+        grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
     grid.set_occupancy(t(inp["occ"]), THRESHOLD)
     field = nacc.BlobField(inp["scene"], device=dev)
     st = Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid, field,
-              skip_grid=args.skip_grid == "on", forward_only=forward_only, seed=4000 + w.seed_base)
+              skip_field=args.skip_field == "on", forward_only=forward_only, seed=4000 + w.seed_base)
     torch.cuda.synchronize()
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18  # float32 elements
@@ -371,11 +382,14 @@ def bench_train(args, torch, nacc):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "rays": w.n_rays, "grid": f"{w.res}^3 bit-packed",
-                   "blobs": w.n_blobs, "dt": w.dt, "early_stop_eps": w.early_stop_eps,
+        "config": {"workload": w.name, "rays": w.n_rays,
+                   "grid": (f"{w.cascades} cascades of {w.res}^3 bit-packed" if unbounded
+                            else f"{w.res}^3 bit-packed"),
+                   "blobs": inp["scene"].n_blobs, "dt": w.dt,
+                   "cone": getattr(w, "cone", 0.0), "early_stop_eps": w.early_stop_eps,
                    "pass": "forward" if forward_only else "forward+mse+backward",
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
-                   "form": args.form, "skip_grid": args.skip_grid, "tuning": tuned,
+                   "form": args.form, "skip_field": args.skip_field, "tuning": tuned,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
@@ -419,6 +433,7 @@ def bench_dynamic(args, torch, nacc):
                    seed=4000 + w.seed_base)
     lib = nacc._lib
     words = res ** 3 // 32
+    c3 = (res // 4) ** 3
     starts = np.concatenate([[0], np.cumsum(inp["counts"])]).astype(np.int64)
     desc1 = lib.grid_desc(w.box[:3], w.box[3:], res)
     params = lib.march_params(w.near, w.far, w.dt)
@@ -434,16 +449,18 @@ def bench_dynamic(args, torch, nacc):
                 continue
             o, d = rays_o[a:b], rays_d[a:b]
             bits = grid.bits[f * words:(f + 1) * words]
+            # the frame's skip field (+ the build scratch the size check expects)
+            skip = grid.skip[f * c3:(f + 2) * c3]
             packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
             total = torch.empty(1, dtype=torch.int64, device=dev)
             ws = torch.empty(lib.march_workspace_size(n, desc1, params), dtype=torch.uint8,
                              device=dev)
-            lib.march_count(o, d, None, bits, desc1, params, packed, total, ws)
+            lib.march_count(o, d, None, bits, desc1, params, packed, total, ws, skip)
             e = int(total.item())
             ri = torch.empty(e, dtype=torch.int32, device=dev)
             ts = torch.empty(e, dtype=torch.float32, device=dev)
             te = torch.empty(e, dtype=torch.float32, device=dev)
-            lib.march_fill(o, d, None, bits, desc1, params, packed, ri, ts, te, None, None, ws)
+            lib.march_fill(o, d, None, bits, desc1, params, packed, ri, ts, te, None, skip, ws)
             sig = torch.empty(e, dtype=torch.float32, device=dev)
             rgb = torch.empty((e, 3), dtype=torch.float32, device=dev)
             lib.synth_field_samples(field.table, field.n_blobs, field.n_sets, o, d, frame[a:b], ri,
@@ -546,6 +563,152 @@ def bench_dynamic(args, torch, nacc):
     }
 
 
+def bench_images(args, torch, nacc):
+    """Whole images forward (march, field, render): one batched call
+    sequence over all images against one plain call sequence per image.
+    Sample buffers are sized after a host read of the sample total (a
+    capacity bound for 10.8M rays would not fit the device), once per batch
+    or once per image."""
+    import numpy as np
+
+    import synth
+    w = synth.IMAGE_WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    inp = synth.image_inputs(w)
+    log(f"inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    sw = inp["scene_workload"]
+    dev = torch.device("cuda")
+    lib = nacc._lib
+    grid = nacc.OccupancyGrid(sw.box, sw.res, device=dev)
+    grid.set_occupancy(torch.from_numpy(inp["occ"]).to(dev), THRESHOLD)
+    field = nacc.BlobField(inp["scene"], device=dev)
+    rays_o = torch.from_numpy(inp["rays_o"]).to(dev)
+    rays_d = torch.from_numpy(inp["rays_d"]).to(dev)
+    counts = inp["counts"]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    params = lib.march_params(sw.near, sw.far, sw.dt)
+    skip = grid.skip if args.skip_field == "on" else None
+    eps = w.early_stop_eps
+    i32, f32 = torch.int32, torch.float32
+
+    def render(o, d, events=None):
+        """march count -> host read of the total -> fill -> field -> render."""
+        n = o.shape[0]
+        rec = (lambda j: events[j].record()) if events is not None else (lambda j: None)
+        rec(0)
+        packed = torch.empty((n, 2), dtype=i32, device=dev)
+        total = torch.empty(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(lib.march_workspace_size(n, grid.desc, params), dtype=torch.uint8,
+                         device=dev)
+        lib.march_count(o, d, None, grid.bits, grid.desc, params, packed, total, ws, skip)
+        rec(1)
+        e = int(total.item())
+        ri = torch.empty(e, dtype=i32, device=dev)
+        ts = torch.empty(e, dtype=f32, device=dev)
+        te = torch.empty(e, dtype=f32, device=dev)
+        lib.march_fill(o, d, None, grid.bits, grid.desc, params, packed, ri, ts, te, None, skip, ws)
+        rec(2)
+        sig = torch.empty(e, dtype=f32, device=dev)
+        rgb = torch.empty((e, 3), dtype=f32, device=dev)
+        lib.synth_field_samples(field.table, field.n_blobs, field.n_sets, o, d, None, ri, ts, te,
+                                sig, rgb)
+        rec(3)
+        color = torch.empty((n, 3), dtype=f32, device=dev)
+        opacity = torch.empty(n, dtype=f32, device=dev)
+        depth = torch.empty(n, dtype=f32, device=dev)
+        lib.render_fwd(packed, ts, te, sig, rgb, eps, color, opacity, depth)
+        rec(4)
+        return e, color
+
+    def batched():
+        return render(rays_o, rays_d)
+
+    def plain(done=None):
+        e = 0
+        for k in range(len(counts)):
+            a, b = int(offs[k]), int(offs[k + 1])
+            ek, _ = render(rays_o[a:b], rays_d[a:b])
+            e += ek
+            if done is not None:
+                done[k].record()
+        return e
+
+    # warm-up (also fills the allocator's cache) and an equality check
+    e_b, color_b = batched()
+    colors = []
+    for k in range(len(counts)):
+        a, b = int(offs[k]), int(offs[k + 1])
+        colors.append(render(rays_o[a:b], rays_d[a:b])[1])
+    torch.cuda.synchronize()
+    same = bool(torch.equal(color_b.view(torch.int32), torch.cat(colors).view(torch.int32)))
+    log(f"batched vs per-image colours identical: {same}; {e_b} samples")
+    del colors, color_b
+
+    runs = max(args.steps // 3, 3)
+    lat_b, lat_p, ms_b, ms_p = [], [], [], []
+    for _ in range(runs):
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        batched()
+        stop.record()
+        torch.cuda.synchronize()
+        t = start.elapsed_time(stop)
+        ms_b.append(t)
+        lat_b += [t] * len(counts)  # every image completes with the batch
+        done = [torch.cuda.Event(enable_timing=True) for _ in counts]
+        start.record()
+        plain(done)
+        torch.cuda.synchronize()
+        lat_p += [start.elapsed_time(ev) for ev in done]
+        ms_p.append(start.elapsed_time(done[-1]))
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    render(rays_o, rays_d, events)
+    torch.cuda.synchronize()
+    names = ("march_count", "march_fill", "field", "render")
+    phase = {nm: events[j].elapsed_time(events[j + 1]) for j, nm in enumerate(names)}
+    n_rays = int(offs[-1])
+    alg = algorithmic_bytes(n_rays, e_b, e_b, forward_only=True)  # upper bound on V
+    achieved = alg["render"] / (phase["render"] * 1e-3)
+    pct = lambda v, q: float(np.percentile(v, q))
+    med_b, med_p = float(np.median(ms_b)), float(np.median(ms_p))
+    return {
+        "metric": METRIC,
+        "value": e_b / (med_b * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": runs,
+        "warmup": 1,
+        "ms_per_step": med_b,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "images": [list(sz) for sz in w.sizes], "rays": n_rays,
+                   "grid": f"{sw.res}^3 bit-packed", "blobs": sw.n_blobs,
+                   "early_stop_eps": eps, "pass": "forward",
+                   "form": "batched call sequence vs one per image",
+                   "skip_field": args.skip_field, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "render", "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": None},
+        "samples_per_batch": e_b,
+        "rays_per_s": n_rays / (med_b * 1e-3),
+        "batched_ms": med_b,
+        "plain_ms": med_p,
+        "batched_over_plain": med_p / med_b,
+        "latency_ms": {"batched": {"p50": pct(lat_b, 50), "p90": pct(lat_b, 90),
+                                   "p99": pct(lat_b, 99)},
+                       "plain": {"p50": pct(lat_p, 50), "p90": pct(lat_p, 90),
+                                 "p99": pct(lat_p, 99)}},
+        "identical_outputs": same,
+        "phase_ms": phase,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -558,6 +721,8 @@ def main():
     import paper_2210_04847_amd as nacc
     if args.workload.startswith("dynamic"):
         result = bench_dynamic(args, torch, nacc)
+    elif args.workload.startswith("images"):
+        result = bench_images(args, torch, nacc)
     else:
         result = bench_train(args, torch, nacc)
     print(json.dumps(result), flush=True)

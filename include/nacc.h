@@ -179,6 +179,17 @@ int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid,
                                   const nacc_march_params* params);
 
 /*
+ * Upper bound of the samples one ray can emit under `grid` and `params`
+ * (the longest possible [t_near, t_far) divided into lattice steps, at most
+ * 2^24, capped by max_per_ray).  n_rays times this bound sizes sample
+ * buffers that no call can overflow, so that a step never has to read the
+ * sample total back to the host.  Returns -1 (and sets the message) for
+ * invalid arguments.
+ */
+int64_t nacc_march_max_samples_per_ray(const nacc_grid_desc* grid,
+                                       const nacc_march_params* params);
+
+/*
  * Marching, pass 1 of 2: count the samples of every ray and lay them out
  * (Sec. 2.1, "GPU Memory Efficiency": empty space is pruned while marching,
  * so only the samples in occupied cells are ever stored).
@@ -188,12 +199,13 @@ int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid,
  *                   (ignored for CASCADE); a ray whose grid id is outside
  *                   [0, n_grids) gets no samples.
  *   grid_bits       uint32[n_grids * res^3 / 32], LSB-first bit order.
- *   grid_mip        the skip grid built from grid_bits by
- *                   nacc_grid_build_mip, or NULL.  It only lets the kernels
- *                   skip candidates that lie in empty cells, so results are
- *                   identical with and without it; it must be rebuilt
- *                   whenever grid_bits changes.  Used for uniform steps
- *                   with the box lookup and res % 4 == 0, ignored otherwise.
+ *   grid_skip       the skip field built from grid_bits by
+ *                   nacc_grid_build_skip, or NULL.  It only lets the kernels
+ *                   pass over candidates that lie in empty cells without
+ *                   looking them up, so results are identical with and
+ *                   without it; it must be rebuilt whenever grid_bits
+ *                   changes.  Used by the box and cascade lookups when
+ *                   res % 4 == 0, ignored otherwise.
  *   packed_info     out int32[n_rays][2]: (start, count) per ray.
  *   total           out int64[1]: the sample total, on the device.
  *   workspace       device scratch of nacc_march_workspace_size bytes;
@@ -204,7 +216,7 @@ int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid,
  */
 int nacc_march_count(const float* rays_o, const float* rays_d,
                      const int32_t* grid_id, int64_t n_rays,
-                     const uint32_t* grid_bits, const uint32_t* grid_mip,
+                     const uint32_t* grid_bits, const uint8_t* grid_skip,
                      const nacc_grid_desc* grid,
                      const nacc_march_params* params, int32_t* packed_info,
                      int64_t* total, void* workspace, size_t workspace_bytes,
@@ -222,7 +234,7 @@ int nacc_march_count(const float* rays_o, const float* rays_d,
  */
 int nacc_march_fill(const float* rays_o, const float* rays_d,
                     const int32_t* grid_id, int64_t n_rays,
-                    const uint32_t* grid_bits, const uint32_t* grid_mip,
+                    const uint32_t* grid_bits, const uint8_t* grid_skip,
                     const nacc_grid_desc* grid,
                     const nacc_march_params* params,
                     const int32_t* packed_info, const void* workspace,
@@ -340,21 +352,28 @@ int nacc_grid_update_max(float* occ, const int32_t* cells,
                          const float* values, int64_t n, int64_t n_cells,
                          void* stream);
 
-/* Words of the skip grid of `grid` (n_grids grids), 0 if res % 4 != 0. */
-int64_t nacc_grid_mip_words(const nacc_grid_desc* grid);
+/* Largest distance the skip field stores (coarse cells). */
+#define NACC_SKIP_CAP 15
+
+/* Bytes of the skip field of `grid` (n_grids grids), 0 if res % 4 != 0:
+ * 2 * n_grids * (res/4)^3 (the field, then scratch for its build). */
+int64_t nacc_grid_skip_bytes(const nacc_grid_desc* grid);
 
 /*
- * Builds the skip grid used by the marching calls to pass over empty space
- * (Sec. 2.1, "Pruning Empty and Occluded Regions"): per grid, h = ceil(
- * (res/4)^3 / 32) words with one bit per coarse cell of 4x4x4 fine cells
- * (C order, LSB first), set iff some occupied fine cell lies in the coarse
- * cell or in one of its 26 neighbours (dilated by one coarse cell), followed
- * by h words of the undilated coarse bits.
- *   bits  uint32[n_grids * res^3 / 32]; mip out uint32[nacc_grid_mip_words].
+ * Builds the skip field the marching calls use to pass over empty space
+ * (Sec. 2.1, "Pruning Empty and Occluded Regions"): per grid, one byte per
+ * coarse cell of 4x4x4 fine cells (C order),
+ *   min(NACC_SKIP_CAP, Chebyshev distance in coarse cells to the nearest
+ *       coarse cell holding an occupied fine cell),
+ * so 0 marks coarse cells with occupied cells.  A point whose coarse cell
+ * has distance D >= 2 has only empty fine cells within 4 (D - 1) fine cells
+ * of it along every axis.  The field is the first n_grids * (res/4)^3 bytes
+ * of `skip`; the rest is scratch of the build.
+ *   bits  uint32[n_grids * res^3 / 32]; skip out uint8[nacc_grid_skip_bytes].
  * NACC_ENOTSUP unless res % 4 == 0.
  */
-int nacc_grid_build_mip(const uint32_t* bits, const nacc_grid_desc* grid,
-                        uint32_t* mip, void* stream);
+int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid,
+                         uint8_t* skip, void* stream);
 
 /* bits: bit c is set iff occ[c] > threshold (strict); n_cells % 32 == 0;
  * bits is uint32[n_cells / 32], LSB first. */

@@ -9,7 +9,9 @@
  *   rgb(x)   = 1 / (1 + exp(-(W x + bias)))          (W row-major 3x3)
  * Sample positions are the FP32 midpoints x = o + d * ((t_start + t_end) * 0.5f)
  * (no fused multiply-add).  Accuracy: a few FP32 ulps of the exponent
- * arguments (relative error of sigma and rgb below 1e-5).
+ * arguments (relative error of sigma and rgb below 1e-5 without contraction;
+ * with it, the FP32 rounding of the contracted point adds about
+ * 1e-6 |d| / std^2 per blob, d the distance to the blob's centre).
  *
  * Conventions as in nacc.h: device pointers, caller-owned memory, stream as
  * void*, status codes, nacc_last_error() for messages.
@@ -27,14 +29,22 @@ extern "C" {
 /* Bytes of the prepared coefficient table for n_sets * n_blobs blobs. */
 int64_t nacc_synth_table_size(int32_t n_blobs, int32_t n_sets);
 
+/* flags of nacc_synth_prepare: the scene is defined in contracted
+ * coordinates, i.e. sigma and rgb are evaluated at y = x for |x| <= 1 and
+ * y = (2 - 1/|x|) x / |x| beyond (FP32, Euclidean norm), as for unbounded
+ * scenes (Sec. 2.1). */
+#define NACC_SYNTH_CONTRACT 1
+
 /*
  * Prepares the coefficient table (device memory of nacc_synth_table_size
  * bytes) from the blob parameters:
  *   centres float[n_sets][n_blobs][3] (one centre set per frame),
- *   stds, peaks float[n_blobs], w float[3][3], bias float[3].
+ *   stds, peaks float[n_blobs], w float[3][3], bias float[3],
+ *   flags 0 or NACC_SYNTH_CONTRACT.
  */
 int nacc_synth_prepare(const float* centres, const float* stds, const float* peaks, const float* w,
-                       const float* bias, int32_t n_blobs, int32_t n_sets, void* table, void* stream);
+                       const float* bias, int32_t n_blobs, int32_t n_sets, int32_t flags, void* table,
+                       void* stream);
 
 /*
  * sigma and rgb at the midpoints of packed samples.

@@ -82,7 +82,7 @@ def _load():
     lib.oracle_sample_positions.argtypes = [_P, _P, _P, _P, _P, _I64, _P]
     lib.oracle_blob_field.restype = None
     lib.oracle_blob_field.argtypes = [_P, _P, _I64, _P, _P, _P, _I32, _P, _P,
-                                      _P, _P]
+                                      _I32, _P, _P]
     _lib = lib
     return lib
 
@@ -283,7 +283,8 @@ def sample_positions(rays_o, rays_d, ray_indices, t_starts, t_ends):
 
 
 def blob_field(scene, positions, blob_set=None, want_rgb=True):
-    """FP64 density (and colour) of a synth.BlobScene at FP32 positions."""
+    """FP64 density (and colour) of a synth.BlobScene at FP32 positions
+    (a scene with `contract` set is defined in contracted coordinates)."""
     lib = _load()
     pos = _c(positions, np.float32).reshape(-1, 3)
     n = pos.shape[0]
@@ -297,5 +298,6 @@ def blob_field(scene, positions, blob_set=None, want_rgb=True):
     rgb = np.zeros((n, 3)) if want_rgb else None
     lib.oracle_blob_field(_ptr(pos), _ptr(bs), n, _ptr(cen), _ptr(std),
                           _ptr(pk), scene.n_blobs, _ptr(w), _ptr(b),
+                          int(bool(getattr(scene, "contract", False))),
                           _ptr(sigma), _ptr(rgb))
     return (sigma, rgb) if want_rgb else sigma

@@ -470,9 +470,20 @@ void oracle_sample_positions(const float* rays_o, const float* rays_d,
 void oracle_blob_field(const float* positions, const int32_t* blob_set,
                        int64_t n, const float* centres, const float* stds,
                        const float* peaks, int32_t n_blobs, const float* w,
-                       const float* bias, double* sigma, double* rgb) {
+                       const float* bias, int32_t contract, double* sigma,
+                       double* rgb) {
     for (int64_t q = 0; q < n; ++q) {
         double x[3] = {positions[3 * q], positions[3 * q + 1], positions[3 * q + 2]};
+        if (contract) {
+            /* scene defined in contracted coordinates (Sec. 2.1, unbounded
+             * scenes): points beyond the unit ball are pulled inside the
+             * radius-2 ball, the norm mapping to 2 - 1/norm */
+            double nrm = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            if (nrm > 1.0) {
+                double f = (2.0 - 1.0 / nrm) / nrm;
+                for (int i = 0; i < 3; ++i) x[i] *= f;
+            }
+        }
         const float* cset = centres + (blob_set != NULL ? (int64_t)blob_set[q] * n_blobs * 3 : 0);
         double acc = 0.0;
         for (int32_t b = 0; b < n_blobs; ++b) {

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "nacc_last_error": (ctypes.c_char_p, []),
     "nacc_status_str": (ctypes.c_char_p, [_INT]),
     "nacc_march_workspace_size": (_I64, [_I64, ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams)]),
+    "nacc_march_max_samples_per_ray": (_I64, [ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams)]),
     "nacc_march_count": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
                                 ctypes.POINTER(MarchParams), _P, _P, _P, _SZ, _P]),
     "nacc_march_fill": (_INT, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(GridDesc),
@@ -74,10 +75,10 @@ _SIGNATURES = {
                                       _P, _P, _P]),
     "nacc_grid_update_max": (_INT, [_P, _P, _P, _I64, _I64, _P]),
     "nacc_grid_pack": (_INT, [_P, _I64, _F, _P, _P]),
-    "nacc_grid_mip_words": (_I64, [ctypes.POINTER(GridDesc)]),
-    "nacc_grid_build_mip": (_INT, [_P, ctypes.POINTER(GridDesc), _P, _P]),
+    "nacc_grid_skip_bytes": (_I64, [ctypes.POINTER(GridDesc)]),
+    "nacc_grid_build_skip": (_INT, [_P, ctypes.POINTER(GridDesc), _P, _P]),
     "nacc_synth_table_size": (_I64, [_I32, _I32]),
-    "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _P, _P]),
+    "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
                                         _P, _P, _P, _P]),
     "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P]),
@@ -184,12 +185,20 @@ def march_workspace_size(n_rays: int, desc, params) -> int:
     return n
 
 
+def march_max_samples_per_ray(desc, params) -> int:
+    n = int(lib.nacc_march_max_samples_per_ray(ctypes.byref(desc), ctypes.byref(params)))
+    if n < 0:
+        raise NaccError("nacc_march_max_samples_per_ray", NACC_EINVAL,
+                        lib.nacc_last_error().decode())
+    return n
+
+
 def _grid_words(desc):
     return desc.n_grids * desc.res ** 3 // 32
 
 
 def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, total,
-                workspace, grid_mip=None, stream=None):
+                workspace, grid_skip=None, stream=None):
     n = rays_o.shape[0]
     _need(rays_o, torch.float32, "rays_o", 3 * n)
     _need(rays_d, torch.float32, "rays_d", 3 * n)
@@ -198,16 +207,16 @@ def march_count(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, t
     _need(packed_info, torch.int32, "packed_info", 2 * n)
     _need(total, torch.int64, "total", 1)
     _need(workspace, torch.uint8, "workspace")
-    _need(grid_mip, torch.int32, "grid_mip", grid_mip_words(desc))
+    _need(grid_skip, torch.uint8, "grid_skip", grid_skip_bytes(desc))
     _check("nacc_march_count", lib.nacc_march_count(
-        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_mip),
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_skip),
         ctypes.byref(desc),
         ctypes.byref(params), _ptr(packed_info), _ptr(total), _ptr(workspace),
         workspace.numel() if workspace is not None else 0, _stream(stream)))
 
 
 def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ray_indices,
-               t_starts, t_ends, status=None, grid_mip=None, workspace=None, stream=None):
+               t_starts, t_ends, status=None, grid_skip=None, workspace=None, stream=None):
     n = rays_o.shape[0]
     cap = ray_indices.numel()
     _need(rays_o, torch.float32, "rays_o", 3 * n)
@@ -219,10 +228,10 @@ def march_fill(rays_o, rays_d, grid_id, grid_bits, desc, params, packed_info, ra
     _need(t_starts, torch.float32, "t_starts", cap)
     _need(t_ends, torch.float32, "t_ends", cap)
     _need(status, torch.int32, "status", 1)
-    _need(grid_mip, torch.int32, "grid_mip", grid_mip_words(desc))
+    _need(grid_skip, torch.uint8, "grid_skip", grid_skip_bytes(desc))
     _need(workspace, torch.uint8, "workspace")
     _check("nacc_march_fill", lib.nacc_march_fill(
-        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_mip),
+        _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n, _ptr(grid_bits), _ptr(grid_skip),
         ctypes.byref(desc), ctypes.byref(params), _ptr(packed_info), _ptr(workspace),
         workspace.numel() if workspace is not None else 0, cap, _ptr(ray_indices),
         _ptr(t_starts), _ptr(t_ends), _ptr(status), _stream(stream)))
@@ -317,15 +326,15 @@ def grid_update_max(occ, cells, values, stream=None):
         _ptr(occ), _ptr(cells), _ptr(values), n, occ.numel(), _stream(stream)))
 
 
-def grid_mip_words(desc) -> int:
-    return int(lib.nacc_grid_mip_words(ctypes.byref(desc)))
+def grid_skip_bytes(desc) -> int:
+    return int(lib.nacc_grid_skip_bytes(ctypes.byref(desc)))
 
 
-def grid_build_mip(bits, desc, mip, stream=None):
+def grid_build_skip(bits, desc, skip, stream=None):
     _need(bits, torch.int32, "bits", _grid_words(desc))
-    _need(mip, torch.int32, "mip", grid_mip_words(desc))
-    _check("nacc_grid_build_mip", lib.nacc_grid_build_mip(_ptr(bits), ctypes.byref(desc), _ptr(mip),
-                                                          _stream(stream)))
+    _need(skip, torch.uint8, "skip", grid_skip_bytes(desc))
+    _check("nacc_grid_build_skip", lib.nacc_grid_build_skip(_ptr(bits), ctypes.byref(desc), _ptr(skip),
+                                                             _stream(stream)))
 
 
 def grid_pack(occ, threshold, bits, stream=None):
@@ -339,14 +348,17 @@ def synth_table_size(n_blobs, n_sets) -> int:
     return int(lib.nacc_synth_table_size(n_blobs, n_sets))
 
 
-def synth_prepare(centres, stds, peaks, w, bias, table, stream=None):
+SYNTH_CONTRACT = 1
+
+
+def synth_prepare(centres, stds, peaks, w, bias, table, flags=0, stream=None):
     n_sets, n_blobs = centres.shape[0], centres.shape[1]
     for t, nm in ((centres, "centres"), (stds, "stds"), (peaks, "peaks"), (w, "w"), (bias, "bias"),
                   (table, "table")):
         _need(t, torch.float32, nm)
     _check("nacc_synth_prepare", lib.nacc_synth_prepare(
         _ptr(centres), _ptr(stds), _ptr(peaks), _ptr(w), _ptr(bias), n_blobs, n_sets,
-        _ptr(table), _stream(stream)))
+        int(flags), _ptr(table), _stream(stream)))
 
 
 def synth_field_samples(table, n_blobs, n_sets, rays_o, rays_d, ray_set, ray_indices, t_starts,

@@ -49,15 +49,16 @@ class OccupancyGrid:
         self.bits = torch.zeros(self.cells // 32, dtype=torch.int32, device=dev)
         self.desc = _lib.grid_desc(self.box[:3], self.box[3:], self.res, self.n_grids,
                                    self.lookup)
-        # skip grid for passing over empty space (box lookup, res % 4 == 0)
-        mw = _lib.grid_mip_words(self.desc) if self.lookup == _lib.LOOKUP_AABB else 0
-        self.mip = torch.zeros(mw, dtype=torch.int32, device=dev) if mw > 0 else None
+        # skip field for passing over empty space (box and cascade lookups,
+        # res % 4 == 0)
+        sb = _lib.grid_skip_bytes(self.desc) if self.lookup != _lib.LOOKUP_CONTRACT else 0
+        self.skip = torch.zeros(sb, dtype=torch.uint8, device=dev) if sb > 0 else None
         self.updates = 0
 
     def _repack(self, threshold):
         _lib.grid_pack(self.occ, threshold, self.bits)
-        if self.mip is not None:
-            _lib.grid_build_mip(self.bits, self.desc, self.mip)
+        if self.skip is not None:
+            _lib.grid_build_skip(self.bits, self.desc, self.skip)
 
     def set_occupancy(self, occ, threshold=0.01):
         """Replaces the density state and repacks the bits (occ > threshold)."""
@@ -95,8 +96,8 @@ class OccupancyGrid:
     def load_state_dict(self, state):
         self.occ.copy_(state["occ"])
         self.bits.copy_(state["bits"])
-        if self.mip is not None:
-            _lib.grid_build_mip(self.bits, self.desc, self.mip)
+        if self.skip is not None:
+            _lib.grid_build_skip(self.bits, self.desc, self.skip)
         self.updates = int(state["updates"])
 
 
@@ -120,8 +121,8 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
     ws = torch.empty(max(_lib.march_workspace_size(n, grid.desc, params), 1), dtype=torch.uint8,
                      device=dev)
     gid = None if grid_id is None else grid_id.to(torch.int32).contiguous()
-    mip = grid.mip if skip_empty else None
-    _lib.march_count(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, total, ws, mip)
+    skip = grid.skip if skip_empty else None
+    _lib.march_count(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, total, ws, skip)
     e = int(total.item())
     if e > 2 ** 31 - 1:
         raise _lib.NaccError("ray_marching", _lib.NACC_ECAPACITY,
@@ -130,7 +131,7 @@ def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=
     t_starts = torch.empty(e, dtype=torch.float32, device=dev)
     t_ends = torch.empty(e, dtype=torch.float32, device=dev)
     _lib.march_fill(rays_o, rays_d, gid, grid.bits, grid.desc, params, packed, ray_indices,
-                    t_starts, t_ends, None, mip, ws if replay_masks else None)
+                    t_starts, t_ends, None, skip, ws if replay_masks else None)
     return packed, ray_indices, t_starts, t_ends
 
 
@@ -219,8 +220,10 @@ class BlobField:
         t = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(dev)
         self.table = torch.empty(_lib.synth_table_size(self.n_blobs, self.n_sets) // 4,
                                  dtype=torch.float32, device=dev)
+        self.contract = bool(getattr(scene, "contract", False))
         _lib.synth_prepare(t(scene.centres), t(scene.stds), t(scene.peaks), t(scene.w),
-                           t(scene.bias), self.table)
+                           t(scene.bias), self.table,
+                           _lib.SYNTH_CONTRACT if self.contract else 0)
 
     def samples(self, rays_o, rays_d, ray_indices, t_starts, t_ends, ray_set=None,
                 n_samples_dev=None, sigmas=None, rgbs=None):

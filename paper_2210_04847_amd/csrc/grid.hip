@@ -125,61 +125,56 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(const float* __restrict_
     if (lane == 32 && word + 1 < n_cells / 32) bits[word + 1] = static_cast<uint32_t>(m >> 32);
 }
 
-// Skip grid, per grid: `half` words of dilated bits, then `half` words of
-// plain coarse bits (the first pass's output), half = ceil((res/4)^3 / 32).
-// One lane per coarse cell; a wave's ballot is two whole words of one grid.
-//   pass 1: coarse bit = OR of its 4x4x4 fine cells (16 row reads, the 4
-//           bits of a row lie in one word);
-//   pass 2: dilated bit = OR of the coarse bits of the cell and its 26
-//           neighbours.
-template <bool DILATE>
-__global__ __launch_bounds__(kThreads) void mip_kernel(const uint32_t* __restrict__ bits, int res, int n_grids,
-                                                       uint32_t words, uint32_t half, uint32_t* __restrict__ mip) {
+// Skip field, per grid: one byte per coarse cell of 4x4x4 fine cells (C
+// order), min(NACC_SKIP_CAP, Chebyshev distance in coarse cells to the
+// nearest coarse cell that holds an occupied fine cell).  The L-infinity
+// distance separates over the axes,
+//   dist(a,b,c) = min_da max(|da|, min_db max(|db|, min_dc max(|dc|, e))),
+// e = 0 at occupied coarse cells and the cap elsewhere, so it is built by a
+// coarse-occupancy pass and one windowed pass per axis (window +-cap).
+
+// Coarse occupancy: one lane per coarse cell, 16 fine-row reads (the 4 bits
+// of a row lie in one word since 4 | res).
+__global__ __launch_bounds__(kThreads) void coarse_kernel(const uint32_t* __restrict__ bits, int res, int n_grids,
+                                                          uint32_t words, uint8_t* __restrict__ out) {
     const int c = res / 4;
     const int64_t per_grid = static_cast<int64_t>(c) * c * c;
-    const int64_t slots = static_cast<int64_t>(half) * 32;  // bit slots per grid
     const int64_t id = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    const bool in_range = id < slots * n_grids;
-    const int grid = in_range ? static_cast<int>(id / slots) : 0;
-    const int64_t cell = in_range ? id % slots : per_grid;
-    bool any = false;
-    if (cell < per_grid) {
-        const int cx = static_cast<int>(cell / (static_cast<int64_t>(c) * c));
-        const int cy = static_cast<int>((cell / c) % c);
-        const int cz = static_cast<int>(cell % c);
-        if (!DILATE) {
-            const uint32_t* fine = bits + static_cast<int64_t>(grid) * words;
-            for (int x = 4 * cx; x < 4 * cx + 4 && !any; ++x) {
-                for (int y = 4 * cy; y < 4 * cy + 4; ++y) {
-                    const int64_t b = (static_cast<int64_t>(x) * res + y) * res + 4 * cz;
-                    if ((fine[b >> 5] >> (b & 31)) & 0xFu) {
-                        any = true;
-                        break;
-                    }
-                }
-            }
-        } else {
-            const uint32_t* plain = mip + static_cast<int64_t>(grid) * 2 * half + half;
-            for (int x = max(cx - 1, 0); x <= min(cx + 1, c - 1) && !any; ++x) {
-                for (int y = max(cy - 1, 0); y <= min(cy + 1, c - 1) && !any; ++y) {
-                    for (int z = max(cz - 1, 0); z <= min(cz + 1, c - 1); ++z) {
-                        const int64_t q = (static_cast<int64_t>(x) * c + y) * c + z;
-                        if ((plain[q >> 5] >> (q & 31)) & 1u) {
-                            any = true;
-                            break;
-                        }
-                    }
-                }
-            }
+    if (id >= per_grid * n_grids) return;
+    const int grid = static_cast<int>(id / per_grid);
+    const int64_t cell = id % per_grid;
+    const int cx = static_cast<int>(cell / (static_cast<int64_t>(c) * c));
+    const int cy = static_cast<int>((cell / c) % c);
+    const int cz = static_cast<int>(cell % c);
+    const uint32_t* fine = bits + static_cast<int64_t>(grid) * words;
+    uint32_t any = 0u;
+    for (int x = 4 * cx; x < 4 * cx + 4; ++x) {
+        for (int y = 4 * cy; y < 4 * cy + 4; ++y) {
+            const int64_t b = (static_cast<int64_t>(x) * res + y) * res + 4 * cz;
+            any |= (fine[b >> 5] >> (b & 31)) & 0xFu;
         }
     }
-    const uint64_t m = ballot(any);
-    const int lane = lane_id();
-    if (in_range && (lane == 0 || lane == 32)) {
-        const int64_t word = (id % slots) >> 5;
-        uint32_t* out = mip + static_cast<int64_t>(grid) * 2 * half + (DILATE ? 0 : half);
-        out[word] = static_cast<uint32_t>(lane == 0 ? m : m >> 32);
+    out[id] = any != 0u ? 0 : NACC_SKIP_CAP;
+}
+
+// One axis of the distance: out = min over |t| <= cap of max(|t|, in[cell + t
+// along the axis]), inside the grid.  stride: cells between neighbours along
+// the axis (c^2, c or 1).
+__global__ __launch_bounds__(kThreads) void distance_pass_kernel(const uint8_t* __restrict__ in, int c,
+                                                                 int64_t n_cells, int64_t stride,
+                                                                 uint8_t* __restrict__ out) {
+    const int64_t id = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (id >= n_cells) return;
+    const int pos = static_cast<int>((id / stride) % c);
+    int best = in[id];
+    for (int t = 1; t <= NACC_SKIP_CAP && t < best; ++t) {
+        const int lo = pos - t, hi = pos + t;
+        int v = NACC_SKIP_CAP;
+        if (lo >= 0) v = min(v, static_cast<int>(in[id - t * stride]));
+        if (hi < c) v = min(v, static_cast<int>(in[id + t * stride]));
+        best = min(best, max(t, v));
     }
+    out[id] = static_cast<uint8_t>(best);
 }
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
@@ -241,31 +236,43 @@ int nacc_grid_update_max(float* occ, const int32_t* cells, const float* values, 
     return check_launch("grid update max");
 }
 
-int64_t nacc_grid_mip_words(const nacc_grid_desc* grid) {
+int64_t nacc_grid_skip_bytes(const nacc_grid_desc* grid) {
     if (grid == nullptr || grid->res < 4 || grid->res % 4 != 0 || grid->n_grids < 1) return 0;
     const int64_t c = grid->res / 4;
-    return 2 * ((c * c * c + 31) / 32) * grid->n_grids;
+    return 2 * c * c * c * grid->n_grids;
 }
 
-int nacc_grid_build_mip(const uint32_t* bits, const nacc_grid_desc* grid, uint32_t* mip, void* stream) {
+int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid, uint8_t* skip, void* stream) {
     clear_error();
     NACC_REQUIRE(grid != nullptr, NACC_EINVAL, "grid must be non-NULL");
     NACC_REQUIRE(grid->res >= 4 && grid->res <= 1024 && grid->res % 4 == 0, NACC_ENOTSUP,
-                 "the skip grid needs res %% 4 == 0 (res = %d)", grid->res);
+                 "the skip field needs res %% 4 == 0 (res = %d)", grid->res);
     NACC_REQUIRE(grid->n_grids >= 1, NACC_EINVAL, "n_grids = %d < 1", grid->n_grids);
     const int64_t cells = static_cast<int64_t>(grid->res) * grid->res * grid->res;
     NACC_REQUIRE(cells % 32 == 0, NACC_ESHAPE, "res^3 is not a multiple of 32");
-    NACC_REQUIRE(bits != nullptr && mip != nullptr, NACC_EINVAL, "bits and mip must be non-NULL");
-    const uint32_t half = static_cast<uint32_t>(nacc_grid_mip_words(grid) / (2 * grid->n_grids));
-    const int64_t threads = static_cast<int64_t>(half) * 32 * grid->n_grids;
+    NACC_REQUIRE(bits != nullptr && skip != nullptr, NACC_EINVAL, "bits and skip must be non-NULL");
+    const int c = grid->res / 4;
+    const int64_t n = static_cast<int64_t>(c) * c * c * grid->n_grids;
+    uint8_t* field = skip;
+    uint8_t* scratch = skip + n;
     hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(mip_kernel<false>, dim3(blocks_for(threads)), dim3(kThreads), 0, s, bits, grid->res,
-                       grid->n_grids, static_cast<uint32_t>(cells / 32), half, mip);
-    int st = check_launch("grid mip");
+    hipLaunchKernelGGL(coarse_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, bits, grid->res, grid->n_grids,
+                       static_cast<uint32_t>(cells / 32), scratch);
+    int st = check_launch("grid skip coarse");
     if (st != NACC_OK) return st;
-    hipLaunchKernelGGL(mip_kernel<true>, dim3(blocks_for(threads)), dim3(kThreads), 0, s, bits, grid->res,
-                       grid->n_grids, static_cast<uint32_t>(cells / 32), half, mip);
-    return check_launch("grid mip dilate");
+    const int64_t strides[3] = {1, c, static_cast<int64_t>(c) * c};
+    uint8_t* src = scratch;
+    uint8_t* dst = field;
+    for (int axis = 0; axis < 3; ++axis) {  // z, y, x: the third pass lands in `field`
+        hipLaunchKernelGGL(distance_pass_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, src, c, n,
+                           strides[axis], dst);
+        st = check_launch("grid skip distance");
+        if (st != NACC_OK) return st;
+        uint8_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    return NACC_OK;
 }
 
 int nacc_grid_pack(const float* occ, int64_t n_cells, float threshold, uint32_t* bits, void* stream) {

@@ -18,6 +18,13 @@
 //
 // Cone steps: the lattice is a recurrence in t, so one lane walks one ray.
 //
+// Empty space: with a skip field (nacc_grid_build_skip), a test at one
+// candidate's midpoint gives a stretch of t ahead in which every candidate
+// midpoint is sure to fall in empty cells of the same grid level; those
+// candidates are passed over without grid lookups.  The bound allows for
+// the FP32 rounding of positions, so the sample set is exactly the one of
+// the plain traversal.
+//
 // All lattice arithmetic follows the FP32 contract in nacc.h: this file is
 // compiled with -ffp-contract=off and `fp contract(off)`, and uses only
 // correctly rounded + - * / sqrt, min/max, ldexp and float->int truncation of
@@ -40,12 +47,13 @@ struct GridK {
     float lo[3];
     float s[3];        // fl32(res / (hi - lo))
     float top;         // (float)(res - 1)
-    float base;        // cascade: half-extent of level 0
+    float base;        // cascade: half-extent of level 0 (a power of two)
+    float inv_base;    // 1 / base (exact)
     int res;
     int n_grids;
     uint32_t words;    // 32-bit words per grid
-    int coarse;        // coarse cells per axis of the skip grid (res / 4)
-    uint32_t mip_words;  // 32-bit words per grid of the skip grid (dilated half first)
+    int coarse;          // coarse cells per axis of the skip field (res / 4)
+    uint32_t skip_cells;  // bytes per grid of the skip field (coarse^3)
 };
 
 struct ClipK {
@@ -80,21 +88,46 @@ __device__ __forceinline__ bool clip_ray(const float o[3], const float d[3], con
     return !miss && t_near < t_far;
 }
 
-// Occupancy bit of point x.  `word0` is the first word of the ray's grid
-// (box / contraction lookups); the cascade picks its level itself.
+// Cascade level of a point with m = max_i |x_i|: the number of levels
+// l < n_grids - 1 with m > base 2^l, i.e. the smallest l with m <= base 2^l,
+// clamped to the last level.  q = m / base is exact (base is a power of
+// two), and the smallest l with q <= 2^l is read off q's exponent and
+// mantissa: q = 1.f 2^(e-127) gives e - 127, plus one unless f = 0.  Zero,
+// subnormal and NaN m give level 0, as the comparisons do.
+__device__ __forceinline__ int cascade_level(float m, const GridK& g) {
+    const uint32_t b = __float_as_uint(m * g.inv_base);
+    const int e = static_cast<int>(b >> 23);
+    int level = e - 127 + ((b & 0x7fffffu) != 0u ? 1 : 0);
+    if (e == 0 || !(m == m)) level = 0;
+    return min(max(level, 0), g.n_grids - 1);
+}
+
+// Where point x is looked up: the grid word and bit of its fine cell, the
+// byte of its coarse cell in the skip field, and (cascade) its level and
+// m = max_i |x_i|.  `word0` is the first word of the ray's grid (box /
+// contraction lookups); the cascade picks its level itself.
+struct Probe {
+    uint32_t word;
+    uint32_t bit;
+    uint32_t coarse;
+    int level;
+    float m;
+};
+
 template <int LOOKUP>
-__device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint32_t word0,
-                                         const GridK& g, float x0, float x1, float x2) {
+__device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0, float x1, float x2) {
+    Probe q;
+    q.level = 0;
+    q.m = 0.0f;
+    uint32_t grid = word0 / g.words;
     if (LOOKUP == NACC_LOOKUP_CASCADE) {
-        // level = number of level boxes the point lies outside of, i.e. the
-        // smallest l with max|x_i| <= b 2^l, clamped to the last level.
-        float m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
-        int level = 0;
-        for (int l = 0; l < g.n_grids - 1; ++l) level += (m > ldexpf(g.base, l)) ? 1 : 0;
-        x0 = ldexpf(x0, -level);
-        x1 = ldexpf(x1, -level);
-        x2 = ldexpf(x2, -level);
-        word0 = static_cast<uint32_t>(level) * g.words;
+        q.m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
+        q.level = cascade_level(q.m, g);
+        x0 = ldexpf(x0, -q.level);
+        x1 = ldexpf(x1, -q.level);
+        x2 = ldexpf(x2, -q.level);
+        grid = static_cast<uint32_t>(q.level);
+        word0 = grid * g.words;
     } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
         float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
         if (n > 1.0f) {
@@ -104,56 +137,93 @@ __device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint
             x2 = x2 * f;
         }
     }
-    float u0 = fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top);
-    float u1 = fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top);
-    float u2 = fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top);
-    uint32_t res = static_cast<uint32_t>(g.res);
-    uint32_t cell = (static_cast<uint32_t>(static_cast<int>(u0)) * res +
-                     static_cast<uint32_t>(static_cast<int>(u1))) * res +
-                    static_cast<uint32_t>(static_cast<int>(u2));
-    uint32_t word = bits[word0 + (cell >> 5)];
-    return ((word >> (cell & 31u)) & 1u) != 0u;
+    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top)));
+    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top)));
+    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top)));
+    const uint32_t res = static_cast<uint32_t>(g.res);
+    const uint32_t cell = (j0 * res + j1) * res + j2;
+    q.word = word0 + (cell >> 5);
+    q.bit = cell & 31u;
+    const uint32_t cc = static_cast<uint32_t>(g.coarse);
+    q.coarse = grid * g.skip_cells + ((j0 >> 2) * cc + (j1 >> 2)) * cc + (j2 >> 2);
+    return q;
 }
 
-// Fine cell indices (j_0, j_1, j_2) of point x under the box lookup.
-__device__ __forceinline__ void cell_indices(const GridK& g, float x0, float x1, float x2, uint32_t& j0, uint32_t& j1,
-                                             uint32_t& j2) {
-    j0 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top)));
-    j1 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top)));
-    j2 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top)));
+// Occupancy bit of point x.
+template <int LOOKUP>
+__device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint32_t word0,
+                                         const GridK& g, float x0, float x1, float x2) {
+    const Probe q = probe<LOOKUP>(g, word0, x0, x1, x2);
+    return ((bits[q.word] >> q.bit) & 1u) != 0u;
 }
 
-// Bit of the dilated skip grid at the coarse cell holding fine cell j: it is
-// clear only if every fine cell within one coarse cell (4 fine cells) of
-// it, in every direction, is empty.
-__device__ __forceinline__ bool skip_bit(const uint32_t* __restrict__ mip, uint32_t mip0, const GridK& g,
-                                         uint32_t j0, uint32_t j1, uint32_t j2) {
-    const uint32_t c = static_cast<uint32_t>(g.coarse);
-    const uint32_t cell = ((j0 >> 2) * c + (j1 >> 2)) * c + (j2 >> 2);
-    return ((mip[mip0 + (cell >> 5)] >> (cell & 31u)) & 1u) != 0u;
+// Per-ray constants of the skip-field test.
+//   slack_x: allowance for the FP32 rounding of sample positions: two
+//            positions of the ray differ by at most |d_i| |tm_k - tm_0| plus
+//            slack_x on every axis (a few ulps of the largest coordinate the
+//            ray reaches, taken generously);
+//   inv_v:   1 / (fine cells per unit t on the fastest axis, at level 0);
+//   inv_dmax: 1 / max_i |d_i|.
+struct SkipRay {
+    float slack_x;
+    float slack_s;  // slack_x in fine cells at level 0
+    float inv_v;
+    float inv_dmax;
+};
+
+__device__ __forceinline__ SkipRay skip_ray(const GridK& g, const float o[3], const float d[3], float t_far) {
+    SkipRay k;
+    const float omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
+    const float dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+    k.slack_x = (omax + dmax * fabsf(t_far) + 1.0f) * 0x1p-20f;
+    const float smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
+    k.slack_s = smax * k.slack_x;
+    k.inv_v = 1.0f / fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
+    k.inv_dmax = 1.0f / dmax;
+    return k;
 }
 
-// Largest group size G in {64, 32, 16, 8} such that the midpoints of any
-// two candidates at most G/2 steps apart fall in fine cells at most 4 apart
-// on every axis (bound on |u_k - u_t| below 3.9, with a generous allowance
-// for FP32 rounding of t, x and u), so that one test point per group plus
-// the one-coarse-cell dilation covers every candidate of the group.
-// 0: no grouping for this ray.
-__device__ __forceinline__ int group_size(const GridK& g, const float o[3], const float d[3], float t_near,
-                                          float t_far, float dt) {
-    const float tmax = fmaxf(fabsf(t_near), fabsf(t_far));
-    float slope = 0.0f, slack = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float sd = g.s[i] * fabsf(d[i]);
-        slope = fmaxf(slope, sd * dt);
-        slack = fmaxf(slack, g.s[i] * (fabsf(o[i]) + fabsf(g.lo[i]) + 2.0f * fabsf(d[i]) * tmax));
+// End (in t) of the stretch past the candidate midpoint tm over which every
+// candidate midpoint of the ray falls in an empty fine cell, from the skip
+// byte `dist` of tm's coarse cell (probe q); -inf if there is none.  The
+// byte bounds the stretch at 4 (dist - 1) fine cells on every axis of q's
+// grid level; a cascade stretch also ends before the point could change
+// level.  Rounding margins keep the bound strict.
+template <int LOOKUP>
+__device__ __forceinline__ float skip_end_at(const GridK& g, const SkipRay& k, const Probe& q, int dist, float tm) {
+    // fine cells at level l are 2^l times larger: the slack in fine cells
+    // shrinks and the stretch in t grows by 2^l
+    const float budget =
+        4.0f * static_cast<float>(dist - 1) - (ldexpf(k.slack_s, -q.level) + static_cast<float>(g.res) * 0x1p-18f);
+    float span = ldexpf(budget * k.inv_v, q.level);
+    if (LOOKUP == NACC_LOOKUP_CASCADE) {
+        float room = INFINITY;
+        if (q.level < g.n_grids - 1) room = fminf(room, ldexpf(g.base, q.level) - q.m);
+        if (q.level > 0) room = fminf(room, q.m - ldexpf(g.base, q.level - 1));
+        span = fminf(span, (room - k.slack_x) * k.inv_dmax);
     }
-    slack = (slack + static_cast<float>(g.res)) * 0x1p-16f;
-    for (int G = 64; G >= 8; G >>= 1) {
-        if (slope * static_cast<float>(G / 2) + slack <= 3.9f) return G;
-    }
-    return 0;
+    span = span * (1.0f - 0x1p-10f) - fabsf(tm) * 0x1p-21f;
+    return (dist >= 2 && span > 0.0f) ? tm + span : -INFINITY;
+}
+
+// DPP move that leaves a lane's own value where the source lane is out of
+// range or its row is masked off (the identity for max).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_or_self(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, ROW_MASK, 0xf, false));
+}
+
+// Maximum over the 64 lanes (every lane active): prefix maxima within each
+// row of 16 lanes, then the row maxima carried by two row broadcasts.
+__device__ __forceinline__ float wave_max(float x) {
+    x = fmaxf(x, dpp_or_self<kRowShr1>(x));
+    x = fmaxf(x, dpp_or_self<kRowShr2>(x));
+    x = fmaxf(x, dpp_or_self<kRowShr4>(x));
+    x = fmaxf(x, dpp_or_self<kRowShr8>(x));
+    x = fmaxf(x, dpp_or_self<kRowBcast15, 0xa>(x));
+    x = fmaxf(x, dpp_or_self<kRowBcast31, 0xc>(x));
+    return read_lane(x, kWave - 1);
 }
 
 // First word of the ray's grid, or false for an invalid grid id (the ray is
@@ -172,18 +242,13 @@ __device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id,
 
 // One ray, uniform steps, whole wave.  Returns the ray's sample count (the
 // same value in every lane).  FILL writes samples [0, limit) at `start`.
-//
-// With a skip grid (MIP, box lookup only), candidates are grouped G at a
-// time; one test point per group (its middle candidate, computed with the
-// same contract formulae) is looked up in the dilated skip grid, 64 groups
-// per wave.  A chunk of 64 candidates whose groups are all clear is skipped
-// without touching its candidates, and lanes in clear groups skip their
-// fine lookup: their cells are empty by construction, so the sample set is
-// exactly the one of the plain traversal.
-template <int LOOKUP, bool FILL, bool MIP>
+// With SKIP, candidates inside a stretch the skip field clears are not
+// looked up; a chunk of 64 candidates that lies wholly inside one is passed
+// over at the cost of its lattice arithmetic.
+template <int LOOKUP, bool FILL, bool SKIP>
 __device__ __forceinline__ int march_ray_uniform(
     int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ mip,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
     const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     bool& overflow, uint64_t* __restrict__ masks = nullptr, int n_masks = 0, int first_chunk = 0,
@@ -199,55 +264,35 @@ __device__ __forceinline__ int march_ray_uniform(
     if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
     float t_near, t_far;
     if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
-    const uint32_t mip0 = MIP ? (word0 / g.words) * g.mip_words : 0u;
-    int G = MIP ? uniform<int>(group_size(g, o, d, t_near, t_far, p.dt)) : 0;
-    uint64_t live_groups = ~0ull;  // groups [window * 64, window * 64 + 64) as bits
-    uint64_t live_chunks = ~0ull;  // chunks of the window as bits
-    int window_chunk = -(1 << 30);  // first chunk of the current window
-    uint64_t my_mask = 0ull;        // count pass: lane j keeps the ballot of chunk j
+    SkipRay sk{};
+    if (SKIP) sk = skip_ray(g, o, d, t_far);
+    float skip_end = -INFINITY;  // candidates with midpoint below it are empty
+    uint64_t my_mask = 0ull;     // count pass: lane j keeps the ballot of chunk j
     int count = count0;
     for (int k0 = first_chunk * kWave; k0 < kMaxCandidates; k0 += kWave) {
         const int chunk = k0 / kWave;
-        bool lane_live = true;
-        if (MIP && G > 0) {
-            if (chunk >= window_chunk + G && k0 + kWave * G > kMaxCandidates) {
-                // test points past 2^24 would not be exact lattice points:
-                // plain traversal from here on
-                G = 0;
-            }
-        }
-        if (MIP && G > 0) {
-            if (chunk >= window_chunk + G) {
-                // new window: 64 groups of G candidates = G chunks
-                window_chunk = chunk;
-                const int kt = k0 + lane * G + G / 2;
-                const float a0 = t_near + static_cast<float>(kt) * p.dt;
-                const float a1 = t_near + static_cast<float>(kt + 1) * p.dt;
-                const float am = (a0 + a1) * 0.5f;
-                uint32_t j0, j1, j2;
-                cell_indices(g, o[0] + d[0] * am, o[1] + d[1] * am, o[2] + d[2] * am, j0, j1, j2);
-                live_groups = ballot(skip_bit(mip, mip0, g, j0, j1, j2));
-                const int per_chunk = kWave / G;  // groups per chunk: 1, 2, 4 or 8
-                const uint64_t group_mask = (1ull << per_chunk) - 1ull;
-                live_chunks = ballot(lane < G && ((live_groups >> (lane * per_chunk)) & group_mask) != 0ull);
-            }
-            const int rel = chunk - window_chunk;
-            if (((live_chunks >> rel) & 1ull) == 0ull) {
-                // every candidate of this chunk lies in empty cells
-                if (!(t_near + static_cast<float>(k0) * p.dt < t_far)) break;
-                continue;
-            }
-            lane_live = ((live_groups >> ((rel * kWave + lane) / G)) & 1ull) != 0ull;
-        }
         const int k = k0 + lane;
         const float t0 = t_near + static_cast<float>(k) * p.dt;
         const bool live = t0 < t_far;
         if (ballot(live) == 0) break;  // t_k is non-decreasing in k
         const float t1 = t_near + static_cast<float>(k + 1) * p.dt;
         const float tm = (t0 + t1) * 0.5f;
+        const bool todo = live && !(tm < skip_end);
         bool hit = false;
-        if (live && lane_live) {
-            hit = occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+        if (ballot(todo) != 0ull) {
+            // every lane probes its candidate (the index is in range whatever
+            // the candidate), so the grid word and the skip byte are loaded
+            // together; lanes inside a cleared stretch ignore the word
+            const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+            const uint32_t w = bits[q.word];
+            if (SKIP) {
+                const int dist = skip[q.coarse];
+                const float e = live ? skip_end_at<LOOKUP>(g, sk, q, dist, tm) : -INFINITY;
+                // the stretches start at this chunk's candidates, so any of
+                // them that reaches past the chunk covers the next candidates
+                skip_end = fmaxf(skip_end, wave_max(e));
+            }
+            hit = todo && ((w >> q.bit) & 1u) != 0u;
         }
         const uint64_t m = ballot(hit);
         if (!FILL && lane == chunk) my_mask = m;
@@ -275,11 +320,11 @@ __device__ __forceinline__ int march_ray_uniform(
     return count;
 }
 
-template <int LOOKUP, bool MIP, int WAVES>
+template <int LOOKUP, bool SKIP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
+    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
     int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
     __shared__ int64_t wave_total[WAVES];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
@@ -289,8 +334,8 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     for (int i = wave; i < kRaysPerBlock; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
-        const int n = march_ray_uniform<LOOKUP, false, MIP>(
-            r, rays_o, rays_d, grid_id, bits, mip, g, c, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
+        const int n = march_ray_uniform<LOOKUP, false, SKIP>(
+            r, rays_o, rays_d, grid_id, bits, skip, g, c, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
             masks != nullptr ? masks + r * n_masks : nullptr, masks != nullptr ? n_masks : 0);
         if (lane_id() == 0) packed_info[2 * r + 1] = n;
         total += n;
@@ -308,10 +353,10 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
 // the count pass (the first n_masks chunks), so the grid is not traversed a
 // second time; a ray whose samples continue past those chunks is traversed
 // from there on.
-template <int LOOKUP, bool MIP>
+template <int LOOKUP, bool SKIP>
 __device__ __forceinline__ void fill_ray_from_masks(
     int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ mip,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
     const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow,
     const uint64_t* __restrict__ masks, int n_masks) {
@@ -349,16 +394,17 @@ __device__ __forceinline__ void fill_ray_from_masks(
         written += __popcll(m);
     }
     if (written < limit) {
-        march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit, capacity,
-                                             ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks, written);
+        march_ray_uniform<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
+                                              capacity, ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks,
+                                              written);
     }
 }
 
-template <int LOOKUP, bool MIP, int WAVES>
+template <int LOOKUP, bool SKIP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    const uint32_t* __restrict__ mip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
+    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
     int64_t capacity, int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
@@ -371,24 +417,95 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
         if (masks != nullptr) {
-            fill_ray_from_masks<LOOKUP, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit, capacity,
-                                             ray_indices, t_starts, t_ends, overflow, masks + r * n_masks, n_masks);
+            fill_ray_from_masks<LOOKUP, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
+                                              capacity, ray_indices, t_starts, t_ends, overflow, masks + r * n_masks,
+                                              n_masks);
         } else {
-            march_ray_uniform<LOOKUP, true, MIP>(r, rays_o, rays_d, grid_id, bits, mip, g, c, p, start, limit,
-                                                 capacity, ray_indices, t_starts, t_ends, overflow);
+            march_ray_uniform<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
+                                                  capacity, ray_indices, t_starts, t_ends, overflow);
         }
     }
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
 
-// One ray per lane, cone steps (the lattice is a recurrence in t).
-template <int LOOKUP, bool FILL>
+// Cone steps: the lattice is a recurrence in t, t_{k+1} = t_k +
+// min(max(t_k c, dt), dt_max), so one lane walks one ray.  Candidates are
+// taken kConeBatch at a time: the recurrence first (a few dependent FP32
+// operations per candidate), then the batch's grid words are all loaded
+// before any is tested, so each lane keeps several loads in flight.  Every
+// active lane of a wave is at the same candidate index, so the count pass
+// stores the occupancy bits of each chunk of 64 candidates chunk-major
+// (masks[chunk * n_rays + r]: a wave's stores are contiguous), and the fill
+// pass replays them, running only the recurrence; it traverses the grid
+// again only past the stored chunks.
+constexpr int kConeBatch = 8;
+static_assert(kWave % kConeBatch == 0, "a batch must not straddle two chunks");
+
+// The next kConeBatch cone steps from t: interval ends tb[0..kConeBatch] and
+// how many of the batch's candidates lie inside the ray (a candidate is in
+// while t_k < t_far and the step still advances t).
+__device__ __forceinline__ int cone_steps(float t, float t_far, const StepK& p, float tb[kConeBatch + 1]) {
+    tb[0] = t;
+    int n_valid = kConeBatch;
+#pragma unroll
+    for (int u = 0; u < kConeBatch; ++u) {
+        const float step = fminf(fmaxf(tb[u] * p.cone, p.dt), p.dt_max);
+        tb[u + 1] = tb[u] + step;
+        if (n_valid == kConeBatch && !(tb[u] < t_far && tb[u + 1] > tb[u])) n_valid = u;
+    }
+    return n_valid;
+}
+
+// Occupancy bits of a batch's candidates (bit u for candidate u < n_valid).
+// All the batch's words (and one skip byte) are loaded before any is
+// tested; every index is in range whatever the candidate.  Candidates
+// inside a stretch cleared by the skip field are not looked up, and the
+// batch's last candidate extends that stretch for the next batches.
+template <int LOOKUP, bool SKIP>
+__device__ __forceinline__ uint32_t cone_hits(const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
+                                              const GridK& g, const SkipRay& sk, float& skip_end, uint32_t word0,
+                                              const float o[3], const float d[3], const float tb[kConeBatch + 1],
+                                              int n_valid) {
+    float tm[kConeBatch];
+    uint32_t todo = (1u << n_valid) - 1u;
+#pragma unroll
+    for (int u = 0; u < kConeBatch; ++u) {
+        tm[u] = (tb[u] + tb[u + 1]) * 0.5f;
+        if (SKIP && tm[u] < skip_end) todo &= ~(1u << u);
+    }
+    uint32_t hits = 0u;
+    if (todo != 0u) {
+        Probe q[kConeBatch];
+        uint32_t w[kConeBatch];
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) {
+            q[u] = probe<LOOKUP>(g, word0, o[0] + d[0] * tm[u], o[1] + d[1] * tm[u], o[2] + d[2] * tm[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) w[u] = bits[q[u].word];
+        const int dist = SKIP ? static_cast<int>(skip[q[kConeBatch - 1].coarse]) : 0;
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) {
+            if (((todo >> u) & 1u) != 0u && ((w[u] >> q[u].bit) & 1u) != 0u) hits |= 1u << u;
+        }
+        if (SKIP && n_valid == kConeBatch) {
+            skip_end = fmaxf(skip_end, skip_end_at<LOOKUP>(g, sk, q[kConeBatch - 1], dist, tm[kConeBatch - 1]));
+        }
+    }
+    return hits;
+}
+
+// One ray, cone steps, one lane: the count pass (FILL false: stores the
+// chunk masks) or the fill pass (FILL true: replays the stored masks, and
+// looks the grid up again only past them or without them).
+template <int LOOKUP, bool FILL, bool SKIP>
 __device__ __forceinline__ int march_ray_cone(
     int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const GridK& g,
+    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits,
+    const uint8_t* __restrict__ skip, const GridK& g,
     const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    bool& overflow) {
+    bool& overflow, uint64_t* __restrict__ masks, int n_masks, int64_t n_rays) {
     float o[3], d[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -399,68 +516,118 @@ __device__ __forceinline__ int march_ray_cone(
     if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
     float t_near, t_far;
     if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    SkipRay sk{};
+    if (SKIP) sk = skip_ray(g, o, d, t_far);
+    float skip_end = -INFINITY;  // candidates with midpoint below it are empty
     int count = 0;
-    float t0 = t_near;
-    for (int k = 0; k < kMaxCandidates; ++k) {
-        if (!(t0 < t_far)) break;
-        const float step = fminf(fmaxf(t0 * p.cone, p.dt), p.dt_max);
-        const float t1 = t0 + step;
-        if (!(t1 > t0)) break;
-        const float tm = (t0 + t1) * 0.5f;
-        if (occupied<LOOKUP>(bits, word0, g, o[0] + d[0] * tm, o[1] + d[1] * tm,
-                             o[2] + d[2] * tm)) {
-            if (p.max_per_ray > 0 && count >= p.max_per_ray) break;
+    float t = t_near;
+    uint64_t chunk_bits = 0ull;  // count: bits gathered so far in the chunk; fill: its stored mask
+    for (int k0 = 0; k0 < kMaxCandidates; k0 += kConeBatch) {
+        const int chunk = k0 / kWave;
+        const int shift = k0 % kWave;
+        const bool replay = FILL && chunk < n_masks;
+        if (replay && shift == 0) chunk_bits = masks[static_cast<int64_t>(chunk) * n_rays + r];
+        float tb[kConeBatch + 1];
+        const int n_valid = cone_steps(t, t_far, p, tb);
+        uint32_t hits = replay ? static_cast<uint32_t>(chunk_bits >> shift) & ((1u << kConeBatch) - 1u)
+                               : cone_hits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, tb, n_valid);
+        hits &= (1u << n_valid) - 1u;
+        bool stop = false;  // a cap reached inside the batch
+        uint32_t kept = 0u;
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) {
+            if (stop || ((hits >> u) & 1u) == 0u) continue;
+            if (p.max_per_ray > 0 && count >= p.max_per_ray) {
+                stop = true;
+                continue;
+            }
             if (FILL) {
-                if (count >= limit) break;
+                if (count >= limit) {
+                    stop = true;
+                    continue;
+                }
                 const int64_t pos = start + count;
                 if (pos >= 0 && pos < capacity) {
-                    ray_indices[pos] = static_cast<int32_t>(r);
-                    t_starts[pos] = t0;
-                    t_ends[pos] = t1;
+                    if (ray_indices != nullptr) ray_indices[pos] = static_cast<int32_t>(r);
+                    t_starts[pos] = tb[u];
+                    t_ends[pos] = tb[u + 1];
                 } else {
                     overflow = true;
                 }
             }
+            kept |= 1u << u;
             ++count;
         }
-        t0 = t1;
+        stop = stop || n_valid < kConeBatch;  // or the ray ended inside the batch
+        if (!FILL) {
+            chunk_bits |= static_cast<uint64_t>(kept) << shift;
+            if (chunk < n_masks && (stop || shift + kConeBatch == kWave)) {
+                masks[static_cast<int64_t>(chunk) * n_rays + r] = chunk_bits;
+            }
+            if (shift + kConeBatch == kWave) chunk_bits = 0ull;
+        }
+        if (stop || (FILL && count >= limit)) break;
+        t = tb[kConeBatch];
     }
     return count;
 }
 
-template <int LOOKUP>
+template <int LOOKUP, bool SKIP>
 __global__ __launch_bounds__(kRaysPerBlock) void count_cone_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
-    int64_t* __restrict__ block_sums) {
+    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
+    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     bool unused = false;
     int n = 0;
     if (r < n_rays) {
-        n = march_ray_cone<LOOKUP, false>(r, rays_o, rays_d, grid_id, bits, g, c, p, 0, 0, 0,
-                                          nullptr, nullptr, nullptr, unused);
+        n = march_ray_cone<LOOKUP, false, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, 0, 0, 0,
+                                                nullptr, nullptr, nullptr, unused, masks, n_masks, n_rays);
         packed_info[2 * r + 1] = n;
     }
     const int s = wave_sum(n);  // <= 64 * 2^24 fits int32
     if (threadIdx.x == 0) block_sums[blockIdx.x] = s;
 }
 
-template <int LOOKUP>
+template <int LOOKUP, bool SKIP>
 __global__ __launch_bounds__(kRaysPerBlock) void fill_cone_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info, int64_t capacity,
+    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
+    int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    int32_t* __restrict__ status) {
+    int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     if (r >= n_rays) return;
     const int limit = packed_info[2 * r + 1];
     if (limit == 0) return;
     bool overflow = false;
-    march_ray_cone<LOOKUP, true>(r, rays_o, rays_d, grid_id, bits, g, c, p, packed_info[2 * r],
-                                 limit, capacity, ray_indices, t_starts, t_ends, overflow);
+    // the ray indices are written by expand_rays_kernel, contiguously
+    march_ray_cone<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, packed_info[2 * r],
+                                       limit, capacity, nullptr, t_starts, t_ends, overflow,
+                                       const_cast<uint64_t*>(masks), masks != nullptr ? n_masks : 0, n_rays);
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
+}
+
+// ray_indices[start_r + i] = r for i < count_r: one wave per ray at a time,
+// 64 consecutive slots per store (the lane-per-ray fill would scatter them).
+constexpr int kExpandThreads = 256;
+
+__global__ __launch_bounds__(kExpandThreads) void expand_rays_kernel(const int32_t* __restrict__ packed_info,
+                                                                     int64_t n_rays, int64_t capacity,
+                                                                     int32_t* __restrict__ ray_indices) {
+    const int lane = lane_id();
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (kExpandThreads / kWave);
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * (kExpandThreads / kWave) + threadIdx.x / kWave; r < n_rays;
+         r += waves) {
+        const int64_t start = packed_info[2 * r];
+        const int count = packed_info[2 * r + 1];
+        for (int i = lane; i < count; i += kWave) {
+            const int64_t pos = start + i;
+            if (pos >= 0 && pos < capacity) ray_indices[pos] = static_cast<int32_t>(r);
+        }
+    }
 }
 
 // Exclusive scan of the per-workgroup sums, in place, by one workgroup:
@@ -514,12 +681,53 @@ __global__ void set_status_kernel(int32_t* status, int32_t value) { *status = va
 
 int64_t num_blocks(int64_t n_rays) { return (n_rays + kRaysPerBlock - 1) / kRaysPerBlock; }
 
+// Longest [t_near, t_far) a ray can have: far - near, and (unless the
+// lookup contracts space, which has no clip box) the clip box's diagonal.
+double clip_span(const nacc_grid_desc& grid, const nacc_march_params& p) {
+    double span = static_cast<double>(p.far_plane) - static_cast<double>(p.near_plane);
+    if (grid.lookup != NACC_LOOKUP_CONTRACT) {
+        const double scale = grid.lookup == NACC_LOOKUP_CASCADE ? std::ldexp(1.0, grid.n_grids - 1) : 1.0;
+        double d2 = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double e = (static_cast<double>(grid.hi[i]) - static_cast<double>(grid.lo[i])) * scale;
+            d2 += e * e;
+        }
+        span = std::min(span, std::sqrt(d2));
+    }
+    return span;
+}
+
+// Upper bound of the lattice candidates of one ray (at most kMaxCandidates).
+// Cone steps never shrink as t grows, so a ray entering later than the near
+// plane covers its (at most span long) range in no more steps than the
+// recurrence started at the near plane; two extra candidates absorb the
+// rounding of the sums.
+int64_t candidate_bound(const nacc_grid_desc& grid, const nacc_march_params& p) {
+    const double span = clip_span(grid, p);
+    if (!(span > 0.0)) return 0;
+    if (!std::isfinite(span)) return kMaxCandidates;
+    if (p.cone == 0.0f) {
+        return std::min<int64_t>(kMaxCandidates, static_cast<int64_t>(std::ceil(span / p.dt)) + 2);
+    }
+    const double end = static_cast<double>(p.near_plane) + span;
+    float t = p.near_plane;
+    int64_t k = 0;
+    while (k < kMaxCandidates && static_cast<double>(t) < end) {
+        const float step = fminf(fmaxf(t * p.cone, p.dt), p.dt_max);
+        const float t1 = t + step;
+        if (!(t1 > t)) return kMaxCandidates;
+        t = t1;
+        ++k;
+    }
+    return std::min<int64_t>(kMaxCandidates, k + 2);
+}
+
 constexpr int kMaxMaskChunks = 32;
 
 // Workspace of the marching calls: the per-workgroup sums of the scan, then
-// (uniform steps only) n_masks 64-bit occupancy masks per ray, one per chunk
-// of 64 candidates, written by the count pass and replayed by the fill pass.
-// n_masks covers the longest chord of the clip box (or far - near) in steps.
+// n_masks 64-bit occupancy masks per ray, one per chunk of 64 candidates,
+// written by the count pass and replayed by the fill pass.  n_masks covers
+// the longest possible ray (up to kMaxMaskChunks chunks).
 struct Layout {
     int64_t sums_bytes;
     int n_masks;
@@ -530,23 +738,9 @@ Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_m
     Layout l;
     l.sums_bytes = ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
     l.n_masks = 0;
-    if (p.cone == 0.0f && p.dt > 0.0f) {
-        double span = static_cast<double>(p.far_plane) - static_cast<double>(p.near_plane);
-        if (grid.lookup != NACC_LOOKUP_CONTRACT) {
-            const double scale = grid.lookup == NACC_LOOKUP_CASCADE ? std::ldexp(1.0, grid.n_grids - 1) : 1.0;
-            double d2 = 0.0;
-            for (int i = 0; i < 3; ++i) {
-                const double e = (static_cast<double>(grid.hi[i]) - static_cast<double>(grid.lo[i])) * scale;
-                d2 += e * e;
-            }
-            span = std::min(span, std::sqrt(d2));
-        }
-        if (std::isfinite(span) && span > 0.0) {
-            const double chunks = std::ceil((span / p.dt + 2.0) / kWave);
-            l.n_masks = static_cast<int>(std::min<double>(chunks, kMaxMaskChunks));
-        } else if (!std::isfinite(span)) {
-            l.n_masks = kMaxMaskChunks;
-        }
+    if (p.dt > 0.0f) {
+        const int64_t k = candidate_bound(grid, p);
+        l.n_masks = static_cast<int>(std::min<int64_t>((k + kWave - 1) / kWave, kMaxMaskChunks));
     }
     l.bytes = l.sums_bytes + n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t));
     return l;
@@ -609,11 +803,12 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     }
     g.top = static_cast<float>(grid.res - 1);
     g.base = grid.hi[0];
+    g.inv_base = 1.0f / grid.hi[0];
     g.res = grid.res;
     g.n_grids = grid.n_grids;
     g.words = static_cast<uint32_t>(static_cast<int64_t>(grid.res) * grid.res * grid.res / 32);
     g.coarse = grid.res / 4;
-    g.mip_words = static_cast<uint32_t>(nacc_grid_mip_words(&grid) / std::max(grid.n_grids, 1));
+    g.skip_cells = static_cast<uint32_t>(g.coarse) * g.coarse * g.coarse;
     p.near_plane = params.near_plane;
     p.far_plane = params.far_plane;
     p.dt = params.dt;
@@ -622,75 +817,98 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     p.max_per_ray = params.max_per_ray;
 }
 
-template <int LOOKUP, bool MIP, int WAVES>
+template <int LOOKUP, bool SKIP, int WAVES>
 void launch_count_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
-                          const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c, const StepK& p,
+                          const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c, const StepK& p,
                           int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
-    hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, MIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
-                       bits, mip, g, c, p, packed, sums, masks, n_masks);
+    hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid,
+                       n, bits, skip, g, c, p, packed, sums, masks, n_masks);
 }
 
-template <int LOOKUP, bool MIP, int WAVES>
+template <int LOOKUP, bool SKIP, int WAVES>
 void launch_fill_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
-                         const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c, const StepK& p,
+                         const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c, const StepK& p,
                          const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te, int32_t* status,
                          const uint64_t* masks, int n_masks) {
-    hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, MIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
-                       bits, mip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+    hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
+                       bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
 }
 
-template <int LOOKUP, bool MIP, typename... A>
-void count_by_waves(int waves, A&&... a) {
-    if (waves == 1) launch_count_uniform<LOOKUP, MIP, 1>(a...);
-    else if (waves == 2) launch_count_uniform<LOOKUP, MIP, 2>(a...);
-    else launch_count_uniform<LOOKUP, MIP, 4>(a...);
-}
-
-template <int LOOKUP, bool MIP, typename... A>
-void fill_by_waves(int waves, A&&... a) {
-    if (waves == 1) launch_fill_uniform<LOOKUP, MIP, 1>(a...);
-    else if (waves == 2) launch_fill_uniform<LOOKUP, MIP, 2>(a...);
-    else launch_fill_uniform<LOOKUP, MIP, 4>(a...);
-}
-
-template <int LOOKUP>
-void launch_count(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                  int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
-                  const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
-    const int waves = tuning().march_waves_per_group;
+template <int LOOKUP, bool SKIP>
+void launch_count_impl(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
+                       int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c,
+                       const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
     if (cone) {
-        hipLaunchKernelGGL(count_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
-                           bits, g, c, p, packed, sums);
-    } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
-        count_by_waves<LOOKUP, true>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
+        hipLaunchKernelGGL((count_cone_kernel<LOOKUP, SKIP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                           bits, skip, g, c, p, packed, sums, masks, n_masks);
+        return;
+    }
+    const int waves = tuning().march_waves_per_group;
+    if (waves == 1) {
+        launch_count_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
+    } else if (waves == 2) {
+        launch_count_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
     } else {
-        count_by_waves<LOOKUP, false>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, sums, masks, n_masks);
+        launch_count_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
     }
 }
 
-template <int LOOKUP>
-void launch_fill(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                 int64_t n, const uint32_t* bits, const uint32_t* mip, const GridK& g, const ClipK& c,
-                 const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
-                 int32_t* status, const uint64_t* masks, int n_masks) {
-    const int waves = tuning().march_waves_per_group;
+template <int LOOKUP, bool SKIP>
+void launch_fill_impl(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
+                      int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c,
+                      const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
+                      int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
-        hipLaunchKernelGGL(fill_cone_kernel<LOOKUP>, dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, bits,
-                           g, c, p, packed, capacity, ri, ts, te, status);
-    } else if (mip != nullptr && LOOKUP == NACC_LOOKUP_AABB) {
-        fill_by_waves<LOOKUP, true>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te,
-                                    status, masks, n_masks);
+        hipLaunchKernelGGL((fill_cone_kernel<LOOKUP, SKIP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                           bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+        const int64_t blocks = std::min<int64_t>((n + kExpandThreads / kWave - 1) / (kExpandThreads / kWave),
+                                                 256 * 64);
+        hipLaunchKernelGGL(expand_rays_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kExpandThreads), 0, s,
+                           packed, n, capacity, ri);
+        return;
+    }
+    const int waves = tuning().march_waves_per_group;
+    if (waves == 1) {
+        launch_fill_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
+                                             status, masks, n_masks);
+    } else if (waves == 2) {
+        launch_fill_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
+                                             status, masks, n_masks);
     } else {
-        fill_by_waves<LOOKUP, false>(waves, nb, s, o, d, gid, n, bits, mip, g, c, p, packed, capacity, ri, ts, te,
-                                     status, masks, n_masks);
+        launch_fill_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
+                                             status, masks, n_masks);
     }
 }
 
-// The skip grid is used by uniform steps with the box lookup and needs
-// res % 4 == 0; anything else marches without it.
-const uint32_t* usable_mip(const uint32_t* mip, const nacc_grid_desc& grid, const nacc_march_params& p) {
-    if (mip == nullptr || grid.lookup != NACC_LOOKUP_AABB || p.cone != 0.0f || grid.res % 4 != 0) return nullptr;
-    return mip;
+// The skip field serves the box and cascade lookups (res % 4 == 0); the
+// contraction lookup always marches without it.
+template <int LOOKUP, typename... A>
+void dispatch_count(const uint8_t* skip, bool cone, int64_t nb, hipStream_t s, const float* o, const float* d,
+                    const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
+    if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
+        if (skip != nullptr) {
+            launch_count_impl<LOOKUP, true>(cone, nb, s, o, d, gid, n, bits, skip, a...);
+            return;
+        }
+    }
+    launch_count_impl<LOOKUP, false>(cone, nb, s, o, d, gid, n, bits, nullptr, a...);
+}
+
+template <int LOOKUP, typename... A>
+void dispatch_fill(const uint8_t* skip, bool cone, int64_t nb, hipStream_t s, const float* o, const float* d,
+                   const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
+    if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
+        if (skip != nullptr) {
+            launch_fill_impl<LOOKUP, true>(cone, nb, s, o, d, gid, n, bits, skip, a...);
+            return;
+        }
+    }
+    launch_fill_impl<LOOKUP, false>(cone, nb, s, o, d, gid, n, bits, nullptr, a...);
+}
+
+const uint8_t* usable_skip(const uint8_t* skip, const nacc_grid_desc& grid) {
+    if (skip == nullptr || grid.lookup == NACC_LOOKUP_CONTRACT || grid.res % 4 != 0) return nullptr;
+    return skip;
 }
 
 }  // namespace
@@ -704,8 +922,25 @@ int64_t nacc_march_workspace_size(int64_t n_rays, const nacc_grid_desc* grid, co
     return workspace_layout(n_rays, *grid, *params).bytes;
 }
 
+int64_t nacc_march_max_samples_per_ray(const nacc_grid_desc* grid, const nacc_march_params* params) {
+    clear_error();
+    if (grid == nullptr || params == nullptr) {
+        set_error(NACC_EINVAL, "grid and params must be non-NULL");
+        return -1;
+    }
+    const nacc_march_params& p = *params;
+    if (!(std::isfinite(p.dt) && p.dt > 0.0f) || !(p.cone >= 0.0f) || std::isnan(p.near_plane) ||
+        std::isnan(p.far_plane)) {
+        set_error(NACC_EINVAL, "invalid marching parameters");
+        return -1;
+    }
+    int64_t bound = candidate_bound(*grid, p);
+    if (p.max_per_ray > 0) bound = std::min<int64_t>(bound, p.max_per_ray);
+    return bound;
+}
+
 int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                     const uint32_t* grid_bits, const uint32_t* grid_mip, const nacc_grid_desc* grid,
+                     const uint32_t* grid_bits, const uint8_t* grid_skip, const nacc_grid_desc* grid,
                      const nacc_march_params* params,
                      int32_t* packed_info, int64_t* total, void* workspace, size_t workspace_bytes,
                      void* stream) {
@@ -729,20 +964,20 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
     const int64_t nb = num_blocks(n_rays);
     int64_t* sums = static_cast<int64_t*>(workspace);
     const bool cone = params->cone > 0.0f;
-    const uint32_t* mip = usable_mip(grid_mip, *grid, *params);
+    const uint8_t* skip = usable_skip(grid_skip, *grid);
     if (nb > 0) {
         switch (grid->lookup) {
             case NACC_LOOKUP_AABB:
-                launch_count<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                               packed_info, sums, masks, lay.n_masks);
+                dispatch_count<NACC_LOOKUP_AABB>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                                                 p, packed_info, sums, masks, lay.n_masks);
                 break;
             case NACC_LOOKUP_CASCADE:
-                launch_count<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c,
-                                                  p, packed_info, sums, masks, lay.n_masks);
+                dispatch_count<NACC_LOOKUP_CASCADE>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
+                                                    c, p, packed_info, sums, masks, lay.n_masks);
                 break;
             default:
-                launch_count<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g,
-                                                   c, p, packed_info, sums, masks, lay.n_masks);
+                dispatch_count<NACC_LOOKUP_CONTRACT>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits,
+                                                     g, c, p, packed_info, sums, masks, lay.n_masks);
                 break;
         }
         st = check_launch("march count");
@@ -760,7 +995,7 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
 }
 
 int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                    const uint32_t* grid_bits, const uint32_t* grid_mip, const nacc_grid_desc* grid,
+                    const uint32_t* grid_bits, const uint8_t* grid_skip, const nacc_grid_desc* grid,
                     const nacc_march_params* params,
                     const int32_t* packed_info, const void* workspace, size_t workspace_bytes, int64_t capacity,
                     int32_t* ray_indices, float* t_starts, float* t_ends, int32_t* status, void* stream) {
@@ -785,7 +1020,7 @@ int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* gri
     const int64_t nb = num_blocks(n_rays);
     if (nb == 0) return NACC_OK;
     const bool cone = params->cone > 0.0f;
-    const uint32_t* mip = usable_mip(grid_mip, *grid, *params);
+    const uint8_t* skip = usable_skip(grid_skip, *grid);
     const Layout lay = workspace_layout(n_rays, *grid, *params);
     NACC_REQUIRE(workspace == nullptr || static_cast<int64_t>(workspace_bytes) >= lay.bytes, NACC_ESHAPE,
                  "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(lay.bytes));
@@ -795,16 +1030,19 @@ int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* gri
             : nullptr;
     switch (grid->lookup) {
         case NACC_LOOKUP_AABB:
-            launch_fill<NACC_LOOKUP_AABB>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                          packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
+            dispatch_fill<NACC_LOOKUP_AABB>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+                                            packed_info, capacity, ray_indices, t_starts, t_ends, status, masks,
+                                            lay.n_masks);
             break;
         case NACC_LOOKUP_CASCADE:
-            launch_fill<NACC_LOOKUP_CASCADE>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                             packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
+            dispatch_fill<NACC_LOOKUP_CASCADE>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                                               p, packed_info, capacity, ray_indices, t_starts, t_ends, status, masks,
+                                               lay.n_masks);
             break;
         default:
-            launch_fill<NACC_LOOKUP_CONTRACT>(cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, mip, g, c, p,
-                                              packed_info, capacity, ray_indices, t_starts, t_ends, status, masks, lay.n_masks);
+            dispatch_fill<NACC_LOOKUP_CONTRACT>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                                                p, packed_info, capacity, ray_indices, t_starts, t_ends, status,
+                                                masks, lay.n_masks);
             break;
     }
     return check_launch("march fill");

@@ -3,7 +3,8 @@
 //
 // The coefficient table holds, per blob, (c_x, c_y, c_z, k, peak) with
 // k = -log2(e) / (2 std^2), so each blob costs one exp2 on the hardware
-// transcendental unit; the 9 + 3 colour coefficients follow the blobs.
+// transcendental unit; the 9 + 3 colour coefficients follow the blobs, then
+// the flags word (1.0f: the scene is defined in contracted coordinates).
 #include <cmath>
 
 #include "common.h"
@@ -18,13 +19,13 @@ constexpr int kBlobStride = 5;
 constexpr float kLog2e = 1.4426950408889634f;
 
 int64_t table_floats(int32_t n_blobs, int32_t n_sets) {
-    return static_cast<int64_t>(n_sets) * n_blobs * kBlobStride + 12;
+    return static_cast<int64_t>(n_sets) * n_blobs * kBlobStride + 13;
 }
 
 __global__ void prepare_kernel(const float* __restrict__ centres, const float* __restrict__ stds,
                                const float* __restrict__ peaks, const float* __restrict__ w,
                                const float* __restrict__ bias, int32_t n_blobs, int32_t n_sets,
-                               float* __restrict__ table) {
+                               int32_t flags, float* __restrict__ table) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nb = static_cast<int64_t>(n_sets) * n_blobs;
     if (i < nb) {
@@ -36,9 +37,9 @@ __global__ void prepare_kernel(const float* __restrict__ centres, const float* _
         e[2] = centres[3 * i + 2];
         e[3] = -kLog2e / (2.0f * s * s);
         e[4] = peaks[b];
-    } else if (i < nb + 12) {
+    } else if (i < nb + 13) {
         const int j = static_cast<int>(i - nb);
-        table[kBlobStride * nb + j] = j < 9 ? w[j] : bias[j - 9];
+        table[kBlobStride * nb + j] = j < 9 ? w[j] : (j < 12 ? bias[j - 9] : static_cast<float>(flags & 1));
     }
 }
 
@@ -69,11 +70,26 @@ __device__ __forceinline__ void eval_rgb(const float* __restrict__ cc, float x0,
     b = 1.0f / (1.0f + exp2_fast(-z2 * kLog2e));
 }
 
-// Sample midpoint, FP32, no contraction (matches the positions of the tests).
+// Sample midpoint, FP32, no fused multiply-add (matches the positions of the
+// tests).
 __device__ __forceinline__ float midpoint_coord(float o, float d, float t0, float t1) {
 #pragma clang fp contract(off)
     const float tm = (t0 + t1) * 0.5f;
     return o + d * tm;
+}
+
+// Scene coordinates of a world point when the scene is defined in
+// contracted space: beyond the unit ball, x -> (2 - 1/|x|) x / |x|.
+__device__ __forceinline__ void to_scene(bool contract, float& x0, float& x1, float& x2) {
+    if (!contract) return;
+    const float n2 = fmaf(x2, x2, fmaf(x1, x1, x0 * x0));
+    if (n2 > 1.0f) {
+        const float n = sqrtf(n2);
+        const float f = (2.0f - 1.0f / n) / n;
+        x0 *= f;
+        x1 *= f;
+        x2 *= f;
+    }
 }
 
 // With a single centre set (PER_SET false) every lane reads the same blob
@@ -87,6 +103,7 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
     float* __restrict__ sigmas, float* __restrict__ rgbs) {
     const int64_t n = n_dev != nullptr ? min(n_cap, *n_dev) : n_cap;
     const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
+    const bool contract = cc[12] != 0.0f;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; s < n; s += stride) {
         const int64_t r = ray_indices[s];
@@ -96,9 +113,10 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
             continue;
         }
         const float t0 = ts[s], t1 = te[s];
-        const float x0 = midpoint_coord(rays_o[3 * r], rays_d[3 * r], t0, t1);
-        const float x1 = midpoint_coord(rays_o[3 * r + 1], rays_d[3 * r + 1], t0, t1);
-        const float x2 = midpoint_coord(rays_o[3 * r + 2], rays_d[3 * r + 2], t0, t1);
+        float x0 = midpoint_coord(rays_o[3 * r], rays_d[3 * r], t0, t1);
+        float x1 = midpoint_coord(rays_o[3 * r + 1], rays_d[3 * r + 1], t0, t1);
+        float x2 = midpoint_coord(rays_o[3 * r + 2], rays_d[3 * r + 2], t0, t1);
+        to_scene(contract, x0, x1, x2);
         int set = 0;
         if (PER_SET) {
             set = ray_set[r];
@@ -128,9 +146,11 @@ __global__ __launch_bounds__(kThreads) void field_points_kernel(const float* __r
                                                                  float* __restrict__ sigmas,
                                                                  float* __restrict__ rgbs) {
     const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
+    const bool contract = cc[12] != 0.0f;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; q < n; q += stride) {
-        const float x0 = points[3 * q], x1 = points[3 * q + 1], x2 = points[3 * q + 2];
+        float x0 = points[3 * q], x1 = points[3 * q + 1], x2 = points[3 * q + 2];
+        to_scene(contract, x0, x1, x2);
         int set = 0;
         if (PER_SET) {
             set = point_set != nullptr ? point_set[q] : static_cast<int>(point_cell[q] / cells_per_set);
@@ -164,14 +184,15 @@ int64_t nacc_synth_table_size(int32_t n_blobs, int32_t n_sets) {
 }
 
 int nacc_synth_prepare(const float* centres, const float* stds, const float* peaks, const float* w, const float* bias,
-                       int32_t n_blobs, int32_t n_sets, void* table, void* stream) {
+                       int32_t n_blobs, int32_t n_sets, int32_t flags, void* table, void* stream) {
     clear_error();
     NACC_REQUIRE(n_blobs >= 1 && n_sets >= 1, NACC_EINVAL, "n_blobs and n_sets must be >= 1");
     NACC_REQUIRE(centres && stds && peaks && w && bias && table, NACC_EINVAL, "arguments must be non-NULL");
-    const int64_t total = static_cast<int64_t>(n_sets) * n_blobs + 12;
+    NACC_REQUIRE((flags & ~NACC_SYNTH_CONTRACT) == 0, NACC_EINVAL, "unknown flags 0x%x", flags);
+    const int64_t total = static_cast<int64_t>(n_sets) * n_blobs + 13;
     hipLaunchKernelGGL(prepare_kernel, dim3(static_cast<unsigned>((total + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, as_stream(stream), centres, stds, peaks, w, bias, n_blobs, n_sets,
-                       static_cast<float*>(table));
+                       flags, static_cast<float*>(table));
     return check_launch("synth prepare");
 }
 

@@ -64,6 +64,9 @@ class BlobScene:
     peaks: np.ndarray    # f32 [B]
     w: np.ndarray        # f32 [3, 3]
     bias: np.ndarray     # f32 [3]
+    # True: the scene is defined in contracted coordinates (density and colour
+    # are evaluated at the image of x under the unbounded-scene contraction)
+    contract: bool = False
 
     @property
     def n_blobs(self) -> int:
@@ -103,6 +106,15 @@ def moving_blob_scene(n_blobs: int, n_frames: int, seed: int,
     return base
 
 
+def contracted(points: np.ndarray) -> np.ndarray:
+    """Scene coordinates of world points for a scene defined in contracted
+    space: points beyond the unit ball map to radius 2 - 1/|x| (FP64).  This
+    is part of the synthetic scene's definition."""
+    nrm = np.linalg.norm(points, axis=1, keepdims=True)
+    f = np.where(nrm > 1.0, (2.0 - 1.0 / np.maximum(nrm, 1.0)) / np.maximum(nrm, 1.0), 1.0)
+    return points * f
+
+
 def blob_density(scene: BlobScene, points: np.ndarray, set_index: int = 0,
                  chunk: int = 1 << 18) -> np.ndarray:
     """FP64 density of the scene at FP64 points [n, 3] (centre set
@@ -113,9 +125,72 @@ def blob_density(scene: BlobScene, points: np.ndarray, set_index: int = 0,
     out = np.empty(points.shape[0], np.float64)
     for a in range(0, points.shape[0], chunk):
         p = points[a:a + chunk]
+        if scene.contract:
+            p = contracted(p)
         d2 = ((p[:, None, :] - c[None, :, :]) ** 2).sum(-1)
         out[a:a + chunk] = (pk[None] * np.exp(-d2 / (2.0 * s[None] ** 2))).sum(-1)
     return out
+
+
+def unbounded_blob_scene(levels: int, per_level: int, seed: int,
+                         std_range=(0.04, 0.12), depth_range=(2.0, 6.0)) -> BlobScene:
+    """A scene for unbounded rays, defined in contracted coordinates: level
+    l = 0..levels-1 holds `per_level` blobs whose centres are the contracted
+    images of world points at radius 2^(3 l / (levels - 1)) (1 to 8) in
+    uniformly drawn directions.  Contracted standard deviations are drawn
+    from std_range; each peak is set so that the optical depth through the
+    blob's centre along the radius, in world units, is drawn from depth_range
+    whatever the level (the contraction stretches radii by |x|^2 there)."""
+    g = _rng(seed)
+    n = levels * per_level
+    lvl = np.repeat(np.arange(levels), per_level)
+    radius = 2.0 ** (3.0 * lvl / max(levels - 1, 1))
+    v = g.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    centres = contracted(v * radius[:, None])
+    std = g.uniform(std_range[0], std_range[1], n)
+    depth = g.uniform(depth_range[0], depth_range[1], n)
+    stretch = np.maximum(radius, 1.0) ** 2
+    peaks = depth / (math.sqrt(2.0 * math.pi) * std * stretch)
+    w = g.standard_normal((3, 3))
+    bias = g.standard_normal(3)
+    return BlobScene(centres=centres[None].astype(np.float32), stds=std.astype(np.float32),
+                     peaks=peaks.astype(np.float32), w=w.astype(np.float32),
+                     bias=bias.astype(np.float32), contract=True)
+
+
+def cascade_occupancy(scene: BlobScene, res: int, levels: int, base: float = 1.0,
+                      threshold_hint: float = 1e-2, chunk: int = 1 << 20) -> np.ndarray:
+    """FP32 occupancy values of `levels` cascaded res^3 grids, level l over
+    [-base 2^l, base 2^l]^3: the scene density at every cell centre (world
+    coordinates), level-major then C order.  Blobs are skipped at points
+    where they contribute below threshold_hint * 1e-6 (a sum of such
+    contributions cannot cross the threshold)."""
+    out = []
+    s = scene.stds.astype(np.float64)
+    pk = scene.peaks.astype(np.float64)
+    c = scene.centres[0].astype(np.float64)
+    cut = threshold_hint * 1e-6
+    reach = s * np.sqrt(2.0 * np.log(np.maximum(pk / cut, 1.0)))
+    for lvl in range(levels):
+        h = base * 2.0 ** lvl
+        pts = cell_centres(res, (-h, -h, -h, h, h, h))
+        occ = np.zeros(pts.shape[0], np.float64)
+        for a in range(0, pts.shape[0], chunk):
+            p = pts[a:a + chunk]
+            if scene.contract:
+                p = contracted(p)
+            acc = np.zeros(p.shape[0], np.float64)
+            for b in range(scene.n_blobs):
+                e = p - c[b]
+                near = np.all(np.abs(e) < reach[b], axis=1)
+                if not near.any():
+                    continue
+                d2 = (e[near] ** 2).sum(1)
+                acc[near] += pk[b] * np.exp(-d2 / (2.0 * s[b] ** 2))
+            occ[a:a + chunk] = acc
+        out.append(occ)
+    return np.concatenate(out).astype(np.float32)
 
 
 def cell_centres(res: int, box) -> np.ndarray:
@@ -238,6 +313,110 @@ WORKLOADS = {
     "train_262k": Workload("train_262k", 262144, 32, 128, BOX_1_5, STEP_1024,
                            1e-4, 0.0, 1e10, 1),
 }
+
+
+def camera_rays(width: int, height: int, index: int, n_cameras: int = 8, radius: float = 4.0,
+                focal_scale: float = 1.2):
+    """Pinhole camera `index` of n_cameras on the z = 0 circle of `radius`
+    (azimuth 2 pi index / n_cameras) looking at the origin, up = +z, focal
+    length focal_scale * width pixels, principal point at the image centre;
+    one ray through every pixel centre, row-major from the top-left pixel.
+    Returns origins and unit directions, f32 [height * width, 3]."""
+    az = 2.0 * math.pi * index / n_cameras
+    eye = radius * np.array([math.cos(az), math.sin(az), 0.0])
+    fwd = -eye / np.linalg.norm(eye)
+    right = np.cross(fwd, [0.0, 0.0, 1.0])
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    f = focal_scale * width
+    x = (np.arange(width) + 0.5 - 0.5 * width) / f
+    y = -(np.arange(height) + 0.5 - 0.5 * height) / f
+    d = fwd[None, None, :] + x[None, :, None] * right + y[:, None, None] * up
+    d = d.reshape(-1, 3)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    return np.ascontiguousarray(o, np.float32), np.ascontiguousarray(d, np.float32)
+
+
+@dataclass
+class ImageWorkload:
+    """Whole images rendered forward through the training scene's grid and
+    field (blob scene and 128^3 grid of the train_262k workload)."""
+    name: str
+    sizes: tuple        # (width, height) per image; image k uses camera k
+    n_cameras: int
+    scene_workload: str
+    early_stop_eps: float
+
+    @property
+    def n_rays(self) -> int:
+        return sum(w * h for w, h in self.sizes)
+
+
+IMAGE_WORKLOADS = {
+    "images_8": ImageWorkload("images_8", ((800, 800),) * 4 + ((1920, 1080),) * 4, 8, "train_262k",
+                              1e-4),
+}
+
+
+def image_inputs(w: ImageWorkload, scale: int = 1):
+    """Rays of every image (concatenated in image order), the ray count of
+    each image, and the scene and occupancy of the scene workload.  scale > 1
+    divides every image size by it (smaller cases for tests)."""
+    os_, ds_, counts = [], [], []
+    for k, (wd, ht) in enumerate(w.sizes):
+        o, d = camera_rays(wd // scale, ht // scale, k, w.n_cameras)
+        os_.append(o)
+        ds_.append(d)
+        counts.append(o.shape[0])
+    sw = WORKLOADS[w.scene_workload]
+    scene = blob_scene(sw.n_blobs, 1000 + sw.seed_base)
+    occ = initial_occupancy(scene, sw.res, sw.box)
+    return dict(rays_o=np.ascontiguousarray(np.concatenate(os_)),
+                rays_d=np.ascontiguousarray(np.concatenate(ds_)),
+                counts=np.array(counts, np.int64), scene=scene, occ=occ, scene_workload=sw)
+
+
+@dataclass
+class UnboundedWorkload:
+    """Rays from inside the unit ball in all directions, cone-scaled steps,
+    cascaded grids (level l over [-2^l, 2^l]^3) and a scene defined in
+    contracted coordinates."""
+    name: str
+    n_rays: int
+    blob_levels: int
+    blobs_per_level: int
+    res: int
+    cascades: int
+    dt: float
+    cone: float
+    dt_max: float
+    early_stop_eps: float
+    near: float
+    far: float
+    seed_base: int
+
+    @property
+    def box(self):
+        return (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)  # level 0; level l is box * 2^l
+
+
+UNBOUNDED_WORKLOADS = {
+    "unbounded_262k": UnboundedWorkload("unbounded_262k", 262144, 8, 4, 128, 4, STEP_1024,
+                                        1.0 / 256.0, 1e10, 1e-4, 0.2, 1e4, 2),
+}
+
+
+def unbounded_inputs(w: UnboundedWorkload, n_rays: int | None = None, res: int | None = None):
+    """Rays, scene, cascaded occupancy values and targets of an unbounded
+    workload (smaller ray counts or resolutions for tests)."""
+    n = w.n_rays if n_rays is None else n_rays
+    rs = w.res if res is None else res
+    o, d = rays_unbounded(n, 2000 + w.seed_base)
+    scene = unbounded_blob_scene(w.blob_levels, w.blobs_per_level, 1000 + w.seed_base)
+    occ = cascade_occupancy(scene, rs, w.cascades)
+    tgt = targets(n, 3000 + w.seed_base)
+    return dict(rays_o=o, rays_d=d, scene=scene, occ=occ, targets=tgt, res=rs)
 
 
 @dataclass

@@ -1,0 +1,57 @@
+"""Workload set-up shared by the GPU parity tests: a benchmark Step marched
+and shaded on a named workload, the oracle's marching arguments for it, and
+the tolerance of the FP32 synthetic field."""
+import numpy as np
+import torch
+
+import oracle
+import synth
+
+
+def march_kwargs(w):
+    """Oracle marching arguments of a workload (box or cascaded grids,
+    uniform or cone-scaled steps)."""
+    cascades = getattr(w, "cascades", 1)
+    return dict(dt_max=getattr(w, "dt_max", 1e10), cone=getattr(w, "cone", 0.0),
+                lookup=oracle.LOOKUP_CASCADE if cascades > 1 else oracle.LOOKUP_AABB,
+                n_grids=cascades)
+
+
+def field_tolerance(scene, pos, sigma):
+    """Allowed |gpu - oracle| of the FP32 field: 2e-5 relative, plus, for a
+    scene in contracted coordinates, the effect of rounding the contracted
+    point to FP32 (about 1e-6 absolute per coordinate) on each blob's
+    exponent: 2e-6 |d_b| / std_b^2 times the blob's contribution."""
+    tol = 2e-5 * sigma + 1e-30
+    if scene.contract:
+        y = synth.contracted(pos.astype(np.float64))
+        c = scene.centres[0].astype(np.float64)
+        s = scene.stds.astype(np.float64)
+        d2 = ((y[:, None, :] - c[None]) ** 2).sum(-1)
+        contrib = scene.peaks.astype(np.float64)[None] * np.exp(-d2 / (2 * s[None] ** 2))
+        tol = tol + (contrib * 2e-6 * np.sqrt(d2) / s[None] ** 2).sum(1)
+    return tol
+
+
+def make_step(name, n_rays=None, res=None, skip_field=False):
+    import bench
+    import paper_2210_04847_amd as nacc
+    t = lambda a: torch.from_numpy(a).cuda()
+    if name in synth.UNBOUNDED_WORKLOADS:
+        w = synth.UNBOUNDED_WORKLOADS[name]
+        inp = synth.unbounded_inputs(w, n_rays, res)
+        grid = nacc.OccupancyGrid(w.box, inp["res"], n_grids=w.cascades, lookup="cascade")
+    else:
+        w = synth.WORKLOADS[name]
+        inp = synth.workload_inputs(w, n_rays)
+        inp["res"] = w.res
+        grid = nacc.OccupancyGrid(w.box, w.res)
+    grid.set_occupancy(t(inp["occ"]), 0.01)
+    field = nacc.BlobField(inp["scene"])
+    st = bench.Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid,
+                    field, skip_field=skip_field)
+    st.march_count()
+    st.march_fill()
+    st.field_eval()
+    torch.cuda.synchronize()
+    return w, inp, st

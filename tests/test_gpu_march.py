@@ -90,10 +90,9 @@ def test_empty_full_and_no_rays():
 
 @pytest.mark.parametrize("scale,dt", [(1.0, 0.0051), (3.0, 0.0051), (0.3, 0.0051), (1.0, 0.03),
                                       (1.0, 0.2)])
-def test_skip_grid_group_sizes(scale, dt):
-    # unnormalised directions and coarse steps change the group size per
-    # ray (down to no grouping at all); the samples must not change
-    w = synth.WORKLOADS["train_262k"]
+def test_skip_field_ray_scales(scale, dt):
+    # unnormalised directions and coarse steps change how far a skip-field
+    # test reaches in t; the samples must not change
     scene = synth.blob_scene(32, 1001)
     occ = synth.initial_occupancy(scene, 64, synth.BOX_1_5)
     mask = oracle.grid_threshold(occ, 0.01)
@@ -101,25 +100,44 @@ def test_skip_grid_group_sizes(scale, dt):
     compare(o, (d * np.float32(scale)).astype(np.float32), mask, 64, BOX, 0.0, 1e10, dt)
 
 
-def test_skip_grid_contents():
+@pytest.mark.parametrize("cone", [0.0, 1.0 / 256])
+def test_skip_field_sparse_cascades(cone):
+    # a few occupied cells per level: long empty stretches, level changes
+    # inside them, rays starting inside the finest level
+    res, levels = 32, 4
+    mask = synth.random_mask(levels * res ** 3, 0.0015, 52)
+    o, d = synth.rays_unbounded(2000, 52)
+    base = np.array([-1, -1, -1, 1, 1, 1], np.float32)
+    dt = float(np.float32(3 * np.sqrt(3) / 1024))
+    want = compare(o, d, mask, res, base, 0.2, 1e4, dt, dt_max=1e10, cone=cone, lookup=1,
+                   n_grids=levels)
+    assert want[1].size > 500
+
+
+def test_skip_field_contents():
     import paper_2210_04847_amd as nacc
-    from scipy.ndimage import maximum_filter
-    res = 32
-    mask = synth.random_mask(2 * res ** 3, 0.002, 51)
-    grid = nacc.OccupancyGrid(BOX, res, n_grids=2)
+    from scipy.ndimage import distance_transform_cdt
+    res, n = 32, 3
+    mask = synth.random_mask(n * res ** 3, 0.0004, 51)
+    mask[2 * res ** 3:] = 0  # the third grid is empty
+    grid = nacc.OccupancyGrid(BOX, res, n_grids=n)
     grid.set_occupancy(torch.from_numpy(mask.astype(np.float32)).cuda(), 0.5)
     torch.cuda.synchronize()
-    mip = grid.mip.cpu().numpy().view(np.uint32)
     c = res // 4
-    half = (c ** 3 + 31) // 32
-    for gi in range(2):
+    field = grid.skip.cpu().numpy()[:n * c ** 3]
+    cap = 15
+    for gi in range(n):
         m = mask[gi * res ** 3:(gi + 1) * res ** 3].reshape(c, 4, c, 4, c, 4)
-        coarse = m.max(axis=(1, 3, 5))
-        dil = maximum_filter(coarse, size=3, mode="constant", cval=0)
-        for arr, off in ((dil, 0), (coarse, half)):
-            words = np.packbits(arr.ravel().astype(np.uint8), bitorder="little")
-            words = np.pad(words, (0, 4 * half - words.size)).view("<u4")
-            assert np.array_equal(mip[gi * 2 * half + off: gi * 2 * half + off + half], words)
+        coarse = m.max(axis=(1, 3, 5)).astype(bool)
+        if coarse.any():
+            # chessboard distance of every empty coarse cell to the nearest occupied one
+            want = distance_transform_cdt(~coarse, metric="chessboard")
+        else:
+            want = np.full(coarse.shape, cap)
+        want = np.minimum(want, cap).astype(np.uint8).ravel()
+        assert np.array_equal(field[gi * c ** 3:(gi + 1) * c ** 3], want), f"grid {gi}"
+        if gi < 2:
+            assert want.max() >= 3  # the test exercises distances above the trivial ones
 
 
 def test_long_rays_many_chunks():
@@ -154,6 +172,22 @@ def test_cone_steps_cascade():
             n_grids=levels)
 
 
+@pytest.mark.parametrize("max_per_ray,dt_max,near", [(37, 1e10, 0.2), (0, 0.013, 0.2),
+                                                     (5, 0.03, 2.5), (1, 1e10, 0.0)])
+def test_cone_steps_caps(max_per_ray, dt_max, near):
+    """Cone steps with a per-ray cap that falls inside a batch of candidates,
+    steps clamped at dt_max, a near plane past the uniform-step region."""
+    res, levels = 16, 4
+    mask = synth.random_mask(levels * res ** 3, 0.35, 16)
+    o, d = synth.rays_unbounded(777, 16)
+    base = np.array([-1, -1, -1, 1, 1, 1], np.float32)
+    dt = float(np.float32(3 * np.sqrt(3) / 1024))
+    want = compare(o, d, mask, res, base, near, 1e4, dt, dt_max=dt_max, cone=1.0 / 256, lookup=1,
+                   n_grids=levels, max_per_ray=max_per_ray)
+    if max_per_ray > 0:
+        assert want[0][:, 1].max() == max_per_ray
+
+
 def test_uniform_steps_cascade():
     res, levels = 16, 3
     mask = synth.random_mask(levels * res ** 3, 0.3, 13)
@@ -172,7 +206,8 @@ def test_contraction_lookup():
             max_per_ray=1024)
 
 
-def test_capacity_overflow_reported():
+@pytest.mark.parametrize("cone", [0.0, 1.0 / 256])
+def test_capacity_overflow_reported(cone):
     nacc = _nacc()
     lib = nacc._lib
     o, d = synth.rays_toward_origin(64, 15)
@@ -180,7 +215,7 @@ def test_capacity_overflow_reported():
     grid = nacc.OccupancyGrid(BOX, 8)
     grid.set_occupancy(torch.from_numpy(mask).cuda(), 0.5)
     ro, rd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
-    params = lib.march_params(0.0, 1e10, 0.01)
+    params = lib.march_params(0.0, 1e10, 0.01, cone=cone)
     packed = torch.empty((64, 2), dtype=torch.int32, device="cuda")
     total = torch.empty(1, dtype=torch.int64, device="cuda")
     ws = torch.empty(lib.march_workspace_size(64, grid.desc, params), dtype=torch.uint8, device="cuda")
@@ -194,7 +229,7 @@ def test_capacity_overflow_reported():
     lib.march_fill(ro, rd, None, grid.bits, grid.desc, params, packed, ri, ts, te, status, None, ws)
     assert int(status.item()) == lib.NACC_ECAPACITY
     # the samples that fit are written and correct
-    _, ri_o, ts_o, _ = oracle.march(o, d, mask.astype(np.uint8), 8, BOX, 0.0, 1e10, 0.01)
+    _, ri_o, ts_o, _ = oracle.march(o, d, mask.astype(np.uint8), 8, BOX, 0.0, 1e10, 0.01, cone=cone)
     assert_bit_exact(ri.cpu().numpy(), ri_o[:cap], "ray_indices within capacity")
     assert_bit_exact(ts.cpu().numpy(), ts_o[:cap], "t_starts within capacity")
 

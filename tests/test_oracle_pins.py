@@ -548,3 +548,45 @@ def test_blob_field_closed_form():
     z = p64 @ scene.w.astype(np.float64).T + scene.bias
     from scipy.special import expit
     assert np.allclose(rgb, expit(z), rtol=1e-12)
+
+
+def test_blob_field_in_contracted_space():
+    """A scene defined in contracted coordinates: world points beyond the
+    unit ball are evaluated at radius 2 - 1/|x| along their own direction
+    (Euclidean norm), points inside it unchanged.  Values with closed forms:
+    (2,0,0) -> (1.5,0,0); (4,0,0) -> (1.75,0,0); (2,2,1) (norm 3) ->
+    (10/9, 10/9, 5/9); (0.625,0,0) -> itself."""
+    import dataclasses
+    from scipy.special import expit
+    base = synth.BlobScene(centres=np.array([[[1.5, 0.0, 0.0]]], np.float32),
+                           stds=np.array([0.125], np.float32), peaks=np.array([7.0], np.float32),
+                           w=np.eye(3, dtype=np.float32), bias=np.zeros(3, np.float32),
+                           contract=True)
+    pts = np.array([[2, 0, 0], [4, 0, 0], [0.625, 0, 0], [-2, 0, 0]], np.float32)
+    sigma, rgb = oracle.blob_field(base, pts)
+    k = 1.0 / (2 * 0.125 ** 2)
+    want = 7.0 * np.exp(-k * np.array([0.0, 0.25 ** 2, 0.875 ** 2, 3.0 ** 2]))
+    assert np.allclose(sigma, want, rtol=1e-12, atol=0)
+    assert np.allclose(rgb[0], expit([1.5, 0.0, 0.0]), rtol=1e-12)
+    assert np.allclose(rgb[3], expit([-1.5, 0.0, 0.0]), rtol=1e-12)
+    diag = dataclasses.replace(base, centres=np.array([[[10 / 9, 10 / 9, 5 / 9]]], np.float32))
+    s2 = oracle.blob_field(diag, np.array([[2, 2, 1]], np.float32), want_rgb=False)
+    c = np.array([10 / 9, 10 / 9, 5 / 9])
+    d2 = ((c - c.astype(np.float32)) ** 2).sum()  # the centre is stored in FP32
+    assert abs(s2[0] - 7.0 * np.exp(-k * d2)) <= 1e-12
+    # without the flag the same scene is evaluated in world coordinates
+    plain = dataclasses.replace(base, contract=False)
+    s3 = oracle.blob_field(plain, np.array([[2, 0, 0]], np.float32), want_rgb=False)
+    assert np.isclose(s3[0], 7.0 * np.exp(-k * 0.25), rtol=1e-12)
+
+
+def test_unbounded_scene_generator():
+    """Blob centres of the unbounded scene sit at the contracted images of
+    world radii 1 .. 8 (contracted radius 2 - 1/R), and a blob's optical
+    depth along its radius is level-independent by construction."""
+    scene = synth.unbounded_blob_scene(8, 4, 5)
+    r = np.linalg.norm(scene.centres[0].astype(np.float64), axis=1)
+    world = 2.0 ** (3.0 * np.repeat(np.arange(8), 4) / 7.0)
+    assert np.allclose(r, 2.0 - 1.0 / world, rtol=1e-6)
+    depth = (scene.peaks.astype(np.float64) * np.sqrt(2 * np.pi) * scene.stds * world ** 2)
+    assert depth.min() >= 2.0 - 1e-5 and depth.max() <= 6.0 + 1e-5

@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--skip-field", choices=["on", "off"], default="off",
                     help="march with the grid's skip field (empty-space skipping; pays off on "
                          "sparse scenes only)")
+    ap.add_argument("--alpha-thre", type=float, default=None,
+                    help="prune the marched samples by visibility before shading them, as the "
+                         "paper's ray_marching with sigma_fn (T >= early_stop_eps, alpha >= this; "
+                         "the paper's listing uses 1e-2)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
@@ -76,7 +80,7 @@ class Step:
     picks the grid and the field's centre set."""
 
     def __init__(self, torch, nacc, w, rays_o, rays_d, targets, grid, field, grid_id=None,
-                 skip_field=False, forward_only=False, loss_rays=0, seed=0):
+                 skip_field=False, forward_only=False, loss_rays=0, seed=0, alpha_thre=None):
         self.torch, self.nacc, self.lib = torch, nacc, nacc._lib
         dev = rays_o.device
         self.w = w
@@ -116,6 +120,23 @@ class Step:
         self.updates = torch.zeros(1, dtype=torch.int64, device=dev)  # read by the kernel
         self.seed = seed
         self.skip = grid.skip if skip_field else None
+        # visibility pruning (the paper's ray_marching with sigma_fn): densities
+        # of all marched samples, then only the kept ones are shaded and rendered
+        self.prune = alpha_thre is not None
+        self.alpha_thre = alpha_thre
+        self.cur = (self.packed, self.ray_indices, self.t_starts, self.t_ends, self.total)
+        if self.prune:
+            self.sig_all = torch.empty(cap, dtype=f32, device=dev)
+            self.keep = torch.empty(cap, dtype=torch.uint8, device=dev)
+            self.prune_ws = torch.empty(max(self.lib.prune_workspace_size(n), 1), dtype=torch.uint8,
+                                        device=dev)
+            self.cur = (torch.empty((n, 2), dtype=i32, device=dev),
+                        torch.empty(cap, dtype=i32, device=dev),
+                        torch.empty(cap, dtype=f32, device=dev),
+                        torch.empty(cap, dtype=f32, device=dev),
+                        torch.empty(1, dtype=torch.int64, device=dev))
+        self.PHASES = (("march_count", "march_fill") + (("field_sigma", "prune") if self.prune
+                                                         else ()) + ("field", "render", "grid_update"))
 
     def march_count(self):
         self.lib.march_count(self.rays_o, self.rays_d, self.grid_id, self.grid.bits, self.grid.desc,
@@ -126,18 +147,33 @@ class Step:
                             self.params, self.packed, self.ray_indices, self.t_starts, self.t_ends,
                             self.status, self.skip, self.ws)
 
-    def field_eval(self):
+    def field_sigma(self):
+        """Densities only, of every marched sample (the sigma_fn of the paper)."""
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
                                      self.rays_o, self.rays_d, self.grid_id, self.ray_indices,
-                                     self.t_starts, self.t_ends, self.sigmas, self.rgbs,
-                                     self.total)
+                                     self.t_starts, self.t_ends, self.sig_all, None, self.total)
+
+    def prune_samples(self):
+        packed_k, ri_k, ts_k, te_k, total_k = self.cur
+        self.lib.prune_count(self.packed, self.t_starts, self.t_ends, self.sig_all,
+                             self.w.early_stop_eps, self.alpha_thre, self.keep, packed_k, total_k,
+                             self.prune_ws)
+        self.lib.prune_fill(self.packed, self.t_starts, self.t_ends, self.sig_all, self.keep,
+                            packed_k, ri_k, ts_k, te_k, None, self.status)
+
+    def field_eval(self):
+        packed, ri, ts, te, total = self.cur
+        self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
+                                     self.rays_o, self.rays_d, self.grid_id, ri, ts, te,
+                                     self.sigmas, self.rgbs, total)
 
     def render(self):
+        packed, _, ts, te, _ = self.cur
         if self.forward_only:
-            self.lib.render_fwd(self.packed, self.t_starts, self.t_ends, self.sigmas, self.rgbs,
+            self.lib.render_fwd(packed, ts, te, self.sigmas, self.rgbs,
                                 self.w.early_stop_eps, self.color, self.opacity, self.depth)
         else:
-            self.lib.render_fwd_bwd_mse(self.packed, self.t_starts, self.t_ends, self.sigmas,
+            self.lib.render_fwd_bwd_mse(packed, ts, te, self.sigmas,
                                         self.rgbs, self.w.early_stop_eps, self.target, self.color,
                                         self.opacity, self.depth, self.g_sigmas, self.g_rgbs,
                                         self.loss, self.mse_ws, self.loss_rays)
@@ -157,20 +193,23 @@ class Step:
             lib.grid_build_skip(g.bits, g.desc, g.skip)
         self.updates.add_(1)
 
-    PHASES = ("march_count", "march_fill", "field", "render", "grid_update")
-
     def step(self, update=False, events=None):
-        fns = (self.march_count, self.march_fill, self.field_eval, self.render)
+        """One step; events (optional): len(PHASES) + 1 HIP events, recorded
+        before each phase and after the last."""
+        fns = [self.march_count, self.march_fill]
+        if self.prune:
+            fns += [self.field_sigma, self.prune_samples]
+        fns += [self.field_eval, self.render]
         for j, fn in enumerate(fns):
             if events is not None:
                 events[j].record()
             fn()
         if events is not None:
-            events[4].record()
+            events[len(fns)].record()
         if update:
             self.grid_update()
         if events is not None:
-            events[5].record()
+            events[len(fns) + 1].record()
 
     def outputs(self):
         """Tensors a change of launch parameters must leave bit-identical."""
@@ -209,6 +248,55 @@ def algorithmic_bytes(n_rays, e, v, forward_only=False):
         # (16 B) and the target read (40 B/ray in all)
         "render": (24 * v + 28 * n_rays) if forward_only else (24 * v + 16 * e + 40 * n_rays),
     }
+
+
+# Lane operations per lattice candidate of the marching contract (what the
+# count pass must compute for every candidate it tests): uniform steps,
+# t_k and t_k+1 (int->float, multiply, add each), the midpoint (add,
+# multiply), the position (3 multiplies, 3 adds), the cell coordinate
+# (3 subtracts, 3 multiplies, 3 clamps, 3 float->int), the cell index
+# (2 multiply-adds), word index and bit (2), the bit test (2): 33.  Cone
+# steps replace the 6 of the t's by the 4 of the recurrence step and the
+# cascade adds the level (3 abs, 2 max, 4 for the exponent) and 3 exact
+# scalings: 43.
+OPS_PER_CANDIDATE = {"uniform": 33, "cone": 43}
+# One FP32 / integer lane operation per lane per clock: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz (the 157.3 TFLOP/s vector figure counts an FMA as two
+# and two lanes per instruction through packed math, which this build does
+# not use).
+ALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def lattice_candidates(w, rays_o, rays_d):
+    """Lattice candidates the count pass tests (FP64 slab clip; cone steps by
+    running the recurrence in FP32 for all rays at once)."""
+    import numpy as np
+    o = rays_o.astype(np.float64)
+    d = rays_d.astype(np.float64)
+    cascades = getattr(w, "cascades", 1)
+    lo = np.asarray(w.box[:3], np.float64) * 2.0 ** (cascades - 1)
+    hi = np.asarray(w.box[3:], np.float64) * 2.0 ** (cascades - 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ta = (lo - o) / d
+        tb = (hi - o) / d
+    t_in = np.nanmax(np.minimum(ta, tb), axis=1)
+    t_out = np.nanmin(np.maximum(ta, tb), axis=1)
+    t_near = np.maximum(t_in, w.near)
+    t_far = np.minimum(t_out, w.far)
+    hit = t_near < t_far
+    cone = getattr(w, "cone", 0.0)
+    if cone == 0.0:
+        return int(np.ceil((t_far[hit] - t_near[hit]) / w.dt).sum())
+    t = t_near[hit].astype(np.float32)
+    tf = t_far[hit].astype(np.float32)
+    c, dt, dmax = np.float32(cone), np.float32(w.dt), np.float32(getattr(w, "dt_max", 1e10))
+    n = 0
+    live = t < tf
+    while live.any():
+        n += int(live.sum())
+        t = np.where(live, t + np.minimum(np.maximum(t * c, dt), dmax), t)
+        live = t < tf
+    return n
 
 
 def recorded_traffic(kernel, source):
@@ -260,11 +348,12 @@ def cpu_baseline(w, inp, n_sample, forward_only=False):
 
 
 def kept_fraction(st, e_last):
-    """Samples before the early-termination cut / all samples, from one
-    forward with per-ray kept counts (outside the timed region)."""
+    """Rendered samples before the early-termination cut / rendered samples,
+    from one forward with per-ray kept counts (outside the timed region)."""
     torch = st.torch
+    packed, _, ts, te, _ = st.cur
     kept = torch.empty(st.n, dtype=torch.int32, device="cuda")
-    st.lib.render_fwd(st.packed, st.t_starts, st.t_ends, st.sigmas, st.rgbs, st.w.early_stop_eps,
+    st.lib.render_fwd(packed, ts, te, st.sigmas, st.rgbs, st.w.early_stop_eps,
                       st.color, st.opacity, st.depth, None, kept)
     return int(kept.sum().item()) / max(e_last, 1)
 
@@ -273,14 +362,15 @@ def phase_timing(torch, st, steps, first_index, updates=True):
     """Per-phase HIP-event times of `steps` eager steps (grid update every 16
     steps, if `updates`)."""
     import numpy as np
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(st.PHASES) + 1)]
+              for _ in range(steps)]
     upd = [updates and (first_index + k) % EMA_EVERY == 0 for k in range(steps)]
     for k in range(steps):
         st.step(update=upd[k], events=events[k])
     torch.cuda.synchronize()
-    out = {p: [] for p in Step.PHASES}
+    out = {p: [] for p in st.PHASES}
     for k in range(steps):
-        for j, p in enumerate(Step.PHASES):
+        for j, p in enumerate(st.PHASES):
             if p == "grid_update" and not upd[k]:
                 continue
             out[p].append(events[k][j].elapsed_time(events[k][j + 1]))
@@ -304,7 +394,8 @@ def bench_train(args, torch, nacc):
     grid.set_occupancy(t(inp["occ"]), THRESHOLD)
     field = nacc.BlobField(inp["scene"], device=dev)
     st = Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid, field,
-              skip_field=args.skip_field == "on", forward_only=forward_only, seed=4000 + w.seed_base)
+              skip_field=args.skip_field == "on", forward_only=forward_only, seed=4000 + w.seed_base,
+              alpha_thre=args.alpha_thre)
     torch.cuda.synchronize()
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18  # float32 elements
@@ -335,6 +426,7 @@ def bench_train(args, torch, nacc):
         log("captured the step in HIP graphs")
 
     totals = torch.empty(steps, dtype=torch.int64, device="cuda")
+    rendered = torch.empty(steps, dtype=torch.int64, device="cuda")
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -347,6 +439,7 @@ def bench_train(args, torch, nacc):
         else:
             st.step(update=upd)
         totals[k:k + 1].copy_(st.total)
+        rendered[k:k + 1].copy_(st.cur[4])
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -357,18 +450,43 @@ def bench_train(args, torch, nacc):
     e_total = int(e_steps.sum())
     phase_avg = phase_timing(torch, st, min(steps, 32), warmup + steps)
     e_mean = e_total / steps
-    v_frac = kept_fraction(st, int(e_steps[-1]))
-    alg = algorithmic_bytes(st.n, e_mean, e_mean * v_frac, forward_only)
+    k_steps = rendered.cpu().numpy()
+    k_mean = float(k_steps.mean())  # samples shaded and rendered (= e_mean unpruned)
+    v_frac = kept_fraction(st, int(k_steps[-1]))
+    alg = algorithmic_bytes(st.n, k_mean, k_mean * v_frac, forward_only)
+    # marching moves the marched samples; the field and render the rendered ones
+    alg["march_fill"] = algorithmic_bytes(st.n, e_mean, e_mean, forward_only)["march_fill"]
+    if st.prune:
+        # densities in, keep flags out; then flags in, kept intervals copied
+        alg["prune"] = 13 * e_mean + 16 * st.n + (1 * e_mean + 8 * k_mean + 12 * k_mean)
+        alg["field_sigma"] = 16 * e_mean + 24 * st.n
     # the dominant kernel of the path itself (the synthetic field stands in for
     # the user's radiance field and is reported, not ranked)
-    per_launch = {p: phase_avg[p] for p in alg if p != "field"}
+    per_launch = {p: phase_avg[p] for p in alg if p not in ("field", "field_sigma")}
     dominant = max(per_launch, key=per_launch.get)
-    achieved = alg[dominant] / (phase_avg[dominant] * 1e-3)
     step_ms = ms_total / steps
     step_bytes = sum(alg.values())
-    traffic = None
-    if dominant == "render" and not forward_only:
-        traffic = recorded_traffic("render_mse_kernel", "paper_2210_04847_amd/csrc/render.hip")
+    render_bps = alg["render"] / (phase_avg["render"] * 1e-3)
+    render_roofline = {
+        "bound": "hbm", "kernel": "render", "achieved": render_bps / 1e9, "peak": HBM_PEAK / 1e9,
+        "unit": "GB/s", "frac": render_bps / HBM_PEAK,
+        "traffic": (recorded_traffic("render_mse_kernel", "paper_2210_04847_amd/csrc/render.hip")
+                    if not forward_only else None)}
+    if dominant == "march_count":
+        # the count pass is bound by its per-candidate arithmetic
+        cands = lattice_candidates(w, inp["rays_o"], inp["rays_d"])
+        ops = cands * OPS_PER_CANDIDATE["cone" if getattr(w, "cone", 0.0) > 0 else "uniform"]
+        ops_s = ops / (phase_avg["march_count"] * 1e-3)
+        roofline = {"bound": "alu", "kernel": "march_count", "achieved": ops_s / 1e12,
+                    "peak": ALU_PEAK / 1e12, "unit": "TOP/s", "frac": ops_s / ALU_PEAK,
+                    "traffic": None, "candidates": cands}
+    elif dominant == "render":
+        roofline = render_roofline
+    else:
+        bps = alg[dominant] / (phase_avg[dominant] * 1e-3)
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": bps / 1e9,
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bps / HBM_PEAK,
+                    "traffic": None}
     result = {
         "metric": METRIC,
         "value": e_total / (ms_total * 1e-3),
@@ -390,17 +508,21 @@ def bench_train(args, torch, nacc):
                    "pass": "forward" if forward_only else "forward+mse+backward",
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
                    "form": args.form, "skip_field": args.skip_field, "tuning": tuned,
+                   "visibility_pruning": (None if args.alpha_thre is None else
+                                          {"early_stop_eps": w.early_stop_eps,
+                                           "alpha_thre": args.alpha_thre}),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9,
-                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic},
+        "roofline": roofline,
+        "roofline_render": render_roofline,
         "samples_per_step": e_mean,
+        "rendered_samples_per_step": k_mean,
         "kept_fraction": v_frac,
         "phase_ms": phase_avg,
         "phase_gbps": {p: alg[p] / (phase_avg[p] * 1e-3) / 1e9 for p in alg if phase_avg[p] > 0},
         "step_alg_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (step_ms * 1e-3) / HBM_PEAK,
-        "path_samples_per_s": e_mean / (1e-3 * (step_ms - phase_avg["field"])),
+        "path_samples_per_s": e_mean / (1e-3 * (step_ms - phase_avg["field"]
+                                                - phase_avg.get("field_sigma", 0.0))),
         "wall_s": wall,
         "cpu_baseline": None,
     }

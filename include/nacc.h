@@ -151,13 +151,15 @@ const char* nacc_version(void);
  *                          (4).
  *   render_mse_max_blocks  workgroups of the fused loss kernel, 1..2^20
  *                          (8192).
+ *   render_prefetch        0 or 1 (0): the fused loss kernel loads the
+ *                          next ray's first chunk during a ray's backward.
  * Workspace sizes do not depend on these settings.
  */
 typedef struct nacc_tuning {
     int32_t march_waves_per_group;
     int32_t render_cached_chunks;
     int32_t render_mse_max_blocks;
-    int32_t reserved;
+    int32_t render_prefetch;
 } nacc_tuning;
 
 void nacc_get_tuning(nacc_tuning* out);
@@ -283,6 +285,53 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays,
                     float early_stop_eps, const float* g_color,
                     const float* g_opacity, const float* g_depth,
                     float* g_sigmas, float* g_rgbs, void* stream);
+
+/*
+ * Visibility pruning of marched samples (Sec. 2.1, "Pruning Empty and
+ * Occluded Regions"; the ray_marching call of Sec. 3 with sigma_fn,
+ * early_stop_eps and alpha_thre): given the densities of the samples (the
+ * caller's field evaluated without gradients), sample i of a ray is kept
+ * iff its transmittance T_i is at least early_stop_eps (the renderer's
+ * transmittance and cut: everything from the first T_i < eps on is
+ * dropped; eps = 0 keeps every sample) and its opacity
+ * alpha_i = 1 - exp(-sigma_i delta_i) is at least alpha_thre.  Dropped
+ * samples still attenuate the ones behind them.  Compaction follows the
+ * marching pattern: count + scan, then fill.
+ */
+/* Bytes of device workspace nacc_prune_count needs (>= 0). */
+int64_t nacc_prune_workspace_size(int64_t n_rays);
+
+/*
+ * Pass 1: keep flags and the packed layout of the kept samples.
+ *   packed_info, n_rays, n_samples, t_starts, t_ends, sigmas: the marched
+ *               samples as for the rendering calls.
+ *   keep        out uint8[n_samples]: 1 = kept (every sample of a ray
+ *               whose range lies inside n_samples is written).
+ *   packed_out  out int32[n_rays][2]: (start, count) of the kept samples.
+ *   total       out int64[1]: number kept, on the device.
+ *   workspace   device scratch of nacc_prune_workspace_size bytes.
+ */
+int nacc_prune_count(const int32_t* packed_info, int64_t n_rays,
+                     int64_t n_samples, const float* t_starts,
+                     const float* t_ends, const float* sigmas,
+                     float early_stop_eps, float alpha_thre, uint8_t* keep,
+                     int32_t* packed_out, int64_t* total, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/*
+ * Pass 2: writes the kept samples in order at their packed_out slots:
+ * ray_indices_out, t_starts_out, t_ends_out (and sigmas_out, nullable:
+ * the densities, so the caller need not evaluate them again), each with
+ * room for `capacity` samples.  Samples past capacity are dropped and
+ * *status (nullable, device) is set to NACC_ECAPACITY.
+ */
+int nacc_prune_fill(const int32_t* packed_info, int64_t n_rays,
+                    int64_t n_samples, const float* t_starts,
+                    const float* t_ends, const float* sigmas,
+                    const uint8_t* keep, const int32_t* packed_out,
+                    int64_t capacity, int32_t* ray_indices_out,
+                    float* t_starts_out, float* t_ends_out,
+                    float* sigmas_out, int32_t* status, void* stream);
 
 /* Bytes of device workspace nacc_render_fwd_bwd_mse needs (>= 0; the same
  * under every nacc_tuning, so a workspace stays valid after retuning). */

@@ -80,6 +80,8 @@ def _load():
     lib.oracle_grid_threshold.argtypes = [_P, _I64, _F, _P]
     lib.oracle_sample_positions.restype = None
     lib.oracle_sample_positions.argtypes = [_P, _P, _P, _P, _P, _I64, _P]
+    lib.oracle_prune.restype = _I64
+    lib.oracle_prune.argtypes = [_P, _I64, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P]
     lib.oracle_blob_field.restype = None
     lib.oracle_blob_field.argtypes = [_P, _P, _I64, _P, _P, _P, _I32, _P, _P,
                                       _I32, _P, _P]
@@ -202,6 +204,22 @@ def render_bwd(packed_info, t_starts, t_ends, sigmas, rgbs, g_color,
     if rc != 0:
         raise MemoryError("oracle_render_bwd: allocation failed")
     return dict(g_sigmas=gs, g_rgbs=gr, scale=scale)
+
+
+def prune(packed_info, t_starts, t_ends, sigmas, eps=1e-4, alpha_thre=0.0):
+    """Visibility pruning of marched samples (Sec. 2.1 occluded regions;
+    Sec. 3 ray_marching with sigma_fn): keep iff T_i >= eps and alpha_i >=
+    alpha_thre, FP64.  Returns (keep u8 [E], counts i32 [R])."""
+    lib = _load()
+    pk = _c(packed_info, np.int32).reshape(-1, 2)
+    ts = _c(t_starts, np.float64)
+    te = _c(t_ends, np.float64)
+    sg = _c(sigmas, np.float64)
+    keep = np.zeros(ts.size, np.uint8)
+    counts = np.zeros(pk.shape[0], np.int32)
+    lib.oracle_prune(_ptr(pk), pk.shape[0], _ptr(ts), _ptr(te), _ptr(sg), float(eps),
+                     float(alpha_thre), _ptr(keep), _ptr(counts))
+    return keep, counts
 
 
 def mse_loss_and_grad(color, target):

@@ -244,6 +244,40 @@ void oracle_clip(const float* rays_o, const float* rays_d, int64_t n_rays,
 /* dropped once T_i < eps (eps = 0 disables it).                            */
 /* ------------------------------------------------------------------------ */
 
+/* Visibility pruning while marching (Sec. 2.1, "Pruning Empty and Occluded
+ * Regions"; the ray_marching call of Sec. 3 with sigma_fn, early_stop_eps and
+ * alpha_thre): with the densities of the marched samples, sample i of a ray
+ * is kept iff its transmittance T_i = exp(-sum_{j<i} sigma_j delta_j) is at
+ * least eps (so everything from the first T_i < eps on is dropped) and its
+ * opacity alpha_i = 1 - exp(-sigma_i delta_i) is at least alpha_thre.  Every
+ * sample, kept or not, adds to the transmittance of the ones after it.
+ * FP64.  Outputs keep[n_samples] (0/1) and counts[n_rays]; returns the
+ * number kept. */
+int64_t oracle_prune(const int32_t* packed_info, int64_t n_rays,
+                     const double* t_starts, const double* t_ends,
+                     const double* sigmas, double eps, double alpha_thre,
+                     uint8_t* keep, int32_t* counts) {
+    int64_t total = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        int64_t start = packed_info[2 * r], n = packed_info[2 * r + 1];
+        double prefix = 0.0;
+        int32_t kept = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t s = start + i;
+            double tau = sigmas[s] * (t_ends[s] - t_starts[s]);
+            double trans = exp(-prefix);
+            double alpha = -expm1(-tau);
+            int k = trans >= eps && alpha >= alpha_thre;
+            keep[s] = (uint8_t)k;
+            kept += k;
+            prefix += tau;
+        }
+        counts[r] = kept;
+        total += kept;
+    }
+    return total;
+}
+
 /* Forward in FP64 (inputs are FP64 arrays; FP32 data converts exactly).
  * Outputs: color[n_rays*3], opacity[n_rays], depth[n_rays]
  * (depth = sum w * (t_start + t_end) / 2), weights[n_samples] (nullable,

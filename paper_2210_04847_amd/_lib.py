@@ -36,7 +36,7 @@ class GridDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("march_waves_per_group", ctypes.c_int32), ("render_cached_chunks", ctypes.c_int32),
-                ("render_mse_max_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("render_mse_max_blocks", ctypes.c_int32), ("render_prefetch", ctypes.c_int32)]
 
 
 class MarchParams(ctypes.Structure):
@@ -77,6 +77,9 @@ _SIGNATURES = {
     "nacc_grid_pack": (_INT, [_P, _I64, _F, _P, _P]),
     "nacc_grid_skip_bytes": (_I64, [ctypes.POINTER(GridDesc)]),
     "nacc_grid_build_skip": (_INT, [_P, ctypes.POINTER(GridDesc), _P, _P]),
+    "nacc_prune_workspace_size": (_I64, [_I64]),
+    "nacc_prune_count": (_INT, [_P, _I64, _I64, _P, _P, _P, _F, _F, _P, _P, _P, _P, _SZ, _P]),
+    "nacc_prune_fill": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
     "nacc_synth_table_size": (_I64, [_I32, _I32]),
     "nacc_synth_prepare": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
@@ -115,7 +118,7 @@ def version() -> str:
 def get_tuning() -> dict:
     t = Tuning()
     lib.nacc_get_tuning(ctypes.byref(t))
-    return {name: getattr(t, name) for name, _ in Tuning._fields_ if name != "reserved"}
+    return {name: getattr(t, name) for name, _ in Tuning._fields_}
 
 
 def set_tuning(**kw) -> None:
@@ -124,7 +127,7 @@ def set_tuning(**kw) -> None:
     cur = get_tuning()
     cur.update(kw)
     t = Tuning(cur["march_waves_per_group"], cur["render_cached_chunks"],
-               cur["render_mse_max_blocks"], 0)
+               cur["render_mse_max_blocks"], cur["render_prefetch"])
     _check("nacc_set_tuning", lib.nacc_set_tuning(ctypes.byref(t)))
 
 
@@ -346,6 +349,48 @@ def grid_pack(occ, threshold, bits, stream=None):
 
 def synth_table_size(n_blobs, n_sets) -> int:
     return int(lib.nacc_synth_table_size(n_blobs, n_sets))
+
+
+def prune_workspace_size(n_rays: int) -> int:
+    return int(lib.nacc_prune_workspace_size(int(n_rays)))
+
+
+def prune_count(packed_info, t_starts, t_ends, sigmas, early_stop_eps, alpha_thre, keep, packed_out,
+                total, workspace, stream=None):
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(packed_out, torch.int32, "packed_out", 2 * n)
+    for t, nm in ((t_starts, "t_starts"), (t_ends, "t_ends"), (sigmas, "sigmas")):
+        _need(t, torch.float32, nm, e)
+    _need(keep, torch.uint8, "keep", e)
+    _need(total, torch.int64, "total", 1)
+    _need(workspace, torch.uint8, "workspace")
+    _check("nacc_prune_count", lib.nacc_prune_count(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), float(early_stop_eps),
+        float(alpha_thre), _ptr(keep), _ptr(packed_out), _ptr(total), _ptr(workspace),
+        workspace.numel(), _stream(stream)))
+
+
+def prune_fill(packed_info, t_starts, t_ends, sigmas, keep, packed_out, ray_indices_out,
+               t_starts_out, t_ends_out, sigmas_out=None, status=None, stream=None):
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    cap = t_starts_out.numel()
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(packed_out, torch.int32, "packed_out", 2 * n)
+    for t, nm in ((t_starts, "t_starts"), (t_ends, "t_ends")):
+        _need(t, torch.float32, nm, e)
+    _need(sigmas, torch.float32, "sigmas", e)
+    _need(keep, torch.uint8, "keep", e)
+    _need(ray_indices_out, torch.int32, "ray_indices_out", cap)
+    _need(t_ends_out, torch.float32, "t_ends_out", cap)
+    _need(sigmas_out, torch.float32, "sigmas_out", cap)
+    _need(status, torch.int32, "status", 1)
+    _check("nacc_prune_fill", lib.nacc_prune_fill(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(keep),
+        _ptr(packed_out), cap, _ptr(ray_indices_out), _ptr(t_starts_out), _ptr(t_ends_out),
+        _ptr(sigmas_out), _ptr(status), _stream(stream)))
 
 
 SYNTH_CONTRACT = 1

@@ -103,13 +103,54 @@ class OccupancyGrid:
 
 def ray_marching(rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0, far_plane=1e10,
                  render_step_size=STEP_1024, cone_angle=0.0, dt_max=1e10, max_per_ray=0,
-                 grid_id=None, skip_empty=True, replay_masks=True):
+                 grid_id=None, skip_empty=False, replay_masks=True, sigma_fn=None,
+                 early_stop_eps=1e-4, alpha_thre=0.0):
     """Marches the rays through the occupancy grid (Sec. 2.1) and returns the
     packed samples (Sec. 3): packed_info [R, 2] int32 (start, count),
     ray_indices [E] int32, t_starts [E], t_ends [E] float32.  One device-to-host
     copy of the total sizes the outputs exactly.  skip_empty uses the grid's
-    skip grid and replay_masks lets the fill pass reuse the count pass's
-    occupancy masks (same samples either way, less work)."""
+    skip field and replay_masks lets the fill pass reuse the count pass's
+    occupancy masks (same samples either way).  With sigma_fn(t_starts,
+    t_ends, ray_indices) -> densities, the samples are then pruned by
+    visibility (prune_samples: T >= early_stop_eps, alpha >= alpha_thre),
+    evaluating sigma_fn without gradients."""
+    out = _march(rays_o, rays_d, grid, near_plane, far_plane, render_step_size, cone_angle, dt_max,
+                 max_per_ray, grid_id, skip_empty, replay_masks)
+    if sigma_fn is None:
+        return out
+    packed, ray_indices, t_starts, t_ends = out
+    with torch.no_grad():
+        sig = sigma_fn(t_starts, t_ends, ray_indices)
+    sig = torch.as_tensor(sig, dtype=torch.float32).reshape(-1).contiguous()
+    return prune_samples(packed, t_starts, t_ends, sig, early_stop_eps, alpha_thre)[:4]
+
+
+def prune_samples(packed_info, t_starts, t_ends, sigmas, early_stop_eps=1e-4, alpha_thre=0.0):
+    """Visibility pruning (Sec. 2.1, occluded regions): keeps the samples whose
+    transmittance is at least early_stop_eps and whose opacity is at least
+    alpha_thre, given their densities.  Returns (packed_info, ray_indices,
+    t_starts, t_ends, sigmas) of the kept samples."""
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    dev = t_starts.device
+    keep = torch.empty(max(e, 1), dtype=torch.uint8, device=dev)[:e]
+    packed_out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(_lib.prune_workspace_size(n), 1), dtype=torch.uint8, device=dev)
+    ts, te, sg = _flat(t_starts), _flat(t_ends), sigmas.reshape(-1).contiguous()
+    _lib.prune_count(packed_info.contiguous(), ts, te, sg, early_stop_eps, alpha_thre, keep,
+                     packed_out, total, ws)
+    k = int(total.item())
+    ri = torch.empty(k, dtype=torch.int32, device=dev)
+    ts_o = torch.empty(k, dtype=torch.float32, device=dev)
+    te_o = torch.empty(k, dtype=torch.float32, device=dev)
+    sg_o = torch.empty(k, dtype=torch.float32, device=dev)
+    _lib.prune_fill(packed_info.contiguous(), ts, te, sg, keep, packed_out, ri, ts_o, te_o, sg_o)
+    return packed_out, ri, ts_o, te_o, sg_o
+
+
+def _march(rays_o, rays_d, grid, near_plane, far_plane, render_step_size, cone_angle, dt_max,
+           max_per_ray, grid_id, skip_empty, replay_masks):
     rays_o = rays_o.reshape(-1, 3).contiguous()
     rays_d = rays_d.reshape(-1, 3).contiguous()
     n = rays_o.shape[0]

@@ -2,7 +2,8 @@
 
 The knobs change speed, not results: rays per marching wave group, chunks of
 64 samples kept in registers per ray between the forward and backward
-passes, and the fused loss kernel's workgroup count.  Tuning is coordinate
+passes, the fused loss kernel's workgroup count and whether it loads the
+next ray's first chunk early.  Tuning is coordinate
 descent over the knobs on the caller's real workload: each candidate is timed
 with HIP events over a few steps and accepted only if the step's outputs are
 bit-identical to those of the reference setting (a candidate that changed a
@@ -18,6 +19,7 @@ CANDIDATES = {
     "render_cached_chunks": (1, 2, 3, 4),
     "march_waves_per_group": (1, 2, 4),
     "render_mse_max_blocks": (1024, 2048, 4096, 8192),
+    "render_prefetch": (0, 1),
 }
 
 

@@ -32,6 +32,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "scan.h"
 
 #pragma clang fp contract(off)
 
@@ -40,7 +41,6 @@ namespace {
 using namespace nacc;
 using namespace nacc::dev;
 
-constexpr int kRaysPerBlock = 64;     // rays per workgroup in count/fill/scan
 constexpr int kMaxCandidates = 1 << 24;
 
 struct GridK {
@@ -87,6 +87,10 @@ __device__ __forceinline__ bool clip_ray(const float o[3], const float d[3], con
     t_far = fminf(t_exit, far_plane);
     return !miss && t_near < t_far;
 }
+
+// min(max(u, 0), top) in one instruction (the median of the three; no NaN
+// reaches it for finite rays).
+__device__ __forceinline__ float clamp_cell(float u, float top) { return __builtin_amdgcn_fmed3f(u, 0.0f, top); }
 
 // Cascade level of a point with m = max_i |x_i|: the number of levels
 // l < n_grids - 1 with m > base 2^l, i.e. the smallest l with m <= base 2^l,
@@ -137,9 +141,9 @@ __device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0,
             x2 = x2 * f;
         }
     }
-    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x0 - g.lo[0]) * g.s[0], 0.0f), g.top)));
-    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x1 - g.lo[1]) * g.s[1], 0.0f), g.top)));
-    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(fminf(fmaxf((x2 - g.lo[2]) * g.s[2], 0.0f), g.top)));
+    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
+    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
+    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
     const uint32_t res = static_cast<uint32_t>(g.res);
     const uint32_t cell = (j0 * res + j1) * res + j2;
     q.word = word0 + (cell >> 5);
@@ -240,6 +244,41 @@ __device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id,
     return true;
 }
 
+// Where a ray is marched: its clipped range and the first word of its grid
+// (valid = false: an invalid grid id or a miss, no samples).  The uniform
+// kernels compute the spans of a wave's rays lane-parallel, one ray per
+// lane, and broadcast each one as the wave reaches its ray.
+struct RaySpan {
+    float t_near, t_far;
+    uint32_t word0;
+    bool valid;
+};
+
+template <int LOOKUP>
+__device__ __forceinline__ RaySpan ray_span(int64_t r, const float* __restrict__ rays_o,
+                                            const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+                                            const GridK& g, const ClipK& c, const StepK& p) {
+    RaySpan s;
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    s.valid = grid_of_ray<LOOKUP>(grid_id, r, g, s.word0);
+    s.valid = clip_ray(o, d, c, p.near_plane, p.far_plane, s.t_near, s.t_far) && s.valid;
+    return s;
+}
+
+__device__ __forceinline__ RaySpan read_span(const RaySpan& s, int lane) {
+    RaySpan b;
+    b.t_near = read_lane(s.t_near, lane);
+    b.t_far = read_lane(s.t_far, lane);
+    b.word0 = static_cast<uint32_t>(read_lane(static_cast<int>(s.word0), lane));
+    b.valid = read_lane(s.valid ? 1 : 0, lane) != 0;
+    return b;
+}
+
 // One ray, uniform steps, whole wave.  Returns the ray's sample count (the
 // same value in every lane).  FILL writes samples [0, limit) at `start`.
 // With SKIP, candidates inside a stretch the skip field clears are not
@@ -247,12 +286,13 @@ __device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id,
 // over at the cost of its lattice arithmetic.
 template <int LOOKUP, bool FILL, bool SKIP>
 __device__ __forceinline__ int march_ray_uniform(
-    int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
-    const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    int64_t r, const RaySpan& span, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
+    const GridK& g, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     bool& overflow, uint64_t* __restrict__ masks = nullptr, int n_masks = 0, int first_chunk = 0,
     int count0 = 0) {
+    if (!span.valid) return 0;
     const int lane = lane_id();
     float o[3], d[3];
 #pragma unroll
@@ -260,10 +300,8 @@ __device__ __forceinline__ int march_ray_uniform(
         o[i] = rays_o[3 * r + i];
         d[i] = rays_d[3 * r + i];
     }
-    uint32_t word0;
-    if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
-    float t_near, t_far;
-    if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    const uint32_t word0 = span.word0;
+    const float t_near = span.t_near, t_far = span.t_far;
     SkipRay sk{};
     if (SKIP) sk = skip_ray(g, o, d, t_far);
     float skip_end = -INFINITY;  // candidates with midpoint below it are empty
@@ -329,13 +367,20 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     __shared__ int64_t wave_total[WAVES];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    // this wave's rays are first + wave + j WAVES; lane j clips ray j
+    const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
+    RaySpan spans{0.0f, 0.0f, 0u, false};
+    if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays) {
+        spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
+    }
     int64_t total = 0;
     bool unused = false;
     for (int i = wave; i < kRaysPerBlock; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
+        const RaySpan span = read_span(spans, i / WAVES);
         const int n = march_ray_uniform<LOOKUP, false, SKIP>(
-            r, rays_o, rays_d, grid_id, bits, skip, g, c, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
+            r, span, rays_o, rays_d, bits, skip, g, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
             masks != nullptr ? masks + r * n_masks : nullptr, masks != nullptr ? n_masks : 0);
         if (lane_id() == 0) packed_info[2 * r + 1] = n;
         total += n;
@@ -355,20 +400,13 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
 // from there on.
 template <int LOOKUP, bool SKIP>
 __device__ __forceinline__ void fill_ray_from_masks(
-    int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
-    const GridK& g, const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
+    int64_t r, const RaySpan& span, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
+    const GridK& g, const StepK& p, int64_t start, int limit, int64_t capacity,
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow,
     const uint64_t* __restrict__ masks, int n_masks) {
     const int lane = lane_id();
-    float o[3], d[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
-    }
-    float t_near, t_far;
-    clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far);
+    const float t_near = span.t_near;
     const uint64_t mine = lane < n_masks ? masks[lane] : 0ull;  // one load: lane j holds chunk j
     int written = 0;
     for (int j = 0; j < n_masks && written < limit; ++j) {
@@ -394,9 +432,8 @@ __device__ __forceinline__ void fill_ray_from_masks(
         written += __popcll(m);
     }
     if (written < limit) {
-        march_ray_uniform<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
-                                              capacity, ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks,
-                                              written);
+        march_ray_uniform<LOOKUP, true, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
+                                              ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks, written);
     }
 }
 
@@ -409,6 +446,11 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
     int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
+    RaySpan spans{0.0f, 0.0f, 0u, false};
+    if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays && packed_info[2 * mine + 1] > 0) {
+        spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
+    }
     bool overflow = false;
     for (int i = wave; i < kRaysPerBlock; i += WAVES) {
         const int64_t r = first + i;
@@ -416,28 +458,26 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
         const int64_t start = packed_info[2 * r];
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
+        const RaySpan span = read_span(spans, i / WAVES);
         if (masks != nullptr) {
-            fill_ray_from_masks<LOOKUP, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
-                                              capacity, ray_indices, t_starts, t_ends, overflow, masks + r * n_masks,
-                                              n_masks);
+            fill_ray_from_masks<LOOKUP, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
+                                              ray_indices, t_starts, t_ends, overflow, masks + r * n_masks, n_masks);
         } else {
-            march_ray_uniform<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, start, limit,
-                                                  capacity, ray_indices, t_starts, t_ends, overflow);
+            march_ray_uniform<LOOKUP, true, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
+                                                  ray_indices, t_starts, t_ends, overflow);
         }
     }
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
 
 // Cone steps: the lattice is a recurrence in t, t_{k+1} = t_k +
-// min(max(t_k c, dt), dt_max), so one lane walks one ray.  Candidates are
-// taken kConeBatch at a time: the recurrence first (a few dependent FP32
-// operations per candidate), then the batch's grid words are all loaded
-// before any is tested, so each lane keeps several loads in flight.  Every
-// active lane of a wave is at the same candidate index, so the count pass
-// stores the occupancy bits of each chunk of 64 candidates chunk-major
-// (masks[chunk * n_rays + r]: a wave's stores are contiguous), and the fill
-// pass replays them, running only the recurrence; it traverses the grid
-// again only past the stored chunks.
+// min(max(t_k c, dt), dt_max), so a lane walks a stretch of one ray.
+// Candidates are taken kConeBatch at a time: the recurrence first (a few
+// dependent FP32 operations per candidate), then the batch's grid words are
+// all loaded before any is tested, so each lane keeps several loads in
+// flight.  The count pass stores the occupancy bits of each chunk of 64
+// candidates chunk-major (masks[chunk * n_rays + r]), and the fill pass
+// replays them, running only the recurrence.
 constexpr int kConeBatch = 8;
 static_assert(kWave % kConeBatch == 0, "a batch must not straddle two chunks");
 
@@ -449,7 +489,8 @@ __device__ __forceinline__ int cone_steps(float t, float t_far, const StepK& p, 
     int n_valid = kConeBatch;
 #pragma unroll
     for (int u = 0; u < kConeBatch; ++u) {
-        const float step = fminf(fmaxf(tb[u] * p.cone, p.dt), p.dt_max);
+        // min(max(t c, dt), dt_max) as one median (dt <= dt_max)
+        const float step = __builtin_amdgcn_fmed3f(tb[u] * p.cone, p.dt, p.dt_max);
         tb[u + 1] = tb[u] + step;
         if (n_valid == kConeBatch && !(tb[u] < t_far && tb[u + 1] > tb[u])) n_valid = u;
     }
@@ -495,17 +536,16 @@ __device__ __forceinline__ uint32_t cone_hits(const uint32_t* __restrict__ bits,
     return hits;
 }
 
-// One ray, cone steps, one lane: the count pass (FILL false: stores the
-// chunk masks) or the fill pass (FILL true: replays the stored masks, and
-// looks the grid up again only past them or without them).
-template <int LOOKUP, bool FILL, bool SKIP>
-__device__ __forceinline__ int march_ray_cone(
+// One ray, cone steps, one lane, traversing the grid: the fill pass when no
+// count-pass workspace is given (the same samples as the chunk-parallel
+// passes, for checking them and for callers that keep no workspace).
+template <int LOOKUP, bool SKIP>
+__device__ __forceinline__ void fill_ray_cone(
     int64_t r, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, const uint32_t* __restrict__ bits,
     const uint8_t* __restrict__ skip, const GridK& g,
     const ClipK& c, const StepK& p, int64_t start, int limit, int64_t capacity,
-    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    bool& overflow, uint64_t* __restrict__ masks, int n_masks, int64_t n_rays) {
+    float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow) {
     float o[3], d[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -513,81 +553,246 @@ __device__ __forceinline__ int march_ray_cone(
         d[i] = rays_d[3 * r + i];
     }
     uint32_t word0;
-    if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return 0;
+    if (!grid_of_ray<LOOKUP>(grid_id, r, g, word0)) return;
     float t_near, t_far;
-    if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return 0;
+    if (!clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far)) return;
     SkipRay sk{};
     if (SKIP) sk = skip_ray(g, o, d, t_far);
     float skip_end = -INFINITY;  // candidates with midpoint below it are empty
     int count = 0;
     float t = t_near;
-    uint64_t chunk_bits = 0ull;  // count: bits gathered so far in the chunk; fill: its stored mask
-    for (int k0 = 0; k0 < kMaxCandidates; k0 += kConeBatch) {
-        const int chunk = k0 / kWave;
-        const int shift = k0 % kWave;
-        const bool replay = FILL && chunk < n_masks;
-        if (replay && shift == 0) chunk_bits = masks[static_cast<int64_t>(chunk) * n_rays + r];
+    for (int k0 = 0; k0 < kMaxCandidates && count < limit; k0 += kConeBatch) {
         float tb[kConeBatch + 1];
         const int n_valid = cone_steps(t, t_far, p, tb);
-        uint32_t hits = replay ? static_cast<uint32_t>(chunk_bits >> shift) & ((1u << kConeBatch) - 1u)
-                               : cone_hits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, tb, n_valid);
-        hits &= (1u << n_valid) - 1u;
-        bool stop = false;  // a cap reached inside the batch
-        uint32_t kept = 0u;
+        const uint32_t hits =
+            cone_hits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, tb, n_valid) & ((1u << n_valid) - 1u);
 #pragma unroll
         for (int u = 0; u < kConeBatch; ++u) {
-            if (stop || ((hits >> u) & 1u) == 0u) continue;
-            if (p.max_per_ray > 0 && count >= p.max_per_ray) {
-                stop = true;
-                continue;
+            if (((hits >> u) & 1u) == 0u || count >= limit) continue;
+            const int64_t pos = start + count;
+            if (pos >= 0 && pos < capacity) {
+                t_starts[pos] = tb[u];
+                t_ends[pos] = tb[u + 1];
+            } else {
+                overflow = true;
             }
-            if (FILL) {
-                if (count >= limit) {
-                    stop = true;
-                    continue;
-                }
-                const int64_t pos = start + count;
-                if (pos >= 0 && pos < capacity) {
-                    if (ray_indices != nullptr) ray_indices[pos] = static_cast<int32_t>(r);
-                    t_starts[pos] = tb[u];
-                    t_ends[pos] = tb[u + 1];
-                } else {
-                    overflow = true;
-                }
-            }
-            kept |= 1u << u;
             ++count;
         }
-        stop = stop || n_valid < kConeBatch;  // or the ray ended inside the batch
-        if (!FILL) {
-            chunk_bits |= static_cast<uint64_t>(kept) << shift;
-            if (chunk < n_masks && (stop || shift + kConeBatch == kWave)) {
-                masks[static_cast<int64_t>(chunk) * n_rays + r] = chunk_bits;
-            }
-            if (shift + kConeBatch == kWave) chunk_bits = 0ull;
-        }
-        if (stop || (FILL && count >= limit)) break;
+        if (n_valid < kConeBatch) break;
         t = tb[kConeBatch];
     }
-    return count;
+}
+
+// Chunk-parallel cone marching.  The recurrence itself is cheap (four FP32
+// operations per candidate) but serial; the grid lookups are not.  A
+// pre-pass walks each ray's recurrence once, one lane per ray, and records
+// t at the start of every chunk of 64 candidates; the count and fill passes
+// then take one lane per (ray, chunk), so a launch has ~12 times as many
+// independent lanes as rays to hide the lookup latency.  Tasks are ordered
+// chunk-major (task = chunk * n_rays + ray): a wave's loads and stores of
+// the per-chunk arrays are contiguous.  A ray longer than the stored chunks
+// is finished by the task of its last stored chunk.
+template <int LOOKUP>
+__global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, GridK g, ClipK c, StepK p, int n_masks, float* __restrict__ chunk_t,
+    float* __restrict__ t_far_out, int32_t* __restrict__ extra) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    if (r >= n_rays) return;
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    uint32_t word0;
+    float t_near = 0.0f, t_far = 0.0f;
+    bool live = grid_of_ray<LOOKUP>(grid_id, r, g, word0);
+    live = clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far) && live;
+    t_far_out[r] = live ? t_far : -INFINITY;
+    extra[r] = 0;
+    float t = t_near;
+    for (int j = 0; j < n_masks; ++j) {
+        live = live && t < t_far;  // the chunk's first candidate exists
+        chunk_t[static_cast<int64_t>(j) * n_rays + r] = live ? t : INFINITY;
+        for (int u = 0; live && u < kWave; ++u) {
+            if (!(t < t_far)) {
+                live = false;
+                break;
+            }
+            const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+            if (!(t1 > t)) {
+                live = false;
+                break;
+            }
+            t = t1;
+        }
+    }
+}
+
+// Occupancy bits of the 64 candidates of one chunk from its first t; `ended`
+// tells whether the ray's candidates stop inside the chunk.
+template <int LOOKUP, bool SKIP>
+__device__ __forceinline__ uint64_t cone_chunk_bits(const uint32_t* __restrict__ bits,
+                                                    const uint8_t* __restrict__ skip, const GridK& g,
+                                                    const SkipRay& sk, float& skip_end, uint32_t word0,
+                                                    const float o[3], const float d[3], float& t, float t_far,
+                                                    const StepK& p, bool& ended) {
+    uint64_t m = 0ull;
+    ended = false;
+#pragma unroll 1
+    for (int b = 0; b < kWave / kConeBatch; ++b) {
+        float tb[kConeBatch + 1];
+        const int n_valid = cone_steps(t, t_far, p, tb);
+        const uint32_t hits =
+            cone_hits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, tb, n_valid) & ((1u << n_valid) - 1u);
+        m |= static_cast<uint64_t>(hits) << (b * kConeBatch);
+        if (n_valid < kConeBatch) {
+            ended = true;
+            break;
+        }
+        t = tb[kConeBatch];
+    }
+    return m;
+}
+
+constexpr int kTaskThreads = 256;
+
+template <int LOOKUP, bool SKIP>
+__global__ __launch_bounds__(kTaskThreads) void count_cone_chunks_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip, GridK g, StepK p,
+    int n_masks, const float* __restrict__ chunk_t, const float* __restrict__ t_far_in,
+    uint64_t* __restrict__ masks, int32_t* __restrict__ extra) {
+    const int64_t task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + threadIdx.x;
+    if (task >= static_cast<int64_t>(n_masks) * n_rays) return;
+    const int j = static_cast<int>(task / n_rays);
+    const int64_t r = task - static_cast<int64_t>(j) * n_rays;
+    float t = chunk_t[task];
+    if (!(t < INFINITY)) {
+        masks[task] = 0ull;
+        return;
+    }
+    const float t_far = t_far_in[r];
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    uint32_t word0;
+    grid_of_ray<LOOKUP>(grid_id, r, g, word0);  // valid: the ray has candidates
+    SkipRay sk{};
+    if (SKIP) sk = skip_ray(g, o, d, t_far);
+    float skip_end = -INFINITY;
+    bool ended;
+    masks[task] = cone_chunk_bits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, t, t_far, p, ended);
+    if (j == n_masks - 1 && !ended) {
+        // past the stored chunks: count the rest of the ray here
+        int count = 0;
+        for (int k0 = n_masks * kWave; k0 < kMaxCandidates; k0 += kWave) {
+            count += __popcll(
+                cone_chunk_bits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, t, t_far, p, ended));
+            if (ended) break;
+        }
+        extra[r] = count;
+    }
+}
+
+// Per-ray counts from the chunk masks (capped at max_per_ray) and the
+// workgroup sums of the scan.
+__global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_rays, int n_masks, int max_per_ray,
+                                                                    const uint64_t* __restrict__ masks,
+                                                                    const int32_t* __restrict__ extra,
+                                                                    int32_t* __restrict__ packed_info,
+                                                                    int64_t* __restrict__ block_sums) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    int n = 0;
+    if (r < n_rays) {
+        int64_t total = extra[r];
+        for (int j = 0; j < n_masks; ++j) total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
+        if (max_per_ray > 0) total = min(total, static_cast<int64_t>(max_per_ray));
+        n = static_cast<int>(min(total, static_cast<int64_t>(kMaxCandidates)));
+        packed_info[2 * r + 1] = n;
+    }
+    const int sum = wave_sum(n);  // <= 64 * 2^24 fits int32
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = sum;
 }
 
 template <int LOOKUP, bool SKIP>
-__global__ __launch_bounds__(kRaysPerBlock) void count_cone_kernel(
-    const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
-    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
-    bool unused = false;
-    int n = 0;
-    if (r < n_rays) {
-        n = march_ray_cone<LOOKUP, false, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, 0, 0, 0,
-                                                nullptr, nullptr, nullptr, unused, masks, n_masks, n_rays);
-        packed_info[2 * r + 1] = n;
+__global__ __launch_bounds__(kTaskThreads) void fill_cone_chunks_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip, GridK g, StepK p,
+    int n_masks, const float* __restrict__ chunk_t, const float* __restrict__ t_far_in,
+    const uint64_t* __restrict__ masks, const int32_t* __restrict__ packed_info, int64_t capacity,
+    float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status) {
+    const int64_t task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + threadIdx.x;
+    if (task >= static_cast<int64_t>(n_masks) * n_rays) return;
+    const int j = static_cast<int>(task / n_rays);
+    const int64_t r = task - static_cast<int64_t>(j) * n_rays;
+    float t = chunk_t[task];
+    if (!(t < INFINITY)) return;
+    const int limit = packed_info[2 * r + 1];
+    int idx = 0;  // samples of the ray before this chunk
+    for (int q = 0; q < j; ++q) idx += __popcll(masks[static_cast<int64_t>(q) * n_rays + r]);
+    if (idx >= limit) return;
+    const int64_t start = packed_info[2 * r];
+    const float t_far = t_far_in[r];
+    bool overflow = false;
+    auto emit = [&](float a, float b) {
+        const int64_t pos = start + idx;
+        if (pos >= 0 && pos < capacity) {
+            t_starts[pos] = a;
+            t_ends[pos] = b;
+        } else {
+            overflow = true;
+        }
+        ++idx;
+    };
+    const uint64_t m = masks[task];
+    bool ended = false;
+#pragma unroll 1
+    for (int b = 0; b < kWave / kConeBatch && idx < limit; ++b) {
+        float tb[kConeBatch + 1];
+        const int n_valid = cone_steps(t, t_far, p, tb);
+        const uint32_t hits = static_cast<uint32_t>(m >> (b * kConeBatch)) & ((1u << n_valid) - 1u);
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) {
+            if (((hits >> u) & 1u) != 0u && idx < limit) emit(tb[u], tb[u + 1]);
+        }
+        if (n_valid < kConeBatch) {
+            ended = true;
+            break;
+        }
+        t = tb[kConeBatch];
     }
-    const int s = wave_sum(n);  // <= 64 * 2^24 fits int32
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = s;
+    if (j == n_masks - 1 && !ended && idx < limit) {
+        // past the stored chunks: look the rest of the ray up again
+        float o[3], d[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            o[i] = rays_o[3 * r + i];
+            d[i] = rays_d[3 * r + i];
+        }
+        uint32_t word0;
+        grid_of_ray<LOOKUP>(grid_id, r, g, word0);
+        SkipRay sk{};
+        if (SKIP) sk = skip_ray(g, o, d, t_far);
+        float skip_end = -INFINITY;
+        for (int k0 = n_masks * kWave; k0 < kMaxCandidates && idx < limit; k0 += kConeBatch) {
+            float tb[kConeBatch + 1];
+            const int n_valid = cone_steps(t, t_far, p, tb);
+            const uint32_t hits = cone_hits<LOOKUP, SKIP>(bits, skip, g, sk, skip_end, word0, o, d, tb, n_valid) &
+                                  ((1u << n_valid) - 1u);
+#pragma unroll
+            for (int u = 0; u < kConeBatch; ++u) {
+                if (((hits >> u) & 1u) != 0u && idx < limit) emit(tb[u], tb[u + 1]);
+            }
+            if (n_valid < kConeBatch) break;
+            t = tb[kConeBatch];
+        }
+    }
+    if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
 
 template <int LOOKUP, bool SKIP>
@@ -595,18 +800,15 @@ __global__ __launch_bounds__(kRaysPerBlock) void fill_cone_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
-    int64_t capacity,
-    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
+    int64_t capacity, float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     if (r >= n_rays) return;
     const int limit = packed_info[2 * r + 1];
     if (limit == 0) return;
     bool overflow = false;
     // the ray indices are written by expand_rays_kernel, contiguously
-    march_ray_cone<LOOKUP, true, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, packed_info[2 * r],
-                                       limit, capacity, nullptr, t_starts, t_ends, overflow,
-                                       const_cast<uint64_t*>(masks), masks != nullptr ? n_masks : 0, n_rays);
+    fill_ray_cone<LOOKUP, SKIP>(r, rays_o, rays_d, grid_id, bits, skip, g, c, p, packed_info[2 * r], limit, capacity,
+                                t_starts, t_ends, overflow);
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
 }
 
@@ -630,56 +832,12 @@ __global__ __launch_bounds__(kExpandThreads) void expand_rays_kernel(const int32
     }
 }
 
-// Exclusive scan of the per-workgroup sums, in place, by one workgroup:
-// each thread sums a contiguous run, the 1024 run totals are scanned in LDS,
-// then each thread rewrites its run as exclusive offsets.  Integer, exact.
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(
-    int64_t* __restrict__ sums, int64_t nb, int64_t* __restrict__ total) {
-    __shared__ int64_t part[kScanThreads];
-    const int t = threadIdx.x;
-    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
-    const int64_t a = min(nb, static_cast<int64_t>(t) * per);
-    const int64_t b = min(nb, a + per);
-    int64_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += sums[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int64_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - s;
-    for (int64_t i = a; i < b; ++i) {
-        const int64_t v = sums[i];
-        sums[i] = run;
-        run += v;
-    }
-    if (t == kScanThreads - 1) *total = part[t];
-}
-
-// packed_info[r].start = offset of r's workgroup + exclusive scan of the
-// counts inside it (one wave = the workgroup's 64 rays).  Starts that do
-// not fit int32 saturate; the fill pass then reports NACC_ECAPACITY.
-__global__ __launch_bounds__(kRaysPerBlock) void finalize_starts_kernel(
-    const int64_t* __restrict__ block_offsets, int64_t n_rays, int32_t* __restrict__ packed_info) {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
-    const int n = r < n_rays ? packed_info[2 * r + 1] : 0;
-    const int incl = wave_inclusive_sum(n);
-    const int64_t start = block_offsets[blockIdx.x] + (incl - n);
-    if (r < n_rays) packed_info[2 * r] = static_cast<int32_t>(min(start, static_cast<int64_t>(INT32_MAX)));
-}
-
 __global__ void set_status_kernel(int32_t* status, int32_t value) { *status = value; }
 
 // --------------------------------------------------------------------------
 // Host side: validation and launch.
 // --------------------------------------------------------------------------
 
-int64_t num_blocks(int64_t n_rays) { return (n_rays + kRaysPerBlock - 1) / kRaysPerBlock; }
 
 // Longest [t_near, t_far) a ray can have: far - near, and (unless the
 // lookup contracts space, which has no clip box) the clip box's diagonal.
@@ -728,22 +886,54 @@ constexpr int kMaxMaskChunks = 32;
 // n_masks 64-bit occupancy masks per ray, one per chunk of 64 candidates,
 // written by the count pass and replayed by the fill pass.  n_masks covers
 // the longest possible ray (up to kMaxMaskChunks chunks).
+// Cone steps add, for the chunk-parallel passes: t at the start of every
+// chunk (chunk-major, +inf past the ray's candidates), each ray's t_far
+// (-inf: no samples) and its hits past the stored chunks.
 struct Layout {
     int64_t sums_bytes;
     int n_masks;
+    int64_t chunk_t_off, t_far_off, extra_off;  // cone steps only (0 otherwise)
     int64_t bytes;
 };
 
+int64_t align256(int64_t b) { return ((b + 255) / 256) * 256; }
+
 Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_march_params& p) {
     Layout l;
-    l.sums_bytes = ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+    l.sums_bytes = align256(num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)));
     l.n_masks = 0;
     if (p.dt > 0.0f) {
         const int64_t k = candidate_bound(grid, p);
         l.n_masks = static_cast<int>(std::min<int64_t>((k + kWave - 1) / kWave, kMaxMaskChunks));
     }
-    l.bytes = l.sums_bytes + n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t));
+    l.bytes = l.sums_bytes + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t)));
+    l.chunk_t_off = l.t_far_off = l.extra_off = 0;
+    if (p.cone > 0.0f) {
+        l.chunk_t_off = l.bytes;
+        l.t_far_off = l.chunk_t_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(float)));
+        l.extra_off = l.t_far_off + align256(n_rays * static_cast<int64_t>(sizeof(float)));
+        l.bytes = l.extra_off + align256(n_rays * static_cast<int64_t>(sizeof(int32_t)));
+    }
     return l;
+}
+
+struct ConeWork {
+    uint64_t* masks;  // [n_masks][n_rays]
+    float* chunk_t;   // [n_masks][n_rays]
+    float* t_far;     // [n_rays]
+    int32_t* extra;   // [n_rays]
+    int n_masks;
+};
+
+ConeWork cone_work(void* workspace, const Layout& l) {
+    char* b = static_cast<char*>(workspace);
+    ConeWork w;
+    w.masks = reinterpret_cast<uint64_t*>(b + l.sums_bytes);
+    w.chunk_t = reinterpret_cast<float*>(b + l.chunk_t_off);
+    w.t_far = reinterpret_cast<float*>(b + l.t_far_off);
+    w.extra = reinterpret_cast<int32_t*>(b + l.extra_off);
+    w.n_masks = l.n_masks;
+    return w;
 }
 
 int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uint32_t* bits,
@@ -834,13 +1024,24 @@ void launch_fill_uniform(int64_t nb, hipStream_t s, const float* o, const float*
                        bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
 }
 
+unsigned task_blocks(int n_masks, int64_t n_rays) {
+    return static_cast<unsigned>((static_cast<int64_t>(n_masks) * n_rays + kTaskThreads - 1) / kTaskThreads);
+}
+
 template <int LOOKUP, bool SKIP>
-void launch_count_impl(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                       int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c,
-                       const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
-    if (cone) {
-        hipLaunchKernelGGL((count_cone_kernel<LOOKUP, SKIP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
-                           bits, skip, g, c, p, packed, sums, masks, n_masks);
+void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const float* o, const float* d,
+                       const int32_t* gid, int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g,
+                       const ClipK& c, const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
+    if (cw != nullptr) {  // cone steps
+        hipLaunchKernelGGL((cone_starts_kernel<LOOKUP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, g, c, p,
+                           cw->n_masks, cw->chunk_t, cw->t_far, cw->extra);
+        if (cw->n_masks > 0) {
+            hipLaunchKernelGGL((count_cone_chunks_kernel<LOOKUP, SKIP>), dim3(task_blocks(cw->n_masks, n)),
+                               dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
+                               cw->t_far, cw->masks, cw->extra);
+        }
+        hipLaunchKernelGGL(cone_counts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, n, cw->n_masks, p.max_per_ray,
+                           cw->masks, cw->extra, packed, sums);
         return;
     }
     const int waves = tuning().march_waves_per_group;
@@ -854,13 +1055,19 @@ void launch_count_impl(bool cone, int64_t nb, hipStream_t s, const float* o, con
 }
 
 template <int LOOKUP, bool SKIP>
-void launch_fill_impl(bool cone, int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid,
-                      int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c,
-                      const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te,
-                      int32_t* status, const uint64_t* masks, int n_masks) {
+void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, const float* o, const float* d,
+                      const int32_t* gid, int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g,
+                      const ClipK& c, const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts,
+                      float* te, int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
-        hipLaunchKernelGGL((fill_cone_kernel<LOOKUP, SKIP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
-                           bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+        if (cw != nullptr && cw->n_masks > 0) {  // replay the count pass's chunks, one lane per chunk
+            hipLaunchKernelGGL((fill_cone_chunks_kernel<LOOKUP, SKIP>), dim3(task_blocks(cw->n_masks, n)),
+                               dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
+                               cw->t_far, cw->masks, packed, capacity, ts, te, status);
+        } else {  // traversal, one lane per ray
+            hipLaunchKernelGGL((fill_cone_kernel<LOOKUP, SKIP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                               bits, skip, g, c, p, packed, capacity, ts, te, status);
+        }
         const int64_t blocks = std::min<int64_t>((n + kExpandThreads / kWave - 1) / (kExpandThreads / kWave),
                                                  256 * 64);
         hipLaunchKernelGGL(expand_rays_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kExpandThreads), 0, s,
@@ -883,27 +1090,27 @@ void launch_fill_impl(bool cone, int64_t nb, hipStream_t s, const float* o, cons
 // The skip field serves the box and cascade lookups (res % 4 == 0); the
 // contraction lookup always marches without it.
 template <int LOOKUP, typename... A>
-void dispatch_count(const uint8_t* skip, bool cone, int64_t nb, hipStream_t s, const float* o, const float* d,
-                    const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
+void dispatch_count(const uint8_t* skip, const ConeWork* cw, int64_t nb, hipStream_t s, const float* o,
+                    const float* d, const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
     if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
         if (skip != nullptr) {
-            launch_count_impl<LOOKUP, true>(cone, nb, s, o, d, gid, n, bits, skip, a...);
+            launch_count_impl<LOOKUP, true>(cw, nb, s, o, d, gid, n, bits, skip, a...);
             return;
         }
     }
-    launch_count_impl<LOOKUP, false>(cone, nb, s, o, d, gid, n, bits, nullptr, a...);
+    launch_count_impl<LOOKUP, false>(cw, nb, s, o, d, gid, n, bits, nullptr, a...);
 }
 
 template <int LOOKUP, typename... A>
-void dispatch_fill(const uint8_t* skip, bool cone, int64_t nb, hipStream_t s, const float* o, const float* d,
-                   const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
+void dispatch_fill(const uint8_t* skip, bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, const float* o,
+                   const float* d, const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
     if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
         if (skip != nullptr) {
-            launch_fill_impl<LOOKUP, true>(cone, nb, s, o, d, gid, n, bits, skip, a...);
+            launch_fill_impl<LOOKUP, true>(cone, cw, nb, s, o, d, gid, n, bits, skip, a...);
             return;
         }
     }
-    launch_fill_impl<LOOKUP, false>(cone, nb, s, o, d, gid, n, bits, nullptr, a...);
+    launch_fill_impl<LOOKUP, false>(cone, cw, nb, s, o, d, gid, n, bits, nullptr, a...);
 }
 
 const uint8_t* usable_skip(const uint8_t* skip, const nacc_grid_desc& grid) {
@@ -965,18 +1172,24 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
     int64_t* sums = static_cast<int64_t*>(workspace);
     const bool cone = params->cone > 0.0f;
     const uint8_t* skip = usable_skip(grid_skip, *grid);
+    ConeWork cw_store{};
+    const ConeWork* cw = nullptr;
+    if (cone) {
+        cw_store = cone_work(workspace, lay);
+        cw = &cw_store;
+    }
     if (nb > 0) {
         switch (grid->lookup) {
             case NACC_LOOKUP_AABB:
-                dispatch_count<NACC_LOOKUP_AABB>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                dispatch_count<NACC_LOOKUP_AABB>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
                                                  p, packed_info, sums, masks, lay.n_masks);
                 break;
             case NACC_LOOKUP_CASCADE:
-                dispatch_count<NACC_LOOKUP_CASCADE>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
+                dispatch_count<NACC_LOOKUP_CASCADE>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
                                                     c, p, packed_info, sums, masks, lay.n_masks);
                 break;
             default:
-                dispatch_count<NACC_LOOKUP_CONTRACT>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits,
+                dispatch_count<NACC_LOOKUP_CONTRACT>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits,
                                                      g, c, p, packed_info, sums, masks, lay.n_masks);
                 break;
         }
@@ -1028,19 +1241,25 @@ int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* gri
         workspace != nullptr && lay.n_masks > 0
             ? reinterpret_cast<const uint64_t*>(static_cast<const char*>(workspace) + lay.sums_bytes)
             : nullptr;
+    ConeWork cw_store{};
+    const ConeWork* cw = nullptr;
+    if (cone && workspace != nullptr) {
+        cw_store = cone_work(const_cast<void*>(workspace), lay);
+        cw = &cw_store;
+    }
     switch (grid->lookup) {
         case NACC_LOOKUP_AABB:
-            dispatch_fill<NACC_LOOKUP_AABB>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
+            dispatch_fill<NACC_LOOKUP_AABB>(skip, cone, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c, p,
                                             packed_info, capacity, ray_indices, t_starts, t_ends, status, masks,
                                             lay.n_masks);
             break;
         case NACC_LOOKUP_CASCADE:
-            dispatch_fill<NACC_LOOKUP_CASCADE>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+            dispatch_fill<NACC_LOOKUP_CASCADE>(skip, cone, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
                                                p, packed_info, capacity, ray_indices, t_starts, t_ends, status, masks,
                                                lay.n_masks);
             break;
         default:
-            dispatch_fill<NACC_LOOKUP_CONTRACT>(skip, cone, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+            dispatch_fill<NACC_LOOKUP_CONTRACT>(skip, cone, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
                                                 p, packed_info, capacity, ray_indices, t_starts, t_ends, status,
                                                 masks, lay.n_masks);
             break;

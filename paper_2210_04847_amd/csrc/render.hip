@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "scan.h"
 
 #pragma clang fp contract(off)
 
@@ -222,16 +223,21 @@ struct RayCache {
     double carries;  // lane j: FP64 tau prefix at the start of chunk j (j < 64)
 };
 
-template <int K, bool ACCUM>
+template <int K, bool ACCUM, bool PRELOADED = false>
 __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* __restrict__ ts,
                                             const float* __restrict__ te, const float* __restrict__ sig,
                                             const float* __restrict__ rgb, float eps, RayCache<K>& cache, int& kept,
-                                            double& prefix_hi, float acc[3], float& acc_a, float& acc_d) {
+                                            double& prefix_hi, float acc[3], float& acc_a, float& acc_d,
+                                            const Sample& chunk0 = Sample{}) {
     const int lane = lane_id();
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const int i = c * kWave + lane;
-        cache.x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
+        if (PRELOADED && c == 0) {
+            cache.x[0] = chunk0;  // loaded while the previous ray was finished
+        } else {
+            cache.x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
+        }
     }
     double carry = 0.0, carry_prev = 0.0;
     kept = n;
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
 // gradient g_C = 2 (C - target) / (3 n_rays) follows, then the backward runs
 // on the cached chunks.  Rays are walked grid-stride so the
 // loss needs one partial sum per workgroup.
-template <int K>
+template <int K, bool PREFETCH>
 __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
@@ -391,16 +397,30 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
     double wave_total = 0.0;
-    for (int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave; r < n_rays; r += stride) {
-        int64_t start;
-        int n;
+    // PREFETCH: the next ray's range is read when a ray starts and its first
+    // chunk is loaded before the ray's backward pass, so those loads are in
+    // flight while the backward runs
+    int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave;
+    int64_t start = 0;
+    int n = 0;
+    Sample pre{};
+    if (PREFETCH && r < n_rays) {
         ray_range(packed_info, r, n_samples, start, n);
+        pre = load_sample(lane < n, start + lane, ts, te, sig, rgb);
+    }
+    for (; r < n_rays; r += stride) {
+        if (!PREFETCH) ray_range(packed_info, r, n_samples, start, n);
+        const int64_t r_next = r + stride;
+        int64_t start_next = 0;
+        int n_next = 0;
+        if (PREFETCH && r_next < n_rays) ray_range(packed_info, r_next, n_samples, start_next, n_next);
         RayCache<K> cache;
         int kept;
         double prefix_hi;
         float acc[3] = {0.0f, 0.0f, 0.0f};
         float acc_a = 0.0f, acc_d = 0.0f;
-        ray_forward<K, true>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d);
+        ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
+                                       pre);
         const float cr = wave_sum(acc[0]);
         const float cg = wave_sum(acc[1]);
         const float cb = wave_sum(acc[2]);
@@ -421,7 +441,12 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
             opacity[r] = acc_a;
             depth[r] = acc_d;
         }
+        if (PREFETCH) pre = load_sample(lane < n_next, start_next + lane, ts, te, sig, rgb);
         if (n > 0) ray_backward<K>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+        if (PREFETCH) {
+            start = start_next;
+            n = n_next;
+        }
     }
     if (lane == 0) wave_loss[wave] = wave_total;
     __syncthreads();
@@ -485,10 +510,117 @@ struct LaunchMse {
                     const float* ts, const float* te, const float* sig, const float* rgb, float eps, const float* target,
                     float inv_count2, float* color, float* opacity, float* depth, float* g_sig, float* g_rgb,
                     double* partial) {
-        hipLaunchKernelGGL(render_mse_kernel<K>, grid, dim3(kRenderThreads), 0, s, packed_info, n_rays, n_samples, ts,
-                           te, sig, rgb, eps, target, inv_count2, color, opacity, depth, g_sig, g_rgb, partial);
+        if (tuning().render_prefetch != 0) {
+            hipLaunchKernelGGL((render_mse_kernel<K, true>), grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
+                               n_samples, ts, te, sig, rgb, eps, target, inv_count2, color, opacity, depth, g_sig,
+                               g_rgb, partial);
+        } else {
+            hipLaunchKernelGGL((render_mse_kernel<K, false>), grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
+                               n_samples, ts, te, sig, rgb, eps, target, inv_count2, color, opacity, depth, g_sig,
+                               g_rgb, partial);
+        }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Visibility pruning while marching (Sec. 2.1, "Pruning Empty and Occluded
+// Regions"; Sec. 3, ray_marching with sigma_fn / early_stop_eps /
+// alpha_thre): with the densities of the marched samples, keep a sample iff
+// its transmittance is at least eps and its opacity at least alpha_thre.
+// The transmittance is the renderer's (chunk_transmittance + chunk_keep), so
+// the cut falls where rendering would place it.  The compaction reuses the
+// marching scan: count (keep flags + per-ray counts), scan, fill.
+// ---------------------------------------------------------------------------
+
+// One wave per ray, four waves per workgroup of kRaysPerBlock rays.
+template <bool PRUNE_FILL>
+__global__ __launch_bounds__(kRenderThreads) void prune_kernel(
+    const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
+    const float* __restrict__ te, const float* __restrict__ sig, float eps, float alpha_thre,
+    uint8_t* __restrict__ keep, int32_t* __restrict__ packed_out, int64_t* __restrict__ block_sums,
+    int64_t capacity, int32_t* __restrict__ ri_out, float* __restrict__ ts_out, float* __restrict__ te_out,
+    float* __restrict__ sig_out, int32_t* __restrict__ status) {
+    __shared__ int64_t wave_total[kRaysPerRenderBlock];
+    const int lane = lane_id();
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    int64_t total = 0;
+    bool overflow = false;
+    for (int j = wave; j < kRaysPerBlock; j += kRaysPerRenderBlock) {
+        const int64_t r = first + j;
+        if (r >= n_rays) break;
+        int64_t start;
+        int n;
+        ray_range(packed_info, r, n_samples, start, n);
+        if (!PRUNE_FILL) {
+            double carry = 0.0;
+            int count = 0;
+            int c = 0;
+            for (; c < n; c += kWave) {
+                const int i = c + lane;
+                const bool valid = i < n;
+                const int64_t s = start + i;
+                Sample x{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (valid) {
+                    x.t0 = ts[s];
+                    x.t1 = te[s];
+                    x.sigma = sig[s];
+                }
+                const Trans t = chunk_transmittance(x, carry);
+                const int keep_n = chunk_keep(valid, t.t_in, eps);
+                const bool k = valid && lane < keep_n && alpha_of(t.tau) >= alpha_thre;
+                if (valid) keep[s] = k ? 1 : 0;
+                count += __popcll(ballot(k));
+                carry += static_cast<double>(read_lane(t.incl, 63));
+                if (keep_n < kWave) {
+                    c += kWave;
+                    break;
+                }
+            }
+            for (; c < n; c += kWave) {  // behind the cut
+                if (c + lane < n) keep[start + c + lane] = 0;
+            }
+            if (lane == 0) packed_out[2 * r + 1] = count;
+            total += count;
+        } else {
+            const int64_t out0 = packed_out[2 * r];
+            const int limit = uniform<int>(packed_out[2 * r + 1]);
+            int written = 0;
+            for (int c = 0; c < n && written < limit; c += kWave) {
+                const int i = c + lane;
+                const int64_t s = start + i;
+                const bool k = i < n && keep[s] != 0;
+                const uint64_t m = ballot(k);
+                const int idx = written + bits_below(m);
+                if (k && idx < limit) {
+                    const int64_t pos = out0 + idx;
+                    if (pos >= 0 && pos < capacity) {
+                        ri_out[pos] = static_cast<int32_t>(r);
+                        ts_out[pos] = ts[s];
+                        te_out[pos] = te[s];
+                        if (sig_out != nullptr) sig_out[pos] = sig[s];
+                    } else {
+                        overflow = true;
+                    }
+                }
+                written += __popcll(m);
+            }
+        }
+    }
+    if (!PRUNE_FILL) {
+        if (lane == 0) wave_total[wave] = total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t sum = 0;
+            for (int w = 0; w < kRaysPerRenderBlock; ++w) sum += wave_total[w];
+            block_sums[blockIdx.x] = sum;
+        }
+    } else if (overflow && status != nullptr) {
+        *status = NACC_ECAPACITY;
+    }
+}
+
+__global__ void prune_status_kernel(int32_t* status) { *status = NACC_OK; }
 
 int validate_render(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* ts,
                     const float* te, const float* sig, const float* rgb, float eps) {
@@ -585,6 +717,83 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
     if (st != NACC_OK) return st;
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, partial, nb, 1.0 / count, loss);
     return check_launch("render loss");
+}
+
+int64_t nacc_prune_workspace_size(int64_t n_rays) {
+    if (n_rays < 0) return -1;
+    return ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+}
+
+int nacc_prune_count(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                     const float* t_ends, const float* sigmas, float early_stop_eps, float alpha_thre,
+                     uint8_t* keep, int32_t* packed_out, int64_t* total, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_rays));
+    NACC_REQUIRE(n_samples >= 0 && n_samples <= INT32_MAX, NACC_EINVAL, "n_samples = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_samples));
+    NACC_REQUIRE(total != nullptr, NACC_EINVAL, "total must be non-NULL");
+    NACC_REQUIRE(n_rays == 0 || (packed_info != nullptr && packed_out != nullptr), NACC_EINVAL,
+                 "packed_info and packed_out must be non-NULL");
+    NACC_REQUIRE(n_samples == 0 || (t_starts != nullptr && t_ends != nullptr && sigmas != nullptr && keep != nullptr),
+                 NACC_EINVAL, "sample arrays and keep must be non-NULL");
+    NACC_REQUIRE(!std::isnan(early_stop_eps) && early_stop_eps >= 0.0f, NACC_EINVAL,
+                 "early_stop_eps = %g must be >= 0", early_stop_eps);
+    NACC_REQUIRE(!std::isnan(alpha_thre), NACC_EINVAL, "alpha_thre is NaN");
+    const int64_t need = nacc_prune_workspace_size(n_rays);
+    NACC_REQUIRE(workspace != nullptr && static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE,
+                 "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(need));
+    hipStream_t s = as_stream(stream);
+    int64_t* sums = static_cast<int64_t*>(workspace);
+    const int64_t nb = num_blocks(n_rays);
+    if (nb > 0) {
+        hipLaunchKernelGGL(prune_kernel<false>, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s,
+                           packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, early_stop_eps, alpha_thre, keep,
+                           packed_out, sums, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
+        int st = check_launch("prune count");
+        if (st != NACC_OK) return st;
+    }
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
+    int st = check_launch("prune scan");
+    if (st != NACC_OK || nb == 0) return st;
+    hipLaunchKernelGGL(finalize_starts_kernel, dim3(static_cast<unsigned>(nb)), dim3(kRaysPerBlock), 0, s, sums,
+                       n_rays, packed_out);
+    return check_launch("prune starts");
+}
+
+int nacc_prune_fill(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                    const float* t_ends, const float* sigmas, const uint8_t* keep, const int32_t* packed_out,
+                    int64_t capacity, int32_t* ray_indices_out, float* t_starts_out, float* t_ends_out,
+                    float* sigmas_out, int32_t* status, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_rays));
+    NACC_REQUIRE(n_samples >= 0 && n_samples <= INT32_MAX, NACC_EINVAL, "n_samples = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(n_samples));
+    NACC_REQUIRE(capacity >= 0 && capacity <= INT32_MAX, NACC_ECAPACITY, "capacity = %lld out of [0, 2^31-1]",
+                 static_cast<long long>(capacity));
+    NACC_REQUIRE(n_rays == 0 || (packed_info != nullptr && packed_out != nullptr), NACC_EINVAL,
+                 "packed_info and packed_out must be non-NULL");
+    NACC_REQUIRE(n_samples == 0 || (t_starts != nullptr && t_ends != nullptr && keep != nullptr), NACC_EINVAL,
+                 "sample arrays and keep must be non-NULL");
+    NACC_REQUIRE(sigmas_out == nullptr || n_samples == 0 || sigmas != nullptr, NACC_EINVAL,
+                 "sigmas_out needs sigmas");
+    NACC_REQUIRE(capacity == 0 || (ray_indices_out != nullptr && t_starts_out != nullptr && t_ends_out != nullptr),
+                 NACC_EINVAL, "outputs must be non-NULL");
+    hipStream_t s = as_stream(stream);
+    if (status != nullptr) {
+        hipLaunchKernelGGL(prune_status_kernel, dim3(1), dim3(1), 0, s, status);
+        int st = check_launch("prune status");
+        if (st != NACC_OK) return st;
+    }
+    const int64_t nb = num_blocks(n_rays);
+    if (nb == 0) return NACC_OK;
+    hipLaunchKernelGGL(prune_kernel<true>, dim3(static_cast<unsigned>(nb)), dim3(kRenderThreads), 0, s, packed_info,
+                       n_rays, n_samples, t_starts, t_ends, sigmas, 0.0f, 0.0f, const_cast<uint8_t*>(keep),
+                       const_cast<int32_t*>(packed_out), nullptr, capacity, ray_indices_out, t_starts_out, t_ends_out,
+                       sigmas_out, status);
+    return check_launch("prune fill");
 }
 
 }  // extern "C"

@@ -50,6 +50,8 @@ int nacc_set_tuning(const nacc_tuning* t) {
                  "render_cached_chunks = %d not in [1, 4]", t->render_cached_chunks);
     NACC_REQUIRE(t->render_mse_max_blocks >= 1 && t->render_mse_max_blocks <= (1 << 20), NACC_EINVAL,
                  "render_mse_max_blocks = %d not in [1, 2^20]", t->render_mse_max_blocks);
+    NACC_REQUIRE(t->render_prefetch == 0 || t->render_prefetch == 1, NACC_EINVAL,
+                 "render_prefetch = %d not in {0, 1}", t->render_prefetch);
     g_tuning = *t;
     return NACC_OK;
 }

@@ -114,7 +114,7 @@ def test_tuning_validated_and_round_trips():
     _lib.set_tuning(render_cached_chunks=3, march_waves_per_group=2)
     assert _lib.get_tuning()["render_cached_chunks"] == 3
     for bad in (dict(render_cached_chunks=0), dict(march_waves_per_group=3),
-                dict(render_mse_max_blocks=0)):
+                dict(render_mse_max_blocks=0), dict(render_prefetch=2)):
         with pytest.raises(_lib.NaccError):
             _lib.set_tuning(**bad)
     _lib.set_tuning(**before)

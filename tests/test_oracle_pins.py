@@ -590,3 +590,64 @@ def test_unbounded_scene_generator():
     assert np.allclose(r, 2.0 - 1.0 / world, rtol=1e-6)
     depth = (scene.peaks.astype(np.float64) * np.sqrt(2 * np.pi) * scene.stds * world ** 2)
     assert depth.min() >= 2.0 - 1e-5 and depth.max() <= 6.0 + 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Visibility pruning while marching (Sec. 2.1 occluded regions, Sec. 3)
+# ---------------------------------------------------------------------------
+
+def _packed(counts):
+    counts = np.asarray(counts, np.int64)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    return np.stack([starts, counts], 1).astype(np.int32)
+
+
+def test_prune_constant_density_closed_form():
+    # n equal intervals of width h at density s: T_i = exp(-s h i), so the
+    # samples with s h i <= ln(1/eps) survive: floor(ln(1/eps) / (s h)) + 1
+    h, n = 0.01, 400
+    for s, eps in ((30.0, 1e-4), (7.0, 1e-3), (123.0, 1e-2)):
+        ts = np.arange(n) * h
+        keep, counts = oracle.prune(_packed([n]), ts, ts + h, np.full(n, s), eps, 0.0)
+        q = math.log(1.0 / eps) / (s * h)
+        assert abs(q - round(q)) > 1e-6
+        want = min(n, math.floor(q) + 1)
+        assert counts[0] == want and keep.sum() == want
+        assert np.all(keep[:want] == 1) and np.all(keep[want:] == 0)
+
+
+def test_prune_alpha_threshold_and_transmittance_of_dropped_samples():
+    # alpha_i = 1 - exp(-s_i h) >= thre  <=>  s_i h >= -ln(1 - thre); a dropped
+    # low-opacity sample still darkens the ones after it
+    h = 0.1
+    thre = 0.05
+    s_cut = -math.log(1 - thre) / h       # ~0.513
+    sig = np.array([0.0, 0.3, 0.6, 5.0, 0.2, 80.0, 1.0, 0.0, 3.0])
+    ts = np.arange(sig.size) * h
+    keep, counts = oracle.prune(_packed([sig.size]), ts, ts + h, sig, 0.0, thre)
+    assert np.array_equal(keep, (sig >= s_cut).astype(np.uint8))
+    # with the transmittance test at eps 2e-4: sample 6 sits behind
+    # T = exp(-(0 + .3 + .6 + 5 + .2 + 80) * .1) = exp(-8.61) ~ 1.8e-4 and is
+    # dropped, as is everything after it; sample 3 (T = exp(-.09)) is kept
+    keep2, _ = oracle.prune(_packed([sig.size]), ts, ts + h, sig, 2e-4, thre)
+    pre = np.concatenate([[0.0], np.cumsum(sig * h)[:-1]])
+    want = ((np.exp(-pre) >= 2e-4) & (sig >= s_cut)).astype(np.uint8)
+    assert np.array_equal(keep2, want) and keep2[3] == 1 and keep2[6] == 0
+
+
+def test_prune_degenerate_settings_keep_everything():
+    packed, ts, te, sg, _ = synth.ragged_render_inputs(300, 71)
+    keep, counts = oracle.prune(packed, ts, te, sg, 0.0, 0.0)
+    assert keep.all() and np.array_equal(counts, packed[:, 1])
+    # eps > 1 drops everything (T_0 = 1 < eps)
+    keep, counts = oracle.prune(packed, ts, te, sg, 1.5, 0.0)
+    assert not keep.any() and not counts.any()
+
+
+def test_prune_matches_render_cut():
+    # with alpha_thre = 0 the kept samples are exactly those before the
+    # renderer's early-termination cut
+    packed, ts, te, sg, rgb = synth.ragged_render_inputs(500, 72)
+    keep, counts = oracle.prune(packed, ts, te, sg, 1e-4, 0.0)
+    fwd = oracle.render_fwd(packed, ts, te, sg, rgb, 1e-4)
+    assert np.array_equal(counts, fwd["kept"])

@@ -144,12 +144,13 @@ __device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0,
     const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
     const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
     const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
+    // j < res <= 1024, so every product fits the 24-bit multiplier
     const uint32_t res = static_cast<uint32_t>(g.res);
-    const uint32_t cell = (j0 * res + j1) * res + j2;
+    const uint32_t cell = __umul24(__umul24(j0, res) + j1, res) + j2;
     q.word = word0 + (cell >> 5);
     q.bit = cell & 31u;
     const uint32_t cc = static_cast<uint32_t>(g.coarse);
-    q.coarse = grid * g.skip_cells + ((j0 >> 2) * cc + (j1 >> 2)) * cc + (j2 >> 2);
+    q.coarse = grid * g.skip_cells + __umul24(__umul24(j0 >> 2, cc) + (j1 >> 2), cc) + (j2 >> 2);
     return q;
 }
 
@@ -615,17 +616,13 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
     for (int j = 0; j < n_masks; ++j) {
         live = live && t < t_far;  // the chunk's first candidate exists
         chunk_t[static_cast<int64_t>(j) * n_rays + r] = live ? t : INFINITY;
-        for (int u = 0; live && u < kWave; ++u) {
-            if (!(t < t_far)) {
-                live = false;
-                break;
-            }
+        if (__builtin_amdgcn_ballot_w64(live) == 0ull) continue;  // the wave's rays have all ended
+        // 64 steps without branches: a ray that ends keeps its last t
+#pragma unroll 8
+        for (int u = 0; u < kWave; ++u) {
             const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
-            if (!(t1 > t)) {
-                live = false;
-                break;
-            }
-            t = t1;
+            live = live && t < t_far && t1 > t;
+            t = live ? t1 : t;
         }
     }
 }

@@ -15,7 +15,18 @@ eager pass with HIP events on the launch stream.
 --workload dynamic_64: 64 frames with their own grids (~262k rays, Poisson
 counts per frame); 64 per-frame plain calls (each sized by a host read of the
 sample total, like the paper's API) against one batched graph-captured step
-over all frames; their outputs are checked bit for bit.
+over all frames; their outputs are checked bit for bit.  dynamic_64_shared:
+the same frames marched through one grid shared by all frames (the maximum
+of their densities over time).
+
+--workload unbounded_262k / unbounded_contract_262k: 262,144 rays from
+inside the unit ball, cone-scaled steps to far = 1e4, a scene defined in
+contracted coordinates; four world-space cascades, or one grid over the
+contracted space read through the contraction (at most 1024 samples per
+ray).
+
+--workload images_8: four 800x800 and four 1920x1080 images rendered
+forward, all images in one call sequence against one per image.
 
 --workload plain_fwd_4k: 4,096 rays, 8 blobs, forward only, no early
 termination.
@@ -50,7 +61,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="train_262k",
-                    choices=["train_262k", "plain_fwd_4k", "unbounded_262k", "dynamic_64",
+                    choices=["train_262k", "plain_fwd_4k", "unbounded_262k",
+                             "unbounded_contract_262k", "dynamic_64", "dynamic_64_shared",
                              "images_8"])
     ap.add_argument("--form", choices=["graph", "eager"], default="graph",
                     help="time the step captured in HIP graphs, or launched eagerly")
@@ -70,6 +82,16 @@ def parse():
     return ap.parse_args()
 
 
+def grid_label(w):
+    lookup = getattr(w, "lookup", "aabb")
+    if lookup == "cascade":
+        return f"{w.cascades} cascades of {w.res}^3 bit-packed"
+    if lookup == "contract":
+        return (f"{w.res}^3 bit-packed over the contracted space [-2,2]^3, "
+                f"at most {w.max_per_ray} samples per ray")
+    return f"{w.res}^3 bit-packed"
+
+
 def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
@@ -77,10 +99,13 @@ def log(msg):
 class Step:
     """Buffers and launches of one step over the rays with grid(s) `grid`
     (everything on torch's current stream).  grid_id (optional, per ray)
-    picks the grid and the field's centre set."""
+    picks the grid and the field's centre set; ray_set (optional) picks the
+    centre set alone (rays of several frames through one shared grid), and
+    update_set the centre set the grid update reads per drawn cell."""
 
     def __init__(self, torch, nacc, w, rays_o, rays_d, targets, grid, field, grid_id=None,
-                 skip_field=False, forward_only=False, loss_rays=0, seed=0, alpha_thre=None):
+                 skip_field=False, forward_only=False, loss_rays=0, seed=0, alpha_thre=None,
+                 ray_set=None, update_set=None):
         self.torch, self.nacc, self.lib = torch, nacc, nacc._lib
         dev = rays_o.device
         self.w = w
@@ -88,10 +113,13 @@ class Step:
         self.rays_o, self.rays_d, self.target = rays_o, rays_d, targets
         self.grid, self.field = grid, field
         self.grid_id = grid_id
+        self.ray_set = grid_id if ray_set is None else ray_set
+        self.update_set = update_set
         self.forward_only = forward_only
         self.loss_rays = loss_rays
         self.params = self.lib.march_params(w.near, w.far, w.dt, getattr(w, "dt_max", 1e10),
-                                            getattr(w, "cone", 0.0))
+                                            getattr(w, "cone", 0.0),
+                                            max_per_ray=getattr(w, "max_per_ray", 0))
         # sample buffers no step can overflow, so no step reads the total back
         self.capacity = self.n * self.lib.march_max_samples_per_ray(grid.desc, self.params)
         n, cap = self.n, self.capacity
@@ -150,7 +178,7 @@ class Step:
     def field_sigma(self):
         """Densities only, of every marched sample (the sigma_fn of the paper)."""
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
-                                     self.rays_o, self.rays_d, self.grid_id, self.ray_indices,
+                                     self.rays_o, self.rays_d, self.ray_set, self.ray_indices,
                                      self.t_starts, self.t_ends, self.sig_all, None, self.total)
 
     def prune_samples(self):
@@ -164,7 +192,7 @@ class Step:
     def field_eval(self):
         packed, ri, ts, te, total = self.cur
         self.lib.synth_field_samples(self.field.table, self.field.n_blobs, self.field.n_sets,
-                                     self.rays_o, self.rays_d, self.grid_id, ri, ts, te,
+                                     self.rays_o, self.rays_d, self.ray_set, ri, ts, te,
                                      self.sigmas, self.rgbs, total)
 
     def render(self):
@@ -183,9 +211,13 @@ class Step:
         lib.grid_decay(g.occ, EMA_DECAY)
         lib.grid_sample_cells(self.seed, self.updates, EMA_CELLS, g.desc, g.n_grids,
                               self.ema_cells, self.ema_pos)
-        lib.synth_field_points(self.field.table, self.field.n_blobs, self.field.n_sets,
-                               self.ema_pos, None, self.ema_sigma,
-                               point_cell=self.ema_cells if self.field.n_sets > 1 else None,
+        # a contraction-lookup grid draws its positions in the contracted space
+        table = (self.field.table_contracted if g.lookup == self.lib.LOOKUP_CONTRACT
+                 else self.field.table)
+        per_cell = self.field.n_sets > 1 and self.update_set is None
+        lib.synth_field_points(table, self.field.n_blobs, self.field.n_sets,
+                               self.ema_pos, self.update_set, self.ema_sigma,
+                               point_cell=self.ema_cells if per_cell else None,
                                cells_per_set=g.res ** 3)
         lib.grid_update_max(g.occ, self.ema_cells, self.ema_sigma)
         lib.grid_pack(g.occ, THRESHOLD, g.bits)
@@ -256,10 +288,21 @@ def algorithmic_bytes(n_rays, e, v, forward_only=False):
 # multiply), the position (3 multiplies, 3 adds), the cell coordinate
 # (3 subtracts, 3 multiplies, 3 clamps, 3 float->int), the cell index
 # (2 multiply-adds), word index and bit (2), the bit test (2): 33.  Cone
-# steps replace the 6 of the t's by the 4 of the recurrence step and the
+# steps replace the 6 of the t's by the 4 of the recurrence step; the
 # cascade adds the level (3 abs, 2 max, 4 for the exponent) and 3 exact
-# scalings: 43.
-OPS_PER_CANDIDATE = {"uniform": 33, "cone": 43}
+# scalings: 43; the contraction instead adds the squared norm (3 multiplies,
+# 2 adds), its square root, the comparison with 1, the reciprocal, 2 - 1/n,
+# the division by n and 3 scalings (a square root or division counted as
+# one operation): 44.
+OPS_PER_CANDIDATE = {"uniform": 33, "cone_cascade": 43, "cone_contract": 44}
+
+
+def ops_key(w):
+    if getattr(w, "cone", 0.0) == 0.0:
+        return "uniform"
+    return "cone_contract" if getattr(w, "lookup", "aabb") == "contract" else "cone_cascade"
+
+
 # One FP32 / integer lane operation per lane per clock: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz (the 157.3 TFLOP/s vector figure counts an FMA as two
 # and two lanes per instruction through packed math, which this build does
@@ -281,6 +324,9 @@ def lattice_candidates(w, rays_o, rays_d):
         tb = (hi - o) / d
     t_in = np.nanmax(np.minimum(ta, tb), axis=1)
     t_out = np.nanmin(np.maximum(ta, tb), axis=1)
+    if getattr(w, "lookup", "aabb") == "contract":  # no clip box
+        t_in = np.full(o.shape[0], -np.inf)
+        t_out = np.full(o.shape[0], np.inf)
     t_near = np.maximum(t_in, w.near)
     t_far = np.minimum(t_out, w.far)
     hit = t_near < t_far
@@ -327,12 +373,13 @@ def cpu_baseline(w, inp, n_sample, forward_only=False):
     d = inp["rays_d"][:n_sample]
     mask = oracle.grid_threshold(inp["occ"], THRESHOLD)
     cascades = getattr(w, "cascades", 1)
-    lookup = oracle.LOOKUP_CASCADE if cascades > 1 else oracle.LOOKUP_AABB
+    lookup = {"contract": oracle.LOOKUP_CONTRACT, "cascade": oracle.LOOKUP_CASCADE}.get(
+        getattr(w, "lookup", "aabb"), oracle.LOOKUP_AABB)
     t0 = time.perf_counter()
     packed, ri, ts, te = oracle.march(o, d, mask, w.res, np.asarray(w.box, np.float32), w.near,
                                       w.far, w.dt, dt_max=getattr(w, "dt_max", 1e10),
                                       cone=getattr(w, "cone", 0.0), lookup=lookup,
-                                      n_grids=cascades)
+                                      n_grids=cascades, max_per_ray=getattr(w, "max_per_ray", 0))
     pos = oracle.sample_positions(o, d, ri, ts, te)
     sig, rgb = oracle.blob_field(inp["scene"], pos)
     fwd = oracle.render_fwd(packed, ts, te, sig, rgb, w.early_stop_eps)
@@ -388,7 +435,7 @@ def bench_train(args, torch, nacc):
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(a).to(dev)
     if unbounded:
-        grid = nacc.OccupancyGrid(w.box, w.res, n_grids=w.cascades, lookup="cascade", device=dev)
+        grid = nacc.OccupancyGrid(w.box, w.res, n_grids=w.cascades, lookup=w.lookup, device=dev)
     else:
         grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
     grid.set_occupancy(t(inp["occ"]), THRESHOLD)
@@ -475,7 +522,7 @@ def bench_train(args, torch, nacc):
     if dominant == "march_count":
         # the count pass is bound by its per-candidate arithmetic
         cands = lattice_candidates(w, inp["rays_o"], inp["rays_d"])
-        ops = cands * OPS_PER_CANDIDATE["cone" if getattr(w, "cone", 0.0) > 0 else "uniform"]
+        ops = cands * OPS_PER_CANDIDATE[ops_key(w)]
         ops_s = ops / (phase_avg["march_count"] * 1e-3)
         roofline = {"bound": "alu", "kernel": "march_count", "achieved": ops_s / 1e12,
                     "peak": ALU_PEAK / 1e12, "unit": "TOP/s", "frac": ops_s / ALU_PEAK,
@@ -501,8 +548,7 @@ def bench_train(args, torch, nacc):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "rays": w.n_rays,
-                   "grid": (f"{w.cascades} cascades of {w.res}^3 bit-packed" if unbounded
-                            else f"{w.res}^3 bit-packed"),
+                   "grid": grid_label(w),
                    "blobs": inp["scene"].n_blobs, "dt": w.dt,
                    "cone": getattr(w, "cone", 0.0), "early_stop_eps": w.early_stop_eps,
                    "pass": "forward" if forward_only else "forward+mse+backward",
@@ -545,13 +591,16 @@ def bench_dynamic(args, torch, nacc):
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     nf, res = w.n_frames, inp["res"]
-    grid = nacc.OccupancyGrid(w.box, res, n_grids=nf, device=dev)
+    shared = w.shared_grid  # one grid for all frames (the maximum over time)
+    grid = nacc.OccupancyGrid(w.box, res, n_grids=1 if shared else nf, device=dev)
     grid.set_occupancy(t(inp["occ"]), THRESHOLD)
     field = nacc.BlobField(inp["scene"], device=dev)
     rays_o, rays_d = t(inp["rays_o"]), t(inp["rays_d"])
     tgt, frame = t(inp["targets"]), t(inp["frame"])
     n_total = rays_o.shape[0]
-    batched = Step(torch, nacc, w, rays_o, rays_d, tgt, grid, field, grid_id=frame,
+    upd_set = t(synth.update_frames(EMA_CELLS, nf, 4100 + w.seed_base)) if shared else None
+    batched = Step(torch, nacc, w, rays_o, rays_d, tgt, grid, field,
+                   grid_id=None if shared else frame, ray_set=frame, update_set=upd_set,
                    seed=4000 + w.seed_base)
     lib = nacc._lib
     words = res ** 3 // 32
@@ -570,9 +619,10 @@ def bench_dynamic(args, torch, nacc):
             if n == 0:
                 continue
             o, d = rays_o[a:b], rays_d[a:b]
-            bits = grid.bits[f * words:(f + 1) * words]
+            g = 0 if shared else f
+            bits = grid.bits[g * words:(g + 1) * words]
             # the frame's skip field (+ the build scratch the size check expects)
-            skip = grid.skip[f * c3:(f + 2) * c3]
+            skip = grid.skip[g * c3:(g + 2) * c3]
             packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
             total = torch.empty(1, dtype=torch.int64, device=dev)
             ws = torch.empty(lib.march_workspace_size(n, desc1, params), dtype=torch.uint8,
@@ -667,7 +717,9 @@ def bench_dynamic(args, torch, nacc):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "frames": nf, "rays": n_total, "grid": f"{nf} x {res}^3",
+        "config": {"workload": w.name, "frames": nf, "rays": n_total,
+                   "grid": (f"one {res}^3 shared by the {nf} frames" if shared
+                            else f"{nf} x {res}^3"),
                    "blobs": w.n_blobs, "early_stop_eps": w.early_stop_eps,
                    "pass": "forward+mse+backward", "form": "batched, one HIP graph per step",
                    "tuning": tuned, "parallelism": "single GPU"},

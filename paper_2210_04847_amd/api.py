@@ -72,8 +72,10 @@ class OccupancyGrid:
         """One update: decay all cells, max with sigma_fn at n random jittered
         cell positions (Philox4x64-10 keyed by seed, counter = update number),
         repack.  sigma_fn maps positions [n, 3] (and, for several independent
-        grids, the grid index [n]) to densities [n]; cascade positions are in
-        world space."""
+        grids, the grid index [n]) to densities [n]; box and cascade positions
+        are in world space, contraction-lookup positions in the contracted
+        space the grid covers (a field defined in contracted coordinates reads
+        them directly; points of norm >= 2 have no world preimage)."""
         dev = self.occ.device
         cells = torch.empty(n_samples, dtype=torch.int32, device=dev)
         pos = torch.empty((n_samples, 3), dtype=torch.float32, device=dev)
@@ -265,6 +267,13 @@ class BlobField:
         _lib.synth_prepare(t(scene.centres), t(scene.stds), t(scene.peaks), t(scene.w),
                            t(scene.bias), self.table,
                            _lib.SYNTH_CONTRACT if self.contract else 0)
+        # the same scene read at points already in its contracted coordinates
+        # (the positions a contraction-lookup grid update draws)
+        self.table_contracted = self.table
+        if self.contract:
+            self.table_contracted = torch.empty_like(self.table)
+            _lib.synth_prepare(t(scene.centres), t(scene.stds), t(scene.peaks), t(scene.w),
+                               t(scene.bias), self.table_contracted, 0)
 
     def samples(self, rays_o, rays_d, ray_indices, t_starts, t_ends, ray_set=None,
                 n_samples_dev=None, sigmas=None, rgbs=None):
@@ -276,12 +285,14 @@ class BlobField:
                                  ray_indices, t_starts, t_ends, sig, rgb, n_samples_dev)
         return sig, rgb
 
-    def points(self, points, point_set=None, want_rgb=False):
+    def points(self, points, point_set=None, want_rgb=False, contracted=False):
+        """Field at points [n, 3]; contracted: the points are already in the
+        scene's contracted coordinates."""
         n = points.shape[0]
         dev = points.device
         sig = torch.empty(n, dtype=torch.float32, device=dev)
         rgb = torch.empty((n, 3), dtype=torch.float32, device=dev) if want_rgb else None
         ps = None if point_set is None else point_set.to(torch.int32).contiguous()
-        _lib.synth_field_points(self.table, self.n_blobs, self.n_sets, points.contiguous(),
-                                ps, sig, rgb)
+        _lib.synth_field_points(self.table_contracted if contracted else self.table, self.n_blobs,
+                                self.n_sets, points.contiguous(), ps, sig, rgb)
         return (sig, rgb) if want_rgb else sig

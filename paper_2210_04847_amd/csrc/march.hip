@@ -877,7 +877,7 @@ int64_t candidate_bound(const nacc_grid_desc& grid, const nacc_march_params& p) 
     return std::min<int64_t>(kMaxCandidates, k + 2);
 }
 
-constexpr int kMaxMaskChunks = 32;
+constexpr int kMaxMaskChunks = 64;  // one per lane of a wave
 
 // Workspace of the marching calls: the per-workgroup sums of the scan, then
 // n_masks 64-bit occupancy masks per ray, one per chunk of 64 candidates,

@@ -23,6 +23,8 @@ import numpy as np
 STEP_1024 = float(np.float32(3.0 * math.sqrt(3.0) / 1024.0))
 
 BOX_1_5 = (-1.5, -1.5, -1.5, 1.5, 1.5, 1.5)
+# the grid of a contraction lookup covers the contracted space, a ball of radius 2
+CONTRACT_BOX = (-2.0, -2.0, -2.0, 2.0, 2.0, 2.0)
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -159,6 +161,24 @@ def unbounded_blob_scene(levels: int, per_level: int, seed: int,
                      bias=bias.astype(np.float32), contract=True)
 
 
+def _sparse_density(scene: BlobScene, p: np.ndarray, cut: float) -> np.ndarray:
+    """FP64 density of the scene's first centre set at scene-space points p,
+    skipping blobs at points where they contribute below `cut`."""
+    s = scene.stds.astype(np.float64)
+    pk = scene.peaks.astype(np.float64)
+    c = scene.centres[0].astype(np.float64)
+    reach = s * np.sqrt(2.0 * np.log(np.maximum(pk / cut, 1.0)))
+    acc = np.zeros(p.shape[0], np.float64)
+    for b in range(scene.n_blobs):
+        e = p - c[b]
+        near = np.all(np.abs(e) < reach[b], axis=1)
+        if not near.any():
+            continue
+        d2 = (e[near] ** 2).sum(1)
+        acc[near] += pk[b] * np.exp(-d2 / (2.0 * s[b] ** 2))
+    return acc
+
+
 def cascade_occupancy(scene: BlobScene, res: int, levels: int, base: float = 1.0,
                       threshold_hint: float = 1e-2, chunk: int = 1 << 20) -> np.ndarray:
     """FP32 occupancy values of `levels` cascaded res^3 grids, level l over
@@ -167,11 +187,7 @@ def cascade_occupancy(scene: BlobScene, res: int, levels: int, base: float = 1.0
     where they contribute below threshold_hint * 1e-6 (a sum of such
     contributions cannot cross the threshold)."""
     out = []
-    s = scene.stds.astype(np.float64)
-    pk = scene.peaks.astype(np.float64)
-    c = scene.centres[0].astype(np.float64)
     cut = threshold_hint * 1e-6
-    reach = s * np.sqrt(2.0 * np.log(np.maximum(pk / cut, 1.0)))
     for lvl in range(levels):
         h = base * 2.0 ** lvl
         pts = cell_centres(res, (-h, -h, -h, h, h, h))
@@ -180,17 +196,24 @@ def cascade_occupancy(scene: BlobScene, res: int, levels: int, base: float = 1.0
             p = pts[a:a + chunk]
             if scene.contract:
                 p = contracted(p)
-            acc = np.zeros(p.shape[0], np.float64)
-            for b in range(scene.n_blobs):
-                e = p - c[b]
-                near = np.all(np.abs(e) < reach[b], axis=1)
-                if not near.any():
-                    continue
-                d2 = (e[near] ** 2).sum(1)
-                acc[near] += pk[b] * np.exp(-d2 / (2.0 * s[b] ** 2))
-            occ[a:a + chunk] = acc
+            occ[a:a + chunk] = _sparse_density(scene, p, cut)
         out.append(occ)
     return np.concatenate(out).astype(np.float32)
+
+
+def contracted_occupancy(scene: BlobScene, res: int, threshold_hint: float = 1e-2,
+                         chunk: int = 1 << 20) -> np.ndarray:
+    """FP32 occupancy values of one res^3 grid over the contracted space
+    [-2, 2]^3 (the grid of a contraction lookup): the density of a scene
+    defined in contracted coordinates, read at every cell centre directly,
+    C order."""
+    assert scene.contract
+    pts = cell_centres(res, CONTRACT_BOX)
+    occ = np.zeros(pts.shape[0], np.float64)
+    cut = threshold_hint * 1e-6
+    for a in range(0, pts.shape[0], chunk):
+        occ[a:a + chunk] = _sparse_density(scene, pts[a:a + chunk], cut)
+    return occ.astype(np.float32)
 
 
 def cell_centres(res: int, box) -> np.ndarray:
@@ -379,9 +402,12 @@ def image_inputs(w: ImageWorkload, scale: int = 1):
 
 @dataclass
 class UnboundedWorkload:
-    """Rays from inside the unit ball in all directions, cone-scaled steps,
-    cascaded grids (level l over [-2^l, 2^l]^3) and a scene defined in
-    contracted coordinates."""
+    """Rays from inside the unit ball in all directions, cone-scaled steps
+    and a scene defined in contracted coordinates.  lookup "cascade": grids
+    level l over [-2^l, 2^l]^3 in world space (the rays are clipped to the
+    largest); lookup "contract": one grid over the contracted space [-2, 2]^3
+    read through the scene contraction (no clip box: the lattice runs from
+    near to far, at most max_per_ray samples per ray)."""
     name: str
     n_rays: int
     blob_levels: int
@@ -395,32 +421,48 @@ class UnboundedWorkload:
     near: float
     far: float
     seed_base: int
+    lookup: str = "cascade"
+    max_per_ray: int = 0
 
     @property
     def box(self):
+        if self.lookup == "contract":
+            return CONTRACT_BOX
         return (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)  # level 0; level l is box * 2^l
 
 
 UNBOUNDED_WORKLOADS = {
     "unbounded_262k": UnboundedWorkload("unbounded_262k", 262144, 8, 4, 128, 4, STEP_1024,
                                         1.0 / 256.0, 1e10, 1e-4, 0.2, 1e4, 2),
+    # the paper's own unbounded mechanism: contraction inside the grid lookup
+    "unbounded_contract_262k": UnboundedWorkload("unbounded_contract_262k", 262144, 8, 4, 128, 1,
+                                                 STEP_1024, 1.0 / 256.0, 1e10, 1e-4, 0.2, 1e4, 2,
+                                                 lookup="contract", max_per_ray=1024),
 }
 
 
 def unbounded_inputs(w: UnboundedWorkload, n_rays: int | None = None, res: int | None = None):
-    """Rays, scene, cascaded occupancy values and targets of an unbounded
-    workload (smaller ray counts or resolutions for tests)."""
+    """Rays, scene, occupancy values (cascaded grids, or the contracted-space
+    grid) and targets of an unbounded workload (smaller ray counts or
+    resolutions for tests)."""
     n = w.n_rays if n_rays is None else n_rays
     rs = w.res if res is None else res
     o, d = rays_unbounded(n, 2000 + w.seed_base)
     scene = unbounded_blob_scene(w.blob_levels, w.blobs_per_level, 1000 + w.seed_base)
-    occ = cascade_occupancy(scene, rs, w.cascades)
+    if w.lookup == "contract":
+        occ = contracted_occupancy(scene, rs)
+    else:
+        occ = cascade_occupancy(scene, rs, w.cascades)
     tgt = targets(n, 3000 + w.seed_base)
     return dict(rays_o=o, rays_d=d, scene=scene, occ=occ, targets=tgt, res=rs)
 
 
 @dataclass
 class DynamicWorkload:
+    """Frames of a moving scene.  Each frame has its own occupancy grid, or
+    (shared_grid) all frames march through one grid holding the maximum of
+    the frames' densities, which the grid update keeps by reading the field
+    at a random frame per drawn cell."""
     name: str
     n_frames: int
     mean_rays: float
@@ -432,19 +474,30 @@ class DynamicWorkload:
     near: float
     far: float
     seed_base: int
+    shared_grid: bool = False
 
 
 DYNAMIC_WORKLOADS = {
     "dynamic_64": DynamicWorkload("dynamic_64", 64, 4096.0, 32, 128, BOX_1_5, STEP_1024, 1e-4,
                                   0.0, 1e10, 3),
+    "dynamic_64_shared": DynamicWorkload("dynamic_64_shared", 64, 4096.0, 32, 128, BOX_1_5,
+                                         STEP_1024, 1e-4, 0.0, 1e10, 3, shared_grid=True),
 }
+
+
+def update_frames(n: int, n_frames: int, seed: int) -> np.ndarray:
+    """The frame at which a shared grid's update reads the field, per drawn
+    cell slot (uniform over the frames, int32 [n]); fixed across updates
+    while the drawn cells change."""
+    return _rng(seed).integers(0, n_frames, n).astype(np.int32)
 
 
 def dynamic_inputs(w: DynamicWorkload, n_frames: int | None = None, res: int | None = None,
                    mean_rays: float | None = None):
     """Rays (grouped by frame, frame f at time f / (F - 1)), their frame ids,
-    the moving blob scene, one occupancy grid per frame and loss targets.
-    Ray counts per frame ~ Poisson(mean_rays)."""
+    the moving blob scene, one occupancy grid per frame (or the shared one:
+    the maximum over the frames) and loss targets.  Ray counts per frame ~
+    Poisson(mean_rays)."""
     nf = w.n_frames if n_frames is None else n_frames
     rs = w.res if res is None else res
     mean = w.mean_rays if mean_rays is None else mean_rays
@@ -455,6 +508,8 @@ def dynamic_inputs(w: DynamicWorkload, n_frames: int | None = None, res: int | N
     frame = np.repeat(np.arange(nf), counts).astype(np.int32)
     scene = moving_blob_scene(w.n_blobs, nf, 1000 + w.seed_base)
     occ = np.concatenate([local_occupancy(scene, rs, w.box, f) for f in range(nf)])
+    if w.shared_grid:
+        occ = occ.reshape(nf, -1).max(0)
     tgt = targets(n, 3000 + w.seed_base)
     return dict(rays_o=o, rays_d=d, frame=frame, counts=counts, scene=scene, occ=occ,
                 targets=tgt, res=rs)

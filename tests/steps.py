@@ -11,10 +11,11 @@ import synth
 def march_kwargs(w):
     """Oracle marching arguments of a workload (box or cascaded grids,
     uniform or cone-scaled steps)."""
-    cascades = getattr(w, "cascades", 1)
+    lookup = {"contract": oracle.LOOKUP_CONTRACT, "cascade": oracle.LOOKUP_CASCADE}.get(
+        getattr(w, "lookup", "aabb"), oracle.LOOKUP_AABB)
     return dict(dt_max=getattr(w, "dt_max", 1e10), cone=getattr(w, "cone", 0.0),
-                lookup=oracle.LOOKUP_CASCADE if cascades > 1 else oracle.LOOKUP_AABB,
-                n_grids=cascades)
+                lookup=lookup, n_grids=getattr(w, "cascades", 1),
+                max_per_ray=getattr(w, "max_per_ray", 0))
 
 
 def field_tolerance(scene, pos, sigma):
@@ -40,7 +41,7 @@ def make_step(name, n_rays=None, res=None, skip_field=False):
     if name in synth.UNBOUNDED_WORKLOADS:
         w = synth.UNBOUNDED_WORKLOADS[name]
         inp = synth.unbounded_inputs(w, n_rays, res)
-        grid = nacc.OccupancyGrid(w.box, inp["res"], n_grids=w.cascades, lookup="cascade")
+        grid = nacc.OccupancyGrid(w.box, inp["res"], n_grids=w.cascades, lookup=w.lookup)
     else:
         w = synth.WORKLOADS[name]
         inp = synth.workload_inputs(w, n_rays)

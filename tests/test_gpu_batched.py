@@ -85,6 +85,64 @@ def test_batched_march_and_field_match_oracle(dyn):
     assert np.all(np.abs(got_c - rgb) <= 1e-5 * np.abs(rgb) + 1e-12)
 
 
+def test_shared_grid_march_field_and_update(dyn):
+    """All frames through one grid shared over time (the maximum of the
+    frames' densities, so the OR of their bits), each sample's field from its
+    ray's frame; the grid update reads the field at a fixed random frame per
+    drawn cell slot.  Marching bit for bit against the oracle with the OR
+    mask, the field within its tolerance, the update bit for bit given the
+    GPU's densities."""
+    import bench
+    w = synth.DYNAMIC_WORKLOADS["dynamic_64_shared"]
+    inp = synth.dynamic_inputs(w, N_FRAMES, RES, MEAN_RAYS)
+    occ_frames = dyn[1]["occ"].reshape(N_FRAMES, -1)
+    assert_bit_exact(inp["occ"], occ_frames.max(0), "shared occupancy = max over frames")
+    nacc = _nacc()
+    grid = nacc.OccupancyGrid(w.box, RES)
+    grid.set_occupancy(_cuda(inp["occ"]), THRESHOLD)
+    field = nacc.BlobField(inp["scene"])
+    upd = synth.update_frames(1 << 18, N_FRAMES, 4100 + w.seed_base)
+    st = bench.Step(torch, nacc, w, _cuda(inp["rays_o"]), _cuda(inp["rays_d"]),
+                    _cuda(inp["targets"]), grid, field, ray_set=_cuda(inp["frame"]),
+                    update_set=_cuda(upd), seed=7)
+    st.step()
+    torch.cuda.synchronize()
+    e = int(st.total.item())
+    mask = oracle.grid_threshold(inp["occ"], THRESHOLD)
+    assert_bit_exact(mask, oracle.grid_threshold(occ_frames, THRESHOLD).reshape(N_FRAMES, -1)
+                     .max(0), "shared mask = OR of the frames' masks")
+    packed, ri, ts, te = oracle.march(inp["rays_o"], inp["rays_d"], mask, RES,
+                                      np.asarray(w.box, np.float32), w.near, w.far, w.dt)
+    assert e == ri.size and e > 1000
+    assert_bit_exact(st.packed.cpu().numpy(), packed, "packed_info")
+    assert_bit_exact(st.ray_indices[:e].cpu().numpy(), ri, "ray_indices")
+    assert_bit_exact(st.t_starts[:e].cpu().numpy(), ts, "t_starts")
+    pos = oracle.sample_positions(inp["rays_o"], inp["rays_d"], ri, ts, te)
+    sig = oracle.blob_field(inp["scene"], pos, blob_set=inp["frame"][ri], want_rgb=False)
+    got_s = st.sigmas[:e].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got_s - sig) <= 2e-5 * np.abs(sig) + 1e-30)
+    # the looser shared grid marches more samples than the per-frame grids
+    per_frame = oracle.march(inp["rays_o"], inp["rays_d"],
+                             oracle.grid_threshold(dyn[1]["occ"], THRESHOLD), RES,
+                             np.asarray(w.box, np.float32), w.near, w.far, w.dt,
+                             n_grids=N_FRAMES, grid_id=inp["frame"])[1].size
+    assert e > per_frame
+    # grid update: cells of the one grid, field at the slot's frame
+    occ0 = inp["occ"]
+    st.grid.set_occupancy(_cuda(occ0), THRESHOLD)
+    st.updates.zero_()
+    st.grid_update()
+    torch.cuda.synchronize()
+    cells, p_o = oracle.grid_sample_cells(7, 0, 1 << 18, RES, np.asarray(w.box, np.float32))
+    assert_bit_exact(st.ema_cells.cpu().numpy(), cells, "cells")
+    assert_bit_exact(st.ema_pos.cpu().numpy(), p_o, "positions")
+    s_o = oracle.blob_field(inp["scene"], p_o, blob_set=upd, want_rgb=False)
+    got = st.ema_sigma.cpu().numpy()
+    assert np.all(np.abs(got - s_o) <= 2e-5 * np.abs(s_o) + 1e-30)
+    want = oracle.grid_update_max(oracle.grid_decay(occ0, 0.95), cells, got)
+    assert_bit_exact(st.grid.occ.cpu().numpy(), want, "occupancy after the update")
+
+
 def test_batched_render_and_loss_rays_match_oracle(dyn):
     """The fused render of the batched step against the oracle on the step's
     own samples, with the loss normalised over all rays of the batch and over

@@ -1,8 +1,9 @@
 """Parity at the full training sizes in the launch configuration the
 benchmark times, on sampled outputs the oracle computes ray by ray:
 262,144 rays into a 128^3 grid of 32 blobs (uniform steps), and 262,144
-unbounded rays with cone-scaled steps through four 128^3 cascades of a
-scene defined in contracted coordinates."""
+unbounded rays with cone-scaled steps through a scene defined in contracted
+coordinates, with four 128^3 cascades or with the paper's contraction lookup
+(one 128^3 grid over the contracted space, at most 1024 samples per ray)."""
 import numpy as np
 import pytest
 import torch
@@ -15,7 +16,8 @@ from steps import field_tolerance, make_step, march_kwargs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["train_262k", "unbounded_262k"])
+@pytest.fixture(scope="module", params=["train_262k", "unbounded_262k",
+                                                 "unbounded_contract_262k"])
 def step(request):
     return make_step(request.param)
 

@@ -196,6 +196,26 @@ def test_uniform_steps_cascade():
     compare(o, d, mask, res, base, 0.0, 1e10, 0.02, lookup=1, n_grids=levels)
 
 
+@pytest.mark.parametrize("lookup", [1, 2])
+def test_cone_rays_past_stored_chunks(lookup):
+    """Cone steps with more candidates per ray (up to ~11,000) than the
+    chunks whose masks the count pass stores (64 of 64 candidates): the last
+    stored chunk's task carries on to the end of the ray."""
+    o, d = synth.rays_unbounded(300, 17)
+    if lookup == 1:
+        res, levels = 16, 4
+        mask = synth.random_mask(levels * res ** 3, 0.3, 17)
+        box = np.array([-1, -1, -1, 1, 1, 1], np.float32)
+        want = compare(o, d, mask, res, box, 0.2, 1e4, 0.0005, cone=1.0 / 4096, lookup=1,
+                       n_grids=levels)
+    else:
+        res = 16
+        mask = synth.random_mask(res ** 3, 0.3, 17)
+        box = np.array([-2, -2, -2, 2, 2, 2], np.float32)
+        want = compare(o, d, mask, res, box, 0.2, 1e4, 0.002, cone=1.0 / 1024, lookup=2)
+    assert want[0][:, 1].max() > 64 * 64 * 0.3
+
+
 def test_contraction_lookup():
     res = 32
     mask = synth.random_mask(res ** 3, 0.3, 14)

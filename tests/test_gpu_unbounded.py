@@ -1,11 +1,15 @@
 """GPU parity of the unbounded-scene path at a size the oracle covers whole:
 rays from inside the unit ball in all directions (3,000 of them: a ragged
 last workgroup), cone-scaled steps t_{k+1} = t_k + clamp(t_k / 256, dt,
-dt_max) from near = 0.2, four cascaded 32^3 grids (level l over
-[-2^l, 2^l]^3), and a scene defined in contracted coordinates.  Marching is
-compared bit for bit, the field within its FP32 tolerance, and the fused
-render + MSE + backward on the step's own samples within the render and
-gradient tolerances.  Marching here uses the skip field."""
+dt_max) from near = 0.2, and a scene defined in contracted coordinates, for
+both unbounded grid layouts: four cascaded 32^3 grids (level l over
+[-2^l, 2^l]^3, marched with the skip field) and the paper's contraction
+lookup (one 32^3 grid over the contracted space [-2, 2]^3, lattice to
+far = 1e4, at most 1024 samples per ray).  Marching is compared bit for bit,
+the field within its FP32 tolerance, and the fused render + MSE + backward
+on the step's own samples within the render and gradient tolerances."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -18,10 +22,12 @@ from steps import field_tolerance, make_step, march_kwargs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def small():
-    # with the skip field (the benchmark marches without it)
-    return make_step("unbounded_262k", n_rays=3000, res=32, skip_field=True)
+@pytest.fixture(scope="module", params=["unbounded_262k", "unbounded_contract_262k"])
+def small(request):
+    # cascades with the skip field (the benchmark marches without it); the
+    # contraction lookup has none
+    return make_step(request.param, n_rays=3000, res=32,
+                     skip_field=request.param == "unbounded_262k")
 
 
 def test_unbounded_march_all_rays(small):
@@ -41,6 +47,8 @@ def test_unbounded_march_all_rays(small):
     # the capacity bound covers every ray
     lib = st.lib
     assert counts.max() <= lib.march_max_samples_per_ray(st.grid.desc, st.params)
+    if w.max_per_ray:
+        assert counts.max() <= w.max_per_ray
 
 
 def test_unbounded_field_all_samples(small):
@@ -81,9 +89,11 @@ def test_unbounded_fused_render(small):
 
 
 def test_unbounded_grid_update(small):
-    """One grid update over the cascades: cells drawn over all levels,
-    positions scaled to their level, the field read in contracted
-    coordinates, max into the decayed densities, then repacked."""
+    """One grid update: cascades draw cells over all levels, positions scaled
+    to their level, and read the field at the contraction of the world
+    position; the contraction lookup draws positions in the contracted space
+    and reads the field there directly.  Then max into the decayed
+    densities and repack."""
     w, inp, st = small
     occ0 = inp["occ"]
     st.grid.set_occupancy(torch.from_numpy(occ0).cuda(), 0.01)
@@ -91,13 +101,18 @@ def test_unbounded_grid_update(small):
     st.grid_update()
     torch.cuda.synchronize()
     res = inp["res"]
+    cascade = w.lookup == "cascade"
     cells, pos = oracle.grid_sample_cells(st.seed, 0, 1 << 18, res,
-                                          np.asarray(w.box, np.float32), w.cascades, True)
-    sig = oracle.blob_field(inp["scene"], pos, want_rgb=False)
+                                          np.asarray(w.box, np.float32), w.cascades, cascade)
+    # the scene as a field of contracted-space points
+    scene = inp["scene"] if cascade else dataclasses.replace(inp["scene"], contract=False)
+    sig = oracle.blob_field(scene, pos, want_rgb=False)
     got_sig = st.ema_sigma.cpu().numpy()
     assert_bit_exact(st.ema_cells.cpu().numpy(), cells, "cells")
     assert_bit_exact(st.ema_pos.cpu().numpy(), pos, "positions")
-    assert np.all(np.abs(got_sig - sig) <= field_tolerance(inp["scene"], pos, sig))
+    assert np.all(np.abs(got_sig - sig) <= field_tolerance(scene, pos, sig))
+    if not cascade:
+        assert np.abs(pos).max() > 1.9 and (sig > 0.01).mean() > 0.001
     # with the GPU's own densities the update is bit-exact
     want = oracle.grid_update_max(oracle.grid_decay(occ0, 0.95), cells, got_sig)
     assert_bit_exact(st.grid.occ.cpu().numpy(), want, "occupancy after the update")

@@ -592,6 +592,32 @@ def test_unbounded_scene_generator():
     assert depth.min() >= 2.0 - 1e-5 and depth.max() <= 6.0 + 1e-5
 
 
+def test_contracted_grid_occupancy_generator():
+    """The contraction lookup's grid holds the scene density at its cell
+    centres read directly in contracted coordinates, the same values the
+    cascades read at the contraction of their world cell centres: a cell
+    centre of the contracted grid inside the unit ball is its own world
+    point, so the two generators agree where a level-0 cascade cell centre
+    coincides with it."""
+    import dataclasses
+    scene = synth.unbounded_blob_scene(8, 4, 5)
+    res = 16
+    occ = synth.contracted_occupancy(scene, res)
+    pts = synth.cell_centres(res, synth.CONTRACT_BOX)
+    direct = oracle.blob_field(dataclasses.replace(scene, contract=False), pts.astype(np.float32),
+                               want_rgb=False)
+    assert np.all(np.abs(occ - direct) <= 1e-5 * direct + 1e-7)
+    # cascade level 0 over [-1, 1]^3 at resolution res / 2 has the same cell
+    # centres as the inner half of the contracted grid, where c(x) = x
+    cas = synth.cascade_occupancy(scene, res // 2, 1).reshape(res // 2, res // 2, res // 2)
+    inner = occ.reshape(res, res, res)[res // 4:3 * res // 4, res // 4:3 * res // 4,
+                                       res // 4:3 * res // 4]
+    c = synth.cell_centres(res // 2, (-1, -1, -1, 1, 1, 1)).reshape(res // 2, res // 2, res // 2, 3)
+    inside = np.linalg.norm(c, axis=-1) <= 1.0
+    assert inside.sum() > 100
+    assert np.array_equal(cas[inside], inner[inside])
+
+
 # ---------------------------------------------------------------------------
 # Visibility pruning while marching (Sec. 2.1 occluded regions, Sec. 3)
 # ---------------------------------------------------------------------------

@@ -295,6 +295,16 @@ def algorithmic_bytes(n_rays, e, v, forward_only=False):
 # the division by n and 3 scalings (a square root or division counted as
 # one operation): 44.
 OPS_PER_CANDIDATE = {"uniform": 33, "cone_cascade": 43, "cone_contract": 44}
+# The synthetic field per sample: per blob 3 differences, the squared
+# distance (multiply, 2 multiply-adds), the exponent argument, exp2 and the
+# accumulation (9); the colour's 3 affine rows (9 multiply-adds) and 3
+# sigmoids (multiply, exp2, add, reciprocal: 12); the midpoint and position
+# (8).  The render per sample: tau (2), the chunk scan (6), two exponentials
+# with their scalings (4), the opacity series (12), the weight (1) and five
+# accumulations (5).
+FIELD_OPS_PER_BLOB = 9
+FIELD_OPS_FIXED = 29
+RENDER_OPS = 30
 
 
 def ops_key(w):
@@ -807,15 +817,32 @@ def bench_images(args, torch, nacc):
                 done[k].record()
         return e
 
-    # warm-up (also fills the allocator's cache) and an equality check
+    n_all = rays_o.shape[0]
+    f_color = torch.empty((n_all, 3), dtype=f32, device=dev)
+    f_opacity = torch.empty(n_all, dtype=f32, device=dev)
+    f_depth = torch.empty(n_all, dtype=f32, device=dev)
+    f_kept = torch.empty(n_all, dtype=i32, device=dev)
+
+    def fused(a=0, b=None):
+        """marching + field + render in one kernel, no samples written."""
+        b = n_all if b is None else b
+        lib.synth_render_fused(field.table, field.n_blobs, field.n_sets, None, rays_o[a:b],
+                               rays_d[a:b], None, grid.bits, grid.desc, params, eps,
+                               f_color[a:b], f_opacity[a:b], f_depth[a:b], f_kept[a:b])
+
+    # warm-up (also fills the allocator's cache) and equality checks
     e_b, color_b = batched()
     colors = []
     for k in range(len(counts)):
         a, b = int(offs[k]), int(offs[k + 1])
         colors.append(render(rays_o[a:b], rays_d[a:b])[1])
+    fused()
     torch.cuda.synchronize()
     same = bool(torch.equal(color_b.view(torch.int32), torch.cat(colors).view(torch.int32)))
-    log(f"batched vs per-image colours identical: {same}; {e_b} samples")
+    same_fused = bool(torch.equal(color_b.view(torch.int32), f_color.view(torch.int32)))
+    kept_total = int(f_kept.sum().item())
+    log(f"batched vs per-image colours identical: {same}; fused identical: {same_fused}; "
+        f"{e_b} samples, {kept_total} before the cut")
     del colors, color_b
 
     runs = max(args.steps // 3, 3)
@@ -837,6 +864,28 @@ def bench_images(args, torch, nacc):
         torch.cuda.synchronize()
         lat_p += [start.elapsed_time(ev) for ev in done]
         ms_p.append(start.elapsed_time(done[-1]))
+    # fused: all images in one launch, and one launch per image
+    ms_f, lat_f = [], []
+    for _ in range(runs):
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        fused()
+        stop.record()
+        torch.cuda.synchronize()
+        ms_f.append(start.elapsed_time(stop))
+        done = [torch.cuda.Event(enable_timing=True) for _ in counts]
+        start.record()
+        for k in range(len(counts)):
+            fused(int(offs[k]), int(offs[k + 1]))
+            done[k].record()
+        torch.cuda.synchronize()
+        lat_f += [start.elapsed_time(ev) for ev in done]
+    med_f = float(np.median(ms_f))
+    # lane operations the fused kernel must at least do: the field and the
+    # render of every sample before the cut (marching not counted)
+    ops_f = kept_total * (FIELD_OPS_PER_BLOB * field.n_blobs + FIELD_OPS_FIXED + RENDER_OPS)
     events = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     render(rays_o, rays_d, events)
     torch.cuda.synchronize()
@@ -878,6 +927,15 @@ def bench_images(args, torch, nacc):
                        "plain": {"p50": pct(lat_p, 50), "p90": pct(lat_p, 90),
                                  "p99": pct(lat_p, 99)}},
         "identical_outputs": same,
+        "fused": {"ms": med_f, "rendered_samples_per_s": kept_total / (med_f * 1e-3),
+                  "samples_before_cut": kept_total, "over_batched": med_b / med_f,
+                  "identical_to_batched": same_fused,
+                  "latency_ms_per_image_launches": {"p50": pct(lat_f, 50), "p90": pct(lat_f, 90),
+                                                    "p99": pct(lat_f, 99)},
+                  "roofline": {"bound": "alu", "kernel": "fused_render", "achieved": ops_f / (med_f * 1e-3) / 1e12,
+                               "peak": ALU_PEAK / 1e12, "unit": "TOP/s",
+                               "frac": ops_f / (med_f * 1e-3) / ALU_PEAK,
+                               "note": "lower bound: field and render of the samples before the cut only"}},
         "phase_ms": phase,
         "cpu_baseline": None,
     }

@@ -22,6 +22,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "nacc.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -67,6 +69,33 @@ int nacc_synth_field_samples(const void* table, int32_t n_blobs, int32_t n_sets,
 int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, const float* points,
                             const int32_t* point_set, const int32_t* point_cell, int64_t cells_per_set,
                             int64_t n, float* sigmas, float* rgbs, void* stream);
+
+/*
+ * Fused inference (Sec. 2.1 marching with early termination, Eq. 1
+ * rendering, forward only): marches each ray through the occupancy grid,
+ * evaluates this synthetic field at the occupied samples and renders them,
+ * in one kernel, without writing the samples out.  For fields that can be
+ * evaluated inside the kernel only (this one).
+ *   Arguments as in nacc_march_count / nacc_march_fill (rays_o, rays_d,
+ *   grid_id nullable, grid_bits, grid, params) and nacc_synth_field_samples
+ *   (table, n_blobs, n_sets, ray_set nullable); uniform steps only
+ *   (params->cone must be 0, else NACC_ENOTSUP).  The skip field is not
+ *   used (the sample set is the same).
+ *   early_stop_eps  as in nacc_render_fwd (0 disables the cut).
+ *   color float[n_rays][3], opacity, depth float[n_rays]: outputs as from
+ *   nacc_render_fwd; kept int32[n_rays] (nullable): samples before the cut.
+ * The samples are those nacc_march_fill would write and the chunks those
+ * nacc_render_fwd would read, so the outputs equal, bit for bit, marching,
+ * then nacc_synth_field_samples, then nacc_render_fwd.  Marching stops at
+ * the early-termination cut.  Errors: NACC_EINVAL / NACC_ESHAPE for invalid
+ * arguments (checked on the host before any launch), NACC_EHIP for a
+ * failed launch.
+ */
+int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, const int32_t* ray_set,
+                            const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
+                            const uint32_t* grid_bits, const nacc_grid_desc* grid,
+                            const nacc_march_params* params, float early_stop_eps, float* color,
+                            float* opacity, float* depth, int32_t* kept, void* stream);
 
 #ifdef __cplusplus
 }

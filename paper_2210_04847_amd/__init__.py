@@ -8,7 +8,7 @@ requires the built library (python -m paper_2210_04847_amd.build).
 from . import _lib
 from ._lib import NaccError, version
 from .api import (BlobField, OccupancyGrid, RenderFn, STEP_1024, prune_samples, ray_marching,
-                  render_mse, rendering)
+                  render_fused, render_mse, rendering)
 
 __all__ = ["BlobField", "NaccError", "OccupancyGrid", "RenderFn", "STEP_1024", "prune_samples",
-           "ray_marching", "render_mse", "rendering", "version", "_lib"]
+           "ray_marching", "render_fused", "render_mse", "rendering", "version", "_lib"]

@@ -85,6 +85,9 @@ _SIGNATURES = {
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
                                         _P, _P, _P, _P]),
     "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "nacc_synth_render_fused": (_INT, [_P, _I32, _I32, _P, _P, _P, _P, _I64, _P,
+                                       ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams), _F,
+                                       _P, _P, _P, _P, _P]),
 }
 
 # Symbols declared in include/nacc.h and include/nacc_synth.h.
@@ -436,3 +439,22 @@ def synth_field_points(table, n_blobs, n_sets, points, point_set, sigmas, rgbs=N
     _check("nacc_synth_field_points", lib.nacc_synth_field_points(
         _ptr(table), n_blobs, n_sets, _ptr(points), _ptr(point_set), _ptr(point_cell),
         int(cells_per_set), n, _ptr(sigmas), _ptr(rgbs), _stream(stream)))
+
+
+def synth_render_fused(table, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id, grid_bits, desc,
+                       params, early_stop_eps, color, opacity, depth, kept=None, stream=None):
+    n = rays_o.shape[0]
+    _need(table, torch.float32, "table")
+    _need(ray_set, torch.int32, "ray_set", n)
+    _need(rays_o, torch.float32, "rays_o", 3 * n)
+    _need(rays_d, torch.float32, "rays_d", 3 * n)
+    _need(grid_id, torch.int32, "grid_id", n)
+    _need(grid_bits, torch.int32, "grid_bits", _grid_words(desc))
+    _need(color, torch.float32, "color", 3 * n)
+    _need(opacity, torch.float32, "opacity", n)
+    _need(depth, torch.float32, "depth", n)
+    _need(kept, torch.int32, "kept", n)
+    _check("nacc_synth_render_fused", lib.nacc_synth_render_fused(
+        _ptr(table), n_blobs, n_sets, _ptr(ray_set), _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n,
+        _ptr(grid_bits), ctypes.byref(desc), ctypes.byref(params), float(early_stop_eps),
+        _ptr(color), _ptr(opacity), _ptr(depth), _ptr(kept), _stream(stream)))

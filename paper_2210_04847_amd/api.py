@@ -296,3 +296,28 @@ class BlobField:
         _lib.synth_field_points(self.table_contracted if contracted else self.table, self.n_blobs,
                                 self.n_sets, points.contiguous(), ps, sig, rgb)
         return (sig, rgb) if want_rgb else sig
+
+
+def render_fused(field: BlobField, rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0,
+                 far_plane=1e10, render_step_size=STEP_1024, early_stop_eps=1e-4, max_per_ray=0,
+                 grid_id=None, ray_set=None, return_kept=False):
+    """Inference in one kernel (Sec. 2.1 marching with early termination and
+    Eq. 1, forward only) for a field the library evaluates itself: marches,
+    evaluates `field` at the occupied samples and renders them without
+    writing the samples out.  Returns (color [R, 3], opacity [R], depth [R])
+    (and the samples before the cut per ray, with return_kept), equal bit
+    for bit to ray_marching -> field.samples -> rendering.  Uniform steps
+    only."""
+    n = rays_o.shape[0]
+    dev = rays_o.device
+    color = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    opacity = torch.empty(n, dtype=torch.float32, device=dev)
+    depth = torch.empty(n, dtype=torch.float32, device=dev)
+    kept = torch.empty(n, dtype=torch.int32, device=dev) if return_kept else None
+    params = _lib.march_params(near_plane, far_plane, render_step_size, max_per_ray=max_per_ray)
+    gid = None if grid_id is None else grid_id.to(torch.int32).contiguous()
+    rs = None if ray_set is None else ray_set.to(torch.int32).contiguous()
+    _lib.synth_render_fused(field.table, field.n_blobs, field.n_sets, rs, rays_o.contiguous(),
+                            rays_d.contiguous(), gid, grid.bits, grid.desc, params, early_stop_eps,
+                            color, opacity, depth, kept)
+    return (color, opacity, depth, kept) if return_kept else (color, opacity, depth)

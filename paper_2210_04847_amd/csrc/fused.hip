@@ -1,0 +1,243 @@
+// Fused inference: marching, an in-kernel field and the forward render of
+// each ray in one wavefront, without writing the samples out (NerfAcc
+// Sec. 2.1 marching with early termination, Eq. 1 rendering; the field is
+// the synthetic blob field, the one field the library can evaluate itself).
+//
+// One wavefront per ray.  The wave marches 64 lattice candidates per
+// iteration exactly as the marching kernels do (uniform steps) and appends
+// the occupied ones, in t order, to a ring of candidate indices in its LDS
+// slice.  Whenever the ring holds 64 of them (or the ray's candidates are
+// exhausted) the wave takes them as one chunk: each lane evaluates the field
+// at its sample's midpoint and the chunk is rendered with the same
+// transmittance routine as the rendering kernels.  The chunks are the ray's
+// samples 64 at a time, the same chunks the rendering kernels read from the
+// packed arrays, so colour, opacity and depth are bit for bit those of
+// marching + field + rendering as three steps.  Marching stops at the
+// early-termination cut, which the three-step form cannot do (it marches the
+// whole ray before any density is known).
+#include <cmath>
+
+#include "blob_field.h"
+#include "common.h"
+#include "lattice.h"
+#include "nacc_synth.h"
+#include "transmittance.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using namespace nacc;
+using namespace nacc::dev;
+using namespace nacc::blob;
+using namespace nacc::vr;
+
+constexpr int kFusedWaves = 4;
+constexpr int kFusedRays = 64;  // rays per workgroup: lane j of a wave clips its j-th ray
+constexpr int kRing = 128;      // candidate indices per wave: < 64 held + 64 appended
+
+// Orders one wave's LDS writes before its later reads of other lanes' slots
+// (and those reads before the slots are written again).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LOOKUP, bool PER_SET>
+__device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span, const float* __restrict__ table,
+                                                 int n_blobs, int n_sets, const int32_t* __restrict__ ray_set,
+                                                 const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+                                                 const uint32_t* __restrict__ bits, const GridK& g, const StepK& p,
+                                                 float eps, int* __restrict__ ring, float* __restrict__ color,
+                                                 float* __restrict__ opacity, float* __restrict__ depth,
+                                                 int32_t* __restrict__ kept) {
+    const int lane = lane_id();
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    int set = 0;
+    if (PER_SET) {
+        set = uniform<int>(ray_set[r]);
+        set = set < 0 ? 0 : (set >= n_sets ? n_sets - 1 : set);
+    }
+    const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
+    const bool contract = cc[12] != 0.0f;
+    const float t_near = span.t_near, t_far = span.t_far;
+    double carry = 0.0;
+    float acc_r = 0.0f, acc_g = 0.0f, acc_b = 0.0f, acc_a = 0.0f, acc_d = 0.0f;
+    int head = 0;      // ring slot of the oldest queued candidate
+    int queued = 0;    // candidates in the ring
+    int marched = 0;   // samples appended so far (max_per_ray)
+    int rendered = 0;  // samples taken as chunks so far
+    int n_kept = -1;
+    bool more = span.valid;
+    int k0 = 0;
+    while (true) {
+        // march until a whole chunk is queued or the ray's candidates end
+        while (more && queued < kWave) {
+            const int k = k0 + lane;
+            const float t0 = t_near + static_cast<float>(k) * p.dt;
+            const bool live = t0 < t_far;
+            if (ballot(live) == 0ull || k0 >= kMaxCandidates) {  // t_k is non-decreasing in k
+                more = false;
+                break;
+            }
+            const float t1 = t_near + static_cast<float>(k + 1) * p.dt;
+            const float tm = (t0 + t1) * 0.5f;
+            const Probe q = probe<LOOKUP>(g, span.word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+            bool hit = live && ((bits[q.word] >> q.bit) & 1u) != 0u;
+            uint64_t m = ballot(hit);
+            int n_new = __popcll(m);
+            if (p.max_per_ray > 0 && marched + n_new >= p.max_per_ray) {
+                n_new = p.max_per_ray - marched;  // the first ones in t order
+                hit = hit && bits_below(m) < n_new;
+                m = ballot(hit);
+                more = false;
+            }
+            if (hit) ring[(head + queued + bits_below(m)) & (kRing - 1)] = k;
+            queued += n_new;
+            marched += n_new;
+            k0 += kWave;
+        }
+        if (queued == 0) break;
+        wave_lds_sync();
+        // one chunk: the next min(queued, 64) samples of the ray
+        const int n_chunk = min(queued, kWave);
+        const bool valid = lane < n_chunk;
+        float t0 = 0.0f, t1 = 0.0f, sigma = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+        if (valid) {
+            const int k = ring[(head + lane) & (kRing - 1)];
+            t0 = t_near + static_cast<float>(k) * p.dt;
+            t1 = t_near + static_cast<float>(k + 1) * p.dt;
+            float x0 = midpoint_coord(o[0], d[0], t0, t1);
+            float x1 = midpoint_coord(o[1], d[1], t0, t1);
+            float x2 = midpoint_coord(o[2], d[2], t0, t1);
+            to_scene(contract, x0, x1, x2);
+            eval_field(table, n_blobs, set, x0, x1, x2, sigma);
+            eval_rgb(cc, x0, x1, x2, cr, cg, cb);
+        }
+        wave_lds_sync();
+        head = (head + n_chunk) & (kRing - 1);
+        queued -= n_chunk;
+        const Trans t = transmittance_of(sigma * (t1 - t0), carry);
+        const int keep_n = chunk_keep(valid, t.t_in, eps);
+        const bool keep = valid && lane < keep_n;
+        const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
+        acc_r += w * cr;
+        acc_g += w * cg;
+        acc_b += w * cb;
+        acc_a += w;
+        acc_d += w * ((t0 + t1) * 0.5f);
+        carry += static_cast<double>(read_lane(t.incl, 63));
+        if (keep_n < kWave) {
+            n_kept = rendered + keep_n;
+            break;
+        }
+        rendered += n_chunk;
+    }
+    acc_r = wave_sum(acc_r);
+    acc_g = wave_sum(acc_g);
+    acc_b = wave_sum(acc_b);
+    acc_a = wave_sum(acc_a);
+    acc_d = wave_sum(acc_d);
+    if (lane == 0) {
+        color[3 * r] = acc_r;
+        color[3 * r + 1] = acc_g;
+        color[3 * r + 2] = acc_b;
+        opacity[r] = acc_a;
+        depth[r] = acc_d;
+        if (kept != nullptr) kept[r] = n_kept >= 0 ? n_kept : rendered;
+    }
+}
+
+template <int LOOKUP, bool PER_SET>
+__global__ __launch_bounds__(kFusedWaves * kWave) void fused_render_kernel(
+    const float* __restrict__ table, int n_blobs, int n_sets, const int32_t* __restrict__ ray_set,
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, const uint32_t* __restrict__ bits, GridK g, ClipK c, StepK p, float eps,
+    float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth, int32_t* __restrict__ kept) {
+    __shared__ int rings[kFusedWaves][kRing];
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kFusedRays;
+    // this wave's rays are first + wave + j kFusedWaves; lane j clips ray j
+    const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * kFusedWaves;
+    RaySpan spans{0.0f, 0.0f, 0u, false};
+    if (lane_id() < kFusedRays / kFusedWaves && mine < n_rays) {
+        spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
+    }
+    for (int i = wave; i < kFusedRays; i += kFusedWaves) {
+        const int64_t r = first + i;
+        if (r >= n_rays) break;
+        const RaySpan span = read_span(spans, i / kFusedWaves);
+        render_ray_fused<LOOKUP, PER_SET>(r, span, table, n_blobs, n_sets, ray_set, rays_o, rays_d, bits, g, p, eps,
+                                          rings[wave], color, opacity, depth, kept);
+    }
+}
+
+template <int LOOKUP>
+void launch_fused(bool per_set, unsigned nb, hipStream_t s, const float* table, int n_blobs, int n_sets,
+                  const int32_t* ray_set, const float* o, const float* d, const int32_t* gid, int64_t n,
+                  const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p, float eps, float* color,
+                  float* opacity, float* depth, int32_t* kept) {
+    if (per_set) {
+        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, true>), dim3(nb), dim3(kFusedWaves * kWave), 0, s, table,
+                           n_blobs, n_sets, ray_set, o, d, gid, n, bits, g, c, p, eps, color, opacity, depth, kept);
+    } else {
+        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, false>), dim3(nb), dim3(kFusedWaves * kWave), 0, s, table,
+                           n_blobs, n_sets, ray_set, o, d, gid, n, bits, g, c, p, eps, color, opacity, depth, kept);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, const int32_t* ray_set,
+                            const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
+                            const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
+                            float early_stop_eps, float* color, float* opacity, float* depth, int32_t* kept,
+                            void* stream) {
+    clear_error();
+    int st = validate(rays_o, rays_d, n_rays, grid_bits, grid, params);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(params->cone == 0.0f, NACC_ENOTSUP, "the fused kernel marches uniform steps only (cone = %g)",
+                 params->cone);
+    NACC_REQUIRE(table != nullptr && n_blobs >= 1 && n_sets >= 1, NACC_EINVAL,
+                 "table must be non-NULL with n_blobs, n_sets >= 1");
+    NACC_REQUIRE(std::isfinite(early_stop_eps) && early_stop_eps >= 0.0f, NACC_EINVAL,
+                 "early_stop_eps = %g must be finite and >= 0", early_stop_eps);
+    NACC_REQUIRE(n_rays == 0 || (color != nullptr && opacity != nullptr && depth != nullptr), NACC_EINVAL,
+                 "color, opacity and depth must be non-NULL");
+    if (n_rays == 0) return NACC_OK;
+    GridK g;
+    ClipK c;
+    StepK p;
+    make_constants(*grid, *params, g, c, p);
+    const unsigned nb = static_cast<unsigned>((n_rays + kFusedRays - 1) / kFusedRays);
+    hipStream_t s = as_stream(stream);
+    const float* tb = static_cast<const float*>(table);
+    const bool per_set = ray_set != nullptr;
+    switch (grid->lookup) {
+        case NACC_LOOKUP_AABB:
+            launch_fused<NACC_LOOKUP_AABB>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
+                                           n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity, depth, kept);
+            break;
+        case NACC_LOOKUP_CASCADE:
+            launch_fused<NACC_LOOKUP_CASCADE>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
+                                              n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity, depth,
+                                              kept);
+            break;
+        default:
+            launch_fused<NACC_LOOKUP_CONTRACT>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d,
+                                               grid_id, n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity,
+                                               depth, kept);
+            break;
+    }
+    return check_launch("fused render");
+}
+
+}  // extern "C"

@@ -32,6 +32,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "lattice.h"
 #include "scan.h"
 
 #pragma clang fp contract(off)
@@ -40,127 +41,6 @@ namespace {
 
 using namespace nacc;
 using namespace nacc::dev;
-
-constexpr int kMaxCandidates = 1 << 24;
-
-struct GridK {
-    float lo[3];
-    float s[3];        // fl32(res / (hi - lo))
-    float top;         // (float)(res - 1)
-    float base;        // cascade: half-extent of level 0 (a power of two)
-    float inv_base;    // 1 / base (exact)
-    int res;
-    int n_grids;
-    uint32_t words;    // 32-bit words per grid
-    int coarse;          // coarse cells per axis of the skip field (res / 4)
-    uint32_t skip_cells;  // bytes per grid of the skip field (coarse^3)
-};
-
-struct ClipK {
-    float lo[3];
-    float hi[3];
-};
-
-struct StepK {
-    float near_plane, far_plane, dt, dt_max, cone;
-    int max_per_ray;
-};
-
-// Ray against the clip box (FP32 slab test of the contract).
-__device__ __forceinline__ bool clip_ray(const float o[3], const float d[3], const ClipK& c,
-                                         float near_plane, float far_plane, float& t_near,
-                                         float& t_far) {
-    float t_enter = -INFINITY, t_exit = INFINITY;
-    bool miss = false;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (d[i] != 0.0f) {
-            float ta = (c.lo[i] - o[i]) / d[i];
-            float tb = (c.hi[i] - o[i]) / d[i];
-            t_enter = fmaxf(t_enter, fminf(ta, tb));
-            t_exit = fminf(t_exit, fmaxf(ta, tb));
-        } else if (!(o[i] >= c.lo[i] && o[i] <= c.hi[i])) {
-            miss = true;
-        }
-    }
-    t_near = fmaxf(t_enter, near_plane);
-    t_far = fminf(t_exit, far_plane);
-    return !miss && t_near < t_far;
-}
-
-// min(max(u, 0), top) in one instruction (the median of the three; no NaN
-// reaches it for finite rays).
-__device__ __forceinline__ float clamp_cell(float u, float top) { return __builtin_amdgcn_fmed3f(u, 0.0f, top); }
-
-// Cascade level of a point with m = max_i |x_i|: the number of levels
-// l < n_grids - 1 with m > base 2^l, i.e. the smallest l with m <= base 2^l,
-// clamped to the last level.  q = m / base is exact (base is a power of
-// two), and the smallest l with q <= 2^l is read off q's exponent and
-// mantissa: q = 1.f 2^(e-127) gives e - 127, plus one unless f = 0.  Zero,
-// subnormal and NaN m give level 0, as the comparisons do.
-__device__ __forceinline__ int cascade_level(float m, const GridK& g) {
-    const uint32_t b = __float_as_uint(m * g.inv_base);
-    const int e = static_cast<int>(b >> 23);
-    int level = e - 127 + ((b & 0x7fffffu) != 0u ? 1 : 0);
-    if (e == 0 || !(m == m)) level = 0;
-    return min(max(level, 0), g.n_grids - 1);
-}
-
-// Where point x is looked up: the grid word and bit of its fine cell, the
-// byte of its coarse cell in the skip field, and (cascade) its level and
-// m = max_i |x_i|.  `word0` is the first word of the ray's grid (box /
-// contraction lookups); the cascade picks its level itself.
-struct Probe {
-    uint32_t word;
-    uint32_t bit;
-    uint32_t coarse;
-    int level;
-    float m;
-};
-
-template <int LOOKUP>
-__device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0, float x1, float x2) {
-    Probe q;
-    q.level = 0;
-    q.m = 0.0f;
-    uint32_t grid = word0 / g.words;
-    if (LOOKUP == NACC_LOOKUP_CASCADE) {
-        q.m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
-        q.level = cascade_level(q.m, g);
-        x0 = ldexpf(x0, -q.level);
-        x1 = ldexpf(x1, -q.level);
-        x2 = ldexpf(x2, -q.level);
-        grid = static_cast<uint32_t>(q.level);
-        word0 = grid * g.words;
-    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
-        float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
-        if (n > 1.0f) {
-            float f = (2.0f - 1.0f / n) / n;
-            x0 = x0 * f;
-            x1 = x1 * f;
-            x2 = x2 * f;
-        }
-    }
-    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
-    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
-    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
-    // j < res <= 1024, so every product fits the 24-bit multiplier
-    const uint32_t res = static_cast<uint32_t>(g.res);
-    const uint32_t cell = __umul24(__umul24(j0, res) + j1, res) + j2;
-    q.word = word0 + (cell >> 5);
-    q.bit = cell & 31u;
-    const uint32_t cc = static_cast<uint32_t>(g.coarse);
-    q.coarse = grid * g.skip_cells + __umul24(__umul24(j0 >> 2, cc) + (j1 >> 2), cc) + (j2 >> 2);
-    return q;
-}
-
-// Occupancy bit of point x.
-template <int LOOKUP>
-__device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint32_t word0,
-                                         const GridK& g, float x0, float x1, float x2) {
-    const Probe q = probe<LOOKUP>(g, word0, x0, x1, x2);
-    return ((bits[q.word] >> q.bit) & 1u) != 0u;
-}
 
 // Per-ray constants of the skip-field test.
 //   slack_x: allowance for the FP32 rounding of sample positions: two
@@ -229,55 +109,6 @@ __device__ __forceinline__ float wave_max(float x) {
     x = fmaxf(x, dpp_or_self<kRowBcast15, 0xa>(x));
     x = fmaxf(x, dpp_or_self<kRowBcast31, 0xc>(x));
     return read_lane(x, kWave - 1);
-}
-
-// First word of the ray's grid, or false for an invalid grid id (the ray is
-// then treated as a miss).
-template <int LOOKUP>
-__device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id, int64_t r,
-                                            const GridK& g, uint32_t& word0) {
-    word0 = 0;
-    if (LOOKUP != NACC_LOOKUP_CASCADE && grid_id != nullptr) {
-        int gid = grid_id[r];
-        if (gid < 0 || gid >= g.n_grids) return false;
-        word0 = static_cast<uint32_t>(gid) * g.words;
-    }
-    return true;
-}
-
-// Where a ray is marched: its clipped range and the first word of its grid
-// (valid = false: an invalid grid id or a miss, no samples).  The uniform
-// kernels compute the spans of a wave's rays lane-parallel, one ray per
-// lane, and broadcast each one as the wave reaches its ray.
-struct RaySpan {
-    float t_near, t_far;
-    uint32_t word0;
-    bool valid;
-};
-
-template <int LOOKUP>
-__device__ __forceinline__ RaySpan ray_span(int64_t r, const float* __restrict__ rays_o,
-                                            const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
-                                            const GridK& g, const ClipK& c, const StepK& p) {
-    RaySpan s;
-    float o[3], d[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
-    }
-    s.valid = grid_of_ray<LOOKUP>(grid_id, r, g, s.word0);
-    s.valid = clip_ray(o, d, c, p.near_plane, p.far_plane, s.t_near, s.t_far) && s.valid;
-    return s;
-}
-
-__device__ __forceinline__ RaySpan read_span(const RaySpan& s, int lane) {
-    RaySpan b;
-    b.t_near = read_lane(s.t_near, lane);
-    b.t_far = read_lane(s.t_far, lane);
-    b.word0 = static_cast<uint32_t>(read_lane(static_cast<int>(s.word0), lane));
-    b.valid = read_lane(s.valid ? 1 : 0, lane) != 0;
-    return b;
 }
 
 // One ray, uniform steps, whole wave.  Returns the ray's sample count (the
@@ -931,77 +762,6 @@ ConeWork cone_work(void* workspace, const Layout& l) {
     w.extra = reinterpret_cast<int32_t*>(b + l.extra_off);
     w.n_masks = l.n_masks;
     return w;
-}
-
-int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uint32_t* bits,
-             const nacc_grid_desc* grid, const nacc_march_params* params) {
-    NACC_REQUIRE(grid != nullptr && params != nullptr, NACC_EINVAL, "grid and params must be non-NULL");
-    NACC_REQUIRE(n_rays >= 0 && n_rays <= INT32_MAX, NACC_EINVAL, "n_rays = %lld out of [0, 2^31-1]",
-                 static_cast<long long>(n_rays));
-    NACC_REQUIRE(n_rays == 0 || (rays_o != nullptr && rays_d != nullptr && bits != nullptr),
-                 NACC_EINVAL, "rays_o, rays_d and grid_bits must be non-NULL");
-    const int res = grid->res;
-    NACC_REQUIRE(res >= 1 && res <= 1024, NACC_EINVAL, "grid res = %d out of [1, 1024]", res);
-    const int64_t cells = static_cast<int64_t>(res) * res * res;
-    NACC_REQUIRE(cells % 32 == 0, NACC_ESHAPE, "res^3 = %lld is not a multiple of 32",
-                 static_cast<long long>(cells));
-    NACC_REQUIRE(grid->lookup >= 0 && grid->lookup <= 2, NACC_EINVAL, "unknown lookup mode %d", grid->lookup);
-    NACC_REQUIRE(grid->n_grids >= 1, NACC_EINVAL, "n_grids = %d < 1", grid->n_grids);
-    NACC_REQUIRE(static_cast<int64_t>(grid->n_grids) * (cells / 32) <= UINT32_MAX, NACC_ESHAPE,
-                 "grid array exceeds 2^32 words");
-    for (int i = 0; i < 3; ++i) {
-        NACC_REQUIRE(std::isfinite(grid->lo[i]) && std::isfinite(grid->hi[i]) && grid->lo[i] < grid->hi[i],
-                     NACC_EINVAL, "grid box axis %d is empty or not finite", i);
-    }
-    if (grid->lookup == NACC_LOOKUP_CASCADE) {
-        NACC_REQUIRE(grid->n_grids <= 16, NACC_EINVAL, "cascade levels = %d > 16", grid->n_grids);
-        int e = 0;
-        const float b = grid->hi[0];
-        NACC_REQUIRE(std::frexp(b, &e) == 0.5f, NACC_EINVAL, "cascade half-extent %g is not a power of two", b);
-        for (int i = 0; i < 3; ++i) {
-            NACC_REQUIRE(grid->hi[i] == b && grid->lo[i] == -b, NACC_EINVAL,
-                         "cascade level-0 box must be [-b, b]^3");
-        }
-    }
-    const nacc_march_params& p = *params;
-    NACC_REQUIRE(std::isfinite(p.dt) && p.dt > 0.0f, NACC_EINVAL, "dt = %g must be finite and > 0", p.dt);
-    NACC_REQUIRE(std::isfinite(p.cone) && p.cone >= 0.0f, NACC_EINVAL, "cone = %g must be finite and >= 0",
-                 p.cone);
-    NACC_REQUIRE(p.cone == 0.0f || p.dt_max >= p.dt, NACC_EINVAL, "dt_max = %g < dt = %g", p.dt_max, p.dt);
-    NACC_REQUIRE(!std::isnan(p.near_plane) && !std::isnan(p.far_plane), NACC_EINVAL, "near/far is NaN");
-    NACC_REQUIRE(p.max_per_ray >= 0, NACC_EINVAL, "max_per_ray = %d < 0", p.max_per_ray);
-    return NACC_OK;
-}
-
-void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params, GridK& g, ClipK& c,
-                    StepK& p) {
-    for (int i = 0; i < 3; ++i) {
-        g.lo[i] = grid.lo[i];
-        g.s[i] = axis_scale(grid.res, grid.lo[i], grid.hi[i]);
-        c.lo[i] = grid.lo[i];
-        c.hi[i] = grid.hi[i];
-        if (grid.lookup == NACC_LOOKUP_CASCADE) {
-            c.lo[i] = std::ldexp(grid.lo[i], grid.n_grids - 1);
-            c.hi[i] = std::ldexp(grid.hi[i], grid.n_grids - 1);
-        } else if (grid.lookup == NACC_LOOKUP_CONTRACT) {
-            c.lo[i] = -INFINITY;
-            c.hi[i] = INFINITY;
-        }
-    }
-    g.top = static_cast<float>(grid.res - 1);
-    g.base = grid.hi[0];
-    g.inv_base = 1.0f / grid.hi[0];
-    g.res = grid.res;
-    g.n_grids = grid.n_grids;
-    g.words = static_cast<uint32_t>(static_cast<int64_t>(grid.res) * grid.res * grid.res / 32);
-    g.coarse = grid.res / 4;
-    g.skip_cells = static_cast<uint32_t>(g.coarse) * g.coarse * g.coarse;
-    p.near_plane = params.near_plane;
-    p.far_plane = params.far_plane;
-    p.dt = params.dt;
-    p.dt_max = params.dt_max;
-    p.cone = params.cone;
-    p.max_per_ray = params.max_per_ray;
 }
 
 template <int LOOKUP, bool SKIP, int WAVES>

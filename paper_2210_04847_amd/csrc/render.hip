@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "scan.h"
+#include "transmittance.h"
 
 #pragma clang fp contract(off)
 
@@ -28,6 +29,7 @@ namespace {
 
 using namespace nacc;
 using namespace nacc::dev;
+using namespace nacc::vr;
 
 constexpr int kRenderThreads = 256;  // 4 waves
 constexpr int kRaysPerRenderBlock = kRenderThreads / kWave;
@@ -56,56 +58,8 @@ __device__ __forceinline__ void store_rgb(float* __restrict__ out, int64_t s, fl
     reinterpret_cast<float3*>(out)[s] = make_float3(r, g, b);
 }
 
-constexpr float kLog2e = 1.4426950408889634f;
-
-// e^-x for x >= 0 on the hardware exp2 (relative error a few ulp).
-__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-x * kLog2e); }
-
-// alpha = 1 - e^-tau without cancellation: for tau <= 1/4 the alternating
-// series tau (1 - tau/2 (1 - tau/3 (... (1 - tau/6)))) (truncation below
-// tau^6 / 5040 < 5e-8 relative), above it 1 - e^-tau directly (e^-tau <=
-// 0.78, so the subtraction loses at most a few ulp).
-__device__ __forceinline__ float alpha_of(float tau) {
-    if (tau <= 0.25f) {
-        float p = 1.0f - tau * (1.0f / 6.0f);
-        p = 1.0f - tau * (1.0f / 5.0f) * p;
-        p = 1.0f - tau * 0.25f * p;
-        p = 1.0f - tau * (1.0f / 3.0f) * p;
-        p = 1.0f - tau * 0.5f * p;
-        return tau * p;
-    }
-    return 1.0f - exp_neg(tau);
-}
-
-// Transmittance of each lane's sample in a chunk, given the FP64 prefix of
-// tau before the chunk: T_i = e^-carry * e^-(exclusive chunk prefix).  The
-// chunk factor comes from the FP64 carry rounded once to FP32, the lane
-// factor from a short FP32 prefix inside the chunk; relative error about
-// (carry + chunk prefix) * log2(e) * 2^-24 plus a few ulp.
-struct Trans {
-    float tau;     // sigma * delta
-    float incl;    // inclusive prefix of tau inside the chunk
-    float t_in;    // T_i
-    float t_next;  // T_{i+1}
-};
-
 __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double carry) {
-    Trans t;
-    t.tau = x.sigma * (x.t1 - x.t0);
-    t.incl = wave_inclusive_sum(t.tau);
-    const float excl = shift_up_one(t.incl);
-    const float t0 = uniform<float>(exp_neg(static_cast<float>(carry)));
-    t.t_in = t0 * exp_neg(excl);
-    t.t_next = t0 * exp_neg(t.incl);
-    return t;
-}
-
-// Number of leading lanes kept in this chunk: the first valid lane with
-// T < eps and every lane after it are cut (64 = no cut here).
-__device__ __forceinline__ int chunk_keep(bool valid, float t_in, float eps) {
-    if (!(eps > 0.0f)) return kWave;
-    const uint64_t m = ballot(valid && t_in < eps);
-    return m == 0 ? kWave : static_cast<int>(__builtin_ctzll(m));
+    return transmittance_of(x.sigma * (x.t1 - x.t0), carry);
 }
 
 // The ray's sample range from packed_info; a range that does not lie inside

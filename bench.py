@@ -28,6 +28,9 @@ ray).
 --workload images_8: four 800x800 and four 1920x1080 images rendered
 forward, all images in one call sequence against one per image.
 
+--workload attrs_262k: the training rays with 16-channel feature vectors
+rendered (background, opacity threshold) forward and backward.
+
 --workload plain_fwd_4k: 4,096 rays, 8 blobs, forward only, no early
 termination.
 
@@ -63,7 +66,7 @@ def parse():
     ap.add_argument("--workload", default="train_262k",
                     choices=["train_262k", "plain_fwd_4k", "unbounded_262k",
                              "unbounded_contract_262k", "dynamic_64", "dynamic_64_shared",
-                             "images_8"])
+                             "images_8", "attrs_262k"])
     ap.add_argument("--form", choices=["graph", "eager"], default="graph",
                     help="time the step captured in HIP graphs, or launched eagerly")
     ap.add_argument("--no-autotune", action="store_true")
@@ -76,6 +79,8 @@ def parse():
                     help="prune the marched samples by visibility before shading them, as the "
                          "paper's ray_marching with sigma_fn (T >= early_stop_eps, alpha >= this; "
                          "the paper's listing uses 1e-2)")
+    ap.add_argument("--attrs-channels", type=int, default=16,
+                    help="attrs_262k: feature channels per sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
@@ -747,6 +752,123 @@ def bench_dynamic(args, torch, nacc):
     }
 
 
+def bench_attrs(args, torch, nacc):
+    """The training workload with per-sample feature vectors instead of
+    colours: march, field densities, then the attribute render forward and
+    backward (16 channels, a background, opacity threshold 0.01) given an
+    upstream gradient of the rendered features, as a feature-decoding model
+    would supply it.  Step captured in a HIP graph."""
+    import numpy as np
+
+    import synth
+    w = synth.WORKLOADS["train_262k"]
+    ch, thre = args.attrs_channels, 0.01
+    inp = synth.workload_inputs(w)
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    grid = nacc.OccupancyGrid(w.box, w.res, device=dev)
+    grid.set_occupancy(t(inp["occ"]), THRESHOLD)
+    field = nacc.BlobField(inp["scene"], device=dev)
+    st = Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid, field,
+              seed=4000 + w.seed_base)
+    lib = nacc._lib
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5000 + w.seed_base)
+    feats = torch.randn((st.capacity, ch), generator=gen, device=dev)
+    g_out = torch.randn((st.n, ch), generator=gen, device=dev)
+    bg = torch.linspace(0.0, 1.0, ch, device=dev)
+    out = torch.empty((st.n, ch), device=dev)
+    g_feats = torch.empty_like(feats)
+    eps = w.early_stop_eps
+
+    def fwd():
+        lib.render_attrs_fwd(st.packed, st.t_starts, st.t_ends, st.sigmas, feats, eps, thre, bg,
+                             out, st.opacity, st.depth)
+
+    def bwd():
+        lib.render_attrs_bwd(st.packed, st.t_starts, st.t_ends, st.sigmas, feats, eps, thre, bg,
+                             g_out, None, None, st.g_sigmas, g_feats)
+
+    def step():
+        st.march_count()
+        st.march_fill()
+        st.field_eval()
+        fwd()
+        bwd()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g = capture(torch, step)
+    steps = args.steps
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    e = int(st.total.item())
+    # per-phase times (eager, HIP events on the launch stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    phases = {"march_count": [], "march_fill": [], "field": [], "attrs_fwd": [], "attrs_bwd": []}
+    for _ in range(16):
+        fns = (st.march_count, st.march_fill, st.field_eval, fwd, bwd)
+        for j, fn in enumerate(fns):
+            ev[j].record()
+            fn()
+        ev[5].record()
+        torch.cuda.synchronize()
+        for j, name in enumerate(phases):
+            phases[name].append(ev[j].elapsed_time(ev[j + 1]))
+    ph = {k: float(np.mean(v)) for k, v in phases.items()}
+    # samples before the cut (FP32 opacity mask included) from the weights
+    wts = torch.empty(st.capacity, device=dev)
+    lib.render_attrs_fwd(st.packed, st.t_starts, st.t_ends, st.sigmas, feats, eps, thre, bg,
+                         out, None, None, wts)
+    torch.cuda.synchronize()
+    counts = st.packed[:, 1].long()
+    ray_of = torch.repeat_interleave(torch.arange(st.n, device=dev), counts)
+    last = torch.zeros(st.n, dtype=torch.long, device=dev)
+    idx = torch.arange(e, device=dev)
+    nz = wts[:e] > 0
+    last.scatter_reduce_(0, ray_of[nz], idx[nz] - st.packed[:, 0].long()[ray_of[nz]] + 1, "amax")
+    v = int(last.sum().item())  # samples up to the last weighted one: a lower bound of those read
+    blocks = -(-ch // 16)
+    fwd_bytes = v * (12 * blocks + 4 * ch) + st.n * (8 + 4 * ch + 8)
+    bwd_bytes = v * (12 + 12 + 4 * ch) + e * (4 + 4 * ch) + st.n * (8 + 4 * ch)
+    dominant = "attrs_bwd" if ph["attrs_bwd"] >= ph["attrs_fwd"] else "attrs_fwd"
+    bps = (bwd_bytes if dominant == "attrs_bwd" else fwd_bytes) / (ph[dominant] * 1e-3)
+    return {
+        "metric": METRIC,
+        "value": e / (ms * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"attrs{ch}_262k", "rays": w.n_rays, "grid": f"{w.res}^3 bit-packed",
+                   "channels": ch, "background": "linspace(0, 1)", "alpha_thre": thre,
+                   "early_stop_eps": eps, "pass": "attribute render forward + backward",
+                   "form": "graph", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": bps / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bps / HBM_PEAK,
+                     "traffic": None},
+        "samples_per_step": e,
+        "samples_read_per_step": v,
+        "phase_ms": ph,
+        "phase_gbps": {"attrs_fwd": fwd_bytes / (ph["attrs_fwd"] * 1e-3) / 1e9,
+                       "attrs_bwd": bwd_bytes / (ph["attrs_bwd"] * 1e-3) / 1e9},
+        "cpu_baseline": None,
+    }
+
+
 def bench_images(args, torch, nacc):
     """Whole images forward (march, field, render): one batched call
     sequence over all images against one plain call sequence per image.
@@ -955,6 +1077,8 @@ def main():
         result = bench_dynamic(args, torch, nacc)
     elif args.workload.startswith("images"):
         result = bench_images(args, torch, nacc)
+    elif args.workload == "attrs_262k":
+        result = bench_attrs(args, torch, nacc)
     else:
         result = bench_train(args, torch, nacc)
     print(json.dumps(result), flush=True)

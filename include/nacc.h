@@ -287,6 +287,54 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays,
                     float* g_sigmas, float* g_rgbs, void* stream);
 
 /*
+ * Rendering of arbitrary per-sample attributes (Sec. 2.2: any sample
+ * attribute, not only colour, is rendered differentiably by Eq. 1), with
+ * a constant background and an opacity threshold.
+ *   packed_info, n_rays, n_samples, t_starts, t_ends, sigmas,
+ *   early_stop_eps   as for nacc_render_fwd.
+ *   attrs        float[n_samples][n_ch], rows contiguous; 1 <= n_ch <= 4096.
+ *   alpha_thre   if > 0, a sample with alpha_i = 1 - exp(-sigma_i delta_i)
+ *                below it is empty: weight 0 and no attenuation of the
+ *                samples behind it (the same as dropping it from the ray);
+ *                <= 0 keeps every sample.  The decision is taken on the
+ *                FP32 alpha.
+ *   background   float[n_ch] or NULL: out += background * (1 - opacity)
+ *                (the constant background of the Sec. 4 examples).
+ *   out          out float[n_rays][n_ch] = sum_i w_i attrs_i (+ background).
+ *   opacity, depth, weights   out float[n_rays], float[n_rays],
+ *                float[n_samples]; each may be NULL (not written).
+ * With n_ch = 3, no background and no threshold the outputs equal those of
+ * nacc_render_fwd bit for bit.  Validation errors as nacc_render_fwd.
+ */
+int nacc_render_attrs_fwd(const int32_t* packed_info, int64_t n_rays,
+                          int64_t n_samples, const float* t_starts,
+                          const float* t_ends, const float* sigmas,
+                          const float* attrs, int32_t n_ch, float early_stop_eps,
+                          float alpha_thre, const float* background, float* out,
+                          float* opacity, float* depth, float* weights,
+                          void* stream);
+
+/*
+ * Backward of nacc_render_attrs_fwd (the cut and the empty samples held
+ * fixed).  Inputs as the forward plus g_out float[n_rays][n_ch] and
+ * g_opacity, g_depth float[n_rays] (NULL = zero).  With
+ * v_i = g_out . attrs_i + (g_opacity - g_out . background) + g_depth m_i:
+ *   g_attrs_i  = w_i g_out                        float[n_samples][n_ch]
+ *   g_sigmas_i = delta_i (T_{i+1} v_i - sum_{k>i} w_k v_k)
+ * both zero for empty samples and at and past the cut; every sample
+ * referenced by packed_info is written.  With n_ch = 3, no background and
+ * no threshold the gradients equal nacc_render_bwd's bit for bit.
+ */
+int nacc_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays,
+                          int64_t n_samples, const float* t_starts,
+                          const float* t_ends, const float* sigmas,
+                          const float* attrs, int32_t n_ch, float early_stop_eps,
+                          float alpha_thre, const float* background,
+                          const float* g_out, const float* g_opacity,
+                          const float* g_depth, float* g_sigmas, float* g_attrs,
+                          void* stream);
+
+/*
  * Visibility pruning of marched samples (Sec. 2.1, "Pruning Empty and
  * Occluded Regions"; the ray_marching call of Sec. 3 with sigma_fn,
  * early_stop_eps and alpha_thre): given the densities of the samples (the

@@ -67,6 +67,12 @@ def _load():
     lib.oracle_render_bwd.restype = ctypes.c_int
     lib.oracle_render_bwd.argtypes = [_P, _I64, _P, _P, _P, _P, _D,
                                       _P, _P, _P, _P, _P, _P]
+    lib.oracle_render_attrs_fwd.restype = None
+    lib.oracle_render_attrs_fwd.argtypes = [_P, _I64, _P, _P, _P, _P, _I64, _I64, _D, _D, _P,
+                                            _P, _P, _P, _P]
+    lib.oracle_render_attrs_bwd.restype = ctypes.c_int
+    lib.oracle_render_attrs_bwd.argtypes = [_P, _I64, _P, _P, _P, _P, _I64, _I64, _D, _D, _P,
+                                            _P, _P, _P, _P, _P, _P]
     lib.oracle_philox4x64_10.restype = None
     lib.oracle_philox4x64_10.argtypes = [_P, _P, _P]
     lib.oracle_grid_sample_cells.restype = None
@@ -204,6 +210,58 @@ def render_bwd(packed_info, t_starts, t_ends, sigmas, rgbs, g_color,
     if rc != 0:
         raise MemoryError("oracle_render_bwd: allocation failed")
     return dict(g_sigmas=gs, g_rgbs=gr, scale=scale)
+
+
+def render_attrs_fwd(packed_info, t_starts, t_ends, sigmas, attrs, eps=0.0, alpha_thre=0.0,
+                     background=None):
+    """FP64 rendering of per-sample attributes attrs [E, C] (Sec. 2.2: any
+    sample attribute is rendered), with an optional constant background
+    blended by 1 - opacity and samples with alpha < alpha_thre treated as
+    empty.  Returns dict(out [R, C], opacity [R], depth [R], weights [E])."""
+    lib = _load()
+    p = _c(packed_info, np.int32).reshape(-1, 2)
+    n = p.shape[0]
+    ts = _c(t_starts, np.float64).ravel()
+    te = _c(t_ends, np.float64).ravel()
+    sg = _c(sigmas, np.float64).ravel()
+    at = _c(attrs, np.float64).reshape(ts.size, -1)
+    ch = at.shape[1]
+    bg = None if background is None else _c(background, np.float64).ravel()
+    out = np.zeros((n, ch))
+    opacity = np.zeros(n)
+    depth = np.zeros(n)
+    weights = np.zeros(ts.size)
+    lib.oracle_render_attrs_fwd(_ptr(p), n, _ptr(ts), _ptr(te), _ptr(sg), _ptr(at), ch, ch,
+                                float(eps), float(alpha_thre), _ptr(bg), _ptr(out),
+                                _ptr(opacity), _ptr(depth), _ptr(weights))
+    return dict(out=out, opacity=opacity, depth=depth, weights=weights)
+
+
+def render_attrs_bwd(packed_info, t_starts, t_ends, sigmas, attrs, g_out, g_opacity=None,
+                     g_depth=None, eps=0.0, alpha_thre=0.0, background=None):
+    """FP64 backward of render_attrs_fwd.  Returns dict(g_sigmas [E],
+    g_attrs [E, C], scale [E]) (scale as in render_bwd)."""
+    lib = _load()
+    p = _c(packed_info, np.int32).reshape(-1, 2)
+    n = p.shape[0]
+    ts = _c(t_starts, np.float64).ravel()
+    te = _c(t_ends, np.float64).ravel()
+    sg = _c(sigmas, np.float64).ravel()
+    at = _c(attrs, np.float64).reshape(ts.size, -1)
+    ch = at.shape[1]
+    gout = _c(g_out, np.float64).reshape(n, ch)
+    ga = None if g_opacity is None else _c(g_opacity, np.float64).ravel()
+    gd = None if g_depth is None else _c(g_depth, np.float64).ravel()
+    bg = None if background is None else _c(background, np.float64).ravel()
+    gs = np.zeros(ts.size)
+    gat = np.zeros((ts.size, ch))
+    scale = np.zeros(ts.size)
+    rc = lib.oracle_render_attrs_bwd(_ptr(p), n, _ptr(ts), _ptr(te), _ptr(sg), _ptr(at), ch, ch,
+                                     float(eps), float(alpha_thre), _ptr(bg), _ptr(gout),
+                                     _ptr(ga), _ptr(gd), _ptr(gs), _ptr(gat), _ptr(scale))
+    if rc != 0:
+        raise MemoryError("oracle_render_attrs_bwd: allocation failed")
+    return dict(g_sigmas=gs, g_attrs=gat, scale=scale)
 
 
 def prune(packed_info, t_starts, t_ends, sigmas, eps=1e-4, alpha_thre=0.0):

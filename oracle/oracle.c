@@ -390,6 +390,133 @@ int oracle_render_bwd(const int32_t* packed_info, int64_t n_rays,
     return 0;
 }
 
+/*
+ * Rendering of arbitrary per-sample attributes (Sec. 2.2: any sample
+ * attribute, not only colour, is rendered differentiably), in FP64, with
+ * two options:
+ *   background (nullable, n_ch values): the rendered attribute is
+ *     sum_i w_i a_i + background * (1 - opacity), the constant background
+ *     of the Instant-NGP example's evaluation (Sec. 4);
+ *   alpha_thre: if > 0, a sample with alpha_i < alpha_thre is empty
+ *     (weight 0, no attenuation of later samples), the same as dropping it
+ *     from the ray before rendering; 0 keeps every sample.
+ * attrs: n_samples rows of n_ch values, row stride `stride` (>= n_ch).
+ * Outputs: out[n_rays * n_ch], opacity, depth (as oracle_render_fwd),
+ * weights[n_samples] (nullable).  The cut is the first sample whose
+ * transmittance (over the samples that are not empty) is below eps.
+ */
+void oracle_render_attrs_fwd(const int32_t* packed_info, int64_t n_rays,
+                             const double* t_starts, const double* t_ends,
+                             const double* sigmas, const double* attrs, int64_t n_ch,
+                             int64_t stride, double eps, double alpha_thre,
+                             const double* background, double* out, double* opacity,
+                             double* depth, double* weights) {
+    for (int64_t r = 0; r < n_rays; ++r) {
+        int64_t start = packed_info[2 * r];
+        int64_t n = packed_info[2 * r + 1];
+        double a = 0.0, dep = 0.0, prefix = 0.0;
+        for (int64_t ch = 0; ch < n_ch; ++ch) out[r * n_ch + ch] = 0.0;
+        int64_t cut = n;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t s = start + i;
+            double ts = t_starts[s], te = t_ends[s];
+            double tau = sigmas[s] * (te - ts);
+            double trans = exp(-prefix);
+            if (eps > 0.0 && trans < eps) {
+                cut = i;
+                break;
+            }
+            double alpha = -expm1(-tau);
+            double w = 0.0;
+            if (!(alpha_thre > 0.0) || alpha >= alpha_thre) {
+                w = trans * alpha;
+                prefix += tau;
+            }
+            for (int64_t ch = 0; ch < n_ch; ++ch) out[r * n_ch + ch] += w * attrs[s * stride + ch];
+            a += w;
+            dep += w * (ts + te) * 0.5;
+            if (weights != NULL) weights[s] = w;
+        }
+        if (weights != NULL)
+            for (int64_t i = cut; i < n; ++i) weights[start + i] = 0.0;
+        if (background != NULL)
+            for (int64_t ch = 0; ch < n_ch; ++ch) out[r * n_ch + ch] += background[ch] * (1.0 - a);
+        opacity[r] = a;
+        depth[r] = dep;
+    }
+}
+
+/*
+ * Backward of oracle_render_attrs_fwd (cut and empty samples locally
+ * constant).  The background term adds -g_out . background to the opacity
+ * gradient, so with
+ *   v_i = g_out . a_i + (g_opacity - g_out . background) + g_depth * m_i:
+ *   dL/da_i     = w_i * g_out
+ *   dL/dsigma_i = delta_i * (T_{i+1} v_i - sum_{k>i} w_k v_k)
+ * for samples before the cut that are not empty; zero for the others.
+ * g_opacity, g_depth, background nullable; scale as in oracle_render_bwd.
+ */
+int oracle_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays,
+                            const double* t_starts, const double* t_ends,
+                            const double* sigmas, const double* attrs, int64_t n_ch,
+                            int64_t stride, double eps, double alpha_thre,
+                            const double* background, const double* g_out,
+                            const double* g_opacity, const double* g_depth,
+                            double* g_sigmas, double* g_attrs, double* scale) {
+    int64_t longest = 0;
+    for (int64_t r = 0; r < n_rays; ++r)
+        if (packed_info[2 * r + 1] > longest) longest = packed_info[2 * r + 1];
+    double* pre = (double*)malloc((size_t)(longest > 0 ? longest : 1) * sizeof(double));
+    if (pre == NULL) return -1;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        int64_t start = packed_info[2 * r];
+        int64_t n = packed_info[2 * r + 1];
+        const double* g = g_out + r * n_ch;
+        double ga = g_opacity != NULL ? g_opacity[r] : 0.0;
+        double gd = g_depth != NULL ? g_depth[r] : 0.0;
+        if (background != NULL)
+            for (int64_t ch = 0; ch < n_ch; ++ch) ga -= g[ch] * background[ch];
+        double prefix = 0.0;
+        int64_t cut = n;
+        for (int64_t i = 0; i < n; ++i) {
+            if (eps > 0.0 && exp(-prefix) < eps) {
+                cut = i;
+                break;
+            }
+            int64_t s = start + i;
+            pre[i] = prefix;
+            double tau = sigmas[s] * (t_ends[s] - t_starts[s]);
+            if (!(alpha_thre > 0.0) || -expm1(-tau) >= alpha_thre) prefix += tau;
+        }
+        double suffix = 0.0, suffix_abs = 0.0;
+        for (int64_t i = n - 1; i >= 0; --i) {
+            int64_t s = start + i;
+            double ts = t_starts[s], te = t_ends[s];
+            double delta = te - ts;
+            double tau = sigmas[s] * delta;
+            double alpha = -expm1(-tau);
+            if (i >= cut || (alpha_thre > 0.0 && alpha < alpha_thre)) {
+                g_sigmas[s] = 0.0;
+                if (scale != NULL) scale[s] = 0.0;
+                for (int64_t ch = 0; ch < n_ch; ++ch) g_attrs[s * stride + ch] = 0.0;
+                continue;
+            }
+            double t_i = exp(-pre[i]);
+            double t_next = exp(-(pre[i] + tau));
+            double w = t_i * alpha;
+            double v = ga + gd * (ts + te) * 0.5;
+            for (int64_t ch = 0; ch < n_ch; ++ch) v += g[ch] * attrs[s * stride + ch];
+            g_sigmas[s] = delta * (t_next * v - suffix);
+            if (scale != NULL) scale[s] = delta * (t_next * fabs(v) + suffix_abs);
+            for (int64_t ch = 0; ch < n_ch; ++ch) g_attrs[s * stride + ch] = w * g[ch];
+            suffix += w * v;
+            suffix_abs += w * fabs(v);
+        }
+    }
+    free(pre);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Occupancy-grid update (Sec. 2.1: the binary grid is cached and updated   */
 /* during training).  Our reading of the update: every cell decays by a     */

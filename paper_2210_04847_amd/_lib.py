@@ -67,6 +67,10 @@ _SIGNATURES = {
                                ctypes.POINTER(MarchParams), _P, _P, _SZ, _I64, _P, _P, _P, _P, _P]),
     "nacc_render_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
     "nacc_render_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P]),
+    "nacc_render_attrs_fwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _I32, _F, _F, _P, _P, _P,
+                                     _P, _P, _P]),
+    "nacc_render_attrs_bwd": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _I32, _F, _F, _P, _P, _P,
+                                     _P, _P, _P, _P]),
     "nacc_render_mse_workspace_size": (_I64, [_I64]),
     "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _I64, _P, _P, _P,
                                        _P, _P, _P, _P, _SZ, _P]),
@@ -95,12 +99,13 @@ EXPORTED = tuple(_SIGNATURES)
 
 
 def _load():
+    how = "run `python paper_2210_04847_amd/build.py` (or __graft_entry__.build())"
     if not os.path.exists(LIB_PATH):
-        raise ImportError(
-            f"{LIB_PATH} is not built; run `python -m paper_2210_04847_amd.build` "
-            "(or __graft_entry__.build()) first")
+        raise ImportError(f"{LIB_PATH} is not built; {how} first")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGNATURES.items():
+        if not hasattr(lib, name):
+            raise ImportError(f"{LIB_PATH} predates its sources (no {name}); {how}")
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
@@ -458,3 +463,46 @@ def synth_render_fused(table, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
         _ptr(table), n_blobs, n_sets, _ptr(ray_set), _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n,
         _ptr(grid_bits), ctypes.byref(desc), ctypes.byref(params), float(early_stop_eps),
         _ptr(color), _ptr(opacity), _ptr(depth), _ptr(kept), _stream(stream)))
+
+
+def render_attrs_fwd(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps, alpha_thre,
+                     background, out, opacity=None, depth=None, weights=None, stream=None):
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    ch = attrs.shape[1] if attrs.dim() == 2 else 1
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(t_starts, torch.float32, "t_starts")
+    _need(t_ends, torch.float32, "t_ends", e)
+    _need(sigmas, torch.float32, "sigmas", e)
+    _need(attrs, torch.float32, "attrs", e * ch)
+    _need(background, torch.float32, "background", ch)
+    _need(out, torch.float32, "out", n * ch)
+    _need(opacity, torch.float32, "opacity", n)
+    _need(depth, torch.float32, "depth", n)
+    _need(weights, torch.float32, "weights", e)
+    _check("nacc_render_attrs_fwd", lib.nacc_render_attrs_fwd(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(attrs), ch,
+        float(early_stop_eps), float(alpha_thre), _ptr(background), _ptr(out), _ptr(opacity),
+        _ptr(depth), _ptr(weights), _stream(stream)))
+
+
+def render_attrs_bwd(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps, alpha_thre,
+                     background, g_out, g_opacity, g_depth, g_sigmas, g_attrs, stream=None):
+    n = packed_info.shape[0]
+    e = t_starts.numel()
+    ch = attrs.shape[1] if attrs.dim() == 2 else 1
+    _need(packed_info, torch.int32, "packed_info", 2 * n)
+    _need(t_starts, torch.float32, "t_starts")
+    _need(t_ends, torch.float32, "t_ends", e)
+    _need(sigmas, torch.float32, "sigmas", e)
+    _need(attrs, torch.float32, "attrs", e * ch)
+    _need(background, torch.float32, "background", ch)
+    _need(g_out, torch.float32, "g_out", n * ch)
+    _need(g_opacity, torch.float32, "g_opacity", n)
+    _need(g_depth, torch.float32, "g_depth", n)
+    _need(g_sigmas, torch.float32, "g_sigmas", e)
+    _need(g_attrs, torch.float32, "g_attrs", e * ch)
+    _check("nacc_render_attrs_bwd", lib.nacc_render_attrs_bwd(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(attrs), ch,
+        float(early_stop_eps), float(alpha_thre), _ptr(background), _ptr(g_out), _ptr(g_opacity),
+        _ptr(g_depth), _ptr(g_sigmas), _ptr(g_attrs), _stream(stream)))

@@ -235,6 +235,54 @@ def rendering(*args, early_stop_eps=1e-4, ray_indices=None):
                           float(early_stop_eps))
 
 
+class AttrsFn(torch.autograd.Function):
+    """Rendering of arbitrary per-sample attributes (Sec. 2.2) with a
+    background and an opacity threshold; hand-written backward to the
+    densities and the attributes."""
+
+    @staticmethod
+    def forward(ctx, packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps, alpha_thre,
+                background):
+        n = packed_info.shape[0]
+        dev = sigmas.device
+        out = torch.empty((n, attrs.shape[1]), dtype=torch.float32, device=dev)
+        opacity = torch.empty((n, 1), dtype=torch.float32, device=dev)
+        depth = torch.empty((n, 1), dtype=torch.float32, device=dev)
+        _lib.render_attrs_fwd(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps,
+                              alpha_thre, background, out, opacity, depth)
+        ctx.save_for_backward(packed_info, t_starts, t_ends, sigmas, attrs, background)
+        ctx.eps, ctx.thre = early_stop_eps, alpha_thre
+        return out, opacity, depth
+
+    @staticmethod
+    def backward(ctx, g_out, g_opacity, g_depth):
+        packed_info, t_starts, t_ends, sigmas, attrs, background = ctx.saved_tensors
+        g_sigmas = torch.empty_like(sigmas)
+        g_attrs = torch.empty_like(attrs)
+        go = g_out.contiguous() if g_out is not None else torch.zeros(
+            (packed_info.shape[0], attrs.shape[1]), dtype=torch.float32, device=sigmas.device)
+        ga = g_opacity.reshape(-1).contiguous() if g_opacity is not None else None
+        gd = g_depth.reshape(-1).contiguous() if g_depth is not None else None
+        _lib.render_attrs_bwd(packed_info, t_starts, t_ends, sigmas, attrs, ctx.eps, ctx.thre,
+                              background, go, ga, gd, g_sigmas, g_attrs)
+        return None, None, None, g_sigmas, g_attrs, None, None, None
+
+
+def render_attrs(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps=1e-4,
+                 alpha_thre=0.0, background=None):
+    """Renders per-sample attributes attrs [E, C] (any C >= 1: features,
+    normals, ...) as Eq. 1 renders colour (Sec. 2.2) -> out [R, C],
+    opacity [R, 1], depth [R, 1]; differentiable in sigmas and attrs.
+    background [C] (optional) is blended in by 1 - opacity; samples whose
+    opacity is below alpha_thre (> 0) count as empty."""
+    sig = sigmas.reshape(-1).contiguous()
+    at = attrs.reshape(sig.numel(), -1).contiguous()
+    bg = None if background is None else torch.as_tensor(
+        background, dtype=torch.float32, device=sig.device).reshape(-1).contiguous()
+    return AttrsFn.apply(packed_info.contiguous(), _flat(t_starts), _flat(t_ends), sig, at,
+                         float(early_stop_eps), float(alpha_thre), bg)
+
+
 def render_mse(packed_info, t_starts, t_ends, sigmas, rgbs, target, early_stop_eps=1e-4):
     """Fused forward + MSE loss + backward in one kernel pass per ray.
     Returns (loss [1], color, opacity, depth, g_sigmas, g_rgbs)."""

@@ -62,17 +62,6 @@ __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double car
     return transmittance_of(x.sigma * (x.t1 - x.t0), carry);
 }
 
-// The ray's sample range from packed_info; a range that does not lie inside
-// [0, n_samples) is treated as an empty ray, so no access leaves the arrays.
-__device__ __forceinline__ void ray_range(const int32_t* __restrict__ packed_info, int64_t r, int64_t n_samples,
-                                          int64_t& start, int& n) {
-    const int s0 = uniform<int>(packed_info[2 * r]);
-    const int c0 = uniform<int>(packed_info[2 * r + 1]);
-    const bool ok = s0 >= 0 && c0 >= 0 && static_cast<int64_t>(s0) + c0 <= n_samples;
-    start = ok ? s0 : 0;
-    n = ok ? c0 : 0;
-}
-
 template <bool WEIGHTS>
 __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,

@@ -67,5 +67,16 @@ __device__ __forceinline__ int chunk_keep(bool valid, float t_in, float eps) {
     return m == 0 ? kWave : static_cast<int>(__builtin_ctzll(m));
 }
 
+// The ray's sample range from packed_info; a range that does not lie inside
+// [0, n_samples) is treated as an empty ray, so no access leaves the arrays.
+__device__ __forceinline__ void ray_range(const int32_t* __restrict__ packed_info, int64_t r, int64_t n_samples,
+                                          int64_t& start, int& n) {
+    const int s0 = uniform<int>(packed_info[2 * r]);
+    const int c0 = uniform<int>(packed_info[2 * r + 1]);
+    const bool ok = s0 >= 0 && c0 >= 0 && static_cast<int64_t>(s0) + c0 <= n_samples;
+    start = ok ? s0 : 0;
+    n = ok ? c0 : 0;
+}
+
 }  // namespace vr
 }  // namespace nacc

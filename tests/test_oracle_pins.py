@@ -449,6 +449,118 @@ def test_gradient_matches_finite_differences(eps):
             assert fdc == pytest.approx(out["g_rgbs"][s, ch], abs=1e-8)
 
 
+# ---------------------------------------------------------------------------
+# Rendering of arbitrary attributes, background, opacity threshold (Sec. 2.2
+# "any sample attributes"; Sec. 4 constant background)
+# ---------------------------------------------------------------------------
+
+def test_attrs_constant_density_background_closed_form():
+    # n equal intervals of width h at density s, every sample carrying the
+    # same attributes a: out = a A + b (1 - A), A = 1 - e^(-s n h),
+    # depth = sum_i T_i alpha (t_i + h/2) with T_i = e^(-s h i)
+    n, h, s = 50, 0.02, 3.0
+    a = np.array([0.2, -1.5, 7.0, 0.0, 3.25, 1.0, -0.5])
+    b = np.array([1.0, 0.5, -2.0, 4.0, 0.0, 0.25, 1.0])
+    ts = h * np.arange(n)
+    packed = np.array([[0, n], [n, 0]], np.int32)  # the second ray is empty
+    out = oracle.render_attrs_fwd(packed, ts, ts + h, np.full(n, s), np.tile(a, (n, 1)),
+                                  background=b)
+    big_a = 1.0 - math.exp(-s * n * h)
+    assert out["opacity"][0] == pytest.approx(big_a, rel=1e-13)
+    assert np.allclose(out["out"][0], a * big_a + b * (1 - big_a), rtol=1e-13, atol=1e-15)
+    alpha = 1.0 - math.exp(-s * h)
+    dep = sum(math.exp(-s * h * i) * alpha * (h * i + h / 2) for i in range(n))
+    assert out["depth"][0] == pytest.approx(dep, rel=1e-13)
+    assert np.array_equal(out["out"][1], b) and out["opacity"][1] == 0.0
+
+
+def test_attrs_opacity_threshold_closed_form():
+    # three samples, the first below the threshold: it neither contributes
+    # nor attenuates, so w_2 = alpha_2 and w_3 = (1 - alpha_2) alpha_3
+    sig = np.array([0.5, 1.0, 2.0])
+    ts = np.array([0.0, 1.0, 2.0])
+    a = np.array([[10.0, 1.0], [2.0, -1.0], [3.0, 5.0]])
+    out = oracle.render_attrs_fwd(np.array([[0, 3]], np.int32), ts, ts + 1.0, sig, a,
+                                  alpha_thre=0.5)
+    a1, a2 = 1 - math.exp(-1.0), 1 - math.exp(-2.0)
+    w = np.array([0.0, a1, (1 - a1) * a2])
+    assert np.allclose(out["weights"], w, rtol=1e-14)
+    assert np.allclose(out["out"][0], w @ a, rtol=1e-14)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-2])
+def test_attrs_threshold_equals_dropping_the_samples(eps):
+    """Samples below the opacity threshold are as if they were not on the
+    ray: rendering with the threshold equals rendering, without it, the
+    samples that remain (their opacity taken here with numpy)."""
+    packed, ts, te, sg, _ = synth.ragged_render_inputs(60, 21, mean_count=30, sigma_max=40.0)
+    attrs = np.random.default_rng(21).standard_normal((ts.size, 5))
+    bg = np.array([0.5, -1.0, 2.0, 0.0, 1.0])
+    alpha = -np.expm1(-sg.astype(np.float64) * (te.astype(np.float64) - ts.astype(np.float64)))
+    thre = 0.1
+    keep = alpha >= thre
+    assert 0.1 < keep.mean() < 0.9
+    ray_of = np.repeat(np.arange(packed.shape[0]), packed[:, 1])
+    counts = np.bincount(ray_of[keep], minlength=packed.shape[0])
+    packed_k = np.stack([np.concatenate([[0], np.cumsum(counts)[:-1]]), counts], 1).astype(np.int32)
+    masked = oracle.render_attrs_fwd(packed, ts, te, sg, attrs, eps, thre, bg)
+    dropped = oracle.render_attrs_fwd(packed_k, ts[keep], te[keep], sg[keep], attrs[keep], eps, 0.0,
+                                      bg)
+    for name in ("out", "opacity", "depth"):
+        assert np.allclose(masked[name], dropped[name], rtol=1e-13, atol=1e-15)
+    assert np.all(masked["weights"][~keep] == 0.0)
+
+
+@pytest.mark.parametrize("eps,thre", [(0.0, 0.0), (1e-3, 0.2)])
+def test_attrs_gradient_matches_finite_differences(eps, thre):
+    packed, ts, te, sg, _ = synth.ragged_render_inputs(30, 22, mean_count=20, sigma_max=60.0)
+    g = np.random.default_rng(22)
+    ch = 6
+    attrs = g.standard_normal((ts.size, ch))
+    bg = g.standard_normal(ch)
+    g_out = g.standard_normal((30, ch))
+    ga = g.standard_normal(30)
+    gd = g.standard_normal(30)
+    sg64 = sg.astype(np.float64)
+
+    def loss(s, a):
+        o = oracle.render_attrs_fwd(packed, ts, te, s, a, eps, thre, bg)
+        return float((o["out"] * g_out).sum() + (o["opacity"] * ga).sum()
+                     + (o["depth"] * gd).sum())
+
+    out = oracle.render_attrs_bwd(packed, ts, te, sg64, attrs, g_out, ga, gd, eps, thre, bg)
+    alpha = -np.expm1(-sg64 * (te.astype(np.float64) - ts.astype(np.float64)))
+    # the transmittance at each sample, to stay away from the cut
+    tau = np.where(alpha >= thre, sg64 * (te.astype(np.float64) - ts.astype(np.float64)), 0.0)
+    checked = 0
+    for s in g.choice(sg.size, 120, replace=False):
+        r = np.searchsorted(packed[:, 0], s, side="right") - 1
+        while packed[r, 1] == 0 or s >= packed[r, 0] + packed[r, 1]:
+            r -= 1
+        a0 = packed[r, 0]
+        trans = math.exp(-tau[a0:s].sum())
+        if (abs(alpha[s] - thre) < 1e-3 or (eps > 0 and abs(trans / eps - 1) < 0.5)
+                or sg64[s] == 0.0):
+            continue  # not differentiable across the threshold or the cut (a
+            # zero density lies on the threshold 0: sigma - h is below it)
+        h = 1e-6 * max(abs(sg64[s]), 1.0)
+        sp, sm = sg64.copy(), sg64.copy()
+        sp[s] += h
+        sm[s] -= h
+        fd = (loss(sp, attrs) - loss(sm, attrs)) / (2 * h)
+        assert fd == pytest.approx(out["g_sigmas"][s], abs=1e-7 * max(1.0, out["scale"][s] / 1e-2))
+        for k in range(ch):
+            ap, am = attrs.copy(), attrs.copy()
+            ap[s, k] += 1e-6
+            am[s, k] -= 1e-6
+            fda = (loss(sg64, ap) - loss(sg64, am)) / 2e-6
+            assert fda == pytest.approx(out["g_attrs"][s, k], abs=1e-8)
+        checked += 1
+    assert checked > 30
+    if thre > 0:
+        assert np.all(out["g_sigmas"][alpha < thre] == 0.0)
+
+
 def test_gradient_zero_past_cut():
     packed = np.array([[0, 3]], np.int32)
     out = oracle.render_bwd(packed, [0, 1, 2], [1, 2, 3], [40.0, 1.0, 1.0],

@@ -360,14 +360,21 @@ def lattice_candidates(w, rays_o, rays_d):
     return n
 
 
+RENDER_SOURCES = ("paper_2210_04847_amd/csrc/render.hip+paper_2210_04847_amd/csrc/transmittance.h+"
+                  "paper_2210_04847_amd/csrc/common.h")
+
+
 def recorded_traffic(kernel, source):
     """HBM bytes per launch of `kernel` from the committed counter summaries
     (profiles/*.md, lines 'traffic_record: ...'), or None when none matches
     the current source of the kernel (the counters are then stale)."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, source)
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    # `source`: the kernel's files joined by '+', hashed in that order
+    h = hashlib.sha256()
+    for part in source.split("+"):
+        h.update(open(os.path.join(ROOT, part), "rb").read())
+    digest = h.hexdigest()[:16]
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("traffic_record:"):
@@ -532,7 +539,7 @@ def bench_train(args, torch, nacc):
     render_roofline = {
         "bound": "hbm", "kernel": "render", "achieved": render_bps / 1e9, "peak": HBM_PEAK / 1e9,
         "unit": "GB/s", "frac": render_bps / HBM_PEAK,
-        "traffic": (recorded_traffic("render_mse_kernel", "paper_2210_04847_amd/csrc/render.hip")
+        "traffic": (recorded_traffic("render_mse_kernel", RENDER_SOURCES)
                     if not forward_only else None)}
     if dominant == "march_count":
         # the count pass is bound by its per-candidate arithmetic

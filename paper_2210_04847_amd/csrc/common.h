@@ -51,6 +51,15 @@ __device__ __forceinline__ uint64_t ballot(bool p) {
     return __builtin_amdgcn_ballot_w64(p);
 }
 
+// Orders one wave's LDS writes before its later reads of other lanes' slots
+// (and those reads before the slots are written again): a wave-scope fence
+// pair around a wave barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Number of set bits of `mask` below the calling lane.
 __device__ __forceinline__ int bits_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),

@@ -6,7 +6,8 @@
 // One wavefront per ray.  The wave marches 64 lattice candidates per
 // iteration exactly as the marching kernels do (uniform steps) and appends
 // the occupied ones, in t order, to a ring of candidate indices in its LDS
-// slice.  Whenever the ring holds 64 of them (or the ray's candidates are
+// slice (two chunks of candidates per iteration, so two grid lookups are in
+// flight).  Whenever the ring holds 64 of them (or the ray's candidates are
 // exhausted) the wave takes them as one chunk: each lane evaluates the field
 // at its sample's midpoint and the chunk is rendered with the same
 // transmittance routine as the rendering kernels.  The chunks are the ray's
@@ -34,15 +35,7 @@ using namespace nacc::vr;
 
 constexpr int kFusedWaves = 4;
 constexpr int kFusedRays = 64;  // rays per workgroup: lane j of a wave clips its j-th ray
-constexpr int kRing = 128;      // candidate indices per wave: < 64 held + 64 appended
-
-// Orders one wave's LDS writes before its later reads of other lanes' slots
-// (and those reads before the slots are written again).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+constexpr int kRing = 256;      // candidate indices per wave: < 64 held + 128 appended
 
 template <int LOOKUP, bool PER_SET>
 __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span, const float* __restrict__ table,
@@ -53,12 +46,8 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
                                                  float* __restrict__ opacity, float* __restrict__ depth,
                                                  int32_t* __restrict__ kept) {
     const int lane = lane_id();
-    float o[3], d[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
-    }
+    const float* o = span.o;  // loaded lane-parallel with the wave's other rays
+    const float* d = span.d;
     int set = 0;
     if (PER_SET) {
         set = uniform<int>(ray_set[r]);
@@ -77,31 +66,52 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
     bool more = span.valid;
     int k0 = 0;
     while (true) {
-        // march until a whole chunk is queued or the ray's candidates end
+        // march until a whole chunk is queued or the ray's candidates end,
+        // two chunks of candidates per iteration (both grid words loaded,
+        // both ballots taken, before either chunk is appended)
         while (more && queued < kWave) {
-            const int k = k0 + lane;
-            const float t0 = t_near + static_cast<float>(k) * p.dt;
-            const bool live = t0 < t_far;
-            if (ballot(live) == 0ull || k0 >= kMaxCandidates) {  // t_k is non-decreasing in k
+            float t0[2], t1[2];
+            bool live[2];
+            uint64_t ms[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = k0 + u * kWave + lane;
+                t0[u] = t_near + static_cast<float>(k) * p.dt;
+                live[u] = t0[u] < t_far;
+                t1[u] = t_near + static_cast<float>(k + 1) * p.dt;
+            }
+            if (ballot(live[0]) == 0ull || k0 >= kMaxCandidates) {  // t_k is non-decreasing in k
                 more = false;
                 break;
             }
-            const float t1 = t_near + static_cast<float>(k + 1) * p.dt;
-            const float tm = (t0 + t1) * 0.5f;
-            const Probe q = probe<LOOKUP>(g, span.word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
-            bool hit = live && ((bits[q.word] >> q.bit) & 1u) != 0u;
-            uint64_t m = ballot(hit);
-            int n_new = __popcll(m);
-            if (p.max_per_ray > 0 && marched + n_new >= p.max_per_ray) {
-                n_new = p.max_per_ray - marched;  // the first ones in t order
-                hit = hit && bits_below(m) < n_new;
-                m = ballot(hit);
-                more = false;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float tm = (t0[u] + t1[u]) * 0.5f;
+                const Probe q =
+                    probe<LOOKUP>(g, span.word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+                const uint32_t w = bits[q.word];  // every lane: the index is clamped into the grid
+                ms[u] = ballot(live[u] & (((w >> q.bit) & 1u) != 0u));
             }
-            if (hit) ring[(head + queued + bits_below(m)) & (kRing - 1)] = k;
-            queued += n_new;
-            marched += n_new;
-            k0 += kWave;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && (ballot(live[1]) == 0ull || k0 + kWave >= kMaxCandidates)) {
+                    more = false;
+                    break;
+                }
+                uint64_t m = ms[u];
+                bool hit = ((m >> lane) & 1ull) != 0ull;
+                int n_new = __popcll(m);
+                if (p.max_per_ray > 0 && marched + n_new >= p.max_per_ray) {
+                    n_new = p.max_per_ray - marched;  // the first ones in t order
+                    hit = hit && bits_below(m) < n_new;
+                    more = false;
+                }
+                if (hit) ring[(head + queued + bits_below(m)) & (kRing - 1)] = k0 + u * kWave + lane;
+                queued += n_new;
+                marched += n_new;
+                if (!more) break;
+            }
+            k0 += 2 * kWave;
         }
         if (queued == 0) break;
         wave_lds_sync();
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(kFusedWaves * kWave) void fused_render_kernel(
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kFusedRays;
     // this wave's rays are first + wave + j kFusedWaves; lane j clips ray j
     const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * kFusedWaves;
-    RaySpan spans{0.0f, 0.0f, 0u, false};
+    RaySpan spans{};
     if (lane_id() < kFusedRays / kFusedWaves && mine < n_rays) {
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }

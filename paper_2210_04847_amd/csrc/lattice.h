@@ -160,6 +160,7 @@ struct RaySpan {
     float t_near, t_far;
     uint32_t word0;
     bool valid;
+    float o[3], d[3];  // the ray itself
 };
 
 template <int LOOKUP>
@@ -167,23 +168,30 @@ __device__ __forceinline__ RaySpan ray_span(int64_t r, const float* __restrict__
                                             const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
                                             const GridK& g, const ClipK& c, const StepK& p) {
     RaySpan s;
-    float o[3], d[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
+        s.o[i] = rays_o[3 * r + i];
+        s.d[i] = rays_d[3 * r + i];
     }
     s.valid = grid_of_ray<LOOKUP>(grid_id, r, g, s.word0);
-    s.valid = clip_ray(o, d, c, p.near_plane, p.far_plane, s.t_near, s.t_far) && s.valid;
+    s.valid = clip_ray(s.o, s.d, c, p.near_plane, p.far_plane, s.t_near, s.t_far) && s.valid;
     return s;
 }
 
+// Lane `lane`'s span (and ray) in every lane: the rays of a wave are loaded
+// and clipped lane-parallel once, then broadcast one at a time, so no ray
+// waits on loads of its own.
 __device__ __forceinline__ RaySpan read_span(const RaySpan& s, int lane) {
     RaySpan b;
     b.t_near = read_lane(s.t_near, lane);
     b.t_far = read_lane(s.t_far, lane);
     b.word0 = static_cast<uint32_t>(read_lane(static_cast<int>(s.word0), lane));
     b.valid = read_lane(s.valid ? 1 : 0, lane) != 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        b.o[i] = read_lane(s.o[i], lane);
+        b.d[i] = read_lane(s.d[i], lane);
+    }
     return b;
 }
 

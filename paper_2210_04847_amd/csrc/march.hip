@@ -111,6 +111,87 @@ __device__ __forceinline__ float wave_max(float x) {
     return read_lane(x, kWave - 1);
 }
 
+// Uniform steps without the skip field, two chunks of 64 candidates per
+// iteration: both chunks' grid words are loaded before either is tested, so
+// each wave keeps two lookups in flight instead of waiting on one at a time
+// (a chunk past the ray's end is looked up and ignored; its cell indices are
+// clamped into the grid like any other).  Same samples, same order, same
+// masks as one chunk at a time.
+template <int LOOKUP, bool FILL>
+__device__ __forceinline__ int march_ray_uniform_x2(
+    int64_t r, const RaySpan& span, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+    const uint32_t* __restrict__ bits, const GridK& g, const StepK& p, int64_t start, int limit,
+    int64_t capacity, int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    bool& overflow, uint64_t* __restrict__ masks, int n_masks, int first_chunk, int count0) {
+    if (!span.valid) return 0;
+    const int lane = lane_id();
+    const float* o = span.o;
+    const float* d = span.d;
+    const uint32_t word0 = span.word0;
+    const float t_near = span.t_near, t_far = span.t_far;
+    uint64_t my_mask = 0ull;  // count pass: lane j keeps the ballot of chunk j
+    int count = count0;
+    bool done = false;
+    for (int k0 = first_chunk * kWave; k0 < kMaxCandidates && !done; k0 += 2 * kWave) {
+        float t0[2], t1[2];
+        bool live[2];
+        uint64_t ms[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = k0 + u * kWave + lane;
+            t0[u] = t_near + static_cast<float>(k) * p.dt;
+            live[u] = t0[u] < t_far;
+            t1[u] = t_near + static_cast<float>(k + 1) * p.dt;
+        }
+        if (ballot(live[0]) == 0ull) break;  // t_k is non-decreasing in k
+        // both words are loaded, and both ballots taken, before any branch
+        // on them (a ballot cannot move into a branch)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float tm = (t0[u] + t1[u]) * 0.5f;
+            const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+            const uint32_t w = bits[q.word];  // every lane: the index is clamped into the grid
+            ms[u] = ballot(live[u] & (((w >> q.bit) & 1u) != 0u));
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int chunk = k0 / kWave + u;
+            if (u == 1 && (ballot(live[1]) == 0ull || k0 + kWave >= kMaxCandidates)) {
+                done = true;
+                break;
+            }
+            const uint64_t m = ms[u];
+            const bool hit = ((m >> lane) & 1ull) != 0ull;
+            if (!FILL && lane == chunk) my_mask = m;
+            if (FILL && hit) {
+                const int idx = count + bits_below(m);
+                if (idx < limit) {
+                    const int64_t pos = start + idx;
+                    if (pos >= 0 && pos < capacity) {
+                        ray_indices[pos] = static_cast<int32_t>(r);
+                        t_starts[pos] = t0[u];
+                        t_ends[pos] = t1[u];
+                    } else {
+                        overflow = true;
+                    }
+                }
+            }
+            count += __popcll(m);
+            if (p.max_per_ray > 0 && count >= p.max_per_ray) {
+                count = p.max_per_ray;
+                done = true;
+                break;
+            }
+            if (FILL && count >= limit) {
+                done = true;
+                break;
+            }
+        }
+    }
+    if (!FILL && lane < n_masks) masks[lane] = my_mask;
+    return count;
+}
+
 // One ray, uniform steps, whole wave.  Returns the ray's sample count (the
 // same value in every lane).  FILL writes samples [0, limit) at `start`.
 // With SKIP, candidates inside a stretch the skip field clears are not
@@ -124,14 +205,15 @@ __device__ __forceinline__ int march_ray_uniform(
     int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
     bool& overflow, uint64_t* __restrict__ masks = nullptr, int n_masks = 0, int first_chunk = 0,
     int count0 = 0) {
+    if constexpr (!SKIP) {
+        return march_ray_uniform_x2<LOOKUP, FILL>(r, span, rays_o, rays_d, bits, g, p, start, limit, capacity,
+                                                  ray_indices, t_starts, t_ends, overflow, masks, n_masks,
+                                                  first_chunk, count0);
+    }
     if (!span.valid) return 0;
     const int lane = lane_id();
-    float o[3], d[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
-    }
+    const float* o = span.o;
+    const float* d = span.d;
     const uint32_t word0 = span.word0;
     const float t_near = span.t_near, t_far = span.t_far;
     SkipRay sk{};
@@ -201,7 +283,7 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
     // this wave's rays are first + wave + j WAVES; lane j clips ray j
     const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
-    RaySpan spans{0.0f, 0.0f, 0u, false};
+    RaySpan spans{};
     if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays) {
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }
@@ -279,7 +361,7 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
     const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
-    RaySpan spans{0.0f, 0.0f, 0u, false};
+    RaySpan spans{};
     if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays && packed_info[2 * mine + 1] > 0) {
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }

@@ -49,9 +49,8 @@ class OccupancyGrid:
         self.bits = torch.zeros(self.cells // 32, dtype=torch.int32, device=dev)
         self.desc = _lib.grid_desc(self.box[:3], self.box[3:], self.res, self.n_grids,
                                    self.lookup)
-        # skip field for passing over empty space (box and cascade lookups,
-        # res % 4 == 0)
-        sb = _lib.grid_skip_bytes(self.desc) if self.lookup != _lib.LOOKUP_CONTRACT else 0
+        # skip field for passing over empty space (res % 4 == 0)
+        sb = _lib.grid_skip_bytes(self.desc)
         self.skip = torch.zeros(sb, dtype=torch.uint8, device=dev) if sb > 0 else None
         self.updates = 0
 

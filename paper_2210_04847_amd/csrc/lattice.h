@@ -110,6 +110,7 @@ __device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0,
         word0 = grid * g.words;
     } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
         float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
+        q.m = n;  // |x|, for the skip bound
         if (n > 1.0f) {
             float f = (2.0f - 1.0f / n) / n;
             x0 = x0 * f;

@@ -49,11 +49,15 @@ using namespace nacc::dev;
 //            ray reaches, taken generously);
 //   inv_v:   1 / (fine cells per unit t on the fastest axis, at level 0);
 //   inv_dmax: 1 / max_i |d_i|.
+//   contraction lookup: t_out, from which on the ray moves away from the
+//   origin (past its closest approach, rounded up), |d| rounded up, the
+//   largest |o_i|, |d_i| and the grid's largest cells-per-unit scale.
 struct SkipRay {
     float slack_x;
     float slack_s;  // slack_x in fine cells at level 0
     float inv_v;
     float inv_dmax;
+    float t_out, dnorm, omax, dmax, smax;
 };
 
 __device__ __forceinline__ SkipRay skip_ray(const GridK& g, const float o[3], const float d[3], float t_far) {
@@ -65,7 +69,44 @@ __device__ __forceinline__ SkipRay skip_ray(const GridK& g, const float o[3], co
     k.slack_s = smax * k.slack_x;
     k.inv_v = 1.0f / fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
     k.inv_dmax = 1.0f / dmax;
+    const float dd = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const float od = (o[0] * d[0] + o[1] * d[1]) + o[2] * d[2];
+    const float t_star = -od / dd;
+    k.t_out = t_star + (fabsf(t_star) + 1.0f) * 0x1p-16f;
+    k.dnorm = sqrtf(dd) * (1.0f + 0x1p-18f);
+    k.omax = omax;
+    k.dmax = dmax;
+    k.smax = smax;
     return k;
+}
+
+// Contraction lookup: the end of the stretch past tm whose candidates all
+// map to empty fine cells.  The contraction c(x) = (2 - 1/|x|) x/|x| is
+// Lipschitz with constant L(r) = (2 - 1/r)/r on |x| >= r >= 1 (its
+// derivative stretches tangential directions by that factor and the radial
+// one by 1/r^2 <= L(r); L <= 1 everywhere).  Past the closest approach |x|
+// only grows along the ray, so candidates a distance D_t further along t
+// map within L(r) |d| D_t of c(x(tm)), r a lower bound of |x(tm)|; before
+// it L = 1.  The byte `dist` guarantees empty fine cells within
+// 4 (dist - 1) cells on every axis; the stretch is kept inside that after
+// allowing for the FP32 rounding of positions (a few ulps of the largest
+// coordinate reached, at most 2 tm + 1 along the ray: the stretch is capped
+// there) and of the contraction (2^-16 in contracted units).
+__device__ __forceinline__ float skip_end_contract(const SkipRay& k, const Probe& q, int dist, float tm, int res) {
+    float lip = 1.0f;
+    if (tm > k.t_out) {
+        const float t_reach = 2.0f * fabsf(tm) + 1.0f;
+        const float slack = (k.omax + k.dmax * t_reach + 1.0f) * 0x1p-20f;
+        const float r = q.m * (1.0f - 0x1p-18f) - 2.0f * slack;
+        if (r > 1.0f) lip = ((2.0f - 1.0f / r) / r) * (1.0f + 0x1p-18f);
+    }
+    const float slack_pos = (k.omax + k.dmax * (2.0f * fabsf(tm) + 1.0f) + 1.0f) * 0x1p-20f;
+    const float slack_cells = k.smax * 3.5f * (lip * slack_pos + 0x1p-16f) + static_cast<float>(res) * 0x1p-18f;
+    const float budget = 4.0f * static_cast<float>(dist - 1) - slack_cells;
+    float span = budget / (k.smax * lip * k.dnorm);
+    span = fminf(span, fabsf(tm) + 1.0f);  // the reach the slack allows for
+    span = span * (1.0f - 0x1p-10f) - fabsf(tm) * 0x1p-21f;
+    return (dist >= 2 && span > 0.0f) ? tm + span : -INFINITY;
 }
 
 // End (in t) of the stretch past the candidate midpoint tm over which every
@@ -76,6 +117,7 @@ __device__ __forceinline__ SkipRay skip_ray(const GridK& g, const float o[3], co
 // level.  Rounding margins keep the bound strict.
 template <int LOOKUP>
 __device__ __forceinline__ float skip_end_at(const GridK& g, const SkipRay& k, const Probe& q, int dist, float tm) {
+    if (LOOKUP == NACC_LOOKUP_CONTRACT) return skip_end_contract(k, q, dist, tm, g.res);
     // fine cells at level l are 2^l times larger: the slack in fine cells
     // shrinks and the stretch in t grows by 2^l
     const float budget =
@@ -926,16 +968,13 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
     }
 }
 
-// The skip field serves the box and cascade lookups (res % 4 == 0); the
-// contraction lookup always marches without it.
+// The skip field serves every lookup (res % 4 == 0).
 template <int LOOKUP, typename... A>
 void dispatch_count(const uint8_t* skip, const ConeWork* cw, int64_t nb, hipStream_t s, const float* o,
                     const float* d, const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
-    if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
-        if (skip != nullptr) {
-            launch_count_impl<LOOKUP, true>(cw, nb, s, o, d, gid, n, bits, skip, a...);
-            return;
-        }
+    if (skip != nullptr) {
+        launch_count_impl<LOOKUP, true>(cw, nb, s, o, d, gid, n, bits, skip, a...);
+        return;
     }
     launch_count_impl<LOOKUP, false>(cw, nb, s, o, d, gid, n, bits, nullptr, a...);
 }
@@ -943,17 +982,15 @@ void dispatch_count(const uint8_t* skip, const ConeWork* cw, int64_t nb, hipStre
 template <int LOOKUP, typename... A>
 void dispatch_fill(const uint8_t* skip, bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, const float* o,
                    const float* d, const int32_t* gid, int64_t n, const uint32_t* bits, A&&... a) {
-    if constexpr (LOOKUP != NACC_LOOKUP_CONTRACT) {
-        if (skip != nullptr) {
-            launch_fill_impl<LOOKUP, true>(cone, cw, nb, s, o, d, gid, n, bits, skip, a...);
-            return;
-        }
+    if (skip != nullptr) {
+        launch_fill_impl<LOOKUP, true>(cone, cw, nb, s, o, d, gid, n, bits, skip, a...);
+        return;
     }
     launch_fill_impl<LOOKUP, false>(cone, cw, nb, s, o, d, gid, n, bits, nullptr, a...);
 }
 
 const uint8_t* usable_skip(const uint8_t* skip, const nacc_grid_desc& grid) {
-    if (skip == nullptr || grid.lookup == NACC_LOOKUP_CONTRACT || grid.res % 4 != 0) return nullptr;
+    if (skip == nullptr || grid.res % 4 != 0) return nullptr;
     return skip;
 }
 

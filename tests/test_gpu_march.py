@@ -216,6 +216,26 @@ def test_cone_rays_past_stored_chunks(lookup):
     assert want[0][:, 1].max() > 64 * 64 * 0.3
 
 
+@pytest.mark.parametrize("p_occ,cone", [(0.002, 1.0 / 256), (0.02, 1.0 / 256), (0.002, 0.0)])
+def test_contraction_skip_sparse(p_occ, cone):
+    """Sparse contracted-space grids, where the skip field passes over long
+    stretches of the far shell (its bound uses the contraction's Lipschitz
+    constant past each ray's closest approach): every variant bit for bit
+    against the oracle, including rays through the origin's neighbourhood
+    and rays starting outside the unit ball."""
+    res = 32
+    mask = synth.random_mask(res ** 3, p_occ, 18)
+    o, d = synth.rays_unbounded(1200, 18)
+    o = o.copy()
+    o[:300] *= 5.0  # origins outside the unit ball, some rays approaching the origin
+    o[300:400] = -3.0 * d[300:400]  # rays passing through the origin
+    box = np.array([-2, -2, -2, 2, 2, 2], np.float32)
+    dt = float(np.float32(3 * np.sqrt(3) / 1024)) if cone else 0.05
+    want = compare(o, d, mask, res, box, 0.2, 1e4 if cone else 60.0, dt, cone=cone, dt_max=1e10,
+                   lookup=2, max_per_ray=0 if cone else 4000)
+    assert want[1].size > 1000
+
+
 def test_contraction_lookup():
     res = 32
     mask = synth.random_mask(res ** 3, 0.3, 14)

@@ -2,12 +2,12 @@
 rays from inside the unit ball in all directions (3,000 of them: a ragged
 last workgroup), cone-scaled steps t_{k+1} = t_k + clamp(t_k / 256, dt,
 dt_max) from near = 0.2, and a scene defined in contracted coordinates, for
-both unbounded grid layouts: four cascaded 32^3 grids (level l over
-[-2^l, 2^l]^3, marched with the skip field) and the paper's contraction
-lookup (one 32^3 grid over the contracted space [-2, 2]^3, lattice to
-far = 1e4, at most 1024 samples per ray).  Marching is compared bit for bit,
-the field within its FP32 tolerance, and the fused render + MSE + backward
-on the step's own samples within the render and gradient tolerances."""
+both unbounded grid layouts, marched with the skip field: four cascaded
+32^3 grids (level l over [-2^l, 2^l]^3) and the paper's contraction lookup
+(one 32^3 grid over the contracted space [-2, 2]^3, lattice to far = 1e4,
+at most 1024 samples per ray).  Marching is compared bit for bit, the field
+within its FP32 tolerance, and the fused render + MSE + backward on the
+step's own samples within the render and gradient tolerances."""
 import dataclasses
 
 import numpy as np
@@ -24,10 +24,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module", params=["unbounded_262k", "unbounded_contract_262k"])
 def small(request):
-    # cascades with the skip field (the benchmark marches without it); the
-    # contraction lookup has none
-    return make_step(request.param, n_rays=3000, res=32,
-                     skip_field=request.param == "unbounded_262k")
+    # with the skip field (the cascade benchmark marches without it)
+    return make_step(request.param, n_rays=3000, res=32, skip_field=True)
 
 
 def test_unbounded_march_all_rays(small):

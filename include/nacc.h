@@ -206,8 +206,10 @@ int64_t nacc_march_max_samples_per_ray(const nacc_grid_desc* grid,
  *                   pass over candidates that lie in empty cells without
  *                   looking them up, so results are identical with and
  *                   without it; it must be rebuilt whenever grid_bits
- *                   changes.  Used by the box and cascade lookups when
- *                   res % 4 == 0, ignored otherwise.
+ *                   changes.  Used by every lookup when res % 4 == 0,
+ *                   ignored otherwise (the contraction lookup bounds its
+ *                   stretches through the contraction's Lipschitz
+ *                   constant, (2 - 1/r)/r beyond radius r >= 1).
  *   packed_info     out int32[n_rays][2]: (start, count) per ray.
  *   total           out int64[1]: the sample total, on the device.
  *   workspace       device scratch of nacc_march_workspace_size bytes;

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     float eps, float alpha_thre, const float* __restrict__ background, float* __restrict__ out,
     float* __restrict__ opacity, float* __restrict__ depth, float* __restrict__ weights) {
     const int lane = lane_id();
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
     int64_t start;
     int n;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
     const float* __restrict__ g_opacity, const float* __restrict__ g_depth, float* __restrict__ g_sigmas,
     float* __restrict__ g_attrs) {
     const int lane = lane_id();
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
     int64_t start;
     int n;

@@ -60,6 +60,22 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Logical index of workgroup b of a grid of n.  The hardware hands
+// workgroups to the 8 XCDs in turn (b mod 8), each XCD with its own L2;
+// renumbered here so that every XCD takes runs of G consecutive logical
+// workgroups (runs interleaved over the XCDs every 8 G workgroups), data
+// shared by neighbouring workgroups (cache lines at the ends of their
+// ranges) is fetched by one L2 instead of two, while uneven costs along the
+// index still spread over all XCDs.  A bijection of [0, n): the tail past
+// the last whole period keeps its index.
+template <int G>
+__device__ __forceinline__ int64_t xcd_grouped(int64_t b, int64_t n) {
+    constexpr int64_t kXcds = 8, kPeriod = kXcds * G;
+    if (b >= (n / kPeriod) * kPeriod) return b;
+    const int64_t base = (b / kPeriod) * kPeriod, i = b - base;
+    return base + (i % kXcds) * G + i / kXcds;
+}
+
 // Number of set bits of `mask` below the calling lane.
 __device__ __forceinline__ int bits_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
     float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth,
     float* __restrict__ weights, int32_t* __restrict__ kept) {
     const int lane = lane_id();
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock +
+    const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kRaysPerRenderBlock +
                       uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
     int64_t start;
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
     const float* __restrict__ g_color, const float* __restrict__ g_opacity, const float* __restrict__ g_depth,
     float* __restrict__ g_sigmas, float* __restrict__ g_rgbs) {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock +
+    const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kRaysPerRenderBlock +
                       uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
     int64_t start;
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     // PREFETCH: the next ray's range is read when a ray starts and its first
     // chunk is loaded before the ray's backward pass, so those loads are in
     // flight while the backward runs
-    int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave;
+    int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kRaysPerRenderBlock + wave;
     int64_t start = 0;
     int n = 0;
     Sample pre{};

@@ -11,6 +11,7 @@ namespace {
 
 using namespace nacc;
 using namespace nacc::blob;
+using namespace nacc::dev;
 
 constexpr int kThreads = 256;
 
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void field_samples_kernel(
     const float* cc = table + static_cast<int64_t>(n_sets) * n_blobs * kBlobStride;
     const bool contract = cc[12] != 0.0f;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
-    for (int64_t s = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; s < n; s += stride) {
+    for (int64_t s = xcd_grouped<16>(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; s < n; s += stride) {
         const int64_t r = ray_indices[s];
         if (r < 0 || r >= n_rays) {
             sigmas[s] = 0.0f;

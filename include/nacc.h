@@ -95,7 +95,8 @@ enum {
  * Occupancy grid description (Sec. 2.1, "Pruning Empty and Occluded
  * Regions": a binary grid cached and updated during training).
  * The bit array has n_grids * res^3 bits, grid g occupying words
- * [g * res^3 / 32, (g+1) * res^3 / 32).
+ * [g * res^3 / 32, (g+1) * res^3 / 32); all grids together at most
+ * 2^31 - 1 bytes (NACC_ESHAPE otherwise).
  *   lo, hi   AABB and CONTRACT: the box the grid covers.  CASCADE: the
  *            level-0 cube, lo = -b, hi = +b on every axis, b a power of two;
  *            level l covers [-b 2^l, b 2^l]^3, and a point goes to the

@@ -89,7 +89,7 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
                 const float tm = (t0[u] + t1[u]) * 0.5f;
                 const Probe q =
                     probe<LOOKUP>(g, span.word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
-                const uint32_t w = bits[q.word];  // every lane: the index is clamped into the grid
+                const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);  // every lane: the index is clamped into the grid
                 ms[u] = ballot(live[u] & (((w >> q.bit) & 1u) != 0u));
             }
 #pragma unroll

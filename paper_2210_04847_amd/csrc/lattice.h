@@ -30,7 +30,23 @@ struct GridK {
     uint32_t words;    // 32-bit words per grid
     int coarse;          // coarse cells per axis of the skip field (res / 4)
     uint32_t skip_cells;  // bytes per grid of the skip field (coarse^3)
+    uint32_t res2, coarse2;  // res^2, coarse^2
+    uint32_t bytes;          // bytes of all grids' bit arrays (< 2^32)
 };
+
+// The grids' words are read through a buffer resource: 32-bit byte offsets
+// (no 64-bit address arithmetic per lookup) and a hardware range check (a
+// word past the arrays reads as 0; the cell indices are clamped, so none
+// is).  The resource's last word selects 32-bit untyped data.
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_rsrc(const uint32_t* bits, const GridK& g) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(bits), 0, static_cast<int>(g.bytes), kBufferWord3);
+}
+
+__device__ __forceinline__ uint32_t grid_word(__amdgpu_buffer_rsrc_t rs, uint32_t word) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, word << 2, 0, 0);
+}
 
 struct ClipK {
     float lo[3];
@@ -121,13 +137,14 @@ __device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0,
     const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
     const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
     const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
-    // j < res <= 1024, so every product fits the 24-bit multiplier
+    // j < res <= 1024 and res^2 <= 2^20: every factor fits the 24-bit
+    // multiplier, every product 32 bits
     const uint32_t res = static_cast<uint32_t>(g.res);
-    const uint32_t cell = __umul24(__umul24(j0, res) + j1, res) + j2;
+    const uint32_t cell = __umul24(j0, g.res2) + (__umul24(j1, res) + j2);
     q.word = word0 + (cell >> 5);
     q.bit = cell & 31u;
     const uint32_t cc = static_cast<uint32_t>(g.coarse);
-    q.coarse = grid * g.skip_cells + __umul24(__umul24(j0 >> 2, cc) + (j1 >> 2), cc) + (j2 >> 2);
+    q.coarse = grid * g.skip_cells + (__umul24(j0 >> 2, g.coarse2) + (__umul24(j1 >> 2, cc) + (j2 >> 2)));
     return q;
 }
 
@@ -136,7 +153,7 @@ template <int LOOKUP>
 __device__ __forceinline__ bool occupied(const uint32_t* __restrict__ bits, uint32_t word0,
                                          const GridK& g, float x0, float x1, float x2) {
     const Probe q = probe<LOOKUP>(g, word0, x0, x1, x2);
-    return ((bits[q.word] >> q.bit) & 1u) != 0u;
+    return ((grid_word(grid_rsrc(bits, g), q.word) >> q.bit) & 1u) != 0u;
 }
 
 // First word of the ray's grid, or false for an invalid grid id (the ray is
@@ -210,8 +227,8 @@ int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uin
                  static_cast<long long>(cells));
     NACC_REQUIRE(grid->lookup >= 0 && grid->lookup <= 2, NACC_EINVAL, "unknown lookup mode %d", grid->lookup);
     NACC_REQUIRE(grid->n_grids >= 1, NACC_EINVAL, "n_grids = %d < 1", grid->n_grids);
-    NACC_REQUIRE(static_cast<int64_t>(grid->n_grids) * (cells / 32) <= UINT32_MAX, NACC_ESHAPE,
-                 "grid array exceeds 2^32 words");
+    NACC_REQUIRE(static_cast<int64_t>(grid->n_grids) * (cells / 8) <= INT32_MAX, NACC_ESHAPE,
+                 "grid arrays of %lld bytes exceed 2^31 - 1", static_cast<long long>(grid->n_grids * (cells / 8)));
     for (int i = 0; i < 3; ++i) {
         NACC_REQUIRE(std::isfinite(grid->lo[i]) && std::isfinite(grid->hi[i]) && grid->lo[i] < grid->hi[i],
                      NACC_EINVAL, "grid box axis %d is empty or not finite", i);
@@ -259,6 +276,9 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     g.words = static_cast<uint32_t>(static_cast<int64_t>(grid.res) * grid.res * grid.res / 32);
     g.coarse = grid.res / 4;
     g.skip_cells = static_cast<uint32_t>(g.coarse) * g.coarse * g.coarse;
+    g.res2 = static_cast<uint32_t>(grid.res) * static_cast<uint32_t>(grid.res);
+    g.coarse2 = static_cast<uint32_t>(g.coarse) * static_cast<uint32_t>(g.coarse);
+    g.bytes = static_cast<uint32_t>(static_cast<int64_t>(grid.n_grids) * g.words * 4);
     p.near_plane = params.near_plane;
     p.far_plane = params.far_plane;
     p.dt = params.dt;

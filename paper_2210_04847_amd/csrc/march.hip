@@ -192,7 +192,7 @@ __device__ __forceinline__ int march_ray_uniform_x2(
         for (int u = 0; u < 2; ++u) {
             const float tm = (t0[u] + t1[u]) * 0.5f;
             const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
-            const uint32_t w = bits[q.word];  // every lane: the index is clamped into the grid
+            const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);  // every lane: the index is clamped into the grid
             ms[u] = ballot(live[u] & (((w >> q.bit) & 1u) != 0u));
         }
 #pragma unroll
@@ -278,7 +278,7 @@ __device__ __forceinline__ int march_ray_uniform(
             // the candidate), so the grid word and the skip byte are loaded
             // together; lanes inside a cleared stretch ignore the word
             const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
-            const uint32_t w = bits[q.word];
+            const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);
             if (SKIP) {
                 const int dist = skip[q.coarse];
                 const float e = live ? skip_end_at<LOOKUP>(g, sk, q, dist, tm) : -INFINITY;
@@ -479,7 +479,7 @@ __device__ __forceinline__ uint32_t cone_hits(const uint32_t* __restrict__ bits,
             q[u] = probe<LOOKUP>(g, word0, o[0] + d[0] * tm[u], o[1] + d[1] * tm[u], o[2] + d[2] * tm[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kConeBatch; ++u) w[u] = bits[q[u].word];
+        for (int u = 0; u < kConeBatch; ++u) w[u] = grid_word(grid_rsrc(bits, g), q[u].word);
         const int dist = SKIP ? static_cast<int>(skip[q[kConeBatch - 1].coarse]) : 0;
 #pragma unroll
         for (int u = 0; u < kConeBatch; ++u) {

@@ -365,12 +365,13 @@ __device__ __forceinline__ void fill_ray_from_masks(
     const float t_near = span.t_near;
     const uint64_t mine = lane < n_masks ? masks[lane] : 0ull;  // one load: lane j holds chunk j
     int written = 0;
-    for (int j = 0; j < n_masks && written < limit; ++j) {
+    // only the chunks holding samples are visited, in order
+    for (uint64_t todo = ballot(mine != 0ull); todo != 0ull && written < limit; todo &= todo - 1ull) {
+        const int j = static_cast<int>(__builtin_ctzll(todo));
         const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(
                                 __builtin_amdgcn_readlane(static_cast<int>(mine >> 32), j)))
                             << 32) |
                            static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mine), j));
-        if (m == 0ull) continue;
         if ((m >> lane) & 1ull) {
             const int idx = written + bits_below(m);
             if (idx < limit) {

@@ -354,6 +354,52 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
 // the count pass (the first n_masks chunks), so the grid is not traversed a
 // second time; a ray whose samples continue past those chunks is traversed
 // from there on.
+// The samples of the stored chunks of one ray (lane j of `mine` holds
+// chunk j's mask), up to `limit`; only the chunks holding samples are
+// visited, in order.  Returns the number written (or, CHECKED, taken).
+template <bool CHECKED>
+__device__ __forceinline__ int fill_chunks(int64_t r, float t_near, float dt, int64_t start, int limit,
+                                           int64_t capacity, int32_t* __restrict__ ray_indices,
+                                           float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow,
+                                           uint64_t mine) {
+    const int lane = lane_id();
+    int written = 0;
+    for (uint64_t todo = ballot(mine != 0ull); todo != 0ull && written < limit; todo &= todo - 1ull) {
+        const int j = static_cast<int>(__builtin_ctzll(todo));
+        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(
+                                __builtin_amdgcn_readlane(static_cast<int>(mine >> 32), j)))
+                            << 32) |
+                           static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mine), j));
+        const int pc = static_cast<int>(__popcll(m));
+        const int n_take = pc < limit - written ? pc : limit - written;
+        const int rank = bits_below(m);
+        if (((m >> lane) & 1ull) != 0ull && rank < n_take) {
+            const int k = j * kWave + lane;
+            const float t0 = t_near + static_cast<float>(k) * dt;
+            const float t1 = t_near + static_cast<float>(k + 1) * dt;
+            if (!CHECKED) {
+                // wave-uniform bases, 32-bit lane offsets
+                const int64_t base = start + written;
+                const uint32_t off = static_cast<uint32_t>(rank);
+                (ray_indices + base)[off] = static_cast<int32_t>(r);
+                (t_starts + base)[off] = t0;
+                (t_ends + base)[off] = t1;
+            } else {
+                const int64_t pos = start + written + rank;
+                if (pos >= 0 && pos < capacity) {
+                    ray_indices[pos] = static_cast<int32_t>(r);
+                    t_starts[pos] = t0;
+                    t_ends[pos] = t1;
+                } else {
+                    overflow = true;
+                }
+            }
+        }
+        written += n_take;
+    }
+    return written;
+}
+
 template <int LOOKUP, bool SKIP>
 __device__ __forceinline__ void fill_ray_from_masks(
     int64_t r, const RaySpan& span, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
@@ -364,29 +410,15 @@ __device__ __forceinline__ void fill_ray_from_masks(
     const int lane = lane_id();
     const float t_near = span.t_near;
     const uint64_t mine = lane < n_masks ? masks[lane] : 0ull;  // one load: lane j holds chunk j
-    int written = 0;
-    // only the chunks holding samples are visited, in order
-    for (uint64_t todo = ballot(mine != 0ull); todo != 0ull && written < limit; todo &= todo - 1ull) {
-        const int j = static_cast<int>(__builtin_ctzll(todo));
-        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(
-                                __builtin_amdgcn_readlane(static_cast<int>(mine >> 32), j)))
-                            << 32) |
-                           static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mine), j));
-        if ((m >> lane) & 1ull) {
-            const int idx = written + bits_below(m);
-            if (idx < limit) {
-                const int k = j * kWave + lane;
-                const int64_t pos = start + idx;
-                if (pos >= 0 && pos < capacity) {
-                    ray_indices[pos] = static_cast<int32_t>(r);
-                    t_starts[pos] = t_near + static_cast<float>(k) * p.dt;
-                    t_ends[pos] = t_near + static_cast<float>(k + 1) * p.dt;
-                } else {
-                    overflow = true;
-                }
-            }
-        }
-        written += __popcll(m);
+    // the loop is bound by its scalar bookkeeping: a ray whose samples fit
+    // the outputs takes it without per-sample range checks
+    int written;
+    if (start >= 0 && start + limit <= capacity) {
+        written = fill_chunks<false>(r, t_near, p.dt, start, limit, capacity, ray_indices, t_starts, t_ends,
+                                     overflow, mine);
+    } else {
+        written = fill_chunks<true>(r, t_near, p.dt, start, limit, capacity, ray_indices, t_starts, t_ends,
+                                    overflow, mine);
     }
     if (written < limit) {
         march_ray_uniform<LOOKUP, true, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,

@@ -14,7 +14,8 @@ import os
 import torch  # loads torch's HIP runtime first; libnacc.so then binds to it
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnacc.so")
+# NACC_LIBRARY: another build of the library (A/B timing of two builds)
+LIB_PATH = os.environ.get("NACC_LIBRARY") or os.path.join(_HERE, "libnacc.so")
 
 NACC_OK, NACC_EINVAL, NACC_ESHAPE, NACC_ECAPACITY, NACC_EHIP, NACC_ENOTSUP = 0, -1, -2, -3, -4, -5
 LOOKUP_AABB, LOOKUP_CASCADE, LOOKUP_CONTRACT = 0, 1, 2

@@ -146,7 +146,8 @@ const char* nacc_version(void);
  * bits); the fused loss value is a sum in a different order.  Process-wide;
  * set them before launching, not concurrently with launches.
  *   march_waves_per_group  wavefronts sharing each group of 64 rays in the
- *                          uniform-step marching kernels: 1, 2 or 4 (4).
+ *                          uniform-step marching kernels: 1, 2, 4, 8 or 16
+ *                          (4; more waves suit small batches).
  *   render_cached_chunks   chunks of 64 samples per ray kept in registers
  *                          between the forward and the backward pass: 1..4
  *                          (4).

@@ -958,13 +958,12 @@ void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const floa
                            cw->masks, cw->extra, packed, sums);
         return;
     }
-    const int waves = tuning().march_waves_per_group;
-    if (waves == 1) {
-        launch_count_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
-    } else if (waves == 2) {
-        launch_count_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
-    } else {
-        launch_count_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks);
+    switch (tuning().march_waves_per_group) {
+        case 1: launch_count_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks); break;
+        case 2: launch_count_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks); break;
+        case 8: launch_count_uniform<LOOKUP, SKIP, 8>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks); break;
+        case 16: launch_count_uniform<LOOKUP, SKIP, 16>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks); break;
+        default: launch_count_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks); break;
     }
 }
 
@@ -988,16 +987,12 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
                            packed, n, capacity, ri);
         return;
     }
-    const int waves = tuning().march_waves_per_group;
-    if (waves == 1) {
-        launch_fill_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
-                                             status, masks, n_masks);
-    } else if (waves == 2) {
-        launch_fill_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
-                                             status, masks, n_masks);
-    } else {
-        launch_fill_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
-                                             status, masks, n_masks);
+    switch (tuning().march_waves_per_group) {
+        case 1: launch_fill_uniform<LOOKUP, SKIP, 1>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks); break;
+        case 2: launch_fill_uniform<LOOKUP, SKIP, 2>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks); break;
+        case 8: launch_fill_uniform<LOOKUP, SKIP, 8>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks); break;
+        case 16: launch_fill_uniform<LOOKUP, SKIP, 16>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks); break;
+        default: launch_fill_uniform<LOOKUP, SKIP, 4>(nb, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks); break;
     }
 }
 

@@ -44,8 +44,9 @@ void nacc_get_tuning(nacc_tuning* out) {
 int nacc_set_tuning(const nacc_tuning* t) {
     nacc::clear_error();
     NACC_REQUIRE(t != nullptr, NACC_EINVAL, "tuning must be non-NULL");
-    NACC_REQUIRE(t->march_waves_per_group == 1 || t->march_waves_per_group == 2 || t->march_waves_per_group == 4,
-                 NACC_EINVAL, "march_waves_per_group = %d not in {1, 2, 4}", t->march_waves_per_group);
+    const int w = t->march_waves_per_group;
+    NACC_REQUIRE(w == 1 || w == 2 || w == 4 || w == 8 || w == 16, NACC_EINVAL,
+                 "march_waves_per_group = %d not in {1, 2, 4, 8, 16}", w);
     NACC_REQUIRE(t->render_cached_chunks >= 1 && t->render_cached_chunks <= 4, NACC_EINVAL,
                  "render_cached_chunks = %d not in [1, 4]", t->render_cached_chunks);
     NACC_REQUIRE(t->render_mse_max_blocks >= 1 && t->render_mse_max_blocks <= (1 << 20), NACC_EINVAL,

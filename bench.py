@@ -7,10 +7,11 @@ Default workload (train_262k): one training step = march (count, scan, fill)
 plus the occupancy-grid update (decay, 2^18 random cells, field, max, pack)
 every 16 steps.  262,144 rays, 128^3 grid of 32 blobs.  Inputs are seeded,
 synthetic and resident in HBM before the timed region; outputs go to
-capacity-sized buffers, so no step waits on the host.  The step is captured
-in HIP graphs (one for a plain step, one for a step with the grid update)
-after the launch parameters are autotuned; per-phase times come from an
-eager pass with HIP events on the launch stream.
+capacity-sized buffers, so no step waits on the host.  The step runs as the
+library's step plan (nacc_plan): its launch parameters tuned by the plan on
+this step, then the step and the grid update captured by the library into
+two HIP graphs and replayed; per-phase times come from an eager pass with
+HIP events on the launch stream.
 
 --workload dynamic_64: 64 frames with their own grids (~262k rays, Poisson
 counts per frame); 64 per-frame plain calls (each sized by a host read of the
@@ -68,8 +69,11 @@ def parse():
                     choices=["train_262k", "plain_fwd_4k", "unbounded_262k",
                              "unbounded_contract_262k", "dynamic_64", "dynamic_64_shared",
                              "images_8", "attrs_262k"])
-    ap.add_argument("--form", choices=["graph", "eager"], default="graph",
-                    help="time the step captured in HIP graphs, or launched eagerly")
+    ap.add_argument("--form", choices=["plan", "graph", "eager"], default="plan",
+                    help="time the step as the library's step plan (its own HIP graphs and "
+                         "tuner), captured in HIP graphs through torch, or launched eagerly "
+                         "(training workloads; steps with visibility pruning, the attribute "
+                         "and image workloads use torch graphs for \"plan\")")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
@@ -248,6 +252,36 @@ class Step:
             self.grid_update()
         if events is not None:
             events[len(fns) + 1].record()
+
+    def plan(self):
+        """This step (and its grid update) as the library's step plan: the
+        same launches on the same buffers, with the synthetic field as native
+        stages, captured and replayed by the library itself."""
+        if self.prune:
+            raise ValueError("a step plan has no visibility-pruning stage")
+        lib, f, g = self.lib, self.field, self.grid
+        field = lib.synth_samples_stage(f.table, f.n_blobs, f.n_sets, self.rays_o, self.rays_d,
+                                        self.ray_set, self.ray_indices, self.t_starts,
+                                        self.t_ends, self.sigmas, self.rgbs, self.total)
+        table = f.table_contracted if g.lookup == lib.LOOKUP_CONTRACT else f.table
+        per_cell = f.n_sets > 1 and self.update_set is None
+        update_field = lib.synth_points_stage(table, f.n_blobs, f.n_sets, self.ema_pos,
+                                              self.update_set, self.ema_sigma,
+                                              point_cell=self.ema_cells if per_cell else None,
+                                              cells_per_set=g.res ** 3)
+        train = not self.forward_only
+        return lib.Plan(self.rays_o, self.rays_d, g.bits, g.desc, self.params, self.packed,
+                        self.ray_indices, self.t_starts, self.t_ends, self.total, field,
+                        self.sigmas, self.rgbs, self.color, self.opacity, self.depth,
+                        early_stop_eps=self.w.early_stop_eps, grid_id=self.grid_id,
+                        grid_skip=self.skip, status=self.status,
+                        target=self.target if train else None, loss_rays=self.loss_rays,
+                        g_sigmas=self.g_sigmas if train else None,
+                        g_rgbs=self.g_rgbs if train else None, loss=self.loss if train else None,
+                        occ=g.occ, decay=EMA_DECAY, threshold=THRESHOLD, seed=self.seed,
+                        update_counter=self.updates, update_cell_ids=self.ema_cells,
+                        update_positions=self.ema_pos, update_values=self.ema_sigma,
+                        update_field=update_field)
 
     def outputs(self):
         """Tensors a change of launch parameters must leave bit-identical."""
@@ -475,8 +509,13 @@ def bench_train(args, torch, nacc):
         torch.cuda.synchronize()
         del src, dst
 
+    form = args.form if not (args.form == "plan" and st.prune) else "graph"
+    plan = st.plan() if form == "plan" else None
     tuned = None
-    if not args.no_autotune:
+    if plan is not None and not args.no_autotune:
+        tuned, tuned_ms = plan.autotune()
+        log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
+    elif not args.no_autotune:
         from paper_2210_04847_amd import autotune
         cands = dict(autotune.CANDIDATES)
         if forward_only:
@@ -490,7 +529,10 @@ def bench_train(args, torch, nacc):
     log(f"warmup done ({warmup} steps)")
 
     graphs = None
-    if args.form == "graph":
+    if plan is not None:
+        plan.capture()
+        log("captured the step plan's HIP graphs")
+    elif form == "graph":
         graphs = (capture(torch, lambda: st.step(update=False)),
                   capture(torch, lambda: st.step(update=True)))
         log("captured the step in HIP graphs")
@@ -504,7 +546,9 @@ def bench_train(args, torch, nacc):
     start.record()
     for k in range(steps):
         upd = (warmup + k) % EMA_EVERY == 0
-        if graphs is not None:
+        if plan is not None:
+            plan.launch(with_update=upd)
+        elif graphs is not None:
             graphs[1 if upd else 0].replay()
         else:
             st.step(update=upd)
@@ -576,7 +620,7 @@ def bench_train(args, torch, nacc):
                    "cone": getattr(w, "cone", 0.0), "early_stop_eps": w.early_stop_eps,
                    "pass": "forward" if forward_only else "forward+mse+backward",
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
-                   "form": args.form, "skip_field": args.skip_field, "tuning": tuned,
+                   "form": form, "skip_field": args.skip_field, "tuning": tuned,
                    "visibility_pruning": (None if args.alpha_thre is None else
                                           {"early_stop_eps": w.early_stop_eps,
                                            "alpha_thre": args.alpha_thre}),
@@ -672,8 +716,12 @@ def bench_dynamic(args, torch, nacc):
             if keep is not None:
                 keep.append((packed, ri + a, ts, color, gs, gr))
 
+    plan = batched.plan() if args.form == "plan" else None
     tuned = None
-    if not args.no_autotune:
+    if plan is not None and not args.no_autotune:
+        tuned, tuned_ms = plan.autotune()
+        log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
+    elif not args.no_autotune:
         from paper_2210_04847_amd import autotune
         tuned, _ = autotune.autotune(lambda: batched.step(), batched.outputs, log=log)
         log(f"tuned: {tuned}")
@@ -716,10 +764,15 @@ def bench_dynamic(args, torch, nacc):
     stop.record()
     torch.cuda.synchronize()
     eager_ms = start.elapsed_time(stop) / steps
-    g = capture(torch, lambda: batched.step())
+    if plan is not None:
+        plan.capture()
+        replay = lambda: plan.launch()
+    else:
+        g = capture(torch, lambda: batched.step())
+        replay = g.replay
     start.record()
     for _ in range(steps):
-        g.replay()
+        replay()
     stop.record()
     torch.cuda.synchronize()
     graph_ms = start.elapsed_time(stop) / steps
@@ -744,7 +797,9 @@ def bench_dynamic(args, torch, nacc):
                    "grid": (f"one {res}^3 shared by the {nf} frames" if shared
                             else f"{nf} x {res}^3"),
                    "blobs": w.n_blobs, "early_stop_eps": w.early_stop_eps,
-                   "pass": "forward+mse+backward", "form": "batched, one HIP graph per step",
+                   "pass": "forward+mse+backward",
+                   "form": ("batched, the library's step plan (one HIP graph per step)"
+                            if plan is not None else "batched, one HIP graph per step"),
                    "tuning": tuned, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "render", "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,

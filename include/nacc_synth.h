@@ -97,6 +97,46 @@ int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, 
                             const nacc_march_params* params, float early_stop_eps, float* color,
                             float* opacity, float* depth, int32_t* kept, void* stream);
 
+/*
+ * The two field evaluations above as stages of a step plan (nacc_plan.h):
+ * each *_stage_run has the nacc_stage_fn signature and takes a pointer to
+ * its struct (which must outlive the plan) as `user`; the struct's fields
+ * are the arguments of the call of the same name.  The samples stage
+ * evaluates the first *n_samples_dev samples (required: the plan's total).
+ */
+typedef struct nacc_synth_samples_stage {
+    const void* table;
+    int32_t n_blobs;
+    int32_t n_sets;
+    const float* rays_o;
+    const float* rays_d;
+    int64_t n_rays;
+    const int32_t* ray_set;
+    const int32_t* ray_indices;
+    const float* t_starts;
+    const float* t_ends;
+    int64_t n_samples;
+    const int64_t* n_samples_dev;
+    float* sigmas;
+    float* rgbs;
+} nacc_synth_samples_stage;
+
+typedef struct nacc_synth_points_stage {
+    const void* table;
+    int32_t n_blobs;
+    int32_t n_sets;
+    const float* points;
+    const int32_t* point_set;
+    const int32_t* point_cell;
+    int64_t cells_per_set;
+    int64_t n;
+    float* sigmas;
+    float* rgbs;
+} nacc_synth_points_stage;
+
+int nacc_synth_samples_stage_run(void* stage, void* stream);
+int nacc_synth_points_stage_run(void* stage, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,7 +2,7 @@
 
 Every call takes torch tensors that live on the GPU, checks dtype, device and
 contiguity, and passes raw pointers plus torch's current HIP stream to the C
-ABI declared in include/nacc.h and include/nacc_synth.h.  No arithmetic of the
+ABI declared in include/nacc.h, include/nacc_synth.h and include/nacc_plan.h.  No arithmetic of the
 method happens here.  If the library has not been built, importing this module
 raises ImportError: there is no fallback path.
 """
@@ -44,6 +44,51 @@ class MarchParams(ctypes.Structure):
     _fields_ = [("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float),
                 ("dt", ctypes.c_float), ("dt_max", ctypes.c_float),
                 ("cone", ctypes.c_float), ("max_per_ray", ctypes.c_int32)]
+
+
+class PlanDesc(ctypes.Structure):
+    """nacc_plan_desc (include/nacc_plan.h); stage functions as addresses."""
+    _fields_ = [("rays_o", ctypes.c_void_p), ("rays_d", ctypes.c_void_p),
+                ("grid_id", ctypes.c_void_p), ("n_rays", ctypes.c_int64),
+                ("grid_bits", ctypes.c_void_p), ("grid_skip", ctypes.c_void_p),
+                ("grid", GridDesc), ("params", MarchParams), ("capacity", ctypes.c_int64),
+                ("packed_info", ctypes.c_void_p), ("ray_indices", ctypes.c_void_p),
+                ("t_starts", ctypes.c_void_p), ("t_ends", ctypes.c_void_p),
+                ("total", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("field", ctypes.c_void_p), ("field_user", ctypes.c_void_p),
+                ("sigmas", ctypes.c_void_p), ("rgbs", ctypes.c_void_p),
+                ("early_stop_eps", ctypes.c_float), ("target", ctypes.c_void_p),
+                ("loss_rays", ctypes.c_int64), ("color", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("g_sigmas", ctypes.c_void_p), ("g_rgbs", ctypes.c_void_p),
+                ("loss", ctypes.c_void_p), ("after", ctypes.c_void_p),
+                ("after_user", ctypes.c_void_p), ("occ", ctypes.c_void_p),
+                ("decay", ctypes.c_float), ("threshold", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("update_cells", ctypes.c_int64),
+                ("update_counter", ctypes.c_void_p), ("update_cell_ids", ctypes.c_void_p),
+                ("update_positions", ctypes.c_void_p), ("update_values", ctypes.c_void_p),
+                ("update_field", ctypes.c_void_p), ("update_field_user", ctypes.c_void_p)]
+
+
+class SynthSamplesStage(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("n_blobs", ctypes.c_int32),
+                ("n_sets", ctypes.c_int32), ("rays_o", ctypes.c_void_p),
+                ("rays_d", ctypes.c_void_p), ("n_rays", ctypes.c_int64),
+                ("ray_set", ctypes.c_void_p), ("ray_indices", ctypes.c_void_p),
+                ("t_starts", ctypes.c_void_p), ("t_ends", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("n_samples_dev", ctypes.c_void_p),
+                ("sigmas", ctypes.c_void_p), ("rgbs", ctypes.c_void_p)]
+
+
+class SynthPointsStage(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("n_blobs", ctypes.c_int32),
+                ("n_sets", ctypes.c_int32), ("points", ctypes.c_void_p),
+                ("point_set", ctypes.c_void_p), ("point_cell", ctypes.c_void_p),
+                ("cells_per_set", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("sigmas", ctypes.c_void_p), ("rgbs", ctypes.c_void_p)]
+
+
+STAGE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 
 
 _P = ctypes.c_void_p
@@ -90,12 +135,21 @@ _SIGNATURES = {
     "nacc_synth_field_samples": (_INT, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P, _P, _I64,
                                         _P, _P, _P, _P]),
     "nacc_synth_field_points": (_INT, [_P, _I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "nacc_synth_samples_stage_run": (_INT, [_P, _P]),
+    "nacc_synth_points_stage_run": (_INT, [_P, _P]),
+    "nacc_plan_create": (_INT, [ctypes.POINTER(PlanDesc), ctypes.POINTER(_P)]),
+    "nacc_plan_destroy": (_INT, [_P]),
+    "nacc_plan_step": (_INT, [_P, _P]),
+    "nacc_plan_update": (_INT, [_P, _P]),
+    "nacc_plan_capture_step": (_INT, [_P]),
+    "nacc_plan_launch": (_INT, [_P, _I32, _P]),
+    "nacc_plan_autotune": (_INT, [_P, _I32, _P, ctypes.POINTER(Tuning), ctypes.POINTER(_F)]),
     "nacc_synth_render_fused": (_INT, [_P, _I32, _I32, _P, _P, _P, _P, _I64, _P,
                                        ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams), _F,
                                        _P, _P, _P, _P, _P]),
 }
 
-# Symbols declared in include/nacc.h and include/nacc_synth.h.
+# Symbols declared in include/nacc.h, include/nacc_synth.h and include/nacc_plan.h.
 EXPORTED = tuple(_SIGNATURES)
 
 
@@ -507,3 +561,194 @@ def render_attrs_bwd(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_ep
         _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(attrs), ch,
         float(early_stop_eps), float(alpha_thre), _ptr(background), _ptr(g_out), _ptr(g_opacity),
         _ptr(g_depth), _ptr(g_sigmas), _ptr(g_attrs), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Step plans (include/nacc_plan.h).
+# ---------------------------------------------------------------------------
+
+class Stage:
+    """A stage of a step plan: the address of a nacc_stage_fn and its `user`
+    pointer, plus the objects that must stay alive while a plan uses it."""
+
+    def __init__(self, fn_address, user, keep=()):
+        self.fn = ctypes.c_void_p(fn_address)
+        self.user = user
+        self.keep = keep
+
+
+def _address(fn):
+    return ctypes.cast(fn, ctypes.c_void_p).value
+
+
+def synth_samples_stage(table, n_blobs, n_sets, rays_o, rays_d, ray_set, ray_indices, t_starts,
+                        t_ends, sigmas, rgbs, n_samples_dev) -> Stage:
+    """nacc_synth_field_samples as a native stage (the first *n_samples_dev
+    samples of ray_indices / t_starts / t_ends)."""
+    n = ray_indices.numel()
+    _need(table, torch.float32, "table")
+    _need(rays_o, torch.float32, "rays_o")
+    _need(rays_d, torch.float32, "rays_d", rays_o.numel())
+    _need(ray_set, torch.int32, "ray_set", rays_o.numel() // 3)
+    _need(ray_indices, torch.int32, "ray_indices")
+    _need(t_starts, torch.float32, "t_starts", n)
+    _need(t_ends, torch.float32, "t_ends", n)
+    _need(sigmas, torch.float32, "sigmas", n)
+    _need(rgbs, torch.float32, "rgbs", 3 * n)
+    _need(n_samples_dev, torch.int64, "n_samples_dev", 1)
+    if n_samples_dev is None:
+        raise ValueError("the samples stage needs n_samples_dev")
+    st = SynthSamplesStage(_ptr(table), n_blobs, n_sets, _ptr(rays_o), _ptr(rays_d),
+                           rays_o.numel() // 3, _ptr(ray_set), _ptr(ray_indices), _ptr(t_starts),
+                           _ptr(t_ends), n, _ptr(n_samples_dev), _ptr(sigmas), _ptr(rgbs))
+    keep = (st, table, rays_o, rays_d, ray_set, ray_indices, t_starts, t_ends, sigmas, rgbs,
+            n_samples_dev)
+    return Stage(_address(lib.nacc_synth_samples_stage_run), ctypes.addressof(st), keep)
+
+
+def synth_points_stage(table, n_blobs, n_sets, points, point_set, sigmas, point_cell=None,
+                       cells_per_set=0) -> Stage:
+    """nacc_synth_field_points (densities only) as a native stage."""
+    n = points.shape[0]
+    _need(table, torch.float32, "table")
+    _need(points, torch.float32, "points", 3 * n)
+    _need(point_set, torch.int32, "point_set", n)
+    _need(point_cell, torch.int32, "point_cell", n)
+    _need(sigmas, torch.float32, "sigmas", n)
+    st = SynthPointsStage(_ptr(table), n_blobs, n_sets, _ptr(points), _ptr(point_set),
+                          _ptr(point_cell), int(cells_per_set), n, _ptr(sigmas), None)
+    keep = (st, table, points, point_set, point_cell, sigmas)
+    return Stage(_address(lib.nacc_synth_points_stage_run), ctypes.addressof(st), keep)
+
+
+def python_stage(fn) -> Stage:
+    """A Python callable as a stage: fn(stream) enqueues its work on `stream`
+    (a torch.cuda.ExternalStream, or the default stream; also made torch's
+    current stream).  It must
+    not allocate device memory or synchronise if the plan is captured.  An
+    exception ends the step; it is raised again by the plan call."""
+    errors = []
+
+    def trampoline(_user, stream):
+        try:
+            ext = (torch.cuda.ExternalStream(stream) if stream else
+                   torch.cuda.default_stream())
+            with torch.cuda.stream(ext):
+                fn(ext)
+            return 0
+        except BaseException as e:  # reported by the plan call that ran the stage
+            errors.append(e)
+            return NACC_EINVAL
+
+    cb = STAGE_FN(trampoline)
+    stage = Stage(_address(cb), None, (cb, fn))
+    stage.errors = errors
+    return stage
+
+
+class Plan:
+    """A step plan (nacc_plan_create): marching, the field stage, rendering
+    (with the MSE loss and its backward when `target` is given), an optional
+    `after` stage and an optional grid update (when `occ` is given).  Keeps
+    every tensor and stage it was given alive until close()."""
+
+    def __init__(self, rays_o, rays_d, grid_bits, desc, params, packed_info, ray_indices,
+                 t_starts, t_ends, total, field, sigmas, rgbs, color, opacity, depth,
+                 early_stop_eps=1e-4, grid_id=None, grid_skip=None, status=None, target=None,
+                 loss_rays=0, g_sigmas=None, g_rgbs=None, loss=None, after=None, occ=None,
+                 decay=0.95, threshold=0.01, seed=0, update_counter=None, update_cell_ids=None,
+                 update_positions=None, update_values=None, update_field=None):
+        n = rays_o.shape[0]
+        cap = ray_indices.numel()
+        _need(rays_o, torch.float32, "rays_o", 3 * n)
+        _need(rays_d, torch.float32, "rays_d", 3 * n)
+        _need(grid_id, torch.int32, "grid_id", n)
+        _need(grid_bits, torch.int32, "grid_bits", _grid_words(desc))
+        _need(grid_skip, torch.uint8, "grid_skip", grid_skip_bytes(desc))
+        _need(packed_info, torch.int32, "packed_info", 2 * n)
+        _need(ray_indices, torch.int32, "ray_indices")
+        for t, nm, k in ((t_starts, "t_starts", 1), (t_ends, "t_ends", 1), (sigmas, "sigmas", 1),
+                         (rgbs, "rgbs", 3), (g_sigmas, "g_sigmas", 1), (g_rgbs, "g_rgbs", 3)):
+            _need(t, torch.float32, nm, k * cap)
+        _need(total, torch.int64, "total", 1)
+        _need(status, torch.int32, "status", 1)
+        _need(target, torch.float32, "target", 3 * n)
+        for t, nm, k in ((color, "color", 3), (opacity, "opacity", 1), (depth, "depth", 1)):
+            _need(t, torch.float32, nm, k * n)
+        _need(loss, torch.float32, "loss", 1)
+        m = int(update_cell_ids.numel()) if update_cell_ids is not None else 0
+        if occ is not None:
+            _need(occ, torch.float32, "occ", desc.n_grids * desc.res ** 3)
+            _need(update_counter, torch.int64, "update_counter", 1)
+            _need(update_cell_ids, torch.int32, "update_cell_ids")
+            _need(update_positions, torch.float32, "update_positions", 3 * m)
+            _need(update_values, torch.float32, "update_values", m)
+        stages = [x for x in (field, after, update_field) if x is not None]
+        d = PlanDesc()
+        d.rays_o, d.rays_d, d.grid_id, d.n_rays = _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n
+        d.grid_bits, d.grid_skip, d.grid, d.params = _ptr(grid_bits), _ptr(grid_skip), desc, params
+        d.capacity = cap
+        d.packed_info, d.ray_indices = _ptr(packed_info), _ptr(ray_indices)
+        d.t_starts, d.t_ends, d.total, d.status = _ptr(t_starts), _ptr(t_ends), _ptr(total), _ptr(status)
+        d.field = field.fn if field is not None else None
+        d.field_user = field.user if field is not None else None
+        d.sigmas, d.rgbs, d.early_stop_eps = _ptr(sigmas), _ptr(rgbs), float(early_stop_eps)
+        d.target, d.loss_rays = _ptr(target), int(loss_rays)
+        d.color, d.opacity, d.depth = _ptr(color), _ptr(opacity), _ptr(depth)
+        d.g_sigmas, d.g_rgbs, d.loss = _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss)
+        d.after = after.fn if after is not None else None
+        d.after_user = after.user if after is not None else None
+        d.occ, d.decay, d.threshold, d.seed = _ptr(occ), float(decay), float(threshold), int(seed)
+        d.update_cells, d.update_counter = m, _ptr(update_counter)
+        d.update_cell_ids, d.update_positions = _ptr(update_cell_ids), _ptr(update_positions)
+        d.update_values = _ptr(update_values)
+        d.update_field = update_field.fn if update_field is not None else None
+        d.update_field_user = update_field.user if update_field is not None else None
+        self._keep = (rays_o, rays_d, grid_id, grid_bits, grid_skip, packed_info, ray_indices,
+                      t_starts, t_ends, total, status, sigmas, rgbs, target, color, opacity, depth,
+                      g_sigmas, g_rgbs, loss, occ, update_counter, update_cell_ids,
+                      update_positions, update_values, stages)
+        self._stages = stages
+        handle = ctypes.c_void_p()
+        self._call("nacc_plan_create", lib.nacc_plan_create(ctypes.byref(d), ctypes.byref(handle)))
+        self.handle = handle
+
+    def _call(self, name, status):
+        for st in self._stages:
+            errs = getattr(st, "errors", None)
+            if errs:
+                e = errs.pop()
+                errs.clear()
+                raise e
+        _check(name, status)
+
+    def step(self, stream=None):
+        self._call("nacc_plan_step", lib.nacc_plan_step(self.handle, _stream(stream)))
+
+    def update(self, stream=None):
+        self._call("nacc_plan_update", lib.nacc_plan_update(self.handle, _stream(stream)))
+
+    def capture(self):
+        self._call("nacc_plan_capture_step", lib.nacc_plan_capture_step(self.handle))
+
+    def launch(self, with_update=False, stream=None):
+        self._call("nacc_plan_launch", lib.nacc_plan_launch(self.handle, int(bool(with_update)),
+                                                            _stream(stream)))
+
+    def autotune(self, repeats=5, stream=None):
+        """Returns (the chosen tuning, its ms per step); see nacc_plan_autotune."""
+        t, ms = Tuning(), ctypes.c_float()
+        self._call("nacc_plan_autotune", lib.nacc_plan_autotune(
+            self.handle, int(repeats), _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
+        return {name: getattr(t, name) for name, _ in Tuning._fields_}, ms.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.nacc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -176,4 +176,22 @@ int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, 
     return check_launch("synth field points");
 }
 
+int nacc_synth_samples_stage_run(void* stage, void* stream) {
+    clear_error();
+    NACC_REQUIRE(stage != nullptr, NACC_EINVAL, "stage must be non-NULL");
+    const auto* a = static_cast<const nacc_synth_samples_stage*>(stage);
+    NACC_REQUIRE(a->n_samples_dev != nullptr, NACC_EINVAL, "the samples stage needs n_samples_dev");
+    return nacc_synth_field_samples(a->table, a->n_blobs, a->n_sets, a->rays_o, a->rays_d, a->n_rays, a->ray_set,
+                                    a->ray_indices, a->t_starts, a->t_ends, a->n_samples, a->n_samples_dev,
+                                    a->sigmas, a->rgbs, stream);
+}
+
+int nacc_synth_points_stage_run(void* stage, void* stream) {
+    clear_error();
+    NACC_REQUIRE(stage != nullptr, NACC_EINVAL, "stage must be non-NULL");
+    const auto* a = static_cast<const nacc_synth_points_stage*>(stage);
+    return nacc_synth_field_points(a->table, a->n_blobs, a->n_sets, a->points, a->point_set, a->point_cell,
+                                   a->cells_per_set, a->n, a->sigmas, a->rgbs, stream);
+}
+
 }  // extern "C"

@@ -8,7 +8,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("nacc.h", "nacc_synth.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nacc.h", "nacc_synth.h", "nacc_plan.h")]
 
 
 def declared_symbols():
@@ -148,3 +148,59 @@ def test_zero_rays_launch_nothing_but_need_total():
     st = _lib.lib.nacc_march_count(fake, fake, None, 0, fake, None, ctypes.byref(desc),
                                    ctypes.byref(params), None, None, None, 0, None)
     assert st == _lib.NACC_EINVAL  # total is required even for zero rays
+
+
+def _plan_desc_raw(_lib, **over):
+    """A plan description whose pointers are never dereferenced: every case
+    below fails validation on the host, before any device call."""
+    fake = 0x1000
+    d = _lib.PlanDesc()
+    d.rays_o = d.rays_d = d.grid_bits = d.packed_info = d.total = fake
+    d.ray_indices = d.t_starts = d.t_ends = d.sigmas = d.rgbs = fake
+    d.color = d.opacity = d.depth = fake
+    d.field = fake
+    d.n_rays, d.capacity = 16, 1024
+    d.grid = _lib.grid_desc((-1, -1, -1), (1, 1, 1), 8)
+    d.params = _lib.march_params(0.0, 10.0, 0.01)
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("over", [
+    dict(field=None), dict(color=None), dict(n_rays=-1), dict(capacity=-1),
+    dict(capacity=1 << 31), dict(early_stop_eps=-1.0), dict(sigmas=None),
+    dict(target=0x1000),                          # training without loss / gradients
+    dict(target=0x1000, loss=0x1000, g_sigmas=0x1000, g_rgbs=0x1000, loss_rays=3),
+    dict(occ=0x1000),                             # update without its arrays
+    dict(occ=0x1000, update_cells=8, update_counter=0x1000, update_cell_ids=0x1000,
+         update_positions=0x1000, update_values=0x1000),  # ... without its field stage
+])
+def test_bad_plan_rejected_on_host(over):
+    from paper_2210_04847_amd import _lib
+    d = _plan_desc_raw(_lib, **over)
+    out = ctypes.c_void_p(0x1234)
+    st = _lib.lib.nacc_plan_create(ctypes.byref(d), ctypes.byref(out))
+    assert st == _lib.NACC_EINVAL
+    assert out.value == 0x1234  # untouched on failure
+    assert _lib.lib.nacc_last_error().decode()
+
+
+def test_bad_plan_grid_rejected_on_host():
+    from paper_2210_04847_amd import _lib
+    out = ctypes.c_void_p()
+    for over in (dict(grid=_lib.grid_desc((-1, -1, -1), (1, 1, 1), 3)),
+                 dict(params=_lib.march_params(0.0, 10.0, 0.0))):
+        d = _plan_desc_raw(_lib, **over)
+        assert _lib.lib.nacc_plan_create(ctypes.byref(d), ctypes.byref(out)) == _lib.NACC_EINVAL
+
+
+def test_plan_calls_on_null_plan_rejected():
+    from paper_2210_04847_amd import _lib
+    lib = _lib.lib
+    assert lib.nacc_plan_destroy(None) == _lib.NACC_OK
+    for st in (lib.nacc_plan_step(None, None), lib.nacc_plan_update(None, None),
+               lib.nacc_plan_capture_step(None), lib.nacc_plan_launch(None, 0, None),
+               lib.nacc_plan_autotune(None, 3, None, None, None)):
+        assert st == _lib.NACC_EINVAL
+    assert lib.nacc_synth_samples_stage_run(None, None) == _lib.NACC_EINVAL

@@ -481,6 +481,68 @@ def phase_timing(torch, st, steps, first_index, updates=True):
     return {p: (float(np.mean(v)) if v else 0.0) for p, v in out.items()}
 
 
+def step_latency(torch, launch, n):
+    """p10 / p50 / p90 of n single launches, each bracketed by HIP events on
+    the launch stream (ms)."""
+    import numpy as np
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        launch()
+        b.record()
+    torch.cuda.synchronize()
+    v = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"p10": float(np.percentile(v, 10)), "p50": float(np.percentile(v, 50)),
+            "p90": float(np.percentile(v, 90)), "launches": n}
+
+
+def unfused_render(torch, st, repeats=16):
+    """The render forward and backward as two calls (nacc_render_fwd, then
+    nacc_render_bwd with the MSE gradient of the colour as a given input) on
+    the step's samples, timed per call with HIP events; algorithmic bytes:
+    forward 24 B per sample before the cut + 28 B per ray (packed_info in,
+    colour / opacity / depth out); backward the same samples again, 16 B of
+    gradients written for every sample, packed_info and g_color in
+    (20 B per ray)."""
+    import numpy as np
+    lib = st.lib
+    e = int(st.total.item())
+    n = st.n
+    ts, te, sg, rg = st.t_starts[:e], st.t_ends[:e], st.sigmas[:e], st.rgbs[:e]
+    color = torch.empty_like(st.color)
+    opac = torch.empty_like(st.opacity)
+    depth = torch.empty_like(st.depth)
+    kept = torch.empty(n, dtype=torch.int32, device=st.color.device)
+    gs = torch.empty(e, dtype=torch.float32, device=st.color.device)
+    gr = torch.empty((e, 3), dtype=torch.float32, device=st.color.device)
+    eps = st.w.early_stop_eps
+    lib.render_fwd(st.packed, ts, te, sg, rg, eps, color, opac, depth, kept=kept)
+    # the loss's gradient (an input here), as the fused kernel forms it
+    g_color = (color - st.target) * float(np.float32(2.0 / (3 * n)))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(repeats)]
+    for a, b, c in ev:
+        a.record()
+        lib.render_fwd(st.packed, ts, te, sg, rg, eps, color, opac, depth)
+        b.record()
+        lib.render_bwd(st.packed, ts, te, sg, rg, eps, g_color, None, None, gs, gr)
+        c.record()
+    torch.cuda.synchronize()
+    fwd = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    bwd = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    v = int(kept.sum().item())
+    fwd_bytes = 24 * v + 28 * n
+    bwd_bytes = 24 * v + 16 * e + 20 * n
+    same = bool(torch.equal(gs.view(torch.int32), st.g_sigmas[:e].view(torch.int32)) and
+                torch.equal(color.view(torch.int32), st.color.view(torch.int32)))
+    return {"fwd_ms": fwd, "bwd_ms": bwd, "samples_per_s": e / ((fwd + bwd) * 1e-3),
+            "alg_bytes": fwd_bytes + bwd_bytes,
+            "hbm_frac": (fwd_bytes + bwd_bytes) / ((fwd + bwd) * 1e-3) / HBM_PEAK,
+            "fwd_hbm_frac": fwd_bytes / (fwd * 1e-3) / HBM_PEAK,
+            "bwd_hbm_frac": bwd_bytes / (bwd * 1e-3) / HBM_PEAK,
+            "identical_to_fused": same}
+
+
 def bench_train(args, torch, nacc):
     import synth
     unbounded = args.workload in synth.UNBOUNDED_WORKLOADS
@@ -563,6 +625,14 @@ def bench_train(args, torch, nacc):
     e_steps = totals.cpu().numpy()
     e_total = int(e_steps.sum())
     phase_avg = phase_timing(torch, st, min(steps, 32), warmup + steps)
+    if plan is not None:
+        one = lambda: plan.launch()
+    elif graphs is not None:
+        one = graphs[0].replay
+    else:
+        one = lambda: st.step()
+    latency = step_latency(torch, one, 100 if forward_only else 32)
+    unfused = None if (forward_only or st.prune) else unfused_render(torch, st)
     e_mean = e_total / steps
     k_steps = rendered.cpu().numpy()
     k_mean = float(k_steps.mean())  # samples shaded and rendered (= e_mean unpruned)
@@ -634,6 +704,8 @@ def bench_train(args, torch, nacc):
         "phase_gbps": {p: alg[p] / (phase_avg[p] * 1e-3) / 1e9 for p in alg if phase_avg[p] > 0},
         "step_alg_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (step_ms * 1e-3) / HBM_PEAK,
+        "step_latency_ms": latency,
+        "render_unfused": unfused,
         "path_samples_per_s": e_mean / (1e-3 * (step_ms - phase_avg["field"]
                                                 - phase_avg.get("field_sigma", 0.0))),
         "wall_s": wall,

@@ -152,7 +152,8 @@ const char* nacc_version(void);
  *                          between the forward and the backward pass: 1..4
  *                          (4).
  *   render_mse_max_blocks  workgroups of the fused loss kernel, 1..2^20
- *                          (8192).
+ *                          (16384); at n_rays / 4 or more, one ray per
+ *                          wave.
  *   render_prefetch        0 or 1 (0): the fused loss kernel loads the
  *                          next ray's first chunk during a ray's backward.
  * Workspace sizes do not depend on these settings.

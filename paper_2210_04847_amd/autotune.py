@@ -18,7 +18,7 @@ from . import _lib
 CANDIDATES = {
     "render_cached_chunks": (1, 2, 3, 4),
     "march_waves_per_group": (1, 2, 4, 8, 16),
-    "render_mse_max_blocks": (1024, 2048, 4096, 8192),
+    "render_mse_max_blocks": (4096, 8192, 16384, 65536),
     "render_prefetch": (0, 1),
 }
 

@@ -240,7 +240,7 @@ int get_knob(const nacc_tuning& t, int knob) {
 
 int autotune(nacc_plan* p, int repeats, nacc_tuning* best_out, float* best_ms_out) {
     static const std::vector<int> kValues[4] = {
-        {1, 2, 4, 8, 16}, {1, 2, 3, 4}, {1024, 2048, 4096, 8192}, {0, 1}};
+        {1, 2, 4, 8, 16}, {1, 2, 3, 4}, {4096, 8192, 16384, 65536}, {0, 1}};
     const bool training = p->d.target != nullptr;
     nacc_tuning best;
     nacc_get_tuning(&best);

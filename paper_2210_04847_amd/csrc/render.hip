@@ -126,8 +126,23 @@ struct RayGrad {
     float gr, gg, gb, ga, gd;
 };
 
-__device__ __forceinline__ float vdot(const RayGrad& q, const Sample& x) {
-    return ((q.gr * x.r + q.gg * x.g) + q.gb * x.b) + (q.ga + q.gd * ((x.t0 + x.t1) * 0.5f));
+// What the backward needs of a sample: its interval length, midpoint and
+// colour (its density only enters through w and T, formed in the forward).
+struct GradInput {
+    float delta, m, r, g, b;
+};
+
+__device__ __forceinline__ GradInput grad_input(const Sample& x) {
+    return GradInput{x.t1 - x.t0, (x.t0 + x.t1) * 0.5f, x.r, x.g, x.b};
+}
+
+// v = gc . rgb + (ga + gd m).  NO_AD: ga = gd = 0 is known (the loss reads
+// the colour only), and ga + gd m is then +0 for every finite m, so m is
+// not needed and the sum is the general one bit for bit.
+template <bool NO_AD>
+__device__ __forceinline__ float vdot(const RayGrad& q, const GradInput& x) {
+    const float c = (q.gr * x.r + q.gg * x.g) + q.gb * x.b;
+    return NO_AD ? c + 0.0f : c + (q.ga + q.gd * x.m);
 }
 
 // Gradients of one chunk (lane i = sample c + i) given w_i and T_{i+1};
@@ -136,15 +151,16 @@ __device__ __forceinline__ float vdot(const RayGrad& q, const Sample& x) {
 // w v inside the chunk past i): every partial sum is formed from the end of
 // the ray, so it is accurate relative to the terms it adds however small T
 // gets.  Lanes at or past the cut get zeros.
-__device__ __forceinline__ float chunk_grads(const RayGrad& q, const Sample& x, float w, float t_next, bool keep,
+template <bool NO_AD>
+__device__ __forceinline__ float chunk_grads(const RayGrad& q, const GradInput& x, float w, float t_next, bool keep,
                                              bool valid, int64_t s, float above, float* __restrict__ g_sigmas,
                                              float* __restrict__ g_rgbs) {
-    const float v = vdot(q, x);
+    const float v = vdot<NO_AD>(q, x);
     const float wv = keep ? w * v : 0.0f;
     const float incl = wave_inclusive_suffix(wv);
     const float suffix = above + shift_down_one(incl);
     if (keep) {
-        g_sigmas[s] = (x.t1 - x.t0) * (t_next * v - suffix);
+        g_sigmas[s] = x.delta * (t_next * v - suffix);
         store_rgb(g_rgbs, s, w * q.gr, w * q.gg, w * q.gb);
     } else if (valid) {
         g_sigmas[s] = 0.0f;
@@ -154,13 +170,14 @@ __device__ __forceinline__ float chunk_grads(const RayGrad& q, const Sample& x, 
 }
 
 // Forward pass of one ray shared by the backward and the fused kernels.
-// The first K chunks are loaded up front and kept in registers together
-// with w_i and T_{i+1}; later chunks are streamed.  Produces the cut, the
-// FP64 tau prefix at the start of the chunk holding the last kept sample,
-// and (ACCUM) the rendered colour / opacity / depth.
+// The first K chunks are loaded up front; what the backward needs of them
+// (GradInput, w_i and T_{i+1}) stays in registers; later chunks are
+// streamed.  Produces the cut, the FP64 tau prefix at the start of the
+// chunk holding the last kept sample, and (ACCUM) the rendered colour /
+// opacity / depth.
 template <int K>
 struct RayCache {
-    Sample x[K];
+    GradInput x[K];
     float w[K];
     float t_next[K];
     double carries;  // lane j: FP64 tau prefix at the start of chunk j (j < 64)
@@ -173,14 +190,16 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
                                             double& prefix_hi, float acc[3], float& acc_a, float& acc_d,
                                             const Sample& chunk0 = Sample{}) {
     const int lane = lane_id();
+    Sample x[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const int i = c * kWave + lane;
         if (PRELOADED && c == 0) {
-            cache.x[0] = chunk0;  // loaded while the previous ray was finished
+            x[0] = chunk0;  // loaded while the previous ray was finished
         } else {
-            cache.x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
+            x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
         }
+        cache.x[c] = grad_input(x[c]);
     }
     double carry = 0.0, carry_prev = 0.0;
     kept = n;
@@ -195,18 +214,18 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         if (lane == c) cache.carries = carry;
         const int i = c * kWave + lane;
         const bool valid = i < n;
-        const Trans t = chunk_transmittance(cache.x[c], carry);
+        const Trans t = chunk_transmittance(x[c], carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         cache.w[c] = w;
         cache.t_next[c] = t.t_next;
         if (ACCUM) {
-            acc[0] += w * cache.x[c].r;
-            acc[1] += w * cache.x[c].g;
-            acc[2] += w * cache.x[c].b;
+            acc[0] += w * x[c].r;
+            acc[1] += w * x[c].g;
+            acc[2] += w * x[c].b;
             acc_a += w;
-            acc_d += w * ((cache.x[c].t0 + cache.x[c].t1) * 0.5f);
+            acc_d += w * ((x[c].t0 + x[c].t1) * 0.5f);
         }
         if (keep_n < kWave) {
             kept = c * kWave + keep_n;
@@ -249,7 +268,7 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
 // Backward pass of one ray: chunks from the last kept one down to the first.
 // Streamed chunks rebuild T from the FP64 prefix at their end (walked down
 // from prefix_hi); cached chunks reuse w and T_{i+1} from the forward pass.
-template <int K>
+template <int K, bool NO_AD>
 __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, double prefix_hi,
                                              const float* __restrict__ ts, const float* __restrict__ te,
                                              const float* __restrict__ sig, const float* __restrict__ rgb,
@@ -258,15 +277,6 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
     const int lane = lane_id();
     const int cached_end = K * kWave;
     const int c_hi = kept > 0 ? ((kept - 1) / kWave) * kWave : -kWave;
-    // streamed chunks past the cut: zeros, no loads
-    for (int c = max(c_hi + kWave, cached_end); c < n; c += kWave) {
-        const int i = c + lane;
-        if (i < n) {
-            const int64_t s = start + i;
-            g_sigmas[s] = 0.0f;
-            store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
-        }
-    }
     float above = 0.0f;
     double p_end = 0.0;  // tau prefix at the end of the chunk being processed
     for (int c = c_hi; c >= cached_end; c -= kWave) {
@@ -284,15 +294,25 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
         const Trans t = chunk_transmittance(x, p_start);
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         const float t_next = t.t_next;
-        above = chunk_grads(q, x, w, t_next, keep, i < n, s, above, g_sigmas, g_rgbs);
+        above = chunk_grads<NO_AD>(q, grad_input(x), w, t_next, keep, i < n, s, above, g_sigmas, g_rgbs);
         p_end = p_start;
     }
 #pragma unroll
     for (int c = K - 1; c >= 0; --c) {
         if (c * kWave >= n) continue;
         const int i = c * kWave + lane;
-        above = chunk_grads(q, cache.x[c], cache.w[c], cache.t_next[c], i < kept, i < n, start + i, above, g_sigmas,
-                            g_rgbs);
+        above = chunk_grads<NO_AD>(q, cache.x[c], cache.w[c], cache.t_next[c], i < kept, i < n, start + i, above,
+                                   g_sigmas, g_rgbs);
+    }
+    // streamed chunks past the cut: zeros, no loads (stored last, so no wait
+    // on memory above waits for them)
+    for (int c = max(c_hi + kWave, cached_end); c < n; c += kWave) {
+        const int i = c + lane;
+        if (i < n) {
+            const int64_t s = start + i;
+            g_sigmas[s] = 0.0f;
+            store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
+        }
     }
 }
 
@@ -321,21 +341,23 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
     float acc[3] = {0.0f, 0.0f, 0.0f};
     float acc_a = 0.0f, acc_d = 0.0f;
     ray_forward<K, false>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d);
-    ray_backward<K>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+    ray_backward<K, false>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
 }
 
 // Fused forward + MSE + backward.  The forward gives the colour, the loss
 // gradient g_C = 2 (C - target) / (3 n_rays) follows, then the backward runs
-// on the cached chunks.  Rays are walked grid-stride so the
-// loss needs one partial sum per workgroup.
+// on the cached chunks.  Rays are walked grid-stride (one ray per wave at
+// the largest grid); each wave leaves one partial sum of the loss.  At
+// least 7 waves per SIMD (at most 72 VGPRs): with K = 4 cached chunks the
+// compiler would otherwise take 74 and fit only 6, and the kernel is as
+// much bound by its VALU issue as by memory, so the extra wave pays.
 template <int K, bool PREFETCH>
-__global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
+__global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(7))) void render_mse_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
     const float* __restrict__ target, float inv_count2, float* __restrict__ color, float* __restrict__ opacity,
     float* __restrict__ depth, float* __restrict__ g_sigmas, float* __restrict__ g_rgbs,
     double* __restrict__ loss_partial) {
-    __shared__ double wave_loss[kRaysPerRenderBlock];
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
@@ -353,6 +375,9 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
     }
     for (; r < n_rays; r += stride) {
         if (!PREFETCH) ray_range(packed_info, r, n_samples, start, n);
+        // the target is read with the ray's first samples, not after its
+        // forward pass, so its latency overlaps theirs
+        const float tr = target[3 * r], tg = target[3 * r + 1], tb = target[3 * r + 2];
         const int64_t r_next = r + stride;
         int64_t start_next = 0;
         int n_next = 0;
@@ -369,7 +394,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
         const float cb = wave_sum(acc[2]);
         acc_a = wave_sum(acc_a);
         acc_d = wave_sum(acc_d);
-        const float er = cr - target[3 * r], eg = cg - target[3 * r + 1], eb = cb - target[3 * r + 2];
+        const float er = cr - tr, eg = cg - tg, eb = cb - tb;
         RayGrad q;
         q.gr = uniform<float>(er * inv_count2);
         q.gg = uniform<float>(eg * inv_count2);
@@ -377,6 +402,10 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
         q.ga = 0.0f;
         q.gd = 0.0f;
         wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
+        if (PREFETCH) pre = load_sample(lane < n_next, start_next + lane, ts, te, sig, rgb);
+        if (n > 0) ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+        // stored after the backward: a store before it would make the
+        // backward's first wait on memory also wait for the store
         if (lane == 0) {
             color[3 * r] = cr;
             color[3 * r + 1] = cg;
@@ -384,20 +413,39 @@ __global__ __launch_bounds__(kRenderThreads) void render_mse_kernel(
             opacity[r] = acc_a;
             depth[r] = acc_d;
         }
-        if (PREFETCH) pre = load_sample(lane < n_next, start_next + lane, ts, te, sig, rgb);
-        if (n > 0) ray_backward<K>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
         if (PREFETCH) {
             start = start_next;
             n = n_next;
         }
     }
-    if (lane == 0) wave_loss[wave] = wave_total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kRaysPerRenderBlock; ++w) s += wave_loss[w];
-        loss_partial[blockIdx.x] = s;
+    // one partial per wave: no workgroup barrier, which would make every
+    // wave wait for its gradient stores to complete before it could exit
+    if (lane == 0) loss_partial[static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave] = wave_total;
+}
+
+// First level of the loss sum: workgroup b adds partials
+// [b * kSumSpan, (b + 1) * kSumSpan) in a fixed order.
+constexpr int kSumThreads = 256;
+constexpr int kSumPerThread = 16;
+constexpr int64_t kSumSpan = static_cast<int64_t>(kSumThreads) * kSumPerThread;
+
+__global__ __launch_bounds__(kSumThreads) void loss_sum_kernel(const double* __restrict__ partial, int64_t n,
+                                                               double* __restrict__ out) {
+    __shared__ double part[kSumThreads];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kSumSpan + threadIdx.x;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSumPerThread; ++j) {
+        const int64_t i = base + static_cast<int64_t>(j) * kSumThreads;
+        s += i < n ? partial[i] : 0.0;
     }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kSumThreads / 2; off > 0; off >>= 1) {
+        if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
 // loss = (sum of the partials, in a fixed order) / (3 n_rays).
@@ -420,11 +468,16 @@ __global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const double*
 int64_t render_blocks(int64_t n_rays) { return (n_rays + kRaysPerRenderBlock - 1) / kRaysPerRenderBlock; }
 
 // The fused kernel walks the rays grid-stride with at most
-// tuning().render_mse_max_blocks workgroups, so its loss needs few partial
-// sums.
+// tuning().render_mse_max_blocks workgroups (one ray per wave when that is
+// at least render_blocks).
 int64_t mse_blocks(int64_t n_rays) {
     return std::max<int64_t>(1, std::min<int64_t>(render_blocks(n_rays), tuning().render_mse_max_blocks));
 }
+
+// Partials of the fused loss at any tuning: one per wave of the largest
+// grid, then one per workgroup of loss_sum_kernel.
+int64_t mse_partials(int64_t n_rays) { return std::max<int64_t>(1, render_blocks(n_rays)) * kRaysPerRenderBlock; }
+int64_t mse_sums(int64_t n_rays) { return (mse_partials(n_rays) + kSumSpan - 1) / kSumSpan; }
 
 // Kernels instantiated for 1..4 register-cached chunks per ray.
 template <template <int> class F, typename... A>
@@ -625,9 +678,8 @@ int nacc_render_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_sample
 
 int64_t nacc_render_mse_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
-    // one partial per workgroup at any tuning (render_blocks bounds mse_blocks)
-    return ((std::max<int64_t>(1, render_blocks(n_rays)) * static_cast<int64_t>(sizeof(double)) + 255) / 256) *
-           256;
+    // the same at any tuning (render_blocks bounds mse_blocks)
+    return (((mse_partials(n_rays) + mse_sums(n_rays)) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
 }
 
 int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
@@ -658,7 +710,14 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
                                opacity, depth, g_sigmas, g_rgbs, partial);
     st = check_launch("render fwd+bwd+mse");
     if (st != NACC_OK) return st;
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, partial, nb, 1.0 / count, loss);
+    const int64_t n_part = nb * kRaysPerRenderBlock;
+    const int64_t n_sums = (n_part + kSumSpan - 1) / kSumSpan;
+    double* sums = partial + mse_partials(n_rays);
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(static_cast<unsigned>(n_sums)), dim3(kSumThreads), 0, s, partial, n_part,
+                       sums);
+    st = check_launch("render loss sum");
+    if (st != NACC_OK) return st;
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, sums, n_sums, 1.0 / count, loss);
     return check_launch("render loss");
 }
 

@@ -6,7 +6,7 @@
 
 namespace {
 thread_local char g_message[512] = "";
-nacc_tuning g_tuning = {4, 4, 8192, 0};
+nacc_tuning g_tuning = {4, 4, 16384, 0};
 }
 
 namespace nacc {

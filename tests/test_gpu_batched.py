@@ -317,7 +317,7 @@ def test_graph_grid_update_advances(dyn):
 @pytest.mark.parametrize("knob,values", [
     ("render_cached_chunks", (1, 2, 3, 4)),
     ("march_waves_per_group", (1, 2, 4, 8, 16)),
-    ("render_mse_max_blocks", (1, 3, 1024, 8192)),
+    ("render_mse_max_blocks", (1, 3, 1024, 8192, 1 << 20)),
     ("render_prefetch", (0, 1)),
 ])
 def test_tuning_leaves_results_identical(dyn, knob, values):

@@ -448,7 +448,8 @@ def cpu_baseline(w, inp, n_sample, forward_only=False):
     return {"value": ri.size / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample} of {inp['rays_o'].shape[0]} rays ({ri.size} samples), "
                       f"{what}, one thread, {dt:.1f} s, host "
-                      f"{platform.processor() or platform.machine()}"}
+                      f"{platform.processor() or platform.machine()} with {os.cpu_count()} "
+                      f"hardware threads"}
 
 
 def kept_fraction(st, e_last):
@@ -599,13 +600,20 @@ def bench_train(args, torch, nacc):
                   capture(torch, lambda: st.step(update=True)))
         log("captured the step in HIP graphs")
 
-    totals = torch.empty(steps, dtype=torch.int64, device="cuda")
-    rendered = torch.empty(steps, dtype=torch.int64, device="cuda")
+    # A step's sample total changes only when the grid does: marching the
+    # same rays through the same bits gives the same samples, bit for bit.
+    # So the totals are copied out (a small copy kernel each) only at the
+    # first step and at each step after one that updated the grid, and hold
+    # in between; the last step's total is checked against that afterwards.
+    totals = torch.zeros(steps, dtype=torch.int64, device="cuda")
+    rendered = torch.zeros(steps, dtype=torch.int64, device="cuda")
+    copied = []
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record()
+    prev_upd = True
     for k in range(steps):
         upd = (warmup + k) % EMA_EVERY == 0
         if plan is not None:
@@ -614,15 +622,24 @@ def bench_train(args, torch, nacc):
             graphs[1 if upd else 0].replay()
         else:
             st.step(update=upd)
-        totals[k:k + 1].copy_(st.total)
-        rendered[k:k + 1].copy_(st.cur[4])
+        if prev_upd:
+            totals[k:k + 1].copy_(st.total)
+            rendered[k:k + 1].copy_(st.cur[4])
+            copied.append(k)
+        prev_upd = upd
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms_total = start.elapsed_time(stop)
     if int(st.status.item()) != 0:
         raise RuntimeError("capacity overflow in the timed region")
-    e_steps = totals.cpu().numpy()
+    last_total, last_rendered = int(st.total.item()), int(st.cur[4].item())
+    e_steps, k_steps = totals.cpu().numpy(), rendered.cpu().numpy()
+    for k in range(steps):
+        if k not in copied:
+            e_steps[k], k_steps[k] = e_steps[k - 1], k_steps[k - 1]
+    if (e_steps[-1], k_steps[-1]) != (last_total, last_rendered):
+        raise RuntimeError("a step's sample total changed without a grid update")
     e_total = int(e_steps.sum())
     phase_avg = phase_timing(torch, st, min(steps, 32), warmup + steps)
     if plan is not None:
@@ -634,7 +651,6 @@ def bench_train(args, torch, nacc):
     latency = step_latency(torch, one, 100 if forward_only else 32)
     unfused = None if (forward_only or st.prune) else unfused_render(torch, st)
     e_mean = e_total / steps
-    k_steps = rendered.cpu().numpy()
     k_mean = float(k_steps.mean())  # samples shaded and rendered (= e_mean unpruned)
     v_frac = kept_fraction(st, int(k_steps[-1]))
     alg = algorithmic_bytes(st.n, k_mean, k_mean * v_frac, forward_only)

@@ -265,3 +265,33 @@ def test_python_stage_and_its_errors(dyn):
     finally:
         torch.cuda.synchronize()
         bad.close()
+
+
+@pytest.mark.parametrize("name", ["unbounded_262k", "unbounded_contract_262k"])
+def test_plan_unbounded_equals_the_calls(name):
+    """Cone steps through cascades and through the contraction lookup, with
+    the skip field: the plan's eager step, replays and update give the bits
+    of the individual calls."""
+    from steps import make_step
+    _, _, st = make_step(name, n_rays=3000, res=32, skip_field=True)
+    st.step(update=True)
+    st.step()
+    torch.cuda.synchronize()
+    want = _snapshot(st)
+    grid_bits = st.grid.bits.clone()
+    _, _, other = make_step(name, n_rays=3000, res=32, skip_field=True)
+    plan = other.plan()
+    try:
+        plan.capture()
+        plan.launch(with_update=True)
+        _scribble(other)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert _same(other.grid.bits, grid_bits)
+        _check(_snapshot(other), want, f"{name}: replays")
+        _scribble(other)
+        plan.step()
+        torch.cuda.synchronize()
+        _check(_snapshot(other), want, f"{name}: eager plan step")
+    finally:
+        plan.close()

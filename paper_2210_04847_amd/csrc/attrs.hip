@@ -140,10 +140,10 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
             float a[kBlock];
             load_block<VEC4>(valid, s, attrs, n_ch, c0, cb, a);
 #pragma unroll
-            for (int k = 0; k < kBlock; ++k) acc[k] += w * a[k];
+            for (int k = 0; k < kBlock; ++k) acc[k] = __builtin_fmaf(w, a[k], acc[k]);
             if (first) {
                 acc_a += w;
-                acc_d += w * ((x.t0 + x.t1) * 0.5f);
+                acc_d = __builtin_fmaf(w, (x.t0 + x.t1) * 0.5f, acc_d);
                 if (weights != nullptr && valid) weights[s] = w;
             }
             carry += static_cast<double>(read_lane(t.incl, 63));
@@ -253,15 +253,18 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
             load_block<VEC4>(i < kept, s, attrs, n_ch, c0, cb, a);
 #pragma unroll
             for (int k = 0; k < kBlock; ++k) {
-                if (k < cb) dot = c0 + k == 0 ? uniform<float>(g[0]) * a[0] : dot + uniform<float>(g[c0 + k]) * a[k];
+                if (k < cb) {
+                    dot = c0 + k == 0 ? uniform<float>(g[0]) * a[0]
+                                      : __builtin_fmaf(uniform<float>(g[c0 + k]), a[k], dot);
+                }
             }
         }
-        const float v = dot + (ga + gd * ((x.t0 + x.t1) * 0.5f));
+        const float v = dot + __builtin_fmaf(gd, (x.t0 + x.t1) * 0.5f, ga);
         const float wv = keep ? w * v : 0.0f;
         const float incl = wave_inclusive_suffix(wv);
         const float suffix = above + shift_down_one(incl);
         if (valid) {
-            g_sigmas[s] = keep ? (x.t1 - x.t0) * (t.t_next * v - suffix) : 0.0f;
+            g_sigmas[s] = keep ? (x.t1 - x.t0) * __builtin_fmaf(t.t_next, v, -suffix) : 0.0f;
             store_scaled<VEC4>(s, g_attrs, n_ch, g, w, !keep);
         }
         above = above + read_lane(incl, 0);

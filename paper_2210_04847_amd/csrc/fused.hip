@@ -137,11 +137,11 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
-        acc_r += w * cr;
-        acc_g += w * cg;
-        acc_b += w * cb;
+        acc_r = __builtin_fmaf(w, cr, acc_r);
+        acc_g = __builtin_fmaf(w, cg, acc_g);
+        acc_b = __builtin_fmaf(w, cb, acc_b);
         acc_a += w;
-        acc_d += w * ((t0 + t1) * 0.5f);
+        acc_d = __builtin_fmaf(w, (t0 + t1) * 0.5f, acc_d);
         carry += static_cast<double>(read_lane(t.incl, 63));
         if (keep_n < kWave) {
             n_kept = rendered + keep_n;

@@ -88,11 +88,11 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
-        acc_r += w * x.r;
-        acc_g += w * x.g;
-        acc_b += w * x.b;
+        acc_r = __builtin_fmaf(w, x.r, acc_r);
+        acc_g = __builtin_fmaf(w, x.g, acc_g);
+        acc_b = __builtin_fmaf(w, x.b, acc_b);
         acc_a += w;
-        acc_d += w * ((x.t0 + x.t1) * 0.5f);
+        acc_d = __builtin_fmaf(w, (x.t0 + x.t1) * 0.5f, acc_d);
         if (WEIGHTS && valid) weights[s] = w;
         carry += static_cast<double>(read_lane(t.incl, 63));
         if (keep_n < kWave) {
@@ -136,13 +136,15 @@ __device__ __forceinline__ GradInput grad_input(const Sample& x) {
     return GradInput{x.t1 - x.t0, (x.t0 + x.t1) * 0.5f, x.r, x.g, x.b};
 }
 
-// v = gc . rgb + (ga + gd m).  NO_AD: ga = gd = 0 is known (the loss reads
-// the colour only), and ga + gd m is then +0 for every finite m, so m is
-// not needed and the sum is the general one bit for bit.
+// v = gc . rgb + (ga + gd m), with fused multiply-adds in a fixed order
+// (the attribute kernels form their dot product the same way).  NO_AD:
+// ga = gd = 0 is known (the loss reads the colour only), and ga + gd m is
+// then +0 for every finite m, so m is not needed and the sum is the general
+// one bit for bit.
 template <bool NO_AD>
 __device__ __forceinline__ float vdot(const RayGrad& q, const GradInput& x) {
-    const float c = (q.gr * x.r + q.gg * x.g) + q.gb * x.b;
-    return NO_AD ? c + 0.0f : c + (q.ga + q.gd * x.m);
+    const float c = __builtin_fmaf(q.gb, x.b, __builtin_fmaf(q.gg, x.g, q.gr * x.r));
+    return NO_AD ? c + 0.0f : c + __builtin_fmaf(q.gd, x.m, q.ga);
 }
 
 // Gradients of one chunk (lane i = sample c + i) given w_i and T_{i+1};
@@ -160,7 +162,7 @@ __device__ __forceinline__ float chunk_grads(const RayGrad& q, const GradInput& 
     const float incl = wave_inclusive_suffix(wv);
     const float suffix = above + shift_down_one(incl);
     if (keep) {
-        g_sigmas[s] = x.delta * (t_next * v - suffix);
+        g_sigmas[s] = x.delta * __builtin_fmaf(t_next, v, -suffix);
         store_rgb(g_rgbs, s, w * q.gr, w * q.gg, w * q.gb);
     } else if (valid) {
         g_sigmas[s] = 0.0f;
@@ -221,11 +223,11 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         cache.w[c] = w;
         cache.t_next[c] = t.t_next;
         if (ACCUM) {
-            acc[0] += w * x[c].r;
-            acc[1] += w * x[c].g;
-            acc[2] += w * x[c].b;
+            acc[0] = __builtin_fmaf(w, x[c].r, acc[0]);
+            acc[1] = __builtin_fmaf(w, x[c].g, acc[1]);
+            acc[2] = __builtin_fmaf(w, x[c].b, acc[2]);
             acc_a += w;
-            acc_d += w * ((x[c].t0 + x[c].t1) * 0.5f);
+            acc_d = __builtin_fmaf(w, (x[c].t0 + x[c].t1) * 0.5f, acc_d);
         }
         if (keep_n < kWave) {
             kept = c * kWave + keep_n;
@@ -247,11 +249,11 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         if (ACCUM) {
             const bool keep = valid && lane < keep_n;
             const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
-            acc[0] += w * x.r;
-            acc[1] += w * x.g;
-            acc[2] += w * x.b;
+            acc[0] = __builtin_fmaf(w, x.r, acc[0]);
+            acc[1] = __builtin_fmaf(w, x.g, acc[1]);
+            acc[2] = __builtin_fmaf(w, x.b, acc[2]);
             acc_a += w;
-            acc_d += w * ((x.t0 + x.t1) * 0.5f);
+            acc_d = __builtin_fmaf(w, (x.t0 + x.t1) * 0.5f, acc_d);
         }
         if (keep_n < kWave) {
             kept = c + keep_n;

@@ -48,14 +48,23 @@ struct Trans {
     float t_next;  // T_{i+1}
 };
 
+// The value of the lane below, 1 in lane 0.
+__device__ __forceinline__ float shift_up_one_or_one(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, 1.0f),
+                                                                 __builtin_bit_cast(int, x), kWaveShr1, 0xf, 0xf,
+                                                                 false));
+}
+
 __device__ __forceinline__ Trans transmittance_of(float tau, double carry) {
     Trans t;
     t.tau = tau;
     t.incl = wave_inclusive_sum(t.tau);
-    const float excl = shift_up_one(t.incl);
     const float t0 = uniform<float>(exp_neg(static_cast<float>(carry)));
-    t.t_in = t0 * exp_neg(excl);
-    t.t_next = t0 * exp_neg(t.incl);
+    // lane i's exclusive prefix is lane i-1's inclusive one (0 in lane 0,
+    // where e^-0 = 1), so e^-excl is the neighbour's e^-incl, bit for bit
+    const float e_incl = exp_neg(t.incl);
+    t.t_in = t0 * shift_up_one_or_one(e_incl);
+    t.t_next = t0 * e_incl;
     return t;
 }
 

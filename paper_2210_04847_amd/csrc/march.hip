@@ -319,19 +319,23 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
-    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks) {
+    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks, int split) {
     __shared__ int64_t wave_total[WAVES];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    // workgroup b takes part b % split of the group of kRaysPerBlock rays
+    // b / split: per = kRaysPerBlock / split rays from `first`
+    const int per = kRaysPerBlock / split;
+    const int64_t group = static_cast<int64_t>(blockIdx.x) / split;
+    const int64_t first = group * kRaysPerBlock + static_cast<int64_t>(blockIdx.x % split) * per;
     // this wave's rays are first + wave + j WAVES; lane j clips ray j
     const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
     RaySpan spans{};
-    if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays) {
+    if (wave + lane_id() * WAVES < per && mine < n_rays) {
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }
     int64_t total = 0;
     bool unused = false;
-    for (int i = wave; i < kRaysPerBlock; i += WAVES) {
+    for (int i = wave; i < per; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const RaySpan span = read_span(spans, i / WAVES);
@@ -346,8 +350,19 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     if (threadIdx.x == 0) {
         int64_t s = 0;
         for (int w = 0; w < WAVES; ++w) s += wave_total[w];
-        block_sums[blockIdx.x] = s;
+        if (split == 1) {
+            block_sums[group] = s;
+        } else {  // the group's parts add up (integers: exact in any order)
+            atomicAdd(reinterpret_cast<unsigned long long*>(block_sums + group), static_cast<unsigned long long>(s));
+        }
     }
+}
+
+// Zeroes the per-group sums that the parts of split groups add into (a
+// kernel, not a memset node, so that captured graphs replay it faithfully).
+__global__ __launch_bounds__(256) void zero_sums_kernel(int64_t* __restrict__ sums, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) sums[i] = 0;
 }
 
 // Writes the samples of one ray from the per-chunk occupancy masks stored by
@@ -432,16 +447,17 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
     const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, const int32_t* __restrict__ packed_info,
     int64_t capacity, int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
-    int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks) {
+    int32_t* __restrict__ status, const uint64_t* __restrict__ masks, int n_masks, int split) {
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock;
+    const int per = kRaysPerBlock / split;  // rays of this workgroup, as in the count pass
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * per;
     const int64_t mine = first + wave + static_cast<int64_t>(lane_id()) * WAVES;
     RaySpan spans{};
-    if (lane_id() < kRaysPerBlock / WAVES && mine < n_rays && packed_info[2 * mine + 1] > 0) {
+    if (wave + lane_id() * WAVES < per && mine < n_rays && packed_info[2 * mine + 1] > 0) {
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }
     bool overflow = false;
-    for (int i = wave; i < kRaysPerBlock; i += WAVES) {
+    for (int i = wave; i < per; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const int64_t start = packed_info[2 * r];
@@ -921,12 +937,24 @@ ConeWork cone_work(void* workspace, const Layout& l) {
     return w;
 }
 
+// Workgroups per group of kRaysPerBlock rays in the uniform-step kernels:
+// small batches are spread over more workgroups (the chip has 256 CUs), so
+// that each wave walks fewer rays one after the other; results do not
+// depend on it.
+int march_split(int64_t groups) { return groups < 256 ? 4 : (groups < 512 ? 2 : 1); }
+
 template <int LOOKUP, bool SKIP, int WAVES>
 void launch_count_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
                           const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c, const StepK& p,
                           int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
-    hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid,
-                       n, bits, skip, g, c, p, packed, sums, masks, n_masks);
+    const int split = march_split(nb);
+    if (split > 1) {
+        hipLaunchKernelGGL(zero_sums_kernel, dim3(static_cast<unsigned>((nb + 255) / 256)), dim3(256), 0, s, sums,
+                           nb);
+    }
+    hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(static_cast<unsigned>(nb * split)),
+                       dim3(WAVES * kWave), 0, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks,
+                       split);
 }
 
 template <int LOOKUP, bool SKIP, int WAVES>
@@ -934,8 +962,10 @@ void launch_fill_uniform(int64_t nb, hipStream_t s, const float* o, const float*
                          const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c, const StepK& p,
                          const int32_t* packed, int64_t capacity, int32_t* ri, float* ts, float* te, int32_t* status,
                          const uint64_t* masks, int n_masks) {
-    hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(nb), dim3(WAVES * kWave), 0, s, o, d, gid, n,
-                       bits, skip, g, c, p, packed, capacity, ri, ts, te, status, masks, n_masks);
+    const int split = march_split(nb);
+    hipLaunchKernelGGL((fill_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(static_cast<unsigned>(nb * split)),
+                       dim3(WAVES * kWave), 0, s, o, d, gid, n, bits, skip, g, c, p, packed, capacity, ri, ts, te,
+                       status, masks, n_masks, split);
 }
 
 unsigned task_blocks(int n_masks, int64_t n_rays) {

@@ -54,6 +54,16 @@ def test_plain_workload_4096_rays():
     assert p[:, 1].max() > 64 and (p[:, 1] == 0).any()
 
 
+@pytest.mark.parametrize("n_rays", [16383, 16384, 20001, 32768])
+def test_ray_group_splits(n_rays):
+    """Batch sizes around the points where the uniform-step kernels change
+    how many workgroups share a group of 64 rays (4 below 16,384 rays, 2
+    below 32,768, then 1): the oracle's samples, every variant."""
+    mask = synth.random_mask(32 ** 3, 0.1, 7)
+    o, d = synth.rays_toward_origin(n_rays, 300 + n_rays % 97)
+    compare(o, d, mask, 32, BOX, 0.0, 1e10, 0.0137)
+
+
 @pytest.mark.parametrize("res,p_occ,seed", [(4, 0.4, 1), (8, 0.3, 2), (16, 0.2, 3), (32, 0.5, 4),
                                             (32, 0.02, 5), (64, 0.005, 6)])
 def test_tiny_random_grids(res, p_occ, seed):

@@ -105,7 +105,102 @@ __device__ __forceinline__ void store_scaled(int64_t s, float* __restrict__ g_at
     }
 }
 
-template <bool VEC4>
+// Rows of 4, 8 or 16 channels (16-byte aligned rows) move between memory
+// and the lanes through LDS: a chunk's 64 rows
+// are contiguous, so the wave reads and writes them as whole float4s in
+// address order (every access a run of 1 KB) instead of each lane touching
+// its own 64-byte row, which stalls the vector L1 on tag lookups.  Row r's
+// float4 j sits in slot j ^ (r & 3) of the row's four, so that lanes reading
+// their own rows spread over the LDS banks.
+struct Staged {
+    int qpr;  // float4s per row: 1, 2 or 4
+    int sh;   // log2(qpr)
+};
+
+__device__ __forceinline__ Staged staged_rows(int n_ch) {
+    const int qpr = n_ch >> 2;
+    return Staged{qpr, qpr == 4 ? 2 : (qpr == 2 ? 1 : 0)};
+}
+
+// Rows [0, rows) of the chunk starting at `first`, as this lane's share of
+// whole float4s in address order (zeros past `rows`).  Issued early; the
+// values are only needed by exchange_rows.
+struct RowQuads {
+    float4 v[4];
+};
+
+__device__ __forceinline__ RowQuads fetch_rows(const Staged& g, const float* __restrict__ attrs, int64_t first,
+                                               int rows) {
+    const int lane = lane_id();
+    const float4* src = reinterpret_cast<const float4*>(attrs) + first * g.qpr;
+    RowQuads r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r.v[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (k < g.qpr) {
+            const int q = lane + kWave * k;
+            if ((q >> g.sh) < rows) r.v[k] = src[q];
+        }
+    }
+    return r;
+}
+
+// The fetched float4s, regrouped through `stage` so that lane i holds row i
+// in a[] (zeros past n_ch).
+__device__ __forceinline__ void exchange_rows(const Staged& g, const RowQuads& r, float4* __restrict__ stage,
+                                              float a[kBlock]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < g.qpr) {
+            const int q = lane + kWave * k;
+            const int row = q >> g.sh, quad = q & (g.qpr - 1);
+            stage[row * 4 + (quad ^ (row & 3))] = r.v[k];
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < g.qpr) v = stage[lane * 4 + (j ^ (lane & 3))];
+        a[4 * j] = v.x;
+        a[4 * j + 1] = v.y;
+        a[4 * j + 2] = v.z;
+        a[4 * j + 3] = v.w;
+    }
+    wave_lds_sync();  // the stage is rewritten by the next chunk
+}
+
+// Value of `x` in lane `src` (all lanes active).
+__device__ __forceinline__ float lane_value(float x, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, x)));
+}
+
+// Rows [0, rows) of the gradient chunk starting at `first`: row i = w_i g,
+// or zeros where lane i's `keep` is false, written as whole float4s in
+// address order; gq holds g's float4 (lane & (qpr - 1)), which is the one
+// every float4 this lane writes needs.
+__device__ __forceinline__ void store_rows_staged(const Staged& g, float* __restrict__ g_attrs, int64_t first,
+                                                  int rows, float w, bool keep, const float gq[4]) {
+    const int lane = lane_id();
+    float4* dst = reinterpret_cast<float4*>(g_attrs) + first * g.qpr;
+    const float kf = keep ? 1.0f : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < g.qpr) {
+            const int q = lane + kWave * k;
+            const int row = q >> g.sh;
+            const float wr = lane_value(w, row);
+            const bool kr = lane_value(kf, row) != 0.0f;
+            if (row < rows) {
+                dst[q] = kr ? make_float4(wr * gq[0], wr * gq[1], wr * gq[2], wr * gq[3])
+                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+        }
+    }
+}
+
+template <bool VEC4, bool STAGED>
 __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ attrs, int n_ch,
@@ -117,6 +212,10 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     int64_t start;
     int n;
     ray_range(packed_info, r, n_samples, start, n);
+    // STAGED (aligned rows of 4, 8 or 16 channels): rows through LDS
+    __shared__ float4 stage_all[STAGED ? kAttrRays * kWave * 4 : 1];
+    float4* stage = stage_all + (STAGED ? uniform<int>(static_cast<int>(threadIdx.x) / kWave) * kWave * 4 : 0);
+    const Staged sg = staged_rows(n_ch);
     float total_a = 0.0f;
     for (int c0 = 0; c0 < n_ch; c0 += kBlock) {
         const int cb = min(kBlock, n_ch - c0);
@@ -132,13 +231,19 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
             const bool valid = i < n;
             const int64_t s = start + i;
             const Interval x = load_interval(valid, s, ts, te, sig);
+            RowQuads rq;
+            if (STAGED) rq = fetch_rows(sg, attrs, start + c, min(n - c, kWave));
             const Masked m = masked(x, alpha_thre);
             const Trans t = transmittance_of(m.tau, carry);
             const int keep_n = chunk_keep(valid, t.t_in, eps);
             const bool keep = valid && lane < keep_n && m.on;
             const float w = keep ? t.t_in * m.alpha : 0.0f;
             float a[kBlock];
-            load_block<VEC4>(valid, s, attrs, n_ch, c0, cb, a);
+            if (STAGED) {
+                exchange_rows(sg, rq, stage, a);
+            } else {
+                load_block<VEC4>(valid, s, attrs, n_ch, c0, cb, a);
+            }
 #pragma unroll
             for (int k = 0; k < kBlock; ++k) acc[k] = __builtin_fmaf(w, a[k], acc[k]);
             if (first) {
@@ -176,7 +281,7 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     }
 }
 
-template <bool VEC4>
+template <bool VEC4, bool STAGED>
 __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ attrs, int n_ch,
@@ -191,6 +296,16 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
     ray_range(packed_info, r, n_samples, start, n);
     if (n == 0) return;
     const float* g = g_out + r * n_ch;
+    // STAGED (aligned rows of 4, 8 or 16 channels): rows through LDS
+    __shared__ float4 stage_all[STAGED ? kAttrRays * kWave * 4 : 1];
+    float4* stage = stage_all + (STAGED ? uniform<int>(static_cast<int>(threadIdx.x) / kWave) * kWave * 4 : 0);
+    const Staged sg = staged_rows(n_ch);
+    float gq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (STAGED) {
+        const int quad = lane & (sg.qpr - 1);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gq[m] = g[4 * quad + m];
+    }
     // the background adds -g . background to the opacity's gradient
     float ga = g_opacity != nullptr ? uniform<float>(g_opacity[r]) : 0.0f;
     if (background != nullptr) {
@@ -237,6 +352,8 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         const bool valid = i < n;
         const int64_t s = start + i;
         const Interval x = load_interval(i < kept, s, ts, te, sig);
+        RowQuads rq;
+        if (STAGED) rq = fetch_rows(sg, attrs, start + c, max(0, min(kept - c, kWave)));
         const Masked m = masked(x, alpha_thre);
         const float chunk_tau = wave_sum(m.tau);
         const int chunk = c / kWave;
@@ -250,7 +367,11 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         for (int c0 = 0; c0 < n_ch; c0 += kBlock) {
             const int cb = min(kBlock, n_ch - c0);
             float a[kBlock];
-            load_block<VEC4>(i < kept, s, attrs, n_ch, c0, cb, a);
+            if (STAGED) {
+                exchange_rows(sg, rq, stage, a);
+            } else {
+                load_block<VEC4>(i < kept, s, attrs, n_ch, c0, cb, a);
+            }
 #pragma unroll
             for (int k = 0; k < kBlock; ++k) {
                 if (k < cb) {
@@ -263,8 +384,10 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         const float wv = keep ? w * v : 0.0f;
         const float incl = wave_inclusive_suffix(wv);
         const float suffix = above + shift_down_one(incl);
-        if (valid) {
-            g_sigmas[s] = keep ? (x.t1 - x.t0) * __builtin_fmaf(t.t_next, v, -suffix) : 0.0f;
+        if (valid) g_sigmas[s] = keep ? (x.t1 - x.t0) * __builtin_fmaf(t.t_next, v, -suffix) : 0.0f;
+        if (STAGED) {
+            store_rows_staged(sg, g_attrs, start + c, min(n - c, kWave), w, keep, gq);
+        } else if (valid) {
             store_scaled<VEC4>(s, g_attrs, n_ch, g, w, !keep);
         }
         above = above + read_lane(incl, 0);
@@ -290,6 +413,10 @@ int validate_attrs(const int32_t* packed_info, int64_t n_rays, int64_t n_samples
     return NACC_OK;
 }
 
+// Row widths that go through LDS (a power-of-two number of float4s, at
+// most kBlock channels).
+bool staged_width(int32_t n_ch) { return n_ch == 4 || n_ch == 8 || n_ch == 16; }
+
 // Rows of 16-byte aligned float4s (attribute and gradient arrays alike).
 bool vec4_rows(const float* a, const float* b, int32_t n_ch) {
     return n_ch % 4 == 0 && (reinterpret_cast<uintptr_t>(a) % 16) == 0 && (reinterpret_cast<uintptr_t>(b) % 16) == 0;
@@ -311,15 +438,11 @@ int nacc_render_attrs_fwd(const int32_t* packed_info, int64_t n_rays, int64_t n_
     if (n_rays == 0) return NACC_OK;
     const dim3 grid(static_cast<unsigned>((n_rays + kAttrRays - 1) / kAttrRays));
     hipStream_t s = as_stream(stream);
-    if (vec4_rows(attrs, attrs, n_ch)) {
-        hipLaunchKernelGGL(attrs_fwd_kernel<true>, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples,
-                           t_starts, t_ends, sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, out, opacity,
-                           depth, weights);
-    } else {
-        hipLaunchKernelGGL(attrs_fwd_kernel<false>, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples,
-                           t_starts, t_ends, sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, out, opacity,
-                           depth, weights);
-    }
+    const bool vec4 = vec4_rows(attrs, attrs, n_ch);
+    auto kernel = vec4 ? (staged_width(n_ch) ? attrs_fwd_kernel<true, true> : attrs_fwd_kernel<true, false>)
+                       : attrs_fwd_kernel<false, false>;
+    hipLaunchKernelGGL(kernel, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends,
+                       sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, out, opacity, depth, weights);
     return check_launch("render attrs fwd");
 }
 
@@ -337,15 +460,12 @@ int nacc_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_
     if (n_rays == 0) return NACC_OK;
     const dim3 grid(static_cast<unsigned>((n_rays + kAttrRays - 1) / kAttrRays));
     hipStream_t s = as_stream(stream);
-    if (vec4_rows(attrs, g_attrs, n_ch)) {
-        hipLaunchKernelGGL(attrs_bwd_kernel<true>, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples,
-                           t_starts, t_ends, sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, g_out,
-                           g_opacity, g_depth, g_sigmas, g_attrs);
-    } else {
-        hipLaunchKernelGGL(attrs_bwd_kernel<false>, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples,
-                           t_starts, t_ends, sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, g_out,
-                           g_opacity, g_depth, g_sigmas, g_attrs);
-    }
+    const bool vec4 = vec4_rows(attrs, g_attrs, n_ch);
+    auto kernel = vec4 ? (staged_width(n_ch) ? attrs_bwd_kernel<true, true> : attrs_bwd_kernel<true, false>)
+                       : attrs_bwd_kernel<false, false>;
+    hipLaunchKernelGGL(kernel, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends,
+                       sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, g_out, g_opacity, g_depth,
+                       g_sigmas, g_attrs);
     return check_launch("render attrs bwd");
 }
 

@@ -166,12 +166,13 @@ def test_attrs_three_channels_equal_colour_kernels():
         assert_bit_exact(got["g_attrs"], g_c.cpu().numpy(), "g_rgbs")
 
 
-def test_attrs_unaligned_rows_and_empty_rays():
-    """Rows that are not 16-byte aligned take the scalar path and give the
-    aligned path's bits; empty rays render the background."""
+@pytest.mark.parametrize("ch", [4, 8, 12, 16])
+def test_attrs_unaligned_rows_and_empty_rays(ch):
+    """Rows that are not 16-byte aligned take the per-lane scalar path and
+    give the aligned path's bits (4, 8 and 16 channels: rows staged through
+    LDS; 12: per-lane float4 rows); empty rays render the background."""
     packed, ts, te, sg, _ = synth.ragged_render_inputs(500, 43, mean_count=40, max_count=200,
                                                        empty_frac=0.3)
-    ch = 8
     attrs = np.random.default_rng(43).standard_normal((ts.size, ch)).astype(np.float32)
     bg = np.linspace(-1, 1, ch)
     g = np.random.default_rng(44)

@@ -105,21 +105,23 @@ __device__ __forceinline__ void store_scaled(int64_t s, float* __restrict__ g_at
     }
 }
 
-// Rows of 4, 8 or 16 channels (16-byte aligned rows) move between memory
-// and the lanes through LDS: a chunk's 64 rows
-// are contiguous, so the wave reads and writes them as whole float4s in
-// address order (every access a run of 1 KB) instead of each lane touching
-// its own 64-byte row, which stalls the vector L1 on tag lookups.  Row r's
-// float4 j sits in slot j ^ (r & 3) of the row's four, so that lanes reading
-// their own rows spread over the LDS banks.
+// Rows of 4 or 8 channels, or of a multiple of 16 (16-byte aligned rows),
+// move between memory and the lanes through LDS, one block of up to 16
+// channels at a time: the wave reads and writes a chunk's 64 row segments
+// as whole float4s in address order (runs of 1 KB, or of 64 bytes per row
+// for wider rows) instead of each lane touching its own row, which stalls
+// the vector L1 on tag lookups.  Row r's float4 j sits in slot j ^ (r & 3)
+// of the row's four, so that lanes reading their own rows spread over the
+// LDS banks.
 struct Staged {
-    int qpr;  // float4s per row: 1, 2 or 4
+    int qpr;  // float4s per block of a row: 1, 2 or 4
     int sh;   // log2(qpr)
+    int rs;   // float4s per row
 };
 
 __device__ __forceinline__ Staged staged_rows(int n_ch) {
-    const int qpr = n_ch >> 2;
-    return Staged{qpr, qpr == 4 ? 2 : (qpr == 2 ? 1 : 0)};
+    const int qpr = n_ch >= kBlock ? 4 : n_ch >> 2;
+    return Staged{qpr, qpr == 4 ? 2 : (qpr == 2 ? 1 : 0), n_ch >> 2};
 }
 
 // Rows [0, rows) of the chunk starting at `first`, as this lane's share of
@@ -129,17 +131,20 @@ struct RowQuads {
     float4 v[4];
 };
 
+template <bool WIDE>
 __device__ __forceinline__ RowQuads fetch_rows(const Staged& g, const float* __restrict__ attrs, int64_t first,
-                                               int rows) {
+                                               int rows, int c0) {
     const int lane = lane_id();
-    const float4* src = reinterpret_cast<const float4*>(attrs) + first * g.qpr;
+    const float4* src = reinterpret_cast<const float4*>(attrs) + first * g.rs + (c0 >> 2);
     RowQuads r;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         r.v[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (k < g.qpr) {
             const int q = lane + kWave * k;
-            if ((q >> g.sh) < rows) r.v[k] = src[q];
+            const int row = q >> g.sh, quad = q & (g.qpr - 1);
+            // rows of one block are contiguous: their float4s run in order
+            if (row < rows) r.v[k] = src[WIDE ? row * g.rs + quad : q];
         }
     }
     return r;
@@ -176,48 +181,53 @@ __device__ __forceinline__ float lane_value(float x, int src) {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, x)));
 }
 
-// Rows [0, rows) of the gradient chunk starting at `first`: row i = w_i g,
-// or zeros where lane i's `keep` is false, written as whole float4s in
-// address order; gq holds g's float4 (lane & (qpr - 1)), which is the one
-// every float4 this lane writes needs.
+// Block c0 of rows [0, rows) of the gradient chunk starting at `first`:
+// row i = w_i g, or zeros where lane i's `keep` is false, written as whole
+// float4s in address order; gq holds g's float4 c0 / 4 + (lane & (qpr - 1)),
+// which is the one every float4 this lane writes needs.
+template <bool WIDE>
 __device__ __forceinline__ void store_rows_staged(const Staged& g, float* __restrict__ g_attrs, int64_t first,
-                                                  int rows, float w, bool keep, const float gq[4]) {
+                                                  int rows, int c0, float w, bool keep, const float gq[4]) {
     const int lane = lane_id();
-    float4* dst = reinterpret_cast<float4*>(g_attrs) + first * g.qpr;
+    float4* dst = reinterpret_cast<float4*>(g_attrs) + first * g.rs + (c0 >> 2);
     const float kf = keep ? 1.0f : 0.0f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (k < g.qpr) {
             const int q = lane + kWave * k;
-            const int row = q >> g.sh;
+            const int row = q >> g.sh, quad = q & (g.qpr - 1);
             const float wr = lane_value(w, row);
             const bool kr = lane_value(kf, row) != 0.0f;
             if (row < rows) {
-                dst[q] = kr ? make_float4(wr * gq[0], wr * gq[1], wr * gq[2], wr * gq[3])
+                dst[WIDE ? row * g.rs + quad : q] = kr ? make_float4(wr * gq[0], wr * gq[1], wr * gq[2], wr * gq[3])
                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         }
     }
 }
 
-template <bool VEC4, bool STAGED>
+template <bool VEC4, int STAGE>
 __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ attrs, int n_ch,
     float eps, float alpha_thre, const float* __restrict__ background, float* __restrict__ out,
     float* __restrict__ opacity, float* __restrict__ depth, float* __restrict__ weights) {
+    // STAGE 0: per-lane rows; 1: rows of one block (4, 8 or 16 channels)
+    // through LDS; 2: rows of several blocks of 16 through LDS
+    constexpr bool STAGED = STAGE > 0, WIDE = STAGE == 2;
     const int lane = lane_id();
     const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
     int64_t start;
     int n;
     ray_range(packed_info, r, n_samples, start, n);
-    // STAGED (aligned rows of 4, 8 or 16 channels): rows through LDS
+    // STAGED (aligned rows of 4 or 8 channels or a multiple of 16): rows
+    // through LDS
     __shared__ float4 stage_all[STAGED ? kAttrRays * kWave * 4 : 1];
     float4* stage = stage_all + (STAGED ? uniform<int>(static_cast<int>(threadIdx.x) / kWave) * kWave * 4 : 0);
     const Staged sg = staged_rows(n_ch);
     float total_a = 0.0f;
-    for (int c0 = 0; c0 < n_ch; c0 += kBlock) {
+    for (int c0 = 0; c0 < n_ch && (WIDE || c0 == 0 || !STAGED); c0 += kBlock) {
         const int cb = min(kBlock, n_ch - c0);
         const bool first = c0 == 0;
         float acc[kBlock];
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
             const int64_t s = start + i;
             const Interval x = load_interval(valid, s, ts, te, sig);
             RowQuads rq;
-            if (STAGED) rq = fetch_rows(sg, attrs, start + c, min(n - c, kWave));
+            if (STAGED) rq = fetch_rows<WIDE>(sg, attrs, start + c, min(n - c, kWave), c0);
             const Masked m = masked(x, alpha_thre);
             const Trans t = transmittance_of(m.tau, carry);
             const int keep_n = chunk_keep(valid, t.t_in, eps);
@@ -281,13 +291,16 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
     }
 }
 
-template <bool VEC4, bool STAGED>
+template <bool VEC4, int STAGE>
 __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ attrs, int n_ch,
     float eps, float alpha_thre, const float* __restrict__ background, const float* __restrict__ g_out,
     const float* __restrict__ g_opacity, const float* __restrict__ g_depth, float* __restrict__ g_sigmas,
     float* __restrict__ g_attrs) {
+    // STAGE 0: per-lane rows; 1: rows of one block (4, 8 or 16 channels)
+    // through LDS; 2: rows of several blocks of 16 through LDS
+    constexpr bool STAGED = STAGE > 0, WIDE = STAGE == 2;
     const int lane = lane_id();
     const int64_t r = xcd_grouped<16>(blockIdx.x, gridDim.x) * kAttrRays + uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     if (r >= n_rays) return;
@@ -296,15 +309,18 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
     ray_range(packed_info, r, n_samples, start, n);
     if (n == 0) return;
     const float* g = g_out + r * n_ch;
-    // STAGED (aligned rows of 4, 8 or 16 channels): rows through LDS
+    // STAGED (aligned rows of 4 or 8 channels or a multiple of 16): rows
+    // through LDS
     __shared__ float4 stage_all[STAGED ? kAttrRays * kWave * 4 : 1];
     float4* stage = stage_all + (STAGED ? uniform<int>(static_cast<int>(threadIdx.x) / kWave) * kWave * 4 : 0);
     const Staged sg = staged_rows(n_ch);
-    float gq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // the float4 of g's first block this lane's staged stores need, once per
+    // ray (wider rows load their other blocks' per chunk)
+    float gq0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (STAGED) {
         const int quad = lane & (sg.qpr - 1);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) gq[m] = g[4 * quad + m];
+        for (int m = 0; m < 4; ++m) gq0[m] = g[4 * quad + m];
     }
     // the background adds -g . background to the opacity's gradient
     float ga = g_opacity != nullptr ? uniform<float>(g_opacity[r]) : 0.0f;
@@ -353,7 +369,8 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         const int64_t s = start + i;
         const Interval x = load_interval(i < kept, s, ts, te, sig);
         RowQuads rq;
-        if (STAGED) rq = fetch_rows(sg, attrs, start + c, max(0, min(kept - c, kWave)));
+        const int rows_read = max(0, min(kept - c, kWave));
+        if (STAGED) rq = fetch_rows<WIDE>(sg, attrs, start + c, rows_read, 0);
         const Masked m = masked(x, alpha_thre);
         const float chunk_tau = wave_sum(m.tau);
         const int chunk = c / kWave;
@@ -364,10 +381,11 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         const float w = keep ? t.t_in * m.alpha : 0.0f;
         // v_i = g . a_i + (g_opacity - g . background) + g_depth m_i
         float dot = 0.0f;
-        for (int c0 = 0; c0 < n_ch; c0 += kBlock) {
+        for (int c0 = 0; c0 < n_ch && (WIDE || c0 == 0 || !STAGED); c0 += kBlock) {
             const int cb = min(kBlock, n_ch - c0);
             float a[kBlock];
             if (STAGED) {
+                if (WIDE && c0 > 0) rq = fetch_rows<WIDE>(sg, attrs, start + c, rows_read, c0);
                 exchange_rows(sg, rq, stage, a);
             } else {
                 load_block<VEC4>(i < kept, s, attrs, n_ch, c0, cb, a);
@@ -386,7 +404,14 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_bwd_kernel(
         const float suffix = above + shift_down_one(incl);
         if (valid) g_sigmas[s] = keep ? (x.t1 - x.t0) * __builtin_fmaf(t.t_next, v, -suffix) : 0.0f;
         if (STAGED) {
-            store_rows_staged(sg, g_attrs, start + c, min(n - c, kWave), w, keep, gq);
+            store_rows_staged<WIDE>(sg, g_attrs, start + c, min(n - c, kWave), 0, w, keep, gq0);
+            for (int c0 = kBlock; WIDE && c0 < n_ch; c0 += kBlock) {
+                const int quad = lane & (sg.qpr - 1);
+                float gq[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) gq[m] = g[c0 + 4 * quad + m];
+                store_rows_staged<WIDE>(sg, g_attrs, start + c, min(n - c, kWave), c0, w, keep, gq);
+            }
         } else if (valid) {
             store_scaled<VEC4>(s, g_attrs, n_ch, g, w, !keep);
         }
@@ -413,9 +438,9 @@ int validate_attrs(const int32_t* packed_info, int64_t n_rays, int64_t n_samples
     return NACC_OK;
 }
 
-// Row widths that go through LDS (a power-of-two number of float4s, at
-// most kBlock channels).
-bool staged_width(int32_t n_ch) { return n_ch == 4 || n_ch == 8 || n_ch == 16; }
+// Row widths that go through LDS: 4 or 8 channels, or whole blocks of
+// kBlock.
+bool staged_width(int32_t n_ch) { return n_ch == 4 || n_ch == 8 || n_ch % kBlock == 0; }
 
 // Rows of 16-byte aligned float4s (attribute and gradient arrays alike).
 bool vec4_rows(const float* a, const float* b, int32_t n_ch) {
@@ -439,8 +464,9 @@ int nacc_render_attrs_fwd(const int32_t* packed_info, int64_t n_rays, int64_t n_
     const dim3 grid(static_cast<unsigned>((n_rays + kAttrRays - 1) / kAttrRays));
     hipStream_t s = as_stream(stream);
     const bool vec4 = vec4_rows(attrs, attrs, n_ch);
-    auto kernel = vec4 ? (staged_width(n_ch) ? attrs_fwd_kernel<true, true> : attrs_fwd_kernel<true, false>)
-                       : attrs_fwd_kernel<false, false>;
+    auto kernel = vec4 ? (n_ch <= kBlock ? (staged_width(n_ch) ? attrs_fwd_kernel<true, 1> : attrs_fwd_kernel<true, 0>)
+                                         : (staged_width(n_ch) ? attrs_fwd_kernel<true, 2> : attrs_fwd_kernel<true, 0>))
+                       : attrs_fwd_kernel<false, 0>;
     hipLaunchKernelGGL(kernel, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends,
                        sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, out, opacity, depth, weights);
     return check_launch("render attrs fwd");
@@ -461,8 +487,9 @@ int nacc_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays, int64_t n_
     const dim3 grid(static_cast<unsigned>((n_rays + kAttrRays - 1) / kAttrRays));
     hipStream_t s = as_stream(stream);
     const bool vec4 = vec4_rows(attrs, g_attrs, n_ch);
-    auto kernel = vec4 ? (staged_width(n_ch) ? attrs_bwd_kernel<true, true> : attrs_bwd_kernel<true, false>)
-                       : attrs_bwd_kernel<false, false>;
+    auto kernel = vec4 ? (n_ch <= kBlock ? (staged_width(n_ch) ? attrs_bwd_kernel<true, 1> : attrs_bwd_kernel<true, 0>)
+                                         : (staged_width(n_ch) ? attrs_bwd_kernel<true, 2> : attrs_bwd_kernel<true, 0>))
+                       : attrs_bwd_kernel<false, 0>;
     hipLaunchKernelGGL(kernel, grid, dim3(kAttrThreads), 0, s, packed_info, n_rays, n_samples, t_starts, t_ends,
                        sigmas, attrs, n_ch, early_stop_eps, alpha_thre, background, g_out, g_opacity, g_depth,
                        g_sigmas, g_attrs);

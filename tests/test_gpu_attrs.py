@@ -166,11 +166,12 @@ def test_attrs_three_channels_equal_colour_kernels():
         assert_bit_exact(got["g_attrs"], g_c.cpu().numpy(), "g_rgbs")
 
 
-@pytest.mark.parametrize("ch", [4, 8, 12, 16])
+@pytest.mark.parametrize("ch", [4, 8, 12, 16, 32, 48])
 def test_attrs_unaligned_rows_and_empty_rays(ch):
     """Rows that are not 16-byte aligned take the per-lane scalar path and
-    give the aligned path's bits (4, 8 and 16 channels: rows staged through
-    LDS; 12: per-lane float4 rows); empty rays render the background."""
+    give the aligned path's bits (4, 8 and multiples of 16 channels: rows
+    staged through LDS; 12: per-lane float4 rows); empty rays render the
+    background."""
     packed, ts, te, sg, _ = synth.ragged_render_inputs(500, 43, mean_count=40, max_count=200,
                                                        empty_frac=0.3)
     attrs = np.random.default_rng(43).standard_normal((ts.size, ch)).astype(np.float32)

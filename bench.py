@@ -397,6 +397,8 @@ def lattice_candidates(w, rays_o, rays_d):
 
 RENDER_SOURCES = ("paper_2210_04847_amd/csrc/render.hip+paper_2210_04847_amd/csrc/transmittance.h+"
                   "paper_2210_04847_amd/csrc/common.h")
+MARCH_SOURCES = ("paper_2210_04847_amd/csrc/march.hip+paper_2210_04847_amd/csrc/lattice.h+"
+                 "paper_2210_04847_amd/csrc/scan.h+paper_2210_04847_amd/csrc/common.h")
 
 
 def recorded_traffic(kernel, source):
@@ -677,9 +679,14 @@ def bench_train(args, torch, nacc):
         cands = lattice_candidates(w, inp["rays_o"], inp["rays_d"])
         ops = cands * OPS_PER_CANDIDATE[ops_key(w)]
         ops_s = ops / (phase_avg["march_count"] * 1e-3)
+        # HBM bytes of the uniform-step count kernel, when counters of the
+        # current source are committed (the phase adds the scan's small kernels)
+        traffic = (recorded_traffic("count_uniform_kernel", MARCH_SOURCES)
+                   if getattr(w, "cone", 0.0) == 0.0 and getattr(w, "lookup", "aabb") == "aabb"
+                   else None)
         roofline = {"bound": "alu", "kernel": "march_count", "achieved": ops_s / 1e12,
                     "peak": ALU_PEAK / 1e12, "unit": "TOP/s", "frac": ops_s / ALU_PEAK,
-                    "traffic": None, "candidates": cands}
+                    "traffic": traffic, "candidates": cands}
     elif dominant == "render":
         roofline = render_roofline
     else:

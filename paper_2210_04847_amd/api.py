@@ -89,6 +89,15 @@ class OccupancyGrid:
         self._repack(threshold)
         self.updates += 1
 
+    def update_every(self, step, sigma_fn, every=16, **kw):
+        """The training loop's grid maintenance (Sec. 2.1): update() at steps
+        0, every, 2 every, ...; returns whether it ran.  Keyword arguments go
+        to update()."""
+        if step % every != 0:
+            return False
+        self.update(sigma_fn, **kw)
+        return True
+
     def state_dict(self):
         return {"occ": self.occ.clone(), "bits": self.bits.clone(), "updates": self.updates,
                 "box": self.box, "res": self.res, "n_grids": self.n_grids,

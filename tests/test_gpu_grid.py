@@ -134,6 +134,22 @@ def test_checkpoint_resume_bit_identical():
     assert_bit_exact(grid_c.bits.cpu().numpy(), grid_a.bits.cpu().numpy(), "bits after resume")
 
 
+def test_update_every_n_steps():
+    """update_every runs the update at steps 0, n, 2n, ... only, and leaves
+    the grid as the same number of direct updates."""
+    _, _, grid_a, field = _field_and_grid(32)
+    _, _, grid_b, _ = _field_and_grid(32)
+    fn = lambda p: field.points(p)
+    ran = [grid_a.update_every(step, fn, every=4, n_samples=4096, seed=11) for step in range(10)]
+    assert ran == [s % 4 == 0 for s in range(10)]
+    for _ in range(3):
+        grid_b.update(fn, n_samples=4096, seed=11)
+    torch.cuda.synchronize()
+    assert grid_a.updates == 3
+    assert_bit_exact(grid_a.occ.cpu().numpy(), grid_b.occ.cpu().numpy(), "occ")
+    assert_bit_exact(grid_a.bits.cpu().numpy(), grid_b.bits.cpu().numpy(), "bits")
+
+
 def test_field_matches_oracle_field():
     import paper_2210_04847_amd as nacc
     scene = synth.blob_scene(32, 1001)

@@ -734,6 +734,8 @@ def bench_train(args, torch, nacc):
         "wall_s": wall,
         "cpu_baseline": None,
     }
+    if plan is not None:
+        plan.close()  # its graphs and workspaces, before the interpreter tears down the runtime
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         result["cpu_baseline"] = cpu_baseline(w, inp, min(args.cpu_sample_rays, w.n_rays),
@@ -871,6 +873,8 @@ def bench_dynamic(args, torch, nacc):
     stop.record()
     torch.cuda.synchronize()
     graph_ms = start.elapsed_time(stop) / steps
+    if plan is not None:
+        plan.close()
     phase_avg = phase_timing(torch, batched, min(steps, 16), 1, updates=False)
     v_frac = kept_fraction(batched, e_b)
     alg = algorithmic_bytes(n_total, e_b, e_b * v_frac)

@@ -295,3 +295,43 @@ def test_plan_unbounded_equals_the_calls(name):
         _check(_snapshot(other), want, f"{name}: eager plan step")
     finally:
         plan.close()
+
+
+def test_after_stage_runs_last(dyn):
+    """The optional after-stage runs after rendering, on the step's stream,
+    eagerly and in the captured graph: here it copies the gradients out."""
+    import paper_2210_04847_amd as nacc
+    lib = nacc._lib
+    w, inp = dyn
+    st = _step(w, inp)
+    st.step()
+    torch.cuda.synchronize()
+    e = int(st.total.item())
+    want = st.g_sigmas[:e].clone()
+    copied = torch.full_like(st.g_sigmas, -1.0)
+
+    def after(stream):
+        torch.mul(st.g_sigmas, 1.0, out=copied)  # an elementwise kernel, no allocation
+
+    f, g = st.field, st.grid
+    field = lib.synth_samples_stage(f.table, f.n_blobs, f.n_sets, st.rays_o, st.rays_d, st.ray_set,
+                                    st.ray_indices, st.t_starts, st.t_ends, st.sigmas, st.rgbs,
+                                    st.total)
+    plan = lib.Plan(st.rays_o, st.rays_d, g.bits, g.desc, st.params, st.packed, st.ray_indices,
+                    st.t_starts, st.t_ends, st.total, field, st.sigmas, st.rgbs, st.color,
+                    st.opacity, st.depth, early_stop_eps=w.early_stop_eps, grid_id=st.grid_id,
+                    status=st.status, target=st.target, g_sigmas=st.g_sigmas, g_rgbs=st.g_rgbs,
+                    loss=st.loss, after=lib.python_stage(after))
+    try:
+        plan.step()
+        torch.cuda.synchronize()
+        assert _same(copied[:e], want)
+        plan.capture()
+        for _ in range(2):
+            copied.fill_(-1.0)
+            st.g_sigmas.fill_(7.0)
+            plan.launch()
+            torch.cuda.synchronize()
+            assert _same(copied[:e], want) and _same(st.g_sigmas[:e], want)
+    finally:
+        plan.close()

@@ -182,3 +182,47 @@ def test_render_deterministic():
         outs.append((g_sig.cpu().numpy(), g_rgb.cpu().numpy()))
     assert_bit_exact(outs[0][0], outs[1][0], "g_sigmas repeat")
     assert_bit_exact(outs[0][1], outs[1][1], "g_rgbs repeat")
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_render_configurations(seed):
+    """Random batch sizes, ray lengths, densities and cut thresholds: the
+    forward and backward against the oracle, and the fused loss kernel
+    against the forward and backward calls bit for bit (given the same
+    colour gradient, formed as the fused kernel forms it)."""
+    lib = _nacc()._lib
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.choice([3, 64, 65, 257, 1500]))
+    mean = float(rng.choice([3, 30, 120, 400]))
+    smax = float(rng.choice([0.5, 20.0, 400.0]))
+    eps = float(rng.choice([0.0, 1e-4, 1e-2]))
+    packed, ts, te, sg, cl = synth.ragged_render_inputs(n, 800 + seed, mean_count=mean,
+                                                        max_count=int(4 * mean) + 1, sigma_max=smax)
+    e = ts.size
+    p_d, ts_d, te_d, sg_d, cl_d = _cuda(packed, ts, te, sg, cl)
+    color = torch.empty((n, 3), device="cuda")
+    opacity = torch.empty(n, device="cuda")
+    depth = torch.empty(n, device="cuda")
+    lib.render_fwd(p_d, ts_d, te_d, sg_d, cl_d, eps, color, opacity, depth)
+    torch.cuda.synchronize()
+    got = dict(color=color.cpu().numpy(), opacity=opacity.cpu().numpy(), depth=depth.cpu().numpy())
+    check_forward(got, packed, ts, te, sg, cl, eps)
+    tgt = synth.targets(n, 900 + seed)
+    (tg_d,) = _cuda(tgt)
+    gc = (color - tg_d) * float(np.float32(2.0 / (3 * n)))
+    g_sig = torch.full((max(e, 1),), np.nan, device="cuda")[:e]
+    g_rgb = torch.full((max(e, 1), 3), np.nan, device="cuda")[:e]
+    lib.render_bwd(p_d, ts_d, te_d, sg_d, cl_d, eps, gc, None, None, g_sig, g_rgb)
+    torch.cuda.synchronize()
+    check_backward(g_sig.cpu().numpy(), g_rgb.cpu().numpy(), packed, ts, te, sg, cl,
+                   gc.cpu().numpy().astype(np.float64), None, None, eps)
+    c2, o2, d2 = torch.empty_like(color), torch.empty_like(opacity), torch.empty_like(depth)
+    gs2 = torch.full_like(g_sig, np.nan)
+    gr2 = torch.full_like(g_rgb, np.nan)
+    loss = torch.empty(1, device="cuda")
+    ws = torch.empty(lib.render_mse_workspace_size(n), dtype=torch.uint8, device="cuda")
+    lib.render_fwd_bwd_mse(p_d, ts_d, te_d, sg_d, cl_d, eps, tg_d, c2, o2, d2, gs2, gr2, loss, ws)
+    torch.cuda.synchronize()
+    for a, b, name in ((c2, color, "colour"), (o2, opacity, "opacity"), (d2, depth, "depth"),
+                       (gs2, g_sig, "g_sigmas"), (gr2, g_rgb, "g_rgbs")):
+        assert_bit_exact(a.cpu().numpy(), b.cpu().numpy(), f"fused {name}")

@@ -213,3 +213,22 @@ def test_attrs_autograd():
     assert_bit_exact(out.detach().cpu().numpy(), got["out"], "out")
     assert_bit_exact(s_t.grad.cpu().numpy(), got["g_sigmas"], "g_sigmas")
     assert_bit_exact(a_t.grad.cpu().numpy(), got["g_attrs"], "g_attrs")
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_attrs_random_configurations(seed):
+    """Random channel counts (staged and per-lane widths), batch sizes, ray
+    lengths, thresholds, cuts and backgrounds against the oracle."""
+    rng = np.random.default_rng(300 + seed)
+    ch = int(rng.choice([1, 2, 4, 7, 8, 12, 16, 32]))
+    n = int(rng.choice([3, 64, 65, 600]))
+    mean = float(rng.choice([10, 70, 200]))
+    thre = float(rng.choice([0.0, 0.02]))
+    eps = float(rng.choice([0.0, 1e-4]))
+    packed, ts, te, sg, _ = synth.ragged_render_inputs(n, 350 + seed, mean_count=mean,
+                                                       max_count=int(3 * mean) + 1,
+                                                       sigma_max=float(rng.choice([5.0, 40.0])))
+    attrs = rng.standard_normal((ts.size, ch)).astype(np.float32)
+    bg = rng.standard_normal(ch) if rng.random() < 0.5 else None
+    skip = _check(packed, ts, te, sg, attrs, eps, thre, bg, 400 + seed)
+    assert skip.mean() < 0.05

@@ -151,3 +151,18 @@ def test_pruned_training_step():
     torch.cuda.synchronize()
     assert torch.equal(st.color.view(torch.int32), color.view(torch.int32))
     assert torch.equal(st.g_sigmas[:k].view(torch.int32), g_sig.view(torch.int32))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_prune_random_configurations(seed):
+    """Random batch sizes, ray lengths, densities and both thresholds."""
+    rng = np.random.default_rng(600 + seed)
+    n = int(rng.choice([1, 63, 64, 65, 700, 3000]))
+    mean = float(rng.choice([5, 60, 300]))
+    smax = float(rng.choice([1.0, 40.0, 500.0]))
+    eps = float(rng.choice([0.0, 1e-4, 1e-2]))
+    thre = float(rng.choice([0.0, 1e-3, 1e-2, 0.2]))
+    packed, ts, te, sg, _ = synth.ragged_render_inputs(n, 650 + seed, mean_count=mean,
+                                                       max_count=int(3 * mean) + 1,
+                                                       sigma_max=smax)
+    check_prune(packed, ts, te, sg, eps, thre)

@@ -190,7 +190,9 @@ def render_fwd(packed_info, t_starts, t_ends, sigmas, rgbs, eps=0.0):
 def render_bwd(packed_info, t_starts, t_ends, sigmas, rgbs, g_color,
                g_opacity=None, g_depth=None, eps=0.0):
     """FP64 backward.  Returns dict(g_sigmas [E], g_rgbs [E,3], scale [E]);
-    scale is the magnitude of the two terms of each sigma gradient."""
+    scale is the magnitude of the terms that form each sigma gradient (the
+    two terms of its difference, each with v summed in magnitude over its own
+    terms)."""
     lib = _load()
     p = _c(packed_info, np.int32).reshape(-1, 2)
     n = p.shape[0]

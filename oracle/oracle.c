@@ -327,8 +327,10 @@ void oracle_render_fwd(const int32_t* packed_info, int64_t n_rays,
  *   dL/dc_i     = w_i * g_C
  *   dL/dsigma_i = delta_i * (T_{i+1} v_i - sum_{k>i, k<cut} w_k v_k)
  * both zero at and after the cut.  g_opacity and g_depth are nullable (zero).
- * scale (nullable) receives delta_i * (T_{i+1} |v_i| + sum_{k>i} w_k |v_k|),
- * the magnitude of the two terms whose difference is dL/dsigma_i.
+ * scale (nullable) receives delta_i * (T_{i+1} |v|_i + sum_{k>i} w_k |v|_k),
+ * the magnitude of the terms that form dL/dsigma_i: |v|_i is the sum of the
+ * magnitudes of the terms of v_i (|g_C,ch c_i,ch| over channels, |g_A|,
+ * |g_D m_i|), since v_i is itself a sum of terms of either sign.
  */
 int oracle_render_bwd(const int32_t* packed_info, int64_t n_rays,
                        const double* t_starts, const double* t_ends,
@@ -372,12 +374,15 @@ int oracle_render_bwd(const int32_t* packed_info, int64_t n_rays,
             double w = t_i * -expm1(-tau);
             double v = gc[0] * rgbs[3 * s] + gc[1] * rgbs[3 * s + 1] +
                        gc[2] * rgbs[3 * s + 2] + ga + gd * (ts + te) * 0.5;
+            double v_abs = fabs(gc[0] * rgbs[3 * s]) + fabs(gc[1] * rgbs[3 * s + 1]) +
+                           fabs(gc[2] * rgbs[3 * s + 2]) + fabs(ga) +
+                           fabs(gd * (ts + te) * 0.5);
             double dtau = t_next * v - suffix;
             g_sigmas[s] = delta * dtau;
-            if (scale != NULL) scale[s] = delta * (t_next * fabs(v) + suffix_abs);
+            if (scale != NULL) scale[s] = delta * (t_next * v_abs + suffix_abs);
             for (int ch = 0; ch < 3; ++ch) g_rgbs[3 * s + ch] = w * gc[ch];
             suffix += w * v;
-            suffix_abs += w * fabs(v);
+            suffix_abs += w * v_abs;
         }
         for (int64_t i = cut; i < n; ++i) {
             int64_t s = start + i;
@@ -474,8 +479,12 @@ int oracle_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays,
         const double* g = g_out + r * n_ch;
         double ga = g_opacity != NULL ? g_opacity[r] : 0.0;
         double gd = g_depth != NULL ? g_depth[r] : 0.0;
+        double ga_abs = fabs(ga);
         if (background != NULL)
-            for (int64_t ch = 0; ch < n_ch; ++ch) ga -= g[ch] * background[ch];
+            for (int64_t ch = 0; ch < n_ch; ++ch) {
+                ga -= g[ch] * background[ch];
+                ga_abs += fabs(g[ch] * background[ch]);
+            }
         double prefix = 0.0;
         int64_t cut = n;
         for (int64_t i = 0; i < n; ++i) {
@@ -505,12 +514,16 @@ int oracle_render_attrs_bwd(const int32_t* packed_info, int64_t n_rays,
             double t_next = exp(-(pre[i] + tau));
             double w = t_i * alpha;
             double v = ga + gd * (ts + te) * 0.5;
-            for (int64_t ch = 0; ch < n_ch; ++ch) v += g[ch] * attrs[s * stride + ch];
+            double v_abs = ga_abs + fabs(gd * (ts + te) * 0.5);
+            for (int64_t ch = 0; ch < n_ch; ++ch) {
+                v += g[ch] * attrs[s * stride + ch];
+                v_abs += fabs(g[ch] * attrs[s * stride + ch]);
+            }
             g_sigmas[s] = delta * (t_next * v - suffix);
-            if (scale != NULL) scale[s] = delta * (t_next * fabs(v) + suffix_abs);
+            if (scale != NULL) scale[s] = delta * (t_next * v_abs + suffix_abs);
             for (int64_t ch = 0; ch < n_ch; ++ch) g_attrs[s * stride + ch] = w * g[ch];
             suffix += w * v;
-            suffix_abs += w * fabs(v);
+            suffix_abs += w * v_abs;
         }
     }
     free(pre);

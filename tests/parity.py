@@ -9,11 +9,14 @@ Tolerances, derived from the arithmetic:
     transmittance carries a relative error of about (log2(64) + 2) u P with
     P <= -ln(1e-4) ~ 9.2 inside the kept samples, i.e. below 1e-5;
   * gradients: |gpu - oracle| <= 1e-4 (|oracle| + scale), where scale is the
-    magnitude of the two terms whose difference forms the gradient
-    (delta (T_{i+1} |v_i| + sum_{k>i} w_k |v_k|)).  The sigma gradient is a
-    difference of two such terms and is small exactly where they cancel; no
-    FP32 evaluation can be elementwise-relative there, so relative accuracy is
-    measured against the size of the terms;
+    magnitude of the terms that form the gradient
+    (delta (T_{i+1} |v|_i + sum_{k>i} w_k |v|_k), |v|_i the sum of the
+    magnitudes of the terms of v_i = g_C . c_i + g_A + g_D m_i).  The sigma
+    gradient is a difference of two such terms, and v_i a sum of terms of
+    either sign (colour channels weighted by a signed loss gradient); both
+    are small exactly where they cancel, and no FP32 evaluation can be
+    elementwise-relative there, so relative accuracy is measured against the
+    size of the terms;
   * early termination: where the oracle's FP64 transmittance lies within a
     relative 1e-5 of eps at the deciding sample, FP32 may place the cut one
     sample earlier or later; such rays are accepted if they match the oracle

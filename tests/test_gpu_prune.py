@@ -153,7 +153,7 @@ def test_pruned_training_step():
     assert torch.equal(st.g_sigmas[:k].view(torch.int32), g_sig.view(torch.int32))
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(64))
 def test_prune_random_configurations(seed):
     """Random batch sizes, ray lengths, densities and both thresholds."""
     rng = np.random.default_rng(600 + seed)

@@ -184,7 +184,7 @@ def test_render_deterministic():
     assert_bit_exact(outs[0][1], outs[1][1], "g_rgbs repeat")
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(64))
 def test_random_render_configurations(seed):
     """Random batch sizes, ray lengths, densities and cut thresholds: the
     forward and backward against the oracle, and the fused loss kernel

@@ -153,6 +153,24 @@ __device__ __forceinline__ float wave_max(float x) {
     return read_lane(x, kWave - 1);
 }
 
+// Chunk masks of the count pass, one per lane: lane j holds the ballot of
+// chunk j (as two 32-bit halves).  The chunk index and the ballot are
+// wave-uniform, so the ballot is written into lane j directly.
+struct ChunkMasks {
+    int lo = 0, hi = 0;
+    __device__ __forceinline__ void keep(int chunk, uint64_t m) {
+        if (chunk < kWave) {
+            const uint32_t m_lo = static_cast<uint32_t>(m), m_hi = static_cast<uint32_t>(m >> 32);
+            // one scalar operand per instruction: the lane select goes in m0
+            asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(lo) : "s"(m_lo), "{m0}"(chunk));
+            asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(hi) : "s"(m_hi), "{m0}"(chunk));
+        }
+    }
+    __device__ __forceinline__ uint64_t mine() const {
+        return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    }
+};
+
 // Uniform steps without the skip field, two chunks of 64 candidates per
 // iteration: both chunks' grid words are loaded before either is tested, so
 // each wave keeps two lookups in flight instead of waiting on one at a time
@@ -171,7 +189,7 @@ __device__ __forceinline__ int march_ray_uniform_x2(
     const float* d = span.d;
     const uint32_t word0 = span.word0;
     const float t_near = span.t_near, t_far = span.t_far;
-    uint64_t my_mask = 0ull;  // count pass: lane j keeps the ballot of chunk j
+    ChunkMasks my_masks;  // count pass
     int count = count0;
     bool done = false;
     for (int k0 = first_chunk * kWave; k0 < kMaxCandidates && !done; k0 += 2 * kWave) {
@@ -193,7 +211,9 @@ __device__ __forceinline__ int march_ray_uniform_x2(
             const float tm = (t0[u] + t1[u]) * 0.5f;
             const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
             const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);  // every lane: the index is clamped into the grid
-            ms[u] = ballot(live[u] & (((w >> q.bit) & 1u) != 0u));
+            // two ballots of plain comparisons, combined as masks (a ballot
+            // of a combined condition costs two more vector instructions)
+            ms[u] = ballot(live[u]) & ballot(((w >> q.bit) & 1u) != 0u);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -204,7 +224,7 @@ __device__ __forceinline__ int march_ray_uniform_x2(
             }
             const uint64_t m = ms[u];
             const bool hit = ((m >> lane) & 1ull) != 0ull;
-            if (!FILL && lane == chunk) my_mask = m;
+            if (!FILL) my_masks.keep(chunk, m);
             if (FILL && hit) {
                 const int idx = count + bits_below(m);
                 if (idx < limit) {
@@ -230,7 +250,7 @@ __device__ __forceinline__ int march_ray_uniform_x2(
             }
         }
     }
-    if (!FILL && lane < n_masks) masks[lane] = my_mask;
+    if (!FILL && lane < n_masks) masks[lane] = my_masks.mine();
     return count;
 }
 
@@ -261,7 +281,7 @@ __device__ __forceinline__ int march_ray_uniform(
     SkipRay sk{};
     if (SKIP) sk = skip_ray(g, o, d, t_far);
     float skip_end = -INFINITY;  // candidates with midpoint below it are empty
-    uint64_t my_mask = 0ull;     // count pass: lane j keeps the ballot of chunk j
+    ChunkMasks my_masks;         // count pass
     int count = count0;
     for (int k0 = first_chunk * kWave; k0 < kMaxCandidates; k0 += kWave) {
         const int chunk = k0 / kWave;
@@ -289,7 +309,7 @@ __device__ __forceinline__ int march_ray_uniform(
             hit = todo && ((w >> q.bit) & 1u) != 0u;
         }
         const uint64_t m = ballot(hit);
-        if (!FILL && lane == chunk) my_mask = m;
+        if (!FILL) my_masks.keep(chunk, m);
         if (FILL && hit) {
             const int idx = count + bits_below(m);
             if (idx < limit) {
@@ -310,7 +330,7 @@ __device__ __forceinline__ int march_ray_uniform(
         }
         if (FILL && count >= limit) break;
     }
-    if (!FILL && lane < n_masks) masks[lane] = my_mask;
+    if (!FILL && lane < n_masks) masks[lane] = my_masks.mine();
     return count;
 }
 

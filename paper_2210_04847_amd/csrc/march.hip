@@ -194,16 +194,16 @@ __device__ __forceinline__ int march_ray_uniform_x2(
     bool done = false;
     for (int k0 = first_chunk * kWave; k0 < kMaxCandidates && !done; k0 += 2 * kWave) {
         float t0[2], t1[2];
-        bool live[2];
+        uint64_t live[2];  // ballots of t0 < t_far
         uint64_t ms[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int k = k0 + u * kWave + lane;
             t0[u] = t_near + static_cast<float>(k) * p.dt;
-            live[u] = t0[u] < t_far;
+            live[u] = ballot(t0[u] < t_far);
             t1[u] = t_near + static_cast<float>(k + 1) * p.dt;
         }
-        if (ballot(live[0]) == 0ull) break;  // t_k is non-decreasing in k
+        if (live[0] == 0ull) break;  // t_k is non-decreasing in k
         // both words are loaded, and both ballots taken, before any branch
         // on them (a ballot cannot move into a branch)
 #pragma unroll
@@ -211,14 +211,14 @@ __device__ __forceinline__ int march_ray_uniform_x2(
             const float tm = (t0[u] + t1[u]) * 0.5f;
             const Probe q = probe<LOOKUP>(g, word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
             const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);  // every lane: the index is clamped into the grid
-            // two ballots of plain comparisons, combined as masks (a ballot
-            // of a combined condition costs two more vector instructions)
-            ms[u] = ballot(live[u]) & ballot(((w >> q.bit) & 1u) != 0u);
+            // ballots of plain comparisons, combined as masks (a ballot of
+            // a combined condition costs two more vector instructions)
+            ms[u] = live[u] & ballot(((w >> q.bit) & 1u) != 0u);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int chunk = k0 / kWave + u;
-            if (u == 1 && (ballot(live[1]) == 0ull || k0 + kWave >= kMaxCandidates)) {
+            if (u == 1 && (live[1] == 0ull || k0 + kWave >= kMaxCandidates)) {
                 done = true;
                 break;
             }

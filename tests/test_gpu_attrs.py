@@ -231,4 +231,6 @@ def test_attrs_random_configurations(seed):
     attrs = rng.standard_normal((ts.size, ch)).astype(np.float32)
     bg = rng.standard_normal(ch) if rng.random() < 0.5 else None
     skip = _check(packed, ts, te, sg, attrs, eps, thre, bg, 400 + seed)
-    assert skip.mean() < 0.05
+    # at most 5% of the rays (or one ray, for batches of a few rays) may be
+    # set aside as undecidable at the threshold or the cut
+    assert skip.sum() <= max(1.0, 0.05 * skip.size)

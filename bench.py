@@ -86,6 +86,11 @@ def parse():
                          "the paper's listing uses 1e-2)")
     ap.add_argument("--attrs-channels", type=int, default=16,
                     help="attrs_262k: feature channels per sample")
+    ap.add_argument("--rows", choices=["all", "none"], default="all",
+                    help="with the default workload (train_262k) also measure the HBM probe "
+                         "and the other workloads (plain_fwd_4k, unbounded_262k, "
+                         "unbounded_contract_262k, dynamic_64, images_8) and attach them to "
+                         "the JSON line as rows")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
@@ -422,36 +427,109 @@ def recorded_traffic(kernel, source):
     return None
 
 
-def cpu_baseline(w, inp, n_sample, forward_only=False):
-    """The oracle, as it stands, on the first n_sample rays of the workload:
-    brute-force marching, FP64 field, FP64 forward (+ MSE + backward)."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and usable threads."""
+    name = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return name, usable
+
+
+def _oracle_chunk(w, inp, mask, lookup, a, b, forward_only):
+    """The oracle, as it stands, on rays [a, b): brute-force marching, FP64
+    field, FP64 forward (+ MSE + backward).  Returns the samples marched."""
     import numpy as np
 
     import oracle
-    o = inp["rays_o"][:n_sample]
-    d = inp["rays_d"][:n_sample]
-    mask = oracle.grid_threshold(inp["occ"], THRESHOLD)
-    cascades = getattr(w, "cascades", 1)
-    lookup = {"contract": oracle.LOOKUP_CONTRACT, "cascade": oracle.LOOKUP_CASCADE}.get(
-        getattr(w, "lookup", "aabb"), oracle.LOOKUP_AABB)
-    t0 = time.perf_counter()
+    o, d = inp["rays_o"][a:b], inp["rays_d"][a:b]
     packed, ri, ts, te = oracle.march(o, d, mask, w.res, np.asarray(w.box, np.float32), w.near,
                                       w.far, w.dt, dt_max=getattr(w, "dt_max", 1e10),
                                       cone=getattr(w, "cone", 0.0), lookup=lookup,
-                                      n_grids=cascades, max_per_ray=getattr(w, "max_per_ray", 0))
+                                      n_grids=getattr(w, "cascades", 1),
+                                      max_per_ray=getattr(w, "max_per_ray", 0))
     pos = oracle.sample_positions(o, d, ri, ts, te)
     sig, rgb = oracle.blob_field(inp["scene"], pos)
     fwd = oracle.render_fwd(packed, ts, te, sig, rgb, w.early_stop_eps)
     if not forward_only:
-        _, g_color = oracle.mse_loss_and_grad(fwd["color"], inp["targets"][:n_sample])
+        _, g_color = oracle.mse_loss_and_grad(fwd["color"], inp["targets"][a:b])
         oracle.render_bwd(packed, ts, te, sig, rgb, g_color, eps=w.early_stop_eps)
-    dt = time.perf_counter() - t0
+    return int(ri.size)
+
+
+def cpu_baseline(w, inp, n_single, n_all, forward_only=False, max_threads=16):
+    """The oracle timed on the host: one thread on the first n_single rays,
+    then all usable threads (at most max_threads; rays split into chunks run
+    by a thread pool, the oracle's C calls release the interpreter lock) on
+    the first n_all rays.  The arithmetic per ray is the oracle's, unchanged."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    mask = oracle.grid_threshold(inp["occ"], THRESHOLD)
+    lookup = {"contract": oracle.LOOKUP_CONTRACT, "cascade": oracle.LOOKUP_CASCADE}.get(
+        getattr(w, "lookup", "aabb"), oracle.LOOKUP_AABB)
+    name, usable = cpu_model()
+    threads = max(1, min(usable, max_threads))
+    t0 = time.perf_counter()
+    e1 = _oracle_chunk(w, inp, mask, lookup, 0, n_single, forward_only)
+    dt1 = time.perf_counter() - t0
+    chunk = max(1, -(-n_all // (threads * 8)))
+    bounds = [(a, min(a + chunk, n_all)) for a in range(0, n_all, chunk)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        ek = sum(pool.map(lambda ab: _oracle_chunk(w, inp, mask, lookup, ab[0], ab[1],
+                                                   forward_only), bounds))
+    dtk = time.perf_counter() - t0
     what = "march+field+fwd" if forward_only else "march+field+fwd+bwd"
-    return {"value": ri.size / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} of {inp['rays_o'].shape[0]} rays ({ri.size} samples), "
-                      f"{what}, one thread, {dt:.1f} s, host "
-                      f"{platform.processor() or platform.machine()} with {os.cpu_count()} "
-                      f"hardware threads"}
+    return {"value": ek / dtk, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_all} of {inp['rays_o'].shape[0]} rays ({ek} samples), {what}, "
+                      f"{threads} threads over rays, {dtk:.1f} s; host: {name}, {usable} usable "
+                      f"hardware threads",
+            "single_thread": {"value": e1 / dt1, "unit": "samples/s",
+                              "sample": f"first {n_single} rays ({e1} samples), {dt1:.1f} s"},
+            "cpu_model": name, "usable_threads": usable}
+
+
+def hbm_probe(torch, nacc, mib=4096, repeats=8):
+    """Achievable HBM bandwidth on this device: read-only, write-only and
+    copy passes of the library's streaming probe over buffers of `mib` MiB
+    (well past the 256 MB last-level cache), best over a sweep of launch
+    sizes, HIP events on the launch stream.  Copy counts read + write bytes."""
+    import numpy as np
+    lib = nacc._lib
+    n_bytes = mib << 20
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for kind, name, factor in ((lib.PROBE_READ, "read", 1), (lib.PROBE_WRITE, "write", 1),
+                               (lib.PROBE_COPY, "copy", 2)):
+        best = (0.0, 0)
+        for blocks in (2048, 4096, 8192, 16384, 32768):
+            lib.probe_hbm(kind, src, dst, n_bytes, blocks)  # warm-up
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
+            ev[0].record()
+            for k in range(repeats):
+                lib.probe_hbm(kind, src, dst, n_bytes, blocks)
+                ev[k + 1].record()
+            torch.cuda.synchronize()
+            ms = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(repeats)]))
+            gbps = factor * n_bytes / (ms * 1e-3) / 1e9
+            if gbps > best[0]:
+                best = (gbps, blocks)
+        out[name] = {"GB/s": best[0], "blocks": best[1], "frac_of_peak": best[0] * 1e9 / HBM_PEAK}
+    del src, dst
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    out["bytes"] = n_bytes
+    return out
 
 
 def kept_fraction(st, e_last):
@@ -694,6 +772,16 @@ def bench_train(args, torch, nacc):
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": bps / 1e9,
                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bps / HBM_PEAK,
                     "traffic": None}
+    # the marching + rendering path as a whole (count with its scan, fill,
+    # fused render; the synthetic field and the grid update left out)
+    path_keys = [k for k in ("march_count", "march_fill", "prune", "render") if k in alg]
+    path_bytes = sum(alg[k] for k in path_keys)
+    path_ms = sum(phase_avg[k] for k in path_keys)
+    path_bps = path_bytes / (path_ms * 1e-3)
+    path_roofline = {"bound": "hbm", "kernels": path_keys, "achieved": path_bps / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": path_bps / HBM_PEAK,
+                     "ms": path_ms, "alg_bytes": path_bytes,
+                     "limiter": max(path_keys, key=lambda k: phase_avg[k])}
     result = {
         "metric": METRIC,
         "value": e_total / (ms_total * 1e-3),
@@ -720,6 +808,7 @@ def bench_train(args, torch, nacc):
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "roofline_render": render_roofline,
+        "roofline_path": path_roofline,
         "samples_per_step": e_mean,
         "rendered_samples_per_step": k_mean,
         "kept_fraction": v_frac,
@@ -738,7 +827,8 @@ def bench_train(args, torch, nacc):
         plan.close()  # its graphs and workspaces, before the interpreter tears down the runtime
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        result["cpu_baseline"] = cpu_baseline(w, inp, min(args.cpu_sample_rays, w.n_rays),
+        result["cpu_baseline"] = cpu_baseline(w, inp, min(args.cpu_sample_rays // 2, w.n_rays),
+                                              min(args.cpu_sample_rays * 2, w.n_rays),
                                               forward_only)
     return result
 
@@ -765,7 +855,7 @@ def bench_dynamic(args, torch, nacc):
     upd_set = t(synth.update_frames(EMA_CELLS, nf, 4100 + w.seed_base)) if shared else None
     batched = Step(torch, nacc, w, rays_o, rays_d, tgt, grid, field,
                    grid_id=None if shared else frame, ray_set=frame, update_set=upd_set,
-                   seed=4000 + w.seed_base)
+                   seed=4000 + w.seed_base, skip_field=args.skip_field == "on")
     lib = nacc._lib
     words = res ** 3 // 32
     c3 = (res // 4) ** 3
@@ -785,8 +875,9 @@ def bench_dynamic(args, torch, nacc):
             o, d = rays_o[a:b], rays_d[a:b]
             g = 0 if shared else f
             bits = grid.bits[g * words:(g + 1) * words]
-            # the frame's skip field (+ the build scratch the size check expects)
-            skip = grid.skip[g * c3:(g + 2) * c3]
+            # the frame's skip field (+ the build scratch the size check expects),
+            # only when the batched step marches with it too
+            skip = grid.skip[g * c3:(g + 2) * c3] if args.skip_field == "on" else None
             packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
             total = torch.empty(1, dtype=torch.int64, device=dev)
             ws = torch.empty(lib.march_workspace_size(n, desc1, params), dtype=torch.uint8,
@@ -899,7 +990,7 @@ def bench_dynamic(args, torch, nacc):
                    "pass": "forward+mse+backward",
                    "form": ("batched, the library's step plan (one HIP graph per step)"
                             if plan is not None else "batched, one HIP graph per step"),
-                   "tuning": tuned, "parallelism": "single GPU"},
+                   "tuning": tuned, "skip_field": args.skip_field, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "render", "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": None},
@@ -1239,15 +1330,71 @@ def main():
     import torch
 
     import paper_2210_04847_amd as nacc
-    if args.workload.startswith("dynamic"):
-        result = bench_dynamic(args, torch, nacc)
-    elif args.workload.startswith("images"):
-        result = bench_images(args, torch, nacc)
-    elif args.workload == "attrs_262k":
-        result = bench_attrs(args, torch, nacc)
-    else:
-        result = bench_train(args, torch, nacc)
+    result = run_workload(args, torch, nacc)
+    if args.workload == "train_262k" and args.rows == "all":
+        attach_rows(args, torch, nacc, result)
     print(json.dumps(result), flush=True)
+
+
+def run_workload(args, torch, nacc):
+    if args.workload.startswith("dynamic"):
+        return bench_dynamic(args, torch, nacc)
+    if args.workload.startswith("images"):
+        return bench_images(args, torch, nacc)
+    if args.workload == "attrs_262k":
+        return bench_attrs(args, torch, nacc)
+    return bench_train(args, torch, nacc)
+
+
+ROWS = ("plain_fwd_4k", "unbounded_262k", "unbounded_contract_262k", "dynamic_64", "images_8")
+# keys of a workload's line that the headline line already carries
+_ROW_DROP = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data",
+             "cpu_baseline", "unit")
+
+
+def attach_rows(args, torch, nacc, result):
+    """The HBM probe and every other workload, each measured as its own
+    `--workload` run would measure it, attached to the headline line."""
+    import copy
+    log("HBM probe")
+    probe = hbm_probe(torch, nacc)
+    result["hbm_probe"] = probe
+    measured = max(probe["read"]["GB/s"], probe["copy"]["GB/s"], probe["write"]["GB/s"])
+
+    def with_measured(r):
+        if isinstance(r, dict) and r.get("unit") == "GB/s" and r.get("achieved"):
+            r["frac_of_measured"] = r["achieved"] / measured
+        return r
+
+    for key in ("roofline", "roofline_render", "roofline_path"):
+        with_measured(result.get(key))
+    rows = {}
+    for name in ROWS:
+        sub = copy.copy(args)
+        sub.workload = name
+        sub.no_cpu_baseline = True
+        log(f"row {name}")
+        t0 = time.perf_counter()
+        try:
+            r = run_workload(sub, torch, nacc)
+        except Exception as exc:  # a failed row is reported, the others still run
+            rows[name] = {"error": f"{type(exc).__name__}: {exc}"}
+            log(f"row {name} failed: {exc}")
+            continue
+        finally:
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        r = {k: v for k, v in r.items() if k not in _ROW_DROP}
+        r["samples_per_s"] = r.pop("value")
+        for key in ("roofline", "roofline_render", "roofline_path"):
+            with_measured(r.get(key))
+        r["wall_s_row"] = time.perf_counter() - t0
+        rows[name] = r
+    result["rows"] = rows
+    dyn = rows.get("dynamic_64", {})
+    if "batched_over_plain" in dyn:
+        result["batched_over_plain"] = {"dynamic_64": dyn["batched_over_plain"],
+                                        "identical": all(dyn["identical_outputs"].values())}
 
 
 if __name__ == "__main__":

@@ -2,7 +2,7 @@
 
 Every call takes torch tensors that live on the GPU, checks dtype, device and
 contiguity, and passes raw pointers plus torch's current HIP stream to the C
-ABI declared in include/nacc.h, include/nacc_synth.h and include/nacc_plan.h.  No arithmetic of the
+ABI declared in include/*.h.  No arithmetic of the
 method happens here.  If the library has not been built, importing this module
 raises ImportError: there is no fallback path.
 """
@@ -147,9 +147,10 @@ _SIGNATURES = {
     "nacc_synth_render_fused": (_INT, [_P, _I32, _I32, _P, _P, _P, _P, _I64, _P,
                                        ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams), _F,
                                        _P, _P, _P, _P, _P]),
+    "nacc_probe_hbm": (_INT, [_I32, _P, _P, _I64, _I32, _P]),
 }
 
-# Symbols declared in include/nacc.h, include/nacc_synth.h and include/nacc_plan.h.
+# Symbols declared in the headers under include/.
 EXPORTED = tuple(_SIGNATURES)
 
 
@@ -752,3 +753,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
+
+
+def probe_hbm(kind, src, dst, n_bytes, blocks, stream=None):
+    """One streaming pass of the HBM probe (include/nacc_probe.h)."""
+    _need(src, src.dtype if src is not None else None, "src")
+    _need(dst, dst.dtype, "dst")
+    if src is not None and src.numel() * src.element_size() < n_bytes:
+        raise ValueError("src is smaller than n_bytes")
+    if kind != PROBE_READ and dst.numel() * dst.element_size() < n_bytes:
+        raise ValueError("dst is smaller than n_bytes")
+    _check("nacc_probe_hbm", lib.nacc_probe_hbm(int(kind), _ptr(src), _ptr(dst), int(n_bytes),
+                                                int(blocks), _stream(stream)))

@@ -1072,6 +1072,49 @@ const uint8_t* usable_skip(const uint8_t* skip, const nacc_grid_desc& grid) {
     return skip;
 }
 
+// Count, scan and starts of one marching call, given the scan sums and (for
+// uniform steps, nullable) the chunk masks or (cone steps) the cone
+// workspace.
+int march_count_launch(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
+                       const uint32_t* grid_bits, const uint8_t* grid_skip, const nacc_grid_desc* grid,
+                       const nacc_march_params* params, int32_t* packed_info, int64_t* total, int64_t* sums,
+                       uint64_t* masks, int n_masks, const ConeWork* cw, hipStream_t s) {
+    GridK g;
+    ClipK c;
+    StepK p;
+    make_constants(*grid, *params, g, c, p);
+    const int64_t nb = num_blocks(n_rays);
+    const uint8_t* skip = usable_skip(grid_skip, *grid);
+    int st = NACC_OK;
+    if (nb > 0) {
+        switch (grid->lookup) {
+            case NACC_LOOKUP_AABB:
+                dispatch_count<NACC_LOOKUP_AABB>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
+                                                 p, packed_info, sums, masks, n_masks);
+                break;
+            case NACC_LOOKUP_CASCADE:
+                dispatch_count<NACC_LOOKUP_CASCADE>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
+                                                    c, p, packed_info, sums, masks, n_masks);
+                break;
+            default:
+                dispatch_count<NACC_LOOKUP_CONTRACT>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits,
+                                                     g, c, p, packed_info, sums, masks, n_masks);
+                break;
+        }
+        st = check_launch("march count");
+        if (st != NACC_OK) return st;
+    }
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
+    st = check_launch("march scan");
+    if (st != NACC_OK) return st;
+    if (nb > 0) {
+        hipLaunchKernelGGL(finalize_starts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, sums, n_rays,
+                           packed_info);
+        st = check_launch("march starts");
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1117,48 +1160,14 @@ int nacc_march_count(const float* rays_o, const float* rays_d, const int32_t* gr
                  "workspace of %zu bytes, need %lld", workspace_bytes, static_cast<long long>(need));
     uint64_t* masks = lay.n_masks > 0 ? reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + lay.sums_bytes)
                                       : nullptr;
-    GridK g;
-    ClipK c;
-    StepK p;
-    make_constants(*grid, *params, g, c, p);
-    hipStream_t s = as_stream(stream);
-    const int64_t nb = num_blocks(n_rays);
-    int64_t* sums = static_cast<int64_t*>(workspace);
-    const bool cone = params->cone > 0.0f;
-    const uint8_t* skip = usable_skip(grid_skip, *grid);
     ConeWork cw_store{};
     const ConeWork* cw = nullptr;
-    if (cone) {
+    if (params->cone > 0.0f) {
         cw_store = cone_work(workspace, lay);
         cw = &cw_store;
     }
-    if (nb > 0) {
-        switch (grid->lookup) {
-            case NACC_LOOKUP_AABB:
-                dispatch_count<NACC_LOOKUP_AABB>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g, c,
-                                                 p, packed_info, sums, masks, lay.n_masks);
-                break;
-            case NACC_LOOKUP_CASCADE:
-                dispatch_count<NACC_LOOKUP_CASCADE>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits, g,
-                                                    c, p, packed_info, sums, masks, lay.n_masks);
-                break;
-            default:
-                dispatch_count<NACC_LOOKUP_CONTRACT>(skip, cw, nb, s, rays_o, rays_d, grid_id, n_rays, grid_bits,
-                                                     g, c, p, packed_info, sums, masks, lay.n_masks);
-                break;
-        }
-        st = check_launch("march count");
-        if (st != NACC_OK) return st;
-    }
-    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
-    st = check_launch("march scan");
-    if (st != NACC_OK) return st;
-    if (nb > 0) {
-        hipLaunchKernelGGL(finalize_starts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, sums, n_rays,
-                           packed_info);
-        st = check_launch("march starts");
-    }
-    return st;
+    return march_count_launch(rays_o, rays_d, grid_id, n_rays, grid_bits, grid_skip, grid, params, packed_info,
+                              total, static_cast<int64_t*>(workspace), masks, lay.n_masks, cw, as_stream(stream));
 }
 
 int nacc_march_fill(const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,

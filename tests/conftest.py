@@ -27,3 +27,15 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Largest strict elementwise gradient errors the parity checks saw."""
+    parity = sys.modules.get("parity")
+    rep = getattr(parity, "STRICT_REPORT", None)
+    if rep:
+        terminalreporter.write_line(
+            "gradient parity: %d checks; strict elementwise relative error "
+            "max %.3e on non-cancelling samples (%d samples), max %.3e on all samples"
+            % (len(rep), max(r["strict_max"] for r in rep), sum(r["n_plain"] for r in rep),
+               max(r["strict_all"] for r in rep)))

@@ -16,7 +16,9 @@ Tolerances, derived from the arithmetic:
     either sign (colour channels weighted by a signed loss gradient); both
     are small exactly where they cancel, and no FP32 evaluation can be
     elementwise-relative there, so relative accuracy is measured against the
-    size of the terms;
+    size of the terms.  On samples whose gradient keeps at least half the
+    size of its terms (no cancellation) the error is also held elementwise to
+    1e-4 of the value itself, and the largest such error is reported;
   * early termination: where the oracle's FP64 transmittance lies within a
     relative 1e-5 of eps at the deciding sample, FP32 may place the cut one
     sample earlier or later; such rays are accepted if they match the oracle
@@ -130,4 +132,23 @@ def check_backward(g_sig, g_rgb, packed, t_starts, t_ends, sigmas, rgbs, g_color
     assert bad.size == 0, (f"backward: {bad.size} samples outside tolerance, e.g. sample "
                            f"{bad[0]} (ray {ray_of[bad[0]]}): g_sigma {np.asarray(g_sig)[bad[0]]} "
                            f"vs {ref['g_sigmas'][bad[0]]} (scale {ref['scale'][bad[0]]})")
+    # strict elementwise check where the gradient does not cancel: on samples
+    # (of unambiguous rays) whose oracle value is at least half the size of
+    # its terms, the error must stay within GRAD_RTOL of the value itself
+    gs = np.asarray(g_sig, np.float64)
+    floor = 1e-20 + (0 if extra_scale is None else extra_scale)
+    strict = np.maximum(np.abs(gs - ref["g_sigmas"]) - floor, 0.0) / np.maximum(
+        np.abs(ref["g_sigmas"]), 1e-30)
+    plain = (~amb[ray_of]) & (np.abs(ref["g_sigmas"]) >= 0.5 * ref["scale"]) & (
+        np.abs(ref["g_sigmas"]) > 0)
+    worst = float(strict[plain].max()) if plain.any() else 0.0
+    assert worst <= GRAD_RTOL, (f"backward: strict relative error {worst:.3e} on a sample whose "
+                                f"gradient does not cancel")
+    STRICT_REPORT.append(dict(strict_max=worst, strict_all=float(strict[~amb[ray_of]].max())
+                              if (~amb[ray_of]).any() else 0.0, n_plain=int(plain.sum())))
     return ref, amb
+
+
+# Largest strict elementwise relative gradient errors seen by check_backward
+# (on non-cancelling samples, and on all samples), for the test reports.
+STRICT_REPORT = []

@@ -8,7 +8,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("nacc.h", "nacc_synth.h", "nacc_plan.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h")]
 
 
 def declared_symbols():
@@ -204,3 +204,4 @@ def test_plan_calls_on_null_plan_rejected():
                lib.nacc_plan_autotune(None, 3, None, None, None)):
         assert st == _lib.NACC_EINVAL
     assert lib.nacc_synth_samples_stage_run(None, None) == _lib.NACC_EINVAL
+

@@ -184,7 +184,9 @@ def test_render_deterministic():
     assert_bit_exact(outs[0][1], outs[1][1], "g_rgbs repeat")
 
 
-@pytest.mark.parametrize("seed", range(64))
+# seeds 141, 186 and 210 found samples whose colour-gradient dot product
+# cancels across channels to ~3e-5 of its terms: kept as regression cases
+@pytest.mark.parametrize("seed", list(range(64)) + [141, 186, 210])
 def test_random_render_configurations(seed):
     """Random batch sizes, ray lengths, densities and cut thresholds: the
     forward and backward against the oracle, and the fused loss kernel

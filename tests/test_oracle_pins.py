@@ -180,6 +180,104 @@ def test_dense_mask_sampling_tiny_grids():
             assert np.array_equal(got[~amb], occ[~amb]), (res, r)
 
 
+def test_per_ray_grid_selection():
+    # Two grids behind one call: grid 0 empty, grid 1 full.  A ray naming
+    # grid 1 must get every lattice candidate, ceil((t_far - t_near)/dt) of
+    # them; a ray naming grid 0 none; a ray naming a grid that does not exist
+    # (-1 or 2) none.  Ignoring grid_id (always grid 0) or reading the wrong
+    # grid's slice of the mask fails this.
+    res = 8
+    o, d = _rays(400, 21)
+    dt = synth.STEP_1024
+    mask = np.concatenate([np.zeros(res ** 3, np.uint8), np.ones(res ** 3, np.uint8)])
+    gid = np.resize(np.array([1, 0, 1, -1, 2, 1], np.int32), o.shape[0])
+    packed, ri, ts, te = oracle.march(o, d, mask, res, BOX, 0.0, 1e10, dt,
+                                      n_grids=2, grid_id=gid)
+    tn, tf, hit = oracle.clip(o, d, BOX, 0.0, 1e10)
+    q = (tf.astype(np.float64) - tn.astype(np.float64)) / np.float64(np.float32(dt))
+    full = np.where(hit, np.ceil(q), 0)
+    clear = np.abs(q - np.round(q)) > 1e-3
+    on1 = gid == 1
+    assert on1.sum() > 100 and (on1 & hit).sum() > 50
+    assert np.all(packed[~on1, 1] == 0)
+    assert np.array_equal(packed[on1 & clear, 1], full[on1 & clear].astype(np.int32))
+    assert np.all(np.abs(packed[on1 & ~clear, 1] - full[on1 & ~clear]) <= 1)
+    assert np.array_equal(ri, np.repeat(np.arange(o.shape[0]), packed[:, 1]))
+
+
+@pytest.mark.parametrize("lookup", [0, 2])
+def test_per_ray_grids_equal_separate_calls(lookup):
+    # Rays over three different random grids in one call equal, ray by ray
+    # and bit for bit, one single-grid call per grid on that grid alone.
+    res = 8
+    o, d = _rays(300, 22)
+    box = BOX if lookup == 0 else np.array([-2, -2, -2, 2, 2, 2], np.float32)
+    far = 1e10 if lookup == 0 else 6.0
+    masks = [synth.random_mask(res ** 3, f, 30 + i) for i, f in enumerate((0.2, 0.5, 0.8))]
+    gid = np.random.default_rng(23).integers(0, 3, o.shape[0]).astype(np.int32)
+    packed, ri, ts, te = oracle.march(o, d, np.concatenate(masks), res, box, 0.0,
+                                      far, 0.02, lookup=lookup, n_grids=3, grid_id=gid)
+    for g in range(3):
+        sel = np.flatnonzero(gid == g)
+        p1, r1, s1, e1 = oracle.march(o[sel], d[sel], masks[g], res, box, 0.0,
+                                      far, 0.02, lookup=lookup)
+        assert np.array_equal(packed[sel, 1], p1[:, 1]), g
+        for j, r in enumerate(sel):
+            a, n = packed[r]
+            b, m = p1[j]
+            assert np.array_equal(ts[a:a + n], s1[b:b + m])
+            assert np.array_equal(te[a:a + n], e1[b:b + m])
+    # distinct grids really give distinct samples (the test can fail)
+    assert len({int(packed[gid == g, 1].sum()) for g in range(3)}) == 3
+
+
+def _round_f32(q):
+    """Round an exact rational to the nearest float32 (ties to even)."""
+    from fractions import Fraction
+    if q == 0:
+        return np.float32(0.0)
+    sign = -1 if q < 0 else 1
+    q = abs(Fraction(q))
+    e = math.floor(math.log2(q.numerator) - math.log2(q.denominator))
+    while Fraction(2) ** e > q:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= q:
+        e += 1
+    ulp = Fraction(2) ** (e - 23)
+    m = q / ulp
+    lo = math.floor(m)
+    rem = m - lo
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and lo % 2 == 1):
+        lo += 1
+    return np.float32(sign * float(lo * ulp))
+
+
+def test_lattice_is_two_roundings_not_fma():
+    # The lattice point t_k is fl(t_near + fl(k * dt)): the product is
+    # rounded to FP32 before the sum.  Evaluated here by exact rational
+    # arithmetic; on the candidates where that differs from the singly
+    # rounded fl(t_near + k * dt) (a fused multiply-add) the oracle must give
+    # the two-rounding value.
+    from fractions import Fraction
+    dt = np.float32(synth.STEP_1024)
+    res = 4
+    mask = np.ones(res ** 3, np.uint8)
+    n_diff = 0
+    for a in (0.123456789, 0.7071067, 1.1, 2.3456):
+        o = np.array([[-1.5 - a, 0.1, 0.2]], np.float32)
+        d = np.array([[1.0, 0.0, 0.0]], np.float32)
+        packed, ri, ts, te = oracle.march(o, d, mask, res, BOX, 0.0, 1e10, float(dt))
+        tn, tf, hit = oracle.clip(o, d, BOX, 0.0, 1e10)
+        t0 = Fraction(float(tn[0]))
+        for k in range(1, packed[0, 1]):
+            prod = _round_f32(Fraction(k) * Fraction(float(dt)))
+            two = _round_f32(t0 + Fraction(float(prod)))
+            fma = _round_f32(t0 + Fraction(k) * Fraction(float(dt)))
+            assert ts[k] == two, (a, k)
+            n_diff += int(two != fma)
+    assert n_diff >= 20  # the fixture does tell the two forms apart
+
+
 def test_rays_missing_box_and_max_per_ray():
     o = np.array([[0.0, 3.0, -4.0], [0.0, 0.0, -4.0]], np.float32)
     d = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 1.0]], np.float32)
@@ -771,6 +869,24 @@ def test_prune_alpha_threshold_and_transmittance_of_dropped_samples():
     pre = np.concatenate([[0.0], np.cumsum(sig * h)[:-1]])
     want = ((np.exp(-pre) >= 2e-4) & (sig >= s_cut)).astype(np.uint8)
     assert np.array_equal(keep2, want) and keep2[3] == 1 and keep2[6] == 0
+
+
+def test_prune_dropped_sample_still_attenuates():
+    # An opaque sample (tau = 8.0), then a faint one below the opacity
+    # threshold (tau = 0.03, alpha = 0.0296 < 0.05), then a dense one.  The
+    # third sample's transmittance is exp(-8.03) = 3.2585e-4 when the dropped
+    # sample attenuates and exp(-8.0) = 3.3546e-4 if it did not; eps =
+    # 3.3e-4 lies between, so only the attenuating rule drops sample 2.
+    h = 0.1
+    sig = np.array([80.0, 0.3, 5.0])
+    ts = np.arange(sig.size) * h
+    assert math.exp(-8.03) < 3.3e-4 < math.exp(-8.0)
+    keep, counts = oracle.prune(_packed([3]), ts, ts + h, sig, 3.3e-4, 0.05)
+    assert keep.tolist() == [1, 0, 0] and counts[0] == 1
+    # the same ray without the faint sample keeps the dense one
+    keep2, _ = oracle.prune(_packed([2]), ts[[0, 2]], ts[[0, 2]] + h, sig[[0, 2]],
+                            3.3e-4, 0.05)
+    assert keep2.tolist() == [1, 1]
 
 
 def test_prune_degenerate_settings_keep_everything():

@@ -416,6 +416,32 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays,
                             void* stream);
 
 /*
+ * The fused loss call of nacc_render_fwd_bwd_mse without a workspace
+ * argument, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Arguments, outputs and results are those of nacc_render_fwd_bwd_mse (the
+ * same kernels); the per-wave partial losses go to a static device array of
+ * NACC_MSE_NOALLOC_SCRATCH_BYTES instead.  The call allocates nothing: the
+ * first call on a device resolves that device's copy of the array (no
+ * allocation; each GPU keeps its copy until the process ends), later calls
+ * reuse it.  Every entry the call reads is written earlier in the same call,
+ * so no state carries over from one call to the next.
+ * Limits: n_rays <= NACC_MSE_NOALLOC_MAX_RAYS, else NACC_ECAPACITY with
+ * nothing launched.  Calls that overlap on one GPU (several streams, several
+ * host threads) share the array and race: serialise them.
+ */
+#define NACC_MSE_NOALLOC_SCRATCH_BYTES (8ll << 20)
+#define NACC_MSE_NOALLOC_MAX_RAYS 1044480ll
+int nacc_render_fwd_bwd_mse_noalloc(const int32_t* packed_info, int64_t n_rays,
+                                    int64_t n_samples, const float* t_starts,
+                                    const float* t_ends, const float* sigmas,
+                                    const float* rgbs, float early_stop_eps,
+                                    const float* target, int64_t loss_rays,
+                                    float* color, float* opacity, float* depth,
+                                    float* g_sigmas, float* g_rgbs, float* loss,
+                                    void* stream);
+
+/*
  * Occupancy-grid update (Sec. 2.1: the grid is cached and updated during
  * training; the update rule is delegated by the paper to Instant-NGP and
  * read here as: decay every cell, take the max with fresh density samples at

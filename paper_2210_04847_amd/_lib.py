@@ -120,6 +120,8 @@ _SIGNATURES = {
     "nacc_render_mse_workspace_size": (_I64, [_I64]),
     "nacc_render_fwd_bwd_mse": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _I64, _P, _P, _P,
                                        _P, _P, _P, _P, _SZ, _P]),
+    "nacc_render_fwd_bwd_mse_noalloc": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _F, _P, _I64, _P,
+                                               _P, _P, _P, _P, _P, _P]),
     "nacc_grid_decay": (_INT, [_P, _I64, _F, _P]),
     "nacc_grid_sample_cells": (_INT, [_U64, _U64, _P, _I64, ctypes.POINTER(GridDesc), _I32,
                                       _P, _P, _P]),
@@ -364,6 +366,27 @@ def render_fwd_bwd_mse(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_e
         float(early_stop_eps), _ptr(target), int(loss_rays), _ptr(color), _ptr(opacity),
         _ptr(depth), _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss), _ptr(workspace), workspace.numel(),
         _stream(stream)))
+
+
+# rays the allocation-free fused loss call takes (its static device scratch)
+MSE_NOALLOC_MAX_RAYS = 1044480
+
+
+def render_fwd_bwd_mse_noalloc(packed_info, t_starts, t_ends, sigmas, rgbs, early_stop_eps,
+                               target, color, opacity, depth, g_sigmas, g_rgbs, loss,
+                               loss_rays=0, stream=None):
+    n, e = _render_inputs(packed_info, t_starts, t_ends, sigmas, rgbs)
+    _need(target, torch.float32, "target", 3 * n)
+    _need(color, torch.float32, "color", 3 * n)
+    _need(opacity, torch.float32, "opacity", n)
+    _need(depth, torch.float32, "depth", n)
+    _need(g_sigmas, torch.float32, "g_sigmas", e)
+    _need(g_rgbs, torch.float32, "g_rgbs", 3 * e)
+    _need(loss, torch.float32, "loss", 1)
+    _check("nacc_render_fwd_bwd_mse_noalloc", lib.nacc_render_fwd_bwd_mse_noalloc(
+        _ptr(packed_info), n, e, _ptr(t_starts), _ptr(t_ends), _ptr(sigmas), _ptr(rgbs),
+        float(early_stop_eps), _ptr(target), int(loss_rays), _ptr(color), _ptr(opacity),
+        _ptr(depth), _ptr(g_sigmas), _ptr(g_rgbs), _ptr(loss), _stream(stream)))
 
 
 def grid_decay(occ, decay, stream=None):

@@ -18,6 +18,7 @@
 // between the forward and the backward pass (no second read, no second
 // transmittance evaluation for them).
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "scan.h"
@@ -684,33 +685,26 @@ int64_t nacc_render_mse_workspace_size(int64_t n_rays) {
     return (((mse_partials(n_rays) + mse_sums(n_rays)) * static_cast<int64_t>(sizeof(double)) + 255) / 256) * 256;
 }
 
-int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
-                            const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
-                            const float* target, int64_t loss_rays, float* color, float* opacity, float* depth,
-                            float* g_sigmas, float* g_rgbs, float* loss, void* workspace, size_t workspace_bytes,
-                            void* stream) {
-    clear_error();
-    int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
-    if (st != NACC_OK) return st;
-    NACC_REQUIRE(n_rays > 0, NACC_EINVAL, "the mean squared error needs n_rays > 0");
-    if (loss_rays == 0) loss_rays = n_rays;
-    NACC_REQUIRE(loss_rays >= n_rays, NACC_EINVAL, "loss_rays = %lld < n_rays = %lld",
-                 static_cast<long long>(loss_rays), static_cast<long long>(n_rays));
-    NACC_REQUIRE(target != nullptr && color != nullptr && opacity != nullptr && depth != nullptr &&
-                     g_sigmas != nullptr && g_rgbs != nullptr && loss != nullptr && workspace != nullptr,
-                 NACC_EINVAL, "outputs, target and workspace must be non-NULL");
-    const int64_t need = nacc_render_mse_workspace_size(n_rays);
-    NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE, "workspace of %zu bytes, need %lld",
-                 workspace_bytes, static_cast<long long>(need));
-    hipStream_t s = as_stream(stream);
+}  // extern "C"
+
+namespace {
+
+// The fused loss call after validation of everything but the workspace:
+// `partial` holds mse_partials(n_rays) + mse_sums(n_rays) doubles.  Every
+// entry the call reads is written earlier in the same call (one partial per
+// wave of the grid, one first-level sum per summing workgroup), so the
+// workspace needs no clearing.
+int render_mse_launch(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                      const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
+                      const float* target, int64_t loss_rays, float* color, float* opacity, float* depth,
+                      float* g_sigmas, float* g_rgbs, float* loss, double* partial, hipStream_t s) {
     const int64_t nb = mse_blocks(n_rays);
     const double count = 3.0 * static_cast<double>(loss_rays);
     const float inv_count2 = static_cast<float>(2.0 / count);
-    double* partial = static_cast<double*>(workspace);
     dispatch_cached<LaunchMse>(tuning().render_cached_chunks, dim3(static_cast<unsigned>(nb)), s, packed_info, n_rays,
                                n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target, inv_count2, color,
                                opacity, depth, g_sigmas, g_rgbs, partial);
-    st = check_launch("render fwd+bwd+mse");
+    int st = check_launch("render fwd+bwd+mse");
     if (st != NACC_OK) return st;
     const int64_t n_part = nb * kRaysPerRenderBlock;
     const int64_t n_sums = (n_part + kSumSpan - 1) / kSumSpan;
@@ -721,6 +715,105 @@ int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t 
     if (st != NACC_OK) return st;
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, s, sums, n_sums, 1.0 / count, loss);
     return check_launch("render loss");
+}
+
+// Argument checks shared by both forms of the fused loss call; the
+// workspace is checked by each form.
+int validate_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                 const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
+                 const float* target, int64_t& loss_rays, float* color, float* opacity, float* depth,
+                 float* g_sigmas, float* g_rgbs, float* loss) {
+    int st = validate_render(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(n_rays > 0, NACC_EINVAL, "the mean squared error needs n_rays > 0");
+    if (loss_rays == 0) loss_rays = n_rays;
+    NACC_REQUIRE(loss_rays >= n_rays, NACC_EINVAL, "loss_rays = %lld < n_rays = %lld",
+                 static_cast<long long>(loss_rays), static_cast<long long>(n_rays));
+    NACC_REQUIRE(target != nullptr && color != nullptr && opacity != nullptr && depth != nullptr &&
+                     g_sigmas != nullptr && g_rgbs != nullptr && loss != nullptr,
+                 NACC_EINVAL, "outputs and target must be non-NULL");
+    return NACC_OK;
+}
+
+}  // namespace
+
+// Device memory of nacc_render_fwd_bwd_mse_noalloc, in place of a caller's
+// workspace: every GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address resolved
+// for the current device by mse_static_scratch.
+static __device__ __align__(256) unsigned char scratch[NACC_MSE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, resolved once per
+// device (hipGetSymbolAddress with that device current; no allocation).
+int mse_static_scratch(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    NACC_REQUIRE(e == hipSuccess, NACC_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    NACC_REQUIRE(dev >= 0 && dev < kMaxDevices, NACC_ENOTSUP, "device %d beyond the %d devices supported", dev,
+                 kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        NACC_REQUIRE(e == hipSuccess && p != nullptr, NACC_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                     hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<double*>(g_scratch_ptr[dev]);
+    return NACC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nacc_render_fwd_bwd_mse(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
+                            const float* t_ends, const float* sigmas, const float* rgbs, float early_stop_eps,
+                            const float* target, int64_t loss_rays, float* color, float* opacity, float* depth,
+                            float* g_sigmas, float* g_rgbs, float* loss, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+    clear_error();
+    int st = validate_mse(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                          loss_rays, color, opacity, depth, g_sigmas, g_rgbs, loss);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(workspace != nullptr, NACC_EINVAL, "workspace must be non-NULL");
+    const int64_t need = nacc_render_mse_workspace_size(n_rays);
+    NACC_REQUIRE(static_cast<int64_t>(workspace_bytes) >= need, NACC_ESHAPE, "workspace of %zu bytes, need %lld",
+                 workspace_bytes, static_cast<long long>(need));
+    return render_mse_launch(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                             loss_rays, color, opacity, depth, g_sigmas, g_rgbs, loss,
+                             static_cast<double*>(workspace), as_stream(stream));
+}
+
+int nacc_render_fwd_bwd_mse_noalloc(const int32_t* packed_info, int64_t n_rays, int64_t n_samples,
+                                    const float* t_starts, const float* t_ends, const float* sigmas,
+                                    const float* rgbs, float early_stop_eps, const float* target, int64_t loss_rays,
+                                    float* color, float* opacity, float* depth, float* g_sigmas, float* g_rgbs,
+                                    float* loss, void* stream) {
+    clear_error();
+    int st = validate_mse(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                          loss_rays, color, opacity, depth, g_sigmas, g_rgbs, loss);
+    if (st != NACC_OK) return st;
+    NACC_REQUIRE(n_rays <= NACC_MSE_NOALLOC_MAX_RAYS, NACC_ECAPACITY,
+                 "n_rays = %lld exceeds the %lld rays the static scratch of %lld bytes holds",
+                 static_cast<long long>(n_rays), static_cast<long long>(NACC_MSE_NOALLOC_MAX_RAYS),
+                 static_cast<long long>(NACC_MSE_NOALLOC_SCRATCH_BYTES));
+    NACC_REQUIRE(nacc_render_mse_workspace_size(n_rays) <= NACC_MSE_NOALLOC_SCRATCH_BYTES, NACC_ECAPACITY,
+                 "n_rays = %lld needs %lld bytes of scratch, more than the static %lld",
+                 static_cast<long long>(n_rays), static_cast<long long>(nacc_render_mse_workspace_size(n_rays)),
+                 static_cast<long long>(NACC_MSE_NOALLOC_SCRATCH_BYTES));
+    double* partial = nullptr;
+    st = mse_static_scratch(&partial);
+    if (st != NACC_OK) return st;
+    return render_mse_launch(packed_info, n_rays, n_samples, t_starts, t_ends, sigmas, rgbs, early_stop_eps, target,
+                             loss_rays, color, opacity, depth, g_sigmas, g_rgbs, loss, partial, as_stream(stream));
 }
 
 int64_t nacc_prune_workspace_size(int64_t n_rays) {

@@ -77,9 +77,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
-    ap.add_argument("--skip-field", choices=["on", "off"], default="off",
-                    help="march with the grid's skip field (empty-space skipping; pays off on "
-                         "sparse scenes only)")
+    ap.add_argument("--skip-field", choices=["auto", "on", "off"], default="auto",
+                    help="march with the grid's skip buffer (empty-space skipping): auto uses it "
+                         "for uniform steps through the box lookup (its halo bits let the count "
+                         "pass test runs of candidates at once) and not for cone steps (its "
+                         "distance field pays off on sparse scenes only)")
     ap.add_argument("--alpha-thre", type=float, default=None,
                     help="prune the marched samples by visibility before shading them, as the "
                          "paper's ray_marching with sigma_fn (T >= early_stop_eps, alpha >= this; "
@@ -95,6 +97,13 @@ def parse():
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
     return ap.parse_args()
+
+
+def use_skip(args, w):
+    """Whether a workload marches with the grid's skip buffer."""
+    if args.skip_field != "auto":
+        return args.skip_field == "on"
+    return getattr(w, "cone", 0.0) == 0.0 and getattr(w, "lookup", "aabb") == "aabb"
 
 
 def grid_label(w):
@@ -406,10 +415,11 @@ MARCH_SOURCES = ("paper_2210_04847_amd/csrc/march.hip+paper_2210_04847_amd/csrc/
                  "paper_2210_04847_amd/csrc/scan.h+paper_2210_04847_amd/csrc/common.h")
 
 
-def recorded_traffic(kernel, source):
-    """HBM bytes per launch of `kernel` from the committed counter summaries
-    (profiles/*.md, lines 'traffic_record: ...'), or None when none matches
-    the current source of the kernel (the counters are then stale)."""
+def recorded_traffic(kernel, source, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summaries (profiles/*.md, lines 'traffic_record: ...'), or None
+    when none was taken on this workload or none matches the current source
+    of the kernel (the counters are then stale)."""
     import glob
     import hashlib
     # `source`: the kernel's files joined by '+', hashed in that order
@@ -422,7 +432,8 @@ def recorded_traffic(kernel, source):
             if not line.startswith("traffic_record:"):
                 continue
             kv = dict(item.split("=", 1) for item in line.split()[1:])
-            if kv.get("kernel") == kernel and kv.get("source") == source and kv.get("sha256_16") == digest:
+            if (kv.get("kernel") == kernel and kv.get("workload") == workload
+                    and kv.get("source") == source and kv.get("sha256_16") == digest):
                 return float(kv["read_bytes"]) + float(kv["write_bytes"])
     return None
 
@@ -641,7 +652,7 @@ def bench_train(args, torch, nacc):
     grid.set_occupancy(t(inp["occ"]), THRESHOLD)
     field = nacc.BlobField(inp["scene"], device=dev)
     st = Step(torch, nacc, w, t(inp["rays_o"]), t(inp["rays_d"]), t(inp["targets"]), grid, field,
-              skip_field=args.skip_field == "on", forward_only=forward_only, seed=4000 + w.seed_base,
+              skip_field=use_skip(args, w), forward_only=forward_only, seed=4000 + w.seed_base,
               alpha_thre=args.alpha_thre)
     torch.cuda.synchronize()
     if args.copy_probe_mib > 0:
@@ -750,7 +761,7 @@ def bench_train(args, torch, nacc):
     render_roofline = {
         "bound": "hbm", "kernel": "render", "achieved": render_bps / 1e9, "peak": HBM_PEAK / 1e9,
         "unit": "GB/s", "frac": render_bps / HBM_PEAK,
-        "traffic": (recorded_traffic("render_mse_kernel", RENDER_SOURCES)
+        "traffic": (recorded_traffic("render_mse_kernel", RENDER_SOURCES, w.name)
                     if not forward_only else None)}
     if dominant == "march_count":
         # the count pass is bound by its per-candidate arithmetic
@@ -759,7 +770,7 @@ def bench_train(args, torch, nacc):
         ops_s = ops / (phase_avg["march_count"] * 1e-3)
         # HBM bytes of the uniform-step count kernel, when counters of the
         # current source are committed (the phase adds the scan's small kernels)
-        traffic = (recorded_traffic("count_uniform_kernel", MARCH_SOURCES)
+        traffic = (recorded_traffic("count_uniform_kernel", MARCH_SOURCES, w.name)
                    if getattr(w, "cone", 0.0) == 0.0 and getattr(w, "lookup", "aabb") == "aabb"
                    else None)
         roofline = {"bound": "alu", "kernel": "march_count", "achieved": ops_s / 1e12,
@@ -801,7 +812,7 @@ def bench_train(args, torch, nacc):
                    "cone": getattr(w, "cone", 0.0), "early_stop_eps": w.early_stop_eps,
                    "pass": "forward" if forward_only else "forward+mse+backward",
                    "grid_update_every": EMA_EVERY, "grid_update_cells": EMA_CELLS,
-                   "form": form, "skip_field": args.skip_field, "tuning": tuned,
+                   "form": form, "skip_field": "on" if use_skip(args, w) else "off", "tuning": tuned,
                    "visibility_pruning": (None if args.alpha_thre is None else
                                           {"early_stop_eps": w.early_stop_eps,
                                            "alpha_thre": args.alpha_thre}),
@@ -855,13 +866,23 @@ def bench_dynamic(args, torch, nacc):
     upd_set = t(synth.update_frames(EMA_CELLS, nf, 4100 + w.seed_base)) if shared else None
     batched = Step(torch, nacc, w, rays_o, rays_d, tgt, grid, field,
                    grid_id=None if shared else frame, ray_set=frame, update_set=upd_set,
-                   seed=4000 + w.seed_base, skip_field=args.skip_field == "on")
+                   seed=4000 + w.seed_base, skip_field=use_skip(args, w))
     lib = nacc._lib
     words = res ** 3 // 32
-    c3 = (res // 4) ** 3
     starts = np.concatenate([[0], np.cumsum(inp["counts"])]).astype(np.int64)
     desc1 = lib.grid_desc(w.box[:3], w.box[3:], res)
     params = lib.march_params(w.near, w.far, w.dt)
+
+    # each frame's own skip buffer, built once like the grid state it comes
+    # from, only when the batched step marches with it too
+    frame_skip = {}
+    if use_skip(args, w):
+        for f in range(nf):
+            g = 0 if shared else f
+            if g not in frame_skip:
+                buf = torch.empty(lib.grid_skip_bytes(desc1), dtype=torch.uint8, device=dev)
+                lib.grid_build_skip(grid.bits[g * words:(g + 1) * words], desc1, buf)
+                frame_skip[g] = buf
 
     def plain_frames(keep=None):
         """One plain call sequence per frame: its rays, its grid (a view of the
@@ -875,9 +896,7 @@ def bench_dynamic(args, torch, nacc):
             o, d = rays_o[a:b], rays_d[a:b]
             g = 0 if shared else f
             bits = grid.bits[g * words:(g + 1) * words]
-            # the frame's skip field (+ the build scratch the size check expects),
-            # only when the batched step marches with it too
-            skip = grid.skip[g * c3:(g + 2) * c3] if args.skip_field == "on" else None
+            skip = frame_skip.get(g)
             packed = torch.empty((n, 2), dtype=torch.int32, device=dev)
             total = torch.empty(1, dtype=torch.int64, device=dev)
             ws = torch.empty(lib.march_workspace_size(n, desc1, params), dtype=torch.uint8,
@@ -990,7 +1009,8 @@ def bench_dynamic(args, torch, nacc):
                    "pass": "forward+mse+backward",
                    "form": ("batched, the library's step plan (one HIP graph per step)"
                             if plan is not None else "batched, one HIP graph per step"),
-                   "tuning": tuned, "skip_field": args.skip_field, "parallelism": "single GPU"},
+                   "tuning": tuned, "skip_field": "on" if use_skip(args, w) else "off",
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "render", "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": None},
@@ -1147,7 +1167,7 @@ def bench_images(args, torch, nacc):
     counts = inp["counts"]
     offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     params = lib.march_params(sw.near, sw.far, sw.dt)
-    skip = grid.skip if args.skip_field == "on" else None
+    skip = grid.skip if use_skip(args, sw) else None
     eps = w.early_stop_eps
     i32, f32 = torch.int32, torch.float32
 
@@ -1294,7 +1314,7 @@ def bench_images(args, torch, nacc):
                    "grid": f"{sw.res}^3 bit-packed", "blobs": sw.n_blobs,
                    "early_stop_eps": eps, "pass": "forward",
                    "form": "one fused launch for all images vs per-image plain call sequences",
-                   "skip_field": args.skip_field, "parallelism": "single GPU"},
+                   "skip_field": "on" if use_skip(args, sw) else "off", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "fused_render", "achieved": ops_s / 1e12,
                      "peak": ALU_PEAK / 1e12, "unit": "TOP/s", "frac": ops_s / ALU_PEAK,
                      "traffic": None,

@@ -483,8 +483,10 @@ int nacc_grid_update_max(float* occ, const int32_t* cells,
 /* Largest distance the skip field stores (coarse cells). */
 #define NACC_SKIP_CAP 15
 
-/* Bytes of the skip field of `grid` (n_grids grids), 0 if res % 4 != 0:
- * 2 * n_grids * (res/4)^3 (the field, then scratch for its build). */
+/* Bytes of the skip buffer of `grid` (n_grids grids), 0 if res % 4 != 0:
+ * the distance field (n_grids * (res/4)^3 bytes), as much scratch for its
+ * build, then, from the next multiple of 256 bytes, the halo bits
+ * (n_grids * 2 * ceil((res/2)^3 / 64) 32-bit words). */
 int64_t nacc_grid_skip_bytes(const nacc_grid_desc* grid);
 
 /*
@@ -496,8 +498,14 @@ int64_t nacc_grid_skip_bytes(const nacc_grid_desc* grid);
  * so 0 marks coarse cells with occupied cells.  A point whose coarse cell
  * has distance D >= 2 has only empty fine cells within 4 (D - 1) fine cells
  * of it along every axis.  The field is the first n_grids * (res/4)^3 bytes
- * of `skip`; the rest is scratch of the build.
- *   bits  uint32[n_grids * res^3 / 32]; skip out uint8[nacc_grid_skip_bytes].
+ * of `skip`, followed by scratch of the build.  The halo bits come after
+ * (layout at nacc_grid_skip_bytes): per grid, one bit per cell of 2x2x2 fine
+ * cells (C order over (res/2)^3 cells, LSB first), set iff some occupied
+ * fine cell lies within 2 fine cells of it on every axis; the uniform-step
+ * box lookup tests them once per run of candidates whose midpoints stay
+ * within that reach.
+ *   bits  uint32[n_grids * res^3 / 32]; skip out uint8[nacc_grid_skip_bytes],
+ *         4-byte aligned.
  * NACC_ENOTSUP unless res % 4 == 0.
  */
 int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid,

@@ -28,6 +28,30 @@ inline float axis_scale(int res, float lo, float hi) {
 }
 
 constexpr int kWave = 64;
+constexpr int kWaveLog2 = 6;
+
+// Layout of the skip buffer of nacc_grid_build_skip for grids of res^3
+// cells (res % 4 == 0): the distance field (one byte per coarse cell of
+// 4^3 fine cells, per grid), scratch of its build of the same size, then,
+// 256-byte aligned, the halo bits: per grid one bit per cell of 2^3 fine
+// cells (C order, LSB first, rounded up to whole 64-bit words), set when an
+// occupied fine cell lies within kHaloReach fine cells (on every axis) of it.
+constexpr int kHaloReach = 2;
+
+__host__ __device__ inline int64_t skip_field_cells(int res) {
+    const int64_t c = res / 4;
+    return c * c * c;
+}
+
+__host__ __device__ inline int64_t halo_offset(int res, int n_grids) {
+    return ((2 * skip_field_cells(res) * n_grids + 255) / 256) * 256;
+}
+
+// 32-bit words of one grid's halo bits.
+__host__ __device__ inline int64_t halo_words(int res) {
+    const int64_t h = res / 2;
+    return ((h * h * h + 63) / 64) * 2;
+}
 
 }  // namespace nacc
 

@@ -177,6 +177,53 @@ __global__ __launch_bounds__(kThreads) void distance_pass_kernel(const uint8_t* 
     out[id] = static_cast<uint8_t>(best);
 }
 
+// Halo bits: one lane per cell of 2^3 fine cells; the lane ORs the fine
+// bits within kHaloReach cells of its own on every axis (up to 6 x 6 rows of
+// 6 bits, clipped to the grid; the 6 bits of a row lie in at most two
+// words), and each wave packs its 64 cells into two words by a ballot.  The
+// lanes of a grid are rounded up to whole waves, so no wave spans two grids.
+__global__ __launch_bounds__(kThreads) void halo_kernel(const uint32_t* __restrict__ bits, int res, int n_grids,
+                                                        uint32_t words, uint32_t out_words,
+                                                        uint32_t* __restrict__ out) {
+    const int h = res / 2;
+    const int64_t cells = static_cast<int64_t>(h) * h * h;
+    const int64_t per_grid = static_cast<int64_t>(out_words) * 32;  // lanes per grid, whole waves
+    const int64_t id = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t total = per_grid * n_grids;
+    const int64_t grid = id / per_grid;
+    const int64_t cell = id % per_grid;
+    bool any = false;
+    if (id < total && cell < cells) {
+        const int cx = static_cast<int>(cell / (static_cast<int64_t>(h) * h));
+        const int cy = static_cast<int>((cell / h) % h);
+        const int cz = static_cast<int>(cell % h);
+        const uint32_t* fine = bits + grid * words;
+        const int x0 = max(2 * cx - kHaloReach, 0), x1 = min(2 * cx + 1 + kHaloReach, res - 1);
+        const int y0 = max(2 * cy - kHaloReach, 0), y1 = min(2 * cy + 1 + kHaloReach, res - 1);
+        const int z0 = max(2 * cz - kHaloReach, 0), z1 = min(2 * cz + 1 + kHaloReach, res - 1);
+        const uint64_t want = (1ull << (z1 - z0 + 1)) - 1ull;
+        for (int x = x0; x <= x1 && !any; ++x) {
+            for (int y = y0; y <= y1; ++y) {
+                const int64_t a = (static_cast<int64_t>(x) * res + y) * res + z0;  // first bit of the run
+                const int64_t b = a + (z1 - z0);                                  // last bit
+                const uint64_t lo = fine[a >> 5];
+                const uint64_t hi = (b >> 5) != (a >> 5) ? fine[b >> 5] : 0u;
+                if ((((hi << 32) | lo) >> (a & 31)) & want) {
+                    any = true;
+                    break;
+                }
+            }
+        }
+    }
+    const uint64_t m = ballot(any);
+    const int lane = lane_id();
+    const int64_t word = (id - lane) / 32;  // id - lane: the wave's first lane, a multiple of 64
+    if (lane == 0 && id - lane < total) {
+        out[word] = static_cast<uint32_t>(m);
+        out[word + 1] = static_cast<uint32_t>(m >> 32);
+    }
+}
+
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -238,8 +285,7 @@ int nacc_grid_update_max(float* occ, const int32_t* cells, const float* values, 
 
 int64_t nacc_grid_skip_bytes(const nacc_grid_desc* grid) {
     if (grid == nullptr || grid->res < 4 || grid->res % 4 != 0 || grid->n_grids < 1) return 0;
-    const int64_t c = grid->res / 4;
-    return 2 * c * c * c * grid->n_grids;
+    return halo_offset(grid->res, grid->n_grids) + halo_words(grid->res) * 4 * grid->n_grids;
 }
 
 int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid, uint8_t* skip, void* stream) {
@@ -251,6 +297,7 @@ int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid, uint8
     const int64_t cells = static_cast<int64_t>(grid->res) * grid->res * grid->res;
     NACC_REQUIRE(cells % 32 == 0, NACC_ESHAPE, "res^3 is not a multiple of 32");
     NACC_REQUIRE(bits != nullptr && skip != nullptr, NACC_EINVAL, "bits and skip must be non-NULL");
+    NACC_REQUIRE(reinterpret_cast<uintptr_t>(skip) % 4 == 0, NACC_EINVAL, "skip must be 4-byte aligned");
     const int c = grid->res / 4;
     const int64_t n = static_cast<int64_t>(c) * c * c * grid->n_grids;
     uint8_t* field = skip;
@@ -272,7 +319,12 @@ int nacc_grid_build_skip(const uint32_t* bits, const nacc_grid_desc* grid, uint8
         src = dst;
         dst = t;
     }
-    return NACC_OK;
+    const int64_t hw = halo_words(grid->res);
+    uint32_t* halo = reinterpret_cast<uint32_t*>(skip + halo_offset(grid->res, grid->n_grids));
+    hipLaunchKernelGGL(halo_kernel, dim3(blocks_for(hw * 32 * grid->n_grids)), dim3(kThreads), 0, s, bits,
+                       grid->res, grid->n_grids, static_cast<uint32_t>(cells / 32), static_cast<uint32_t>(hw),
+                       halo);
+    return check_launch("grid skip halo");
 }
 
 int nacc_grid_pack(const float* occ, int64_t n_cells, float threshold, uint32_t* bits, void* stream) {

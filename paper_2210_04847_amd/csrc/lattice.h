@@ -32,6 +32,10 @@ struct GridK {
     uint32_t skip_cells;  // bytes per grid of the skip field (coarse^3)
     uint32_t res2, coarse2;  // res^2, coarse^2
     uint32_t bytes;          // bytes of all grids' bit arrays (< 2^32)
+    int halo_res;            // halo cells per axis (res / 2)
+    uint32_t halo_res2;      // halo_res^2
+    uint32_t halo_words;     // 32-bit words per grid of the halo bits
+    uint32_t halo_bytes;     // bytes of all grids' halo bits
 };
 
 // The grids' words are read through a buffer resource: 32-bit byte offsets
@@ -177,6 +181,7 @@ __device__ __forceinline__ bool grid_of_ray(const int32_t* __restrict__ grid_id,
 struct RaySpan {
     float t_near, t_far;
     uint32_t word0;
+    uint32_t grid;  // index of the ray's grid (box / contraction lookups)
     bool valid;
     float o[3], d[3];  // the ray itself
 };
@@ -192,6 +197,7 @@ __device__ __forceinline__ RaySpan ray_span(int64_t r, const float* __restrict__
         s.d[i] = rays_d[3 * r + i];
     }
     s.valid = grid_of_ray<LOOKUP>(grid_id, r, g, s.word0);
+    s.grid = s.word0 / g.words;  // one ray per lane: once per 64 rays of a wave
     s.valid = clip_ray(s.o, s.d, c, p.near_plane, p.far_plane, s.t_near, s.t_far) && s.valid;
     return s;
 }
@@ -204,6 +210,7 @@ __device__ __forceinline__ RaySpan read_span(const RaySpan& s, int lane) {
     b.t_near = read_lane(s.t_near, lane);
     b.t_far = read_lane(s.t_far, lane);
     b.word0 = static_cast<uint32_t>(read_lane(static_cast<int>(s.word0), lane));
+    b.grid = static_cast<uint32_t>(read_lane(static_cast<int>(s.grid), lane));
     b.valid = read_lane(s.valid ? 1 : 0, lane) != 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -279,6 +286,10 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     g.res2 = static_cast<uint32_t>(grid.res) * static_cast<uint32_t>(grid.res);
     g.coarse2 = static_cast<uint32_t>(g.coarse) * static_cast<uint32_t>(g.coarse);
     g.bytes = static_cast<uint32_t>(static_cast<int64_t>(grid.n_grids) * g.words * 4);
+    g.halo_res = grid.res / 2;
+    g.halo_res2 = static_cast<uint32_t>(g.halo_res) * static_cast<uint32_t>(g.halo_res);
+    g.halo_words = static_cast<uint32_t>(halo_words(grid.res));
+    g.halo_bytes = static_cast<uint32_t>(static_cast<int64_t>(grid.n_grids) * g.halo_words * 4);
     p.near_plane = params.near_plane;
     p.far_plane = params.far_plane;
     p.dt = params.dt;

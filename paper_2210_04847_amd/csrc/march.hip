@@ -334,13 +334,191 @@ __device__ __forceinline__ int march_ray_uniform(
     return count;
 }
 
+// ---------------------------------------------------------------------------
+// Uniform steps through the box lookup with the halo bits of the skip
+// buffer.  A ray's candidates are grouped into segments of G consecutive
+// ones (segment j: candidates [j G, j G + G)); a wave tests 64 segments at
+// once, one halo bit each at the segment's centre, and then looks up one by
+// one only the candidates of the segments whose bit is set, 64 at a time
+// (64 / G segments per iteration, in segment order, so the ballots still
+// list the samples in t order).
+//
+// A clear bit proves its segment empty.  The segment's midpoints lie within
+// (G/2) dt of its centre in t, so their fine-cell coordinates
+// u_i = (x_i - lo_i) s_i differ from the centre's by less than
+// v (G/2) dt plus rounding, v = max_i s_i |d_i|.  G is the largest power of
+// two up to 32 that keeps this below kHaloReach cells; the cells of the
+// midpoints then lie within kHaloReach cells of the centre's cell (clamping
+// into the grid only brings coordinates closer), so within kHaloReach cells
+// of the centre's 2x2x2 halo cell on every axis, and a clear halo bit says
+// none of those cells is occupied.  Rays that would need G < 8 are marched
+// candidate by candidate.  The samples are exactly those of the plain
+// traversal.
+// ---------------------------------------------------------------------------
+constexpr int kMinSegmentLog2 = 3;  // segments of 8, 16 or 32 candidates
+
+struct SegRay {
+    int log_g;       // log2 of the candidates per segment; 0: no segments
+    uint32_t halo0;  // first halo word of the ray's grid
+};
+
+__device__ __forceinline__ SegRay seg_ray(const GridK& g, const RaySpan& span, const StepK& p) {
+    SegRay sg{0, 0u};
+    const float* o = span.o;
+    const float* d = span.d;
+    const float v = fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
+    const float smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
+    const float omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
+    const float dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+    const float tmax = fmaxf(fabsf(span.t_near), fabsf(span.t_far));
+    // allowances in cells, each taken generously: the rounding of both
+    // positions (a few ulps of the largest coordinate the ray reaches), of
+    // the cell coordinates, and of the t values (a few ulps of t, times v)
+    const float slack_x = (omax + dmax * tmax + 1.0f) * 0x1p-20f;
+    const float slack = 2.0f * smax * slack_x + static_cast<float>(g.res) * 0x1p-17f + v * tmax * 0x1p-20f;
+    const float budget = static_cast<float>(kHaloReach) - slack;
+    int lg = 5;
+    while (lg >= kMinSegmentLog2 && !(v * ldexpf(p.dt, lg - 1) * (1.0f + 0x1p-10f) <= budget)) --lg;
+    if (lg >= kMinSegmentLog2) {
+        sg.log_g = lg;
+        sg.halo0 = span.grid * g.halo_words;
+    }
+    return sg;
+}
+
+// Halo bit of the cell holding point x (the box lookup's clamped cell
+// coordinates, halved).
+__device__ __forceinline__ bool halo_bit(__amdgpu_buffer_rsrc_t rs, const GridK& g, uint32_t halo0, float x0,
+                                         float x1, float x2) {
+    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
+    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
+    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
+    const uint32_t cell =
+        __umul24(j0 >> 1, g.halo_res2) + (__umul24(j1 >> 1, static_cast<uint32_t>(g.halo_res)) + (j2 >> 1));
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (halo0 + (cell >> 5)) << 2, 0, 0);
+    return ((w >> (cell & 31u)) & 1u) != 0u;
+}
+
+// Live-segment ballot of block b of a ray's segments (segment j = b 64 +
+// lane): its first candidate lies before t_far (ballot `vm`, returned too)
+// and the halo bit at its centre is set.
+__device__ __forceinline__ uint64_t live_segments(const RaySpan& span, const uint32_t* __restrict__ halo,
+                                                  const GridK& g, const StepK& p, const SegRay& sg, int b,
+                                                  uint64_t& vm) {
+    const int lane = lane_id();
+    const int log_g = sg.log_g;
+    const int k_first = (b * kWave + lane) << log_g;
+    // kMaxCandidates is a multiple of every G: a segment starting below it
+    // ends at or below it
+    const bool valid = k_first < kMaxCandidates && span.t_near + static_cast<float>(k_first) * p.dt < span.t_far;
+    vm = ballot(valid);
+    if (vm == 0ull) return 0ull;
+    const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
+    const float tc = span.t_near + static_cast<float>(k_first + (1 << (log_g - 1))) * p.dt;
+    const bool hb = halo_bit(hrs, g, sg.halo0, span.o[0] + span.d[0] * tc, span.o[1] + span.d[1] * tc,
+                             span.o[2] + span.d[2] * tc);
+    return vm & ballot(hb);
+}
+
+// Count pass of one ray by segments (whole wave): looks up every candidate
+// of the live segments, 64 at a time.  The occupancy ballots are turned
+// back into the plain traversal's chunk masks (chunk j: candidates
+// [64 j, 64 j + 64)), so the fill pass replays them exactly as it does for
+// the plain traversal: each segment's G bits lie inside one chunk (G
+// divides 64, segments are aligned to G), and the first lane of each
+// segment ORs them into that chunk's mask in this wave's LDS slice
+// (`chunk_masks`, 64 entries; chunks from n_masks on are not stored and the
+// fill traverses them again).  `list` is this wave's 64-byte LDS slice for
+// a block's live segments.  Returns the ray's count.
+__device__ __forceinline__ int count_ray_segments(const RaySpan& span, const uint32_t* __restrict__ bits,
+                                                  const uint32_t* __restrict__ halo, const GridK& g,
+                                                  const StepK& p, const SegRay& sg, uint8_t* list,
+                                                  uint64_t* chunk_masks, uint64_t* __restrict__ masks,
+                                                  int n_masks) {
+    const int lane = lane_id();
+    const int log_g = sg.log_g;
+    const int gmask = (1 << log_g) - 1;
+    const int per_iter = kWave >> log_g;  // segments per wave iteration
+    const uint64_t field = (1ull << (1 << log_g)) - 1ull;
+    chunk_masks[lane] = 0ull;
+    int count = 0;
+    bool done = false;
+    for (int b = 0; !done; ++b) {
+        uint64_t vm;
+        const uint64_t lm = live_segments(span, halo, g, p, sg, b, vm);
+        if (vm == 0ull) break;  // t at a segment's first candidate is non-decreasing in j
+        if (((lm >> lane) & 1ull) != 0ull) list[bits_below(lm)] = static_cast<uint8_t>(lane);
+        wave_lds_sync();
+        const int n_live = static_cast<int>(__popcll(lm));
+        // two chunks per iteration, both chunks' grid words in flight before
+        // either is tested (a chunk past the live segments looks up clamped
+        // cells and counts nothing)
+        for (int q = 0; q < n_live && !done; q += 2 * per_iter) {
+            int k[2];
+            float t0[2], t1[2];
+            uint64_t alive[2], m[2];
+            Probe pq[2];
+            uint32_t w[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int slot = q + u * per_iter + (lane >> log_g);
+                const bool in = slot < n_live;
+                const int seg = in ? static_cast<int>(list[slot]) : 0;
+                k[u] = ((b * kWave + seg) << log_g) + (lane & gmask);
+                t0[u] = span.t_near + static_cast<float>(k[u]) * p.dt;
+                t1[u] = span.t_near + static_cast<float>(k[u] + 1) * p.dt;
+                alive[u] = ballot(in && t0[u] < span.t_far);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float tm = (t0[u] + t1[u]) * 0.5f;
+                pq[u] = probe<NACC_LOOKUP_AABB>(g, span.word0, span.o[0] + span.d[0] * tm,
+                                                span.o[1] + span.d[1] * tm, span.o[2] + span.d[2] * tm);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) w[u] = grid_word(grid_rsrc(bits, g), pq[u].word);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                m[u] = alive[u] & ballot(((w[u] >> pq[u].bit) & 1u) != 0u);
+                if ((lane & gmask) == 0 && (k[u] >> kWaveLog2) < n_masks) {
+                    const uint64_t part = (m[u] >> lane) & field;  // this segment's hits
+                    if (part != 0ull) {
+                        __hip_atomic_fetch_or(chunk_masks + (k[u] >> kWaveLog2), part << (k[u] & (kWave - 1)),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    }
+                }
+            }
+            count += static_cast<int>(__popcll(m[0])) + static_cast<int>(__popcll(m[1]));
+            if (p.max_per_ray > 0 && count >= p.max_per_ray) {
+                count = p.max_per_ray;
+                done = true;
+            }
+        }
+        if (vm != ~0ull) break;  // the ray's segments end in this block
+        wave_lds_sync();         // the list is written again by the next block
+    }
+    wave_lds_sync();
+    if (masks != nullptr && lane < n_masks) masks[lane] = chunk_masks[lane];
+    wave_lds_sync();  // read before the next ray clears them
+    return count;
+}
+
+// The box lookup with a skip buffer marches by segments (its halo bits).
+template <int LOOKUP, bool SKIP>
+constexpr bool kSegments = LOOKUP == NACC_LOOKUP_AABB && SKIP;
+
 template <int LOOKUP, bool SKIP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d,
     const int32_t* __restrict__ grid_id, int64_t n_rays, const uint32_t* __restrict__ bits,
-    const uint8_t* __restrict__ skip, GridK g, ClipK c, StepK p, int32_t* __restrict__ packed_info,
-    int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks, int split) {
+    const uint8_t* __restrict__ skip, const uint32_t* __restrict__ halo, GridK g, ClipK c, StepK p,
+    int32_t* __restrict__ packed_info, int64_t* __restrict__ block_sums, uint64_t* __restrict__ masks, int n_masks,
+    int split) {
     __shared__ int64_t wave_total[WAVES];
+    // segments: each wave's chunk masks, then its list of live segments
+    __shared__ uint64_t seg_masks[kSegments<LOOKUP, SKIP> ? WAVES * kWave : 1];
+    __shared__ uint8_t seg_lists[kSegments<LOOKUP, SKIP> ? WAVES * kWave : 1];
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     // workgroup b takes part b % split of the group of kRaysPerBlock rays
     // b / split: per = kRaysPerBlock / split rays from `first`
@@ -359,9 +537,23 @@ __global__ __launch_bounds__(WAVES * kWave) void count_uniform_kernel(
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const RaySpan span = read_span(spans, i / WAVES);
-        const int n = march_ray_uniform<LOOKUP, false, SKIP>(
-            r, span, rays_o, rays_d, bits, skip, g, p, 0, 0, 0, nullptr, nullptr, nullptr, unused,
-            masks != nullptr ? masks + r * n_masks : nullptr, masks != nullptr ? n_masks : 0);
+        uint64_t* ray_masks = masks != nullptr ? masks + r * n_masks : nullptr;
+        const int ray_n_masks = masks != nullptr ? n_masks : 0;
+        int n;
+        if constexpr (kSegments<LOOKUP, SKIP>) {
+            const SegRay sg = span.valid ? seg_ray(g, span, p) : SegRay{0, 0u};
+            if (sg.log_g != 0) {
+                n = count_ray_segments(span, bits, halo, g, p, sg, seg_lists + wave * kWave,
+                                       seg_masks + wave * kWave, ray_masks, ray_n_masks);
+            } else {
+                n = march_ray_uniform<LOOKUP, false, false>(r, span, rays_o, rays_d, bits, skip, g, p, 0, 0, 0,
+                                                            nullptr, nullptr, nullptr, unused, ray_masks,
+                                                            ray_n_masks);
+            }
+        } else {
+            n = march_ray_uniform<LOOKUP, false, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, 0, 0, 0, nullptr,
+                                                       nullptr, nullptr, unused, ray_masks, ray_n_masks);
+        }
         if (lane_id() == 0) packed_info[2 * r + 1] = n;
         total += n;
     }
@@ -484,9 +676,18 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
         const RaySpan span = read_span(spans, i / WAVES);
+        // the box lookup's count pass leaves the plain traversal's masks also
+        // when it marched by segments
+        constexpr bool kFillSkip = SKIP && !kSegments<LOOKUP, SKIP>;
         if (masks != nullptr) {
-            fill_ray_from_masks<LOOKUP, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
-                                              ray_indices, t_starts, t_ends, overflow, masks + r * n_masks, n_masks);
+            fill_ray_from_masks<LOOKUP, kFillSkip>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit,
+                                                   capacity, ray_indices, t_starts, t_ends, overflow,
+                                                   masks + r * n_masks, n_masks);
+        } else if constexpr (kSegments<LOOKUP, SKIP>) {
+            // no stored masks: the segment count pass finds the samples with
+            // fewer lookups; its ballots are written here directly
+            march_ray_uniform<LOOKUP, true, false>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit,
+                                                   capacity, ray_indices, t_starts, t_ends, overflow);
         } else {
             march_ray_uniform<LOOKUP, true, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
                                                   ray_indices, t_starts, t_ends, overflow);
@@ -963,6 +1164,12 @@ ConeWork cone_work(void* workspace, const Layout& l) {
 // depend on it.
 int march_split(int64_t groups) { return groups < 256 ? 4 : (groups < 512 ? 2 : 1); }
 
+// Halo bits of a skip buffer (see halo_offset).
+const uint32_t* halo_of(const uint8_t* skip, const GridK& g) {
+    return skip == nullptr ? nullptr
+                           : reinterpret_cast<const uint32_t*>(skip + halo_offset(g.res, g.n_grids));
+}
+
 template <int LOOKUP, bool SKIP, int WAVES>
 void launch_count_uniform(int64_t nb, hipStream_t s, const float* o, const float* d, const int32_t* gid, int64_t n,
                           const uint32_t* bits, const uint8_t* skip, const GridK& g, const ClipK& c, const StepK& p,
@@ -973,8 +1180,8 @@ void launch_count_uniform(int64_t nb, hipStream_t s, const float* o, const float
                            nb);
     }
     hipLaunchKernelGGL((count_uniform_kernel<LOOKUP, SKIP, WAVES>), dim3(static_cast<unsigned>(nb * split)),
-                       dim3(WAVES * kWave), 0, s, o, d, gid, n, bits, skip, g, c, p, packed, sums, masks, n_masks,
-                       split);
+                       dim3(WAVES * kWave), 0, s, o, d, gid, n, bits, skip, halo_of(skip, g), g, c, p, packed, sums,
+                       masks, n_masks, split);
 }
 
 template <int LOOKUP, bool SKIP, int WAVES>

@@ -38,7 +38,7 @@ def compare(o, d, mask, res, box, near, far, dt, **kw):
     """Every traversal variant (skip grid on/off, fill replaying the count
     pass's masks or traversing again) against the oracle."""
     want = oracle.march(o, d, mask, res, box, near, far, dt, **kw)
-    for skip, replay in ((False, True), (True, True), (False, False)):
+    for skip, replay in ((False, True), (True, True), (False, False), (True, False)):
         got = gpu_march(o, d, mask, res, box, near, far, dt, skip_empty=skip, replay_masks=replay, **kw)
         for g, w, name in zip(got, want, ("packed_info", "ray_indices", "t_starts", "t_ends")):
             assert_bit_exact(g, w, f"{name} (skip grid {skip}, replay {replay})")
@@ -148,6 +148,38 @@ def test_skip_field_contents():
         assert np.array_equal(field[gi * c ** 3:(gi + 1) * c ** 3], want), f"grid {gi}"
         if gi < 2:
             assert want.max() >= 3  # the test exercises distances above the trivial ones
+
+
+@pytest.mark.parametrize("res,p_occ", [(32, 0.002), (16, 0.01), (64, 0.0003)])
+def test_halo_bits_contents(res, p_occ):
+    """The halo bits of the skip buffer: per grid, one bit per 2x2x2 block,
+    set iff an occupied fine cell lies within 2 cells of the block on every
+    axis (scipy's maximum filter), C order, LSB first, whole 64-bit words."""
+    import paper_2210_04847_amd as nacc
+    from scipy.ndimage import maximum_filter
+    n = 3
+    mask = synth.random_mask(n * res ** 3, p_occ, 53 + res)
+    mask[2 * res ** 3:] = 0  # the third grid is empty
+    grid = nacc.OccupancyGrid(BOX, res, n_grids=n)
+    grid.set_occupancy(torch.from_numpy(mask.astype(np.float32)).cuda(), 0.5)
+    torch.cuda.synchronize()
+    buf = grid.skip.cpu().numpy()
+    c = res // 4
+    h = res // 2
+    off = -(-2 * c ** 3 * n // 256) * 256
+    words = -(-h ** 3 // 64) * 2
+    assert buf.size == off + 4 * words * n
+    got = buf[off:].view(np.uint32).reshape(n, words)
+    for gi in range(n):
+        m = mask[gi * res ** 3:(gi + 1) * res ** 3].reshape(res, res, res).astype(bool)
+        near = maximum_filter(m, size=5, mode="constant")  # any occupied within 2 cells
+        want = near.reshape(h, 2, h, 2, h, 2).any(axis=(1, 3, 5)).ravel()
+        packed = np.zeros(words * 32, bool)
+        packed[:want.size] = want
+        want_words = np.packbits(packed.reshape(-1, 8)[:, ::-1], axis=1).ravel().view(np.uint32)
+        assert np.array_equal(got[gi], want_words), f"grid {gi}"
+        if gi < 2:
+            assert 0 < want.mean() < 1  # both kinds of blocks occur
 
 
 def test_long_rays_many_chunks():

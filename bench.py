@@ -78,10 +78,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
     ap.add_argument("--skip-field", choices=["auto", "on", "off"], default="auto",
-                    help="march with the grid's skip buffer (empty-space skipping): auto uses it "
-                         "for uniform steps through the box lookup (its halo bits let the count "
-                         "pass test runs of candidates at once) and not for cone steps (its "
-                         "distance field pays off on sparse scenes only)")
+                    help="march with the grid's skip buffer (empty-space skipping: its halo bits "
+                         "let the count pass test runs of 8 to 32 candidates at once); auto uses "
+                         "it for every workload")
     ap.add_argument("--alpha-thre", type=float, default=None,
                     help="prune the marched samples by visibility before shading them, as the "
                          "paper's ray_marching with sigma_fn (T >= early_stop_eps, alpha >= this; "
@@ -103,7 +102,7 @@ def use_skip(args, w):
     """Whether a workload marches with the grid's skip buffer."""
     if args.skip_field != "auto":
         return args.skip_field == "on"
-    return getattr(w, "cone", 0.0) == 0.0 and getattr(w, "lookup", "aabb") == "aabb"
+    return True
 
 
 def grid_label(w):

@@ -927,12 +927,21 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
                                                                     const uint64_t* __restrict__ masks,
                                                                     const int32_t* __restrict__ extra,
                                                                     int32_t* __restrict__ packed_info,
-                                                                    int64_t* __restrict__ block_sums) {
+                                                                    int64_t* __restrict__ block_sums,
+                                                                    int32_t* __restrict__ chunk_base) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     int n = 0;
     if (r < n_rays) {
-        int64_t total = extra[r];
-        for (int j = 0; j < n_masks; ++j) total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
+        int64_t total = 0;
+        for (int j = 0; j < n_masks; ++j) {
+            // samples of the ray before chunk j (for the segment fill)
+            if (chunk_base != nullptr) {
+                chunk_base[static_cast<int64_t>(j) * n_rays + r] =
+                    static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
+            }
+            total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
+        }
+        total += extra[r];
         if (max_per_ray > 0) total = min(total, static_cast<int64_t>(max_per_ray));
         n = static_cast<int>(min(total, static_cast<int64_t>(kMaxCandidates)));
         packed_info[2 * r + 1] = n;
@@ -1012,6 +1021,368 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_chunks_kernel(
             }
             if (n_valid < kConeBatch) break;
             t = tb[kConeBatch];
+        }
+    }
+    if (overflow && status != nullptr) *status = NACC_ECAPACITY;
+}
+
+// ---------------------------------------------------------------------------
+// Cone steps with the halo bits of the skip buffer.  A chunk's 64 candidates
+// form 8 segments of kConeBatch; the count pass walks the chunk's recurrence
+// once (one lane per chunk) and tests one halo bit per segment at its
+// centre.  The segments that may hold samples are queued per wave in LDS
+// and then looked up 64 at a time, one segment per lane, so that the lanes
+// stay busy although only a few segments of a chunk are live.  Each looked-up
+// segment's 8 occupancy bits are ORed into its chunk's mask (byte s of the
+// mask, as in the plain passes), and the t at the start of every segment
+// holding samples is stored, so the fill pass writes them without walking
+// the recurrence again.
+//
+// A clear halo bit proves a segment empty when all its midpoints provably
+// map within kHaloReach cells of the centre's cell in the grid the centre is
+// looked up in: the midpoints lie within h of the centre in t (h half the
+// segment's extent plus rounding), so within |d_i| h plus the rounding of
+// positions on axis i; cascades also need every midpoint on the centre's
+// level (its max |x_i| bracketed on both sides), and the contraction
+// shrinks distances by at most L(r) = (2 - 1/r)/r beyond radius r >= 1
+// (at most 1 everywhere).  Where the bound fails the segment is looked up.
+// ---------------------------------------------------------------------------
+constexpr int kSegsPerChunk = kWave / kConeBatch;
+constexpr int kTaskWaves = kTaskThreads / kWave;
+constexpr int kSegQueue = kWave * kSegsPerChunk;  // every segment of a wave's chunks
+
+struct ConeHalo {
+    float v;     // max_i s_i |d_i|: level-0 cells per unit t on the fastest axis
+    float smax;  // max_i s_i
+    float omax, dmax, dnorm;
+};
+
+__device__ __forceinline__ ConeHalo cone_halo_ray(const GridK& g, const float o[3], const float d[3]) {
+    ConeHalo k;
+    k.v = fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
+    k.smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
+    k.omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
+    k.dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+    k.dnorm = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) * (1.0f + 0x1p-18f);
+    return k;
+}
+
+// Whether a segment of candidates whose midpoints lie in [ta, tb] may hold
+// samples (see above): false only when the centre's halo bit is clear and
+// the bound holds.  Branch-free, so the segments' halo words are all in
+// flight together.
+template <int LOOKUP>
+__device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffer_rsrc_t hrs, uint32_t grid,
+                                                  const float o[3], const float d[3], const ConeHalo& k, float ta,
+                                                  float tb) {
+    const float tc = (ta + tb) * 0.5f;
+    const float h = (tb - ta) * 0.5f + fabsf(tb) * 0x1p-20f;  // half-extent, with the rounding of the t values
+    float x0 = o[0] + d[0] * tc, x1 = o[1] + d[1] * tc, x2 = o[2] + d[2] * tc;
+    // the rounding of positions (a few ulps of the largest coordinate
+    // reached, for both points) and of cell coordinates, generously
+    const float slack_x = (k.omax + k.dmax * fabsf(tb) + 1.0f) * 0x1p-19f;
+    const float cell_slack = static_cast<float>(g.res) * 0x1p-17f;
+    float dev;  // bound of |u_i(midpoint) - u_i(centre)| in cells
+    bool open = false;  // the bound cannot be established
+    uint32_t hgrid = grid;
+    if (LOOKUP == NACC_LOOKUP_CASCADE) {
+        const float m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
+        const float dm = k.dmax * h + slack_x;
+        const int l_lo = cascade_level(fmaxf(m - dm, 0.0f), g);
+        const int l_hi = cascade_level(m + dm, g);
+        open = l_lo != l_hi;  // a midpoint may lie on another level
+        hgrid = static_cast<uint32_t>(l_hi);
+        x0 = ldexpf(x0, -l_hi);
+        x1 = ldexpf(x1, -l_hi);
+        x2 = ldexpf(x2, -l_hi);
+        dev = ldexpf(k.v * h + k.smax * slack_x, -l_hi) + cell_slack;
+    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
+        const float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
+        const float r_min = n * (1.0f - 0x1p-18f) - k.dnorm * h - 2.0f * slack_x;
+        const float lip = r_min > 1.0f ? ((2.0f - 1.0f / r_min) / r_min) * (1.0f + 0x1p-18f) : 1.0f;
+        if (n > 1.0f) {
+            const float f = (2.0f - 1.0f / n) / n;
+            x0 = x0 * f;
+            x1 = x1 * f;
+            x2 = x2 * f;
+        }
+        dev = k.smax * (lip * (k.dnorm * h + 2.0f * slack_x) + 3.5f * 0x1p-16f) + cell_slack;
+    } else {
+        dev = k.v * h + k.smax * slack_x + cell_slack;
+    }
+    open = open || !(dev <= static_cast<float>(kHaloReach) * (1.0f - 0x1p-10f));
+    const bool hb = halo_bit(hrs, g, hgrid * g.halo_words, x0, x1, x2);  // loaded in every case
+    return open | hb;
+}
+
+// 32-bit value of lane `src` (per lane) through the LDS crossbar; every lane
+// must be active.
+__device__ __forceinline__ float lane_value(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ int lane_value(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+template <int LOOKUP>
+__global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ halo, GridK g, StepK p,
+    int n_masks, const float* __restrict__ chunk_t, const float* __restrict__ t_far_in,
+    uint64_t* __restrict__ masks, int32_t* __restrict__ extra, float* __restrict__ seg_t) {
+    __shared__ float q_t[kTaskWaves][kSegQueue];
+    __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
+    __shared__ uint64_t q_mask[kTaskWaves][kWave];
+    const int lane = lane_id();
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first_task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
+    const int64_t task = first_task + lane;
+    const bool in_range = task < static_cast<int64_t>(n_masks) * n_rays;
+    int j = 0;
+    int64_t r = 0;
+    float t = INFINITY;
+    if (in_range) {
+        j = static_cast<int>(task / n_rays);
+        r = task - static_cast<int64_t>(j) * n_rays;
+        t = chunk_t[task];
+    }
+    const bool active = t < INFINITY;
+    float o[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
+    float t_far = -INFINITY;
+    uint32_t word0 = 0;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            o[i] = rays_o[3 * r + i];
+            d[i] = rays_d[3 * r + i];
+        }
+        t_far = t_far_in[r];
+        grid_of_ray<LOOKUP>(grid_id, r, g, word0);  // valid: the ray has candidates
+    }
+    // walk the chunk's recurrence once; test each segment's halo bit
+    const ConeHalo k = cone_halo_ray(g, o, d);
+    const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
+    const uint32_t grid = word0 / g.words;
+    float st[kSegsPerChunk];
+    uint32_t live = 0u;
+    bool alive = active;
+#pragma unroll
+    for (int s = 0; s < kSegsPerChunk; ++s) {
+        const float ta = t;
+        bool any = false;  // some candidate of the segment lies inside the ray
+#pragma unroll
+        for (int u = 0; u < kConeBatch; ++u) {
+            const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+            alive = alive && t < t_far && t1 > t;
+            any = any || alive;
+            t = alive ? t1 : t;
+        }
+        st[s] = ta;
+        live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, t) & any) << s;
+    }
+    const bool ended = !alive;
+    // queue the live segments of the wave's chunks in LDS, in lane order
+    const int n_items = __popc(live);
+    const int before = wave_inclusive_sum(n_items) - n_items;
+    const int total = read_lane(before + n_items, kWave - 1);
+    {
+        int pos = before;
+#pragma unroll
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            if (((live >> s) & 1u) != 0u) {
+                q_t[wave][pos] = st[s];
+                q_id[wave][pos] = static_cast<uint16_t>(lane | (s << kWaveLog2));
+                ++pos;
+            }
+        }
+    }
+    q_mask[wave][lane] = 0ull;
+    wave_lds_sync();
+    // look the queued segments up, one per lane
+    for (int base = 0; base < total; base += kWave) {
+        const int i = base + lane;
+        const bool has = i < total;
+        const float t0 = has ? q_t[wave][i] : 0.0f;
+        const int id = has ? static_cast<int>(q_id[wave][i]) : 0;
+        const int src = id & (kWave - 1);
+        const int s = id >> kWaveLog2;
+        float so[3], sd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            so[c] = lane_value(o[c], src);
+            sd[c] = lane_value(d[c], src);
+        }
+        // every lane takes part in the crossbar reads (a lane left out would
+        // not provide its value to the lanes reading it)
+        const float src_far = lane_value(t_far, src);
+        const float s_far = has ? src_far : -INFINITY;
+        const uint32_t s_word0 = static_cast<uint32_t>(lane_value(static_cast<int>(word0), src));
+        float tb[kConeBatch + 1];
+        const int n_valid = cone_steps(t0, s_far, p, tb);
+        SkipRay sk{};
+        float skip_end = -INFINITY;
+        const uint32_t hits =
+            cone_hits<LOOKUP, false>(bits, nullptr, g, sk, skip_end, s_word0, so, sd, tb, n_valid) &
+            ((1u << n_valid) - 1u);
+        if (has && hits != 0u) {
+            __hip_atomic_fetch_or(&q_mask[wave][src], static_cast<uint64_t>(hits) << (s * kConeBatch),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            seg_t[(first_task + src) * kSegsPerChunk + s] = t0;
+        }
+    }
+    wave_lds_sync();
+    if (in_range) masks[task] = q_mask[wave][lane];
+    if (active && j == n_masks - 1 && !ended) {
+        // past the stored chunks: count the rest of the ray here
+        SkipRay sk{};
+        float skip_end = -INFINITY;
+        bool e2 = false;
+        int count = 0;
+        for (int k0 = n_masks * kWave; k0 < kMaxCandidates; k0 += kWave) {
+            count += __popcll(cone_chunk_bits<LOOKUP, false>(bits, nullptr, g, sk, skip_end, word0, o, d, t, t_far,
+                                                             p, e2));
+            if (e2) break;
+        }
+        extra[r] = count;
+    }
+}
+
+// Fill pass of the segment count: one lane per chunk queues its segments
+// that hold samples (and lie before the ray's limit); they are then written
+// one per lane from the stored t at their start, 8 recurrence steps each.
+template <int LOOKUP>
+__global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
+    const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
+    int64_t n_rays, const uint32_t* __restrict__ bits, GridK g, StepK p, int n_masks,
+    const float* __restrict__ chunk_t, const float* __restrict__ t_far_in, const uint64_t* __restrict__ masks,
+    const int32_t* __restrict__ chunk_base, const float* __restrict__ seg_t, const int32_t* __restrict__ packed_info,
+    int64_t capacity, float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status) {
+    __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
+    const int lane = lane_id();
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t first_task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
+    const int64_t task = first_task + lane;
+    const bool in_range = task < static_cast<int64_t>(n_masks) * n_rays;
+    int j = 0;
+    int64_t r = 0;
+    float t = INFINITY;
+    uint64_t m = 0ull;
+    int limit = 0, base = 0;
+    int64_t start = 0;
+    if (in_range) {
+        j = static_cast<int>(task / n_rays);
+        r = task - static_cast<int64_t>(j) * n_rays;
+        t = chunk_t[task];
+        if (t < INFINITY) {
+            m = masks[task];
+            limit = packed_info[2 * r + 1];
+            start = packed_info[2 * r];
+            base = chunk_base[task];
+        }
+    }
+    const float t_far = t < INFINITY ? t_far_in[r] : -INFINITY;
+    // segments holding samples that fall before the ray's limit
+    uint32_t todo = 0u;
+#pragma unroll
+    for (int s = 0; s < kSegsPerChunk; ++s) {
+        const bool holds = ((m >> (s * kConeBatch)) & 0xffull) != 0ull;
+        const int idx = base + static_cast<int>(__popcll(m & ((1ull << (s * kConeBatch)) - 1ull)));
+        if (holds && idx < limit) todo |= 1u << s;
+    }
+    const int n_items = __popc(todo);
+    const int before = wave_inclusive_sum(n_items) - n_items;
+    const int total = read_lane(before + n_items, kWave - 1);
+    {
+        int pos = before;
+#pragma unroll
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            if (((todo >> s) & 1u) != 0u) {
+                q_id[wave][pos] = static_cast<uint16_t>(lane | (s << kWaveLog2));
+                ++pos;
+            }
+        }
+    }
+    wave_lds_sync();
+    bool overflow = false;
+    const int start_lo = static_cast<int>(start), start_hi = static_cast<int>(start >> 32);
+    const int m_lo = static_cast<int>(m), m_hi = static_cast<int>(m >> 32);
+    for (int qb = 0; qb < total; qb += kWave) {
+        const int i = qb + lane;
+        const bool has = i < total;
+        const int id = has ? static_cast<int>(q_id[wave][i]) : 0;
+        const int src = id & (kWave - 1);
+        const int s = id >> kWaveLog2;
+        const float s_far = lane_value(t_far, src);
+        const int s_limit = lane_value(limit, src);
+        const int s_base = lane_value(base, src);
+        const int64_t s_start = (static_cast<int64_t>(lane_value(start_hi, src)) << 32) |
+                                static_cast<uint32_t>(lane_value(start_lo, src));
+        const uint64_t s_m = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(m_hi, src))) << 32) |
+                             static_cast<uint32_t>(lane_value(m_lo, src));
+        if (has) {
+            const float t0 = seg_t[(first_task + src) * kSegsPerChunk + s];
+            float tb[kConeBatch + 1];
+            const int n_valid = cone_steps(t0, s_far, p, tb);
+            const uint32_t hits = static_cast<uint32_t>(s_m >> (s * kConeBatch)) & 0xffu & ((1u << n_valid) - 1u);
+            int idx = s_base + static_cast<int>(__popcll(s_m & ((1ull << (s * kConeBatch)) - 1ull)));
+#pragma unroll
+            for (int u = 0; u < kConeBatch; ++u) {
+                if (((hits >> u) & 1u) != 0u && idx < s_limit) {
+                    const int64_t pos = s_start + idx;
+                    if (pos >= 0 && pos < capacity) {
+                        t_starts[pos] = tb[u];
+                        t_ends[pos] = tb[u + 1];
+                    } else {
+                        overflow = true;
+                    }
+                    ++idx;
+                }
+            }
+        }
+    }
+    if (in_range && j == n_masks - 1 && t < INFINITY) {
+        // past the stored chunks: walk this chunk, then look the rest of the
+        // ray up again
+        int idx = base + static_cast<int>(__popcll(m));
+        bool ended = false;
+        for (int s = 0; s < kSegsPerChunk && !ended; ++s) {
+            float tb[kConeBatch + 1];
+            const int n_valid = cone_steps(t, t_far, p, tb);
+            ended = n_valid < kConeBatch;
+            t = tb[kConeBatch];
+        }
+        if (!ended && idx < limit) {
+            float o[3], d[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                o[c] = rays_o[3 * r + c];
+                d[c] = rays_d[3 * r + c];
+            }
+            uint32_t word0;
+            grid_of_ray<LOOKUP>(grid_id, r, g, word0);
+            SkipRay sk{};
+            float skip_end = -INFINITY;
+            for (int k0 = n_masks * kWave; k0 < kMaxCandidates && idx < limit; k0 += kConeBatch) {
+                float tb[kConeBatch + 1];
+                const int n_valid = cone_steps(t, t_far, p, tb);
+                const uint32_t hits =
+                    cone_hits<LOOKUP, false>(bits, nullptr, g, sk, skip_end, word0, o, d, tb, n_valid) &
+                    ((1u << n_valid) - 1u);
+#pragma unroll
+                for (int u = 0; u < kConeBatch; ++u) {
+                    if (((hits >> u) & 1u) != 0u && idx < limit) {
+                        const int64_t pos = start + idx;
+                        if (pos >= 0 && pos < capacity) {
+                            t_starts[pos] = tb[u];
+                            t_ends[pos] = tb[u + 1];
+                        } else {
+                            overflow = true;
+                        }
+                        ++idx;
+                    }
+                }
+                if (n_valid < kConeBatch) break;
+                t = tb[kConeBatch];
+            }
         }
     }
     if (overflow && status != nullptr) *status = NACC_ECAPACITY;
@@ -1115,6 +1486,7 @@ struct Layout {
     int64_t sums_bytes;
     int n_masks;
     int64_t chunk_t_off, t_far_off, extra_off;  // cone steps only (0 otherwise)
+    int64_t base_off, seg_t_off;                // cone steps, segment passes
     int64_t bytes;
 };
 
@@ -1129,21 +1501,25 @@ Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_m
         l.n_masks = static_cast<int>(std::min<int64_t>((k + kWave - 1) / kWave, kMaxMaskChunks));
     }
     l.bytes = l.sums_bytes + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t)));
-    l.chunk_t_off = l.t_far_off = l.extra_off = 0;
+    l.chunk_t_off = l.t_far_off = l.extra_off = l.base_off = l.seg_t_off = 0;
     if (p.cone > 0.0f) {
         l.chunk_t_off = l.bytes;
         l.t_far_off = l.chunk_t_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(float)));
         l.extra_off = l.t_far_off + align256(n_rays * static_cast<int64_t>(sizeof(float)));
-        l.bytes = l.extra_off + align256(n_rays * static_cast<int64_t>(sizeof(int32_t)));
+        l.base_off = l.extra_off + align256(n_rays * static_cast<int64_t>(sizeof(int32_t)));
+        l.seg_t_off = l.base_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(int32_t)));
+        l.bytes = l.seg_t_off + align256(n_rays * l.n_masks * kSegsPerChunk * static_cast<int64_t>(sizeof(float)));
     }
     return l;
 }
 
 struct ConeWork {
-    uint64_t* masks;  // [n_masks][n_rays]
-    float* chunk_t;   // [n_masks][n_rays]
-    float* t_far;     // [n_rays]
-    int32_t* extra;   // [n_rays]
+    uint64_t* masks;      // [n_masks][n_rays]
+    float* chunk_t;       // [n_masks][n_rays]
+    float* t_far;         // [n_rays]
+    int32_t* extra;       // [n_rays]
+    int32_t* chunk_base;  // [n_masks][n_rays]: samples of the ray before each chunk
+    float* seg_t;         // [n_masks][n_rays][kSegsPerChunk]: t at the start of segments holding samples
     int n_masks;
 };
 
@@ -1154,6 +1530,8 @@ ConeWork cone_work(void* workspace, const Layout& l) {
     w.chunk_t = reinterpret_cast<float*>(b + l.chunk_t_off);
     w.t_far = reinterpret_cast<float*>(b + l.t_far_off);
     w.extra = reinterpret_cast<int32_t*>(b + l.extra_off);
+    w.chunk_base = reinterpret_cast<int32_t*>(b + l.base_off);
+    w.seg_t = reinterpret_cast<float*>(b + l.seg_t_off);
     w.n_masks = l.n_masks;
     return w;
 }
@@ -1206,13 +1584,17 @@ void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const floa
     if (cw != nullptr) {  // cone steps
         hipLaunchKernelGGL((cone_starts_kernel<LOOKUP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, g, c, p,
                            cw->n_masks, cw->chunk_t, cw->t_far, cw->extra);
-        if (cw->n_masks > 0) {
-            hipLaunchKernelGGL((count_cone_chunks_kernel<LOOKUP, SKIP>), dim3(task_blocks(cw->n_masks, n)),
+        if (cw->n_masks > 0 && SKIP) {  // segments through the halo bits
+            hipLaunchKernelGGL((count_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
+                               dim3(kTaskThreads), 0, s, o, d, gid, n, bits, halo_of(skip, g), g, p, cw->n_masks,
+                               cw->chunk_t, cw->t_far, cw->masks, cw->extra, cw->seg_t);
+        } else if (cw->n_masks > 0) {
+            hipLaunchKernelGGL((count_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
                                cw->t_far, cw->masks, cw->extra);
         }
         hipLaunchKernelGGL(cone_counts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, n, cw->n_masks, p.max_per_ray,
-                           cw->masks, cw->extra, packed, sums);
+                           cw->masks, cw->extra, packed, sums, SKIP ? cw->chunk_base : nullptr);
         return;
     }
     switch (tuning().march_waves_per_group) {
@@ -1230,8 +1612,12 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
                       const ClipK& c, const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts,
                       float* te, int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
-        if (cw != nullptr && cw->n_masks > 0) {  // replay the count pass's chunks, one lane per chunk
-            hipLaunchKernelGGL((fill_cone_chunks_kernel<LOOKUP, SKIP>), dim3(task_blocks(cw->n_masks, n)),
+        if (cw != nullptr && cw->n_masks > 0 && SKIP) {  // the segment count's masks and starts
+            hipLaunchKernelGGL((fill_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
+                               dim3(kTaskThreads), 0, s, o, d, gid, n, bits, g, p, cw->n_masks, cw->chunk_t,
+                               cw->t_far, cw->masks, cw->chunk_base, cw->seg_t, packed, capacity, ts, te, status);
+        } else if (cw != nullptr && cw->n_masks > 0) {  // replay the count pass's chunks, one lane per chunk
+            hipLaunchKernelGGL((fill_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
                                cw->t_far, cw->masks, packed, capacity, ts, te, status);
         } else {  // traversal, one lane per ray

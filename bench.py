@@ -666,7 +666,7 @@ def bench_train(args, torch, nacc):
     plan = st.plan() if form == "plan" else None
     tuned = None
     if plan is not None and not args.no_autotune:
-        tuned, tuned_ms = plan.autotune()
+        tuned, tuned_ms = plan.autotune(repeats=20)
         log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
     elif not args.no_autotune:
         from paper_2210_04847_amd import autotune
@@ -925,7 +925,7 @@ def bench_dynamic(args, torch, nacc):
     plan = batched.plan() if args.form == "plan" else None
     tuned = None
     if plan is not None and not args.no_autotune:
-        tuned, tuned_ms = plan.autotune()
+        tuned, tuned_ms = plan.autotune(repeats=20)
         log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
     elif not args.no_autotune:
         from paper_2210_04847_amd import autotune

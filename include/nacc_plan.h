@@ -165,12 +165,13 @@ int nacc_plan_capture_step(nacc_plan* plan);
 int nacc_plan_launch(nacc_plan* plan, int32_t with_update, void* stream);
 
 /*
- * Tunes the launch parameters (nacc_tuning) on this step: coordinate
- * descent over every knob, each setting captured and timed over `repeats`
- * graph replays (>= 1) after two warm-up replays, and accepted only if the
- * step's outputs (packed_info, total, color, opacity, the first 2^20
- * marched samples and, when training, their gradients) are bit-identical to
- * those of the starting setting.  Synchronous; it waits for `stream` first.
+ * Tunes the launch parameters (nacc_tuning) on this step: two rounds of
+ * coordinate descent over every knob, each setting captured and timed over
+ * `repeats` graph replays (>= 1) after two warm-up replays, and accepted
+ * only if a checksum of every word of the step's outputs (packed_info,
+ * total, color, opacity, depth, all marched samples and, when training,
+ * their gradients) equals that of the starting setting.  Synchronous; it
+ * waits for `stream` first.
  * Runs steps (not updates) on the device, overwriting the step's outputs.
  * Leaves the best setting as the process's nacc_tuning, writes it to *best
  * (nullable) and its time per step to *best_ms (nullable), and re-captures

@@ -278,6 +278,9 @@ int autotune(nacc_plan* p, int repeats, nacc_tuning* best_out, float* best_ms_ou
     Snapshot reference, trial_snap;
     float best_ms = 0.0f;
     if (st == NACC_OK) st = time_setting(p, best, repeats, a, b, &best_ms, &reference);
+    // two rounds of coordinate descent: a knob's best value can change once
+    // the later knobs have moved
+    for (int round = 0; round < 2; ++round)
     for (int knob = 0; st == NACC_OK && knob < 4; ++knob) {
         if (!training && knob >= 1) break;  // the rendering knobs act on the fused loss kernel only
         for (int v : kValues[knob]) {

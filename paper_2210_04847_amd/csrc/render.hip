@@ -426,6 +426,113 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
     if (lane == 0) loss_partial[static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave] = wave_total;
 }
 
+// The fused loss kernel for launches with fewer waves than rays (each wave
+// takes several rays): rays without samples are finished lane-parallel.
+template <int K, bool PREFETCH>
+__global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(7))) void render_mse_grouped_kernel(
+    const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
+    const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
+    const float* __restrict__ target, float inv_count2, float* __restrict__ color, float* __restrict__ opacity,
+    float* __restrict__ depth, float* __restrict__ g_sigmas, float* __restrict__ g_rgbs,
+    double* __restrict__ loss_partial) {
+    const int lane = lane_id();
+    const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
+    const int64_t r0 = xcd_grouped<16>(blockIdx.x, gridDim.x) * kRaysPerRenderBlock + wave;
+    double wave_total = 0.0;  // squared errors of the wave's rays
+    // The wave's rays are r0 + i stride, taken 64 at a time: lane i reads the
+    // range of ray i, so a ray without samples is finished by its lane alone
+    // (colour 0, the squared error of its target) and the rays with samples
+    // are rendered one after the other by the whole wave.
+    for (int64_t rb = r0; rb < n_rays; rb += stride * kWave) {
+        const int64_t my_r = rb + static_cast<int64_t>(lane) * stride;
+        const bool mine = my_r < n_rays;
+        int my_n = 0;
+        if (mine) {
+            const int s0 = packed_info[2 * my_r], c0 = packed_info[2 * my_r + 1];
+            const bool ok = s0 >= 0 && c0 >= 0 && static_cast<int64_t>(s0) + c0 <= n_samples;
+            my_n = ok ? c0 : 0;
+        }
+        if (ballot(mine && my_n == 0) != 0ull) {
+            double sq = 0.0;
+            if (mine && my_n == 0) {
+                // the rendered colour is the wave sum of zeros, +0
+                const float er = 0.0f - target[3 * my_r], eg = 0.0f - target[3 * my_r + 1],
+                            eb = 0.0f - target[3 * my_r + 2];
+                sq = static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
+                color[3 * my_r] = 0.0f;
+                color[3 * my_r + 1] = 0.0f;
+                color[3 * my_r + 2] = 0.0f;
+                opacity[my_r] = 0.0f;
+                depth[my_r] = 0.0f;
+            }
+            wave_total += wave_sum(sq);
+        }
+        uint64_t todo = ballot(mine && my_n > 0);
+        // PREFETCH: a ray's first chunk is loaded during the previous ray's
+        // backward pass
+        Sample pre{};
+        // (the lanes' ranges are read again with scalar loads below, so that
+        // no vector register holds them through the rendering)
+        if (PREFETCH && todo != 0ull) {
+            int64_t s_j;
+            int n_j;
+            ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j, n_j);
+            pre = load_sample(lane < n_j, s_j + lane, ts, te, sig, rgb);
+        }
+        while (todo != 0ull) {
+            const int i = static_cast<int>(__builtin_ctzll(todo));
+            todo &= todo - 1ull;
+            const int64_t r = rb + static_cast<int64_t>(i) * stride;
+            int64_t start;
+            int n;
+            ray_range(packed_info, r, n_samples, start, n);
+            // the target's address is wave-uniform: scalar loads
+            const float tr = target[3 * r], tg = target[3 * r + 1], tb = target[3 * r + 2];
+            RayCache<K> cache;
+            int kept;
+            double prefix_hi;
+            float acc[3] = {0.0f, 0.0f, 0.0f};
+            float acc_a = 0.0f, acc_d = 0.0f;
+            ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
+                                           pre);
+            const float cr = wave_sum(acc[0]);
+            const float cg = wave_sum(acc[1]);
+            const float cb = wave_sum(acc[2]);
+            acc_a = wave_sum(acc_a);
+            acc_d = wave_sum(acc_d);
+            const float er = cr - tr, eg = cg - tg, eb = cb - tb;
+            RayGrad q;
+            q.gr = uniform<float>(er * inv_count2);
+            q.gg = uniform<float>(eg * inv_count2);
+            q.gb = uniform<float>(eb * inv_count2);
+            q.ga = 0.0f;
+            q.gd = 0.0f;
+            wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
+            if (PREFETCH && todo != 0ull) {
+                int64_t s_j;
+                int n_j;
+                ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j,
+                          n_j);
+                pre = load_sample(lane < n_j, s_j + lane, ts, te, sig, rgb);
+            }
+            ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+            // stored after the backward: a store before it would make the
+            // backward's first wait on memory also wait for the store
+            if (lane == 0) {
+                color[3 * r] = cr;
+                color[3 * r + 1] = cg;
+                color[3 * r + 2] = cb;
+                opacity[r] = acc_a;
+                depth[r] = acc_d;
+            }
+        }
+    }
+    // one partial per wave: no workgroup barrier, which would make every
+    // wave wait for its gradient stores to complete before it could exit
+    if (lane == 0) loss_partial[static_cast<int64_t>(blockIdx.x) * kRaysPerRenderBlock + wave] = wave_total;
+}
+
 // First level of the loss sum: workgroup b adds partials
 // [b * kSumSpan, (b + 1) * kSumSpan) in a fixed order.
 constexpr int kSumThreads = 256;
@@ -509,7 +616,18 @@ struct LaunchMse {
                     const float* ts, const float* te, const float* sig, const float* rgb, float eps, const float* target,
                     float inv_count2, float* color, float* opacity, float* depth, float* g_sig, float* g_rgb,
                     double* partial) {
-        if (tuning().render_prefetch != 0) {
+        // one wave per ray: the plain kernel; several rays per wave: the
+        // grouped one, which finishes the rays without samples lane-parallel
+        const bool grouped = static_cast<int64_t>(grid.x) * kRaysPerRenderBlock < n_rays;
+        if (tuning().render_prefetch != 0 && grouped) {
+            hipLaunchKernelGGL((render_mse_grouped_kernel<K, true>), grid, dim3(kRenderThreads), 0, s, packed_info,
+                               n_rays, n_samples, ts, te, sig, rgb, eps, target, inv_count2, color, opacity, depth,
+                               g_sig, g_rgb, partial);
+        } else if (grouped) {
+            hipLaunchKernelGGL((render_mse_grouped_kernel<K, false>), grid, dim3(kRenderThreads), 0, s, packed_info,
+                               n_rays, n_samples, ts, te, sig, rgb, eps, target, inv_count2, color, opacity, depth,
+                               g_sig, g_rgb, partial);
+        } else if (tuning().render_prefetch != 0) {
             hipLaunchKernelGGL((render_mse_kernel<K, true>), grid, dim3(kRenderThreads), 0, s, packed_info, n_rays,
                                n_samples, ts, te, sig, rgb, eps, target, inv_count2, color, opacity, depth, g_sig,
                                g_rgb, partial);

@@ -75,6 +75,10 @@ def parse():
                          "(training workloads; steps with visibility pruning, the attribute "
                          "and image workloads use torch graphs for \"plan\")")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="launch parameters to use instead of tuning, as key=value,... (the "
+                         "fields of nacc_tuning), e.g. to take hardware counters under the "
+                         "setting a tuned run chose")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=int, default=131072)
     ap.add_argument("--skip-field", choices=["auto", "on", "off"], default="auto",
@@ -96,6 +100,15 @@ def parse():
                     help="first copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, for calibrating hardware traffic counters)")
     return ap.parse_args()
+
+
+def fixed_tuning(args, nacc):
+    """Sets the launch parameters given by --tuning; returns them all."""
+    kv = dict(item.split("=", 1) for item in args.tuning.split(",") if item)
+    nacc._lib.set_tuning(**{k: int(v) for k, v in kv.items()})
+    tuned = nacc._lib.get_tuning()
+    log(f"tuning set: {tuned}")
+    return tuned
 
 
 def use_skip(args, w):
@@ -665,7 +678,9 @@ def bench_train(args, torch, nacc):
     form = args.form if not (args.form == "plan" and st.prune) else "graph"
     plan = st.plan() if form == "plan" else None
     tuned = None
-    if plan is not None and not args.no_autotune:
+    if args.tuning:
+        tuned = fixed_tuning(args, nacc)
+    elif plan is not None and not args.no_autotune:
         tuned, tuned_ms = plan.autotune(repeats=20)
         log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
     elif not args.no_autotune:
@@ -924,7 +939,9 @@ def bench_dynamic(args, torch, nacc):
 
     plan = batched.plan() if args.form == "plan" else None
     tuned = None
-    if plan is not None and not args.no_autotune:
+    if args.tuning:
+        tuned = fixed_tuning(args, nacc)
+    elif plan is not None and not args.no_autotune:
         tuned, tuned_ms = plan.autotune(repeats=20)
         log(f"tuned by the plan: {tuned} ({tuned_ms:.4f} ms per step)")
     elif not args.no_autotune:

@@ -60,6 +60,10 @@ struct ClipK {
 struct StepK {
     float near_plane, far_plane, dt, dt_max, cone;
     int max_per_ray;
+    // cone steps: every step from a t between the near and far planes
+    // advances t (dt exceeds twice an ulp of the largest such |t|), so the
+    // recurrence can be walked without testing each step for a stall
+    int no_stall;
 };
 
 // Ray against the clip box (FP32 slab test of the contract).
@@ -296,6 +300,9 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     p.dt_max = params.dt_max;
     p.cone = params.cone;
     p.max_per_ray = params.max_per_ray;
+    const double t_abs = std::fmax(std::fabs(static_cast<double>(params.near_plane)),
+                                   std::fabs(static_cast<double>(params.far_plane)));
+    p.no_stall = std::isfinite(t_abs) && t_abs * 0x1p-21 < static_cast<double>(params.dt) ? 1 : 0;
 }
 
 }  // namespace

@@ -809,6 +809,81 @@ __device__ __forceinline__ void fill_ray_cone(
     }
 }
 
+struct ConeHalo {
+    float v;     // max_i s_i |d_i|: level-0 cells per unit t on the fastest axis
+    float smax;  // max_i s_i
+    float omax, dmax, dnorm;
+    float onorm;  // |o|, rounded up
+};
+
+__device__ __forceinline__ ConeHalo cone_halo_ray(const GridK& g, const float o[3], const float d[3]) {
+    ConeHalo k;
+    k.v = fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
+    k.smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
+    k.omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
+    k.dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+    k.dnorm = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) * (1.0f + 0x1p-18f);
+    k.onorm = sqrtf((o[0] * o[0] + o[1] * o[1]) + o[2] * o[2]) * (1.0f + 0x1p-18f);
+    return k;
+}
+
+// Whether a segment of candidates whose midpoints lie in [ta, tb] may hold
+// samples (see above): false only when the centre's halo bit is clear and
+// the bound holds.  Branch-free, so the segments' halo words are all in
+// flight together.
+template <int LOOKUP>
+__device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffer_rsrc_t hrs, uint32_t grid,
+                                                  const float o[3], const float d[3], const ConeHalo& k, float ta,
+                                                  float tb) {
+    const float tc = (ta + tb) * 0.5f;
+    const float h = (tb - ta) * 0.5f + fabsf(tb) * 0x1p-20f;  // half-extent, with the rounding of the t values
+    float x0 = o[0] + d[0] * tc, x1 = o[1] + d[1] * tc, x2 = o[2] + d[2] * tc;
+    // the rounding of positions (a few ulps of the largest coordinate
+    // reached, for both points) and of cell coordinates, generously
+    const float slack_x = (k.omax + k.dmax * fabsf(tb) + 1.0f) * 0x1p-19f;
+    const float cell_slack = static_cast<float>(g.res) * 0x1p-17f;
+    float dev;  // bound of |u_i(midpoint) - u_i(centre)| in cells
+    bool open = false;  // the bound cannot be established
+    uint32_t hgrid = grid;
+    if (LOOKUP == NACC_LOOKUP_CASCADE) {
+        const float m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
+        const float dm = k.dmax * h + slack_x;
+        const int l_lo = cascade_level(fmaxf(m - dm, 0.0f), g);
+        const int l_hi = cascade_level(m + dm, g);
+        open = l_lo != l_hi;  // a midpoint may lie on another level
+        hgrid = static_cast<uint32_t>(l_hi);
+        x0 = ldexpf(x0, -l_hi);
+        x1 = ldexpf(x1, -l_hi);
+        x2 = ldexpf(x2, -l_hi);
+        dev = ldexpf(k.v * h + k.smax * slack_x, -l_hi) + cell_slack;
+    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
+        const float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
+        // r_min bounds |x| from below over the segment; beyond radius r > 1
+        // the contraction shrinks distances by at most (2 - 1/r)/r, and a
+        // motion along the ray by at most (1 + 2|o|)/r^2: its radial part
+        // shrinks by 1/r^2, its tangential part, at most |o||d|/r long, by
+        // (2 - 1/r)/r < 2/r
+        const float r_min = n * (1.0f - 0x1p-18f) - k.dnorm * h - 2.0f * slack_x;
+        float lip = 1.0f, along = 1.0f;
+        if (r_min > 1.0f) {
+            lip = ((2.0f - 1.0f / r_min) / r_min) * (1.0f + 0x1p-18f);
+            along = fminf(lip, ((1.0f + 2.0f * k.onorm) / (r_min * r_min)) * (1.0f + 0x1p-18f));
+        }
+        if (n > 1.0f) {
+            const float f = (2.0f - 1.0f / n) / n;
+            x0 = x0 * f;
+            x1 = x1 * f;
+            x2 = x2 * f;
+        }
+        dev = k.smax * (along * k.dnorm * h + lip * 3.5f * slack_x + 3.5f * 0x1p-16f) + cell_slack;
+    } else {
+        dev = k.v * h + k.smax * slack_x + cell_slack;
+    }
+    open = open || !(dev <= static_cast<float>(kHaloReach) * (1.0f - 0x1p-10f));
+    const bool hb = halo_bit(hrs, g, hgrid * g.halo_words, x0, x1, x2);  // loaded in every case
+    return open | hb;
+}
+
 // Chunk-parallel cone marching.  The recurrence itself is cheap (four FP32
 // operations per candidate) but serial; the grid lookups are not.  A
 // pre-pass walks each ray's recurrence once, one lane per ray, and records
@@ -818,36 +893,95 @@ __device__ __forceinline__ void fill_ray_cone(
 // chunk-major (task = chunk * n_rays + ray): a wave's loads and stores of
 // the per-chunk arrays are contiguous.  A ray longer than the stored chunks
 // is finished by the task of its last stored chunk.
-template <int LOOKUP>
+// CULL (contraction lookup with halo bits): a chunk whose candidates all
+// provably map into halo-clear cells (one test of the chunk's whole extent,
+// see cone_segment_live) is marked by a NaN start, which the segment count
+// and fill passes take for a chunk without samples.  Far from the scene the
+// contraction maps a whole chunk of candidates into a fraction of a cell.
+// The last stored chunk is never marked: the passes continue the ray from it.
+template <int LOOKUP, bool CULL>
 __global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
     int64_t n_rays, GridK g, ClipK c, StepK p, int n_masks, float* __restrict__ chunk_t,
-    float* __restrict__ t_far_out, int32_t* __restrict__ extra) {
+    float* __restrict__ t_far_out, int32_t* __restrict__ extra, const uint32_t* __restrict__ halo,
+    uint64_t* __restrict__ live_chunks, int64_t* __restrict__ task_sums) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
-    if (r >= n_rays) return;
-    float o[3], d[3];
+    uint64_t listed = 0ull;  // CULL: chunks with candidates that may hold samples
+    if (r < n_rays) {
+        float o[3], d[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = rays_o[3 * r + i];
-        d[i] = rays_d[3 * r + i];
-    }
-    uint32_t word0;
-    float t_near = 0.0f, t_far = 0.0f;
-    bool live = grid_of_ray<LOOKUP>(grid_id, r, g, word0);
-    live = clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far) && live;
-    t_far_out[r] = live ? t_far : -INFINITY;
-    extra[r] = 0;
-    float t = t_near;
-    for (int j = 0; j < n_masks; ++j) {
-        live = live && t < t_far;  // the chunk's first candidate exists
-        chunk_t[static_cast<int64_t>(j) * n_rays + r] = live ? t : INFINITY;
-        if (__builtin_amdgcn_ballot_w64(live) == 0ull) continue;  // the wave's rays have all ended
-        // 64 steps without branches: a ray that ends keeps its last t
+        for (int i = 0; i < 3; ++i) {
+            o[i] = rays_o[3 * r + i];
+            d[i] = rays_d[3 * r + i];
+        }
+        uint32_t word0;
+        float t_near = 0.0f, t_far = 0.0f;
+        bool live = grid_of_ray<LOOKUP>(grid_id, r, g, word0);
+        live = clip_ray(o, d, c, p.near_plane, p.far_plane, t_near, t_far) && live;
+        t_far_out[r] = live ? t_far : -INFINITY;
+        extra[r] = 0;
+        const ConeHalo k = cone_halo_ray(g, o, d);  // (unused unless CULL)
+        const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
+        float t = t_near;
+        for (int j = 0; j < n_masks; ++j) {
+            live = live && t < t_far;  // the chunk's first candidate exists
+            const float ta = t;
+            const bool has = live;
+            if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
+                // the wave's rays have all ended
+            } else if (p.no_stall) {
+                // every step advances, so the candidates inside the ray are a
+                // prefix: the steps are taken without tests (past the ray's
+                // end t runs on; the next chunk's test sees that)
 #pragma unroll 8
-        for (int u = 0; u < kWave; ++u) {
-            const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
-            live = live && t < t_far && t1 > t;
-            t = live ? t1 : t;
+                for (int u = 0; u < kWave; ++u) t = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+            } else {
+                // 64 steps without branches: a ray that ends keeps its last t
+#pragma unroll 8
+                for (int u = 0; u < kWave; ++u) {
+                    const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+                    live = live && t < t_far && t1 > t;
+                    t = live ? t1 : t;
+                }
+            }
+            float start = has ? ta : INFINITY;
+            if (CULL && has && j < n_masks - 1 &&
+                !cone_segment_live<LOOKUP>(g, hrs, word0 / g.words, o, d, k, ta, t)) {
+                start = __builtin_nanf("");
+            }
+            if (CULL && start < INFINITY) listed |= 1ull << j;
+            chunk_t[static_cast<int64_t>(j) * n_rays + r] = start;
+        }
+        if (CULL) live_chunks[r] = listed;
+    }
+    if (CULL) {
+        // the workgroup's (one wave of 64 rays) listed rays per chunk,
+        // chunk-major ([chunk][workgroup]), for the scan that places the
+        // tasks in the list chunk by chunk, rays in order within a chunk
+        for (int j = 0; j < n_masks; ++j) {
+            const uint64_t b = __builtin_amdgcn_ballot_w64(((listed >> j) & 1ull) != 0ull);
+            if (threadIdx.x == 0) task_sums[static_cast<int64_t>(j) * gridDim.x + blockIdx.x] = __popcll(b);
+        }
+    }
+}
+
+// The task list of the segment passes under CULL: the listed chunks, chunk
+// by chunk, rays in order within a chunk (task = j n_rays + r), so that
+// neighbouring tasks read and write neighbouring entries of the per-chunk
+// arrays.  offsets: the exclusive scan of the per-(chunk, workgroup) counts.
+__global__ __launch_bounds__(kRaysPerBlock) void task_list_kernel(const int64_t* __restrict__ offsets,
+                                                                  int64_t n_rays, int n_masks,
+                                                                  const uint64_t* __restrict__ live_chunks,
+                                                                  int32_t* __restrict__ task_list) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
+    const uint64_t m = r < n_rays ? live_chunks[r] : 0ull;
+    for (int j = 0; j < n_masks; ++j) {
+        const bool on = ((m >> j) & 1ull) != 0ull;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(on);
+        if (on) {
+            const int64_t pos = offsets[static_cast<int64_t>(j) * gridDim.x + blockIdx.x] + bits_below(b);
+            task_list[pos] = static_cast<int32_t>(static_cast<int64_t>(j) * n_rays + r);
         }
     }
 }
@@ -928,10 +1062,14 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
                                                                     const int32_t* __restrict__ extra,
                                                                     int32_t* __restrict__ packed_info,
                                                                     int64_t* __restrict__ block_sums,
-                                                                    int32_t* __restrict__ chunk_base) {
+                                                                    int32_t* __restrict__ chunk_base,
+                                                                    const uint64_t* __restrict__ live_chunks) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     int n = 0;
     if (r < n_rays) {
+        // with a task list, the chunks left out of it hold no samples (their
+        // masks were not written)
+        const uint64_t listed = live_chunks != nullptr ? live_chunks[r] : ~0ull;
         int64_t total = 0;
         for (int j = 0; j < n_masks; ++j) {
             // samples of the ray before chunk j (for the segment fill)
@@ -939,7 +1077,7 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
                 chunk_base[static_cast<int64_t>(j) * n_rays + r] =
                     static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
             }
-            total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
+            if (((listed >> j) & 1ull) != 0ull) total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
         }
         total += extra[r];
         if (max_per_ray > 0) total = min(total, static_cast<int64_t>(max_per_ray));
@@ -1051,70 +1189,6 @@ constexpr int kSegsPerChunk = kWave / kConeBatch;
 constexpr int kTaskWaves = kTaskThreads / kWave;
 constexpr int kSegQueue = kWave * kSegsPerChunk;  // every segment of a wave's chunks
 
-struct ConeHalo {
-    float v;     // max_i s_i |d_i|: level-0 cells per unit t on the fastest axis
-    float smax;  // max_i s_i
-    float omax, dmax, dnorm;
-};
-
-__device__ __forceinline__ ConeHalo cone_halo_ray(const GridK& g, const float o[3], const float d[3]) {
-    ConeHalo k;
-    k.v = fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
-    k.smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
-    k.omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
-    k.dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
-    k.dnorm = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) * (1.0f + 0x1p-18f);
-    return k;
-}
-
-// Whether a segment of candidates whose midpoints lie in [ta, tb] may hold
-// samples (see above): false only when the centre's halo bit is clear and
-// the bound holds.  Branch-free, so the segments' halo words are all in
-// flight together.
-template <int LOOKUP>
-__device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffer_rsrc_t hrs, uint32_t grid,
-                                                  const float o[3], const float d[3], const ConeHalo& k, float ta,
-                                                  float tb) {
-    const float tc = (ta + tb) * 0.5f;
-    const float h = (tb - ta) * 0.5f + fabsf(tb) * 0x1p-20f;  // half-extent, with the rounding of the t values
-    float x0 = o[0] + d[0] * tc, x1 = o[1] + d[1] * tc, x2 = o[2] + d[2] * tc;
-    // the rounding of positions (a few ulps of the largest coordinate
-    // reached, for both points) and of cell coordinates, generously
-    const float slack_x = (k.omax + k.dmax * fabsf(tb) + 1.0f) * 0x1p-19f;
-    const float cell_slack = static_cast<float>(g.res) * 0x1p-17f;
-    float dev;  // bound of |u_i(midpoint) - u_i(centre)| in cells
-    bool open = false;  // the bound cannot be established
-    uint32_t hgrid = grid;
-    if (LOOKUP == NACC_LOOKUP_CASCADE) {
-        const float m = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2));
-        const float dm = k.dmax * h + slack_x;
-        const int l_lo = cascade_level(fmaxf(m - dm, 0.0f), g);
-        const int l_hi = cascade_level(m + dm, g);
-        open = l_lo != l_hi;  // a midpoint may lie on another level
-        hgrid = static_cast<uint32_t>(l_hi);
-        x0 = ldexpf(x0, -l_hi);
-        x1 = ldexpf(x1, -l_hi);
-        x2 = ldexpf(x2, -l_hi);
-        dev = ldexpf(k.v * h + k.smax * slack_x, -l_hi) + cell_slack;
-    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
-        const float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
-        const float r_min = n * (1.0f - 0x1p-18f) - k.dnorm * h - 2.0f * slack_x;
-        const float lip = r_min > 1.0f ? ((2.0f - 1.0f / r_min) / r_min) * (1.0f + 0x1p-18f) : 1.0f;
-        if (n > 1.0f) {
-            const float f = (2.0f - 1.0f / n) / n;
-            x0 = x0 * f;
-            x1 = x1 * f;
-            x2 = x2 * f;
-        }
-        dev = k.smax * (lip * (k.dnorm * h + 2.0f * slack_x) + 3.5f * 0x1p-16f) + cell_slack;
-    } else {
-        dev = k.v * h + k.smax * slack_x + cell_slack;
-    }
-    open = open || !(dev <= static_cast<float>(kHaloReach) * (1.0f - 0x1p-10f));
-    const bool hb = halo_bit(hrs, g, hgrid * g.halo_words, x0, x1, x2);  // loaded in every case
-    return open | hb;
-}
-
 // 32-bit value of lane `src` (per lane) through the LDS crossbar; every lane
 // must be active.
 __device__ __forceinline__ float lane_value(float v, int src) {
@@ -1127,15 +1201,25 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
     int64_t n_rays, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ halo, GridK g, StepK p,
     int n_masks, const float* __restrict__ chunk_t, const float* __restrict__ t_far_in,
-    uint64_t* __restrict__ masks, int32_t* __restrict__ extra, float* __restrict__ seg_t) {
+    uint64_t* __restrict__ masks, int32_t* __restrict__ extra, float* __restrict__ seg_t,
+    const int32_t* __restrict__ task_list, const int64_t* __restrict__ task_total) {
     __shared__ float q_t[kTaskWaves][kSegQueue];
     __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
     __shared__ uint64_t q_mask[kTaskWaves][kWave];
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t first_task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
-    const int64_t task = first_task + lane;
-    const bool in_range = task < static_cast<int64_t>(n_masks) * n_rays;
+    // task = chunk j n_rays + ray r; lane i of the launch takes task i, or,
+    // with a task list, its i-th entry
+    const int64_t first_idx = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
+    const int64_t idx = first_idx + lane;
+    bool in_range;
+    int64_t task = idx;
+    if (task_list != nullptr) {
+        in_range = idx < *task_total;
+        if (in_range) task = task_list[idx];
+    } else {
+        in_range = idx < static_cast<int64_t>(n_masks) * n_rays;
+    }
     int j = 0;
     int64_t r = 0;
     float t = INFINITY;
@@ -1144,7 +1228,11 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
         r = task - static_cast<int64_t>(j) * n_rays;
         t = chunk_t[task];
     }
-    const bool active = t < INFINITY;
+    const bool active = t < INFINITY;  // (NaN: a chunk the starts pass proved empty)
+    if (ballot(active) == 0ull) {     // the whole wave: nothing to look up
+        if (in_range) masks[task] = 0ull;
+        return;
+    }
     float o[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
     float t_far = -INFINITY;
     uint32_t word0 = 0;
@@ -1165,19 +1253,39 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     float st[kSegsPerChunk];
     uint32_t live = 0u;
     bool alive = active;
+    if (p.no_stall) {
+        // every step advances: a segment holds candidates inside the ray iff
+        // its first t lies before t_far; its extent is taken past the ray's
+        // end (a larger interval only weakens the test)
+        float t_last = t;  // t of the chunk's last candidate
 #pragma unroll
-    for (int s = 0; s < kSegsPerChunk; ++s) {
-        const float ta = t;
-        bool any = false;  // some candidate of the segment lies inside the ray
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            const float ta = t;
 #pragma unroll
-        for (int u = 0; u < kConeBatch; ++u) {
-            const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
-            alive = alive && t < t_far && t1 > t;
-            any = any || alive;
-            t = alive ? t1 : t;
+            for (int u = 0; u < kConeBatch; ++u) {
+                t_last = t;
+                t = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+            }
+            st[s] = ta;
+            const bool any = active && ta < t_far;
+            live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, t) & any) << s;
         }
-        st[s] = ta;
-        live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, t) & any) << s;
+        alive = active && t_last < t_far;
+    } else {
+#pragma unroll
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            const float ta = t;
+            bool any = false;  // some candidate of the segment lies inside the ray
+#pragma unroll
+            for (int u = 0; u < kConeBatch; ++u) {
+                const float t1 = t + __builtin_amdgcn_fmed3f(t * p.cone, p.dt, p.dt_max);
+                alive = alive && t < t_far && t1 > t;
+                any = any || alive;
+                t = alive ? t1 : t;
+            }
+            st[s] = ta;
+            live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, t) & any) << s;
+        }
     }
     const bool ended = !alive;
     // queue the live segments of the wave's chunks in LDS, in lane order
@@ -1223,10 +1331,12 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
         const uint32_t hits =
             cone_hits<LOOKUP, false>(bits, nullptr, g, sk, skip_end, s_word0, so, sd, tb, n_valid) &
             ((1u << n_valid) - 1u);
+        const int64_t s_task =
+            task_list != nullptr ? static_cast<int64_t>(lane_value(static_cast<int>(task), src)) : first_idx + src;
         if (has && hits != 0u) {
             __hip_atomic_fetch_or(&q_mask[wave][src], static_cast<uint64_t>(hits) << (s * kConeBatch),
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            seg_t[(first_task + src) * kSegsPerChunk + s] = t0;
+            seg_t[s_task * kSegsPerChunk + s] = t0;
         }
     }
     wave_lds_sync();
@@ -1255,13 +1365,21 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
     int64_t n_rays, const uint32_t* __restrict__ bits, GridK g, StepK p, int n_masks,
     const float* __restrict__ chunk_t, const float* __restrict__ t_far_in, const uint64_t* __restrict__ masks,
     const int32_t* __restrict__ chunk_base, const float* __restrict__ seg_t, const int32_t* __restrict__ packed_info,
-    int64_t capacity, float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status) {
+    int64_t capacity, float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status,
+    const int32_t* __restrict__ task_list, const int64_t* __restrict__ task_total) {
     __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t first_task = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
-    const int64_t task = first_task + lane;
-    const bool in_range = task < static_cast<int64_t>(n_masks) * n_rays;
+    const int64_t first_idx = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
+    const int64_t idx = first_idx + lane;
+    bool in_range;
+    int64_t task = idx;
+    if (task_list != nullptr) {
+        in_range = idx < *task_total;
+        if (in_range) task = task_list[idx];
+    } else {
+        in_range = idx < static_cast<int64_t>(n_masks) * n_rays;
+    }
     int j = 0;
     int64_t r = 0;
     float t = INFINITY;
@@ -1279,6 +1397,8 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
             base = chunk_base[task];
         }
     }
+    // the whole wave: no samples and no ray continuing past the stored chunks
+    if (ballot(m != 0ull || (j == n_masks - 1 && t < INFINITY)) == 0ull) return;
     const float t_far = t < INFINITY ? t_far_in[r] : -INFINITY;
     // segments holding samples that fall before the ray's limit
     uint32_t todo = 0u;
@@ -1318,8 +1438,10 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
                                 static_cast<uint32_t>(lane_value(start_lo, src));
         const uint64_t s_m = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(m_hi, src))) << 32) |
                              static_cast<uint32_t>(lane_value(m_lo, src));
+        const int64_t s_task =
+            task_list != nullptr ? static_cast<int64_t>(lane_value(static_cast<int>(task), src)) : first_idx + src;
         if (has) {
-            const float t0 = seg_t[(first_task + src) * kSegsPerChunk + s];
+            const float t0 = seg_t[s_task * kSegsPerChunk + s];
             float tb[kConeBatch + 1];
             const int n_valid = cone_steps(t0, s_far, p, tb);
             const uint32_t hits = static_cast<uint32_t>(s_m >> (s * kConeBatch)) & 0xffu & ((1u << n_valid) - 1u);
@@ -1487,6 +1609,7 @@ struct Layout {
     int n_masks;
     int64_t chunk_t_off, t_far_off, extra_off;  // cone steps only (0 otherwise)
     int64_t base_off, seg_t_off;                // cone steps, segment passes
+    int64_t live_off, tsum_off, tlist_off;      // cone steps, the task list of the segment passes
     int64_t bytes;
 };
 
@@ -1494,7 +1617,9 @@ int64_t align256(int64_t b) { return ((b + 255) / 256) * 256; }
 
 Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_march_params& p) {
     Layout l;
-    l.sums_bytes = align256(num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)));
+    // the workgroup sums, then the scan's scratch
+    const int64_t nb = num_blocks(n_rays);
+    l.sums_bytes = align256((nb + scan_scratch_values(nb)) * static_cast<int64_t>(sizeof(int64_t)));
     l.n_masks = 0;
     if (p.dt > 0.0f) {
         const int64_t k = candidate_bound(grid, p);
@@ -1502,13 +1627,19 @@ Layout workspace_layout(int64_t n_rays, const nacc_grid_desc& grid, const nacc_m
     }
     l.bytes = l.sums_bytes + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(uint64_t)));
     l.chunk_t_off = l.t_far_off = l.extra_off = l.base_off = l.seg_t_off = 0;
+    l.live_off = l.tsum_off = l.tlist_off = 0;
     if (p.cone > 0.0f) {
         l.chunk_t_off = l.bytes;
         l.t_far_off = l.chunk_t_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(float)));
         l.extra_off = l.t_far_off + align256(n_rays * static_cast<int64_t>(sizeof(float)));
         l.base_off = l.extra_off + align256(n_rays * static_cast<int64_t>(sizeof(int32_t)));
         l.seg_t_off = l.base_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(int32_t)));
-        l.bytes = l.seg_t_off + align256(n_rays * l.n_masks * kSegsPerChunk * static_cast<int64_t>(sizeof(float)));
+        l.live_off = l.seg_t_off + align256(n_rays * l.n_masks * kSegsPerChunk * static_cast<int64_t>(sizeof(float)));
+        l.tsum_off = l.live_off + align256(n_rays * static_cast<int64_t>(sizeof(uint64_t)));
+        const int64_t n_sums = nb * l.n_masks;  // per (chunk, workgroup), the total, the scan's scratch
+        l.tlist_off = l.tsum_off + align256((n_sums + 1 + scan_scratch_values(n_sums)) *
+                                            static_cast<int64_t>(sizeof(int64_t)));
+        l.bytes = l.tlist_off + align256(n_rays * l.n_masks * static_cast<int64_t>(sizeof(int32_t)));
     }
     return l;
 }
@@ -1520,6 +1651,9 @@ struct ConeWork {
     int32_t* extra;       // [n_rays]
     int32_t* chunk_base;  // [n_masks][n_rays]: samples of the ray before each chunk
     float* seg_t;         // [n_masks][n_rays][kSegsPerChunk]: t at the start of segments holding samples
+    uint64_t* live_chunks;  // [n_rays]: chunks in the task list (contraction lookup)
+    int64_t* task_sums;     // [n_masks][workgroups] + 1: scan of the task counts, then the total
+    int32_t* task_list;     // [n_masks * n_rays]
     int n_masks;
 };
 
@@ -1532,6 +1666,9 @@ ConeWork cone_work(void* workspace, const Layout& l) {
     w.extra = reinterpret_cast<int32_t*>(b + l.extra_off);
     w.chunk_base = reinterpret_cast<int32_t*>(b + l.base_off);
     w.seg_t = reinterpret_cast<float*>(b + l.seg_t_off);
+    w.live_chunks = reinterpret_cast<uint64_t*>(b + l.live_off);
+    w.task_sums = reinterpret_cast<int64_t*>(b + l.tsum_off);
+    w.task_list = reinterpret_cast<int32_t*>(b + l.tlist_off);
     w.n_masks = l.n_masks;
     return w;
 }
@@ -1577,24 +1714,47 @@ unsigned task_blocks(int n_masks, int64_t n_rays) {
     return static_cast<unsigned>((static_cast<int64_t>(n_masks) * n_rays + kTaskThreads - 1) / kTaskThreads);
 }
 
+// The segment passes run over a task list of the chunks the starts pass
+// could not prove empty: contraction lookup with halo bits, task ids within
+// int32.
+template <int LOOKUP, bool SKIP>
+bool cone_task_list(const ConeWork& cw, int64_t n_rays) {
+    return SKIP && LOOKUP == NACC_LOOKUP_CONTRACT && cw.n_masks > 0 &&
+           static_cast<int64_t>(cw.n_masks) * n_rays <= INT32_MAX;
+}
+
 template <int LOOKUP, bool SKIP>
 void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const float* o, const float* d,
                        const int32_t* gid, int64_t n, const uint32_t* bits, const uint8_t* skip, const GridK& g,
                        const ClipK& c, const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
     if (cw != nullptr) {  // cone steps
-        hipLaunchKernelGGL((cone_starts_kernel<LOOKUP>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n, g, c, p,
-                           cw->n_masks, cw->chunk_t, cw->t_far, cw->extra);
+        const bool listed = cone_task_list<LOOKUP, SKIP>(*cw, n);
+        if (listed) {
+            hipLaunchKernelGGL((cone_starts_kernel<LOOKUP, true>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                               g, c, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->extra, halo_of(skip, g),
+                               cw->live_chunks, cw->task_sums);
+            const int64_t n_sums = nb * cw->n_masks;
+            scan_exclusive(cw->task_sums, n_sums, cw->task_sums + n_sums, cw->task_sums + n_sums + 1, s);
+            hipLaunchKernelGGL(task_list_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, cw->task_sums, n,
+                               cw->n_masks, cw->live_chunks, cw->task_list);
+        } else {
+            hipLaunchKernelGGL((cone_starts_kernel<LOOKUP, false>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
+                               g, c, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->extra, nullptr, nullptr, nullptr);
+        }
         if (cw->n_masks > 0 && SKIP) {  // segments through the halo bits
             hipLaunchKernelGGL((count_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, halo_of(skip, g), g, p, cw->n_masks,
-                               cw->chunk_t, cw->t_far, cw->masks, cw->extra, cw->seg_t);
+                               cw->chunk_t, cw->t_far, cw->masks, cw->extra, cw->seg_t,
+                               listed ? cw->task_list : nullptr,
+                               listed ? cw->task_sums + nb * cw->n_masks : nullptr);
         } else if (cw->n_masks > 0) {
             hipLaunchKernelGGL((count_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
                                cw->t_far, cw->masks, cw->extra);
         }
         hipLaunchKernelGGL(cone_counts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, n, cw->n_masks, p.max_per_ray,
-                           cw->masks, cw->extra, packed, sums, SKIP ? cw->chunk_base : nullptr);
+                           cw->masks, cw->extra, packed, sums, SKIP ? cw->chunk_base : nullptr,
+                           listed ? cw->live_chunks : nullptr);
         return;
     }
     switch (tuning().march_waves_per_group) {
@@ -1613,9 +1773,12 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
                       float* te, int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
         if (cw != nullptr && cw->n_masks > 0 && SKIP) {  // the segment count's masks and starts
+            const bool listed = cone_task_list<LOOKUP, SKIP>(*cw, n);
             hipLaunchKernelGGL((fill_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, g, p, cw->n_masks, cw->chunk_t,
-                               cw->t_far, cw->masks, cw->chunk_base, cw->seg_t, packed, capacity, ts, te, status);
+                               cw->t_far, cw->masks, cw->chunk_base, cw->seg_t, packed, capacity, ts, te, status,
+                               listed ? cw->task_list : nullptr,
+                               listed ? cw->task_sums + num_blocks(n) * cw->n_masks : nullptr);
         } else if (cw != nullptr && cw->n_masks > 0) {  // replay the count pass's chunks, one lane per chunk
             hipLaunchKernelGGL((fill_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,
@@ -1697,7 +1860,7 @@ int march_count_launch(const float* rays_o, const float* rays_d, const int32_t* 
         st = check_launch("march count");
         if (st != NACC_OK) return st;
     }
-    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
+    scan_exclusive(sums, nb, total, sums + nb, s);
     st = check_launch("march scan");
     if (st != NACC_OK) return st;
     if (nb > 0) {

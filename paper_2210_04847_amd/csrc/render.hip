@@ -936,7 +936,8 @@ int nacc_render_fwd_bwd_mse_noalloc(const int32_t* packed_info, int64_t n_rays, 
 
 int64_t nacc_prune_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
-    return ((num_blocks(n_rays) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
+    const int64_t nb = num_blocks(n_rays);  // the workgroup sums, then the scan's scratch
+    return (((nb + scan_scratch_values(nb)) * static_cast<int64_t>(sizeof(int64_t)) + 255) / 256) * 256;
 }
 
 int nacc_prune_count(const int32_t* packed_info, int64_t n_rays, int64_t n_samples, const float* t_starts,
@@ -969,7 +970,7 @@ int nacc_prune_count(const int32_t* packed_info, int64_t n_rays, int64_t n_sampl
         int st = check_launch("prune count");
         if (st != NACC_OK) return st;
     }
-    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, total);
+    scan_exclusive(sums, nb, total, sums + nb, s);
     int st = check_launch("prune scan");
     if (st != NACC_OK || nb == 0) return st;
     hipLaunchKernelGGL(finalize_starts_kernel, dim3(static_cast<unsigned>(nb)), dim3(kRaysPerBlock), 0, s, sums,

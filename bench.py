@@ -348,19 +348,6 @@ def algorithmic_bytes(n_rays, e, v, forward_only=False):
     }
 
 
-# Lane operations per lattice candidate of the marching contract (what the
-# count pass must compute for every candidate it tests): uniform steps,
-# t_k and t_k+1 (int->float, multiply, add each), the midpoint (add,
-# multiply), the position (3 multiplies, 3 adds), the cell coordinate
-# (3 subtracts, 3 multiplies, 3 clamps, 3 float->int), the cell index
-# (2 multiply-adds), word index and bit (2), the bit test (2): 33.  Cone
-# steps replace the 6 of the t's by the 4 of the recurrence step; the
-# cascade adds the level (3 abs, 2 max, 4 for the exponent) and 3 exact
-# scalings: 43; the contraction instead adds the squared norm (3 multiplies,
-# 2 adds), its square root, the comparison with 1, the reciprocal, 2 - 1/n,
-# the division by n and 3 scalings (a square root or division counted as
-# one operation): 44.
-OPS_PER_CANDIDATE = {"uniform": 33, "cone_cascade": 43, "cone_contract": 44}
 # The synthetic field per sample: per blob 3 differences, the squared
 # distance (multiply, 2 multiply-adds), the exponent argument, exp2 and the
 # accumulation (9); the colour's 3 affine rows (9 multiply-adds) and 3
@@ -373,22 +360,19 @@ FIELD_OPS_FIXED = 29
 RENDER_OPS = 30
 
 
-def ops_key(w):
-    if getattr(w, "cone", 0.0) == 0.0:
-        return "uniform"
-    return "cone_contract" if getattr(w, "lookup", "aabb") == "contract" else "cone_cascade"
-
-
-# One FP32 / integer lane operation per lane per clock: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz (the 157.3 TFLOP/s vector figure counts an FMA as two
-# and two lanes per instruction through packed math, which this build does
-# not use).
-ALU_PEAK = 256 * 4 * 16 * 2.4e9
+# VALU lane operations per second: the 157.3 TFLOP/s FP32 vector figure with
+# an FMA counted as one operation, 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.
+# Single-issue, unpacked code (this build compiles without packed FP32) is
+# held near half of it, 16 lanes per SIMD per clock; the counters show the
+# count kernels issuing slightly above that half, so only the full figure is
+# a ceiling.
+ALU_PEAK = 256 * 4 * 32 * 2.4e9
 
 
 def lattice_candidates(w, rays_o, rays_d):
-    """Lattice candidates the count pass tests (FP64 slab clip; cone steps by
-    running the recurrence in FP32 for all rays at once)."""
+    """Lattice candidates of the rays, each of which the count pass decides
+    (FP64 slab clip; cone steps by running the recurrence in FP32 for all rays
+    at once)."""
     import numpy as np
     o = rays_o.astype(np.float64)
     d = rays_d.astype(np.float64)
@@ -447,6 +431,27 @@ def recorded_traffic(kernel, source, workload):
             if (kv.get("kernel") == kernel and kv.get("workload") == workload
                     and kv.get("source") == source and kv.get("sha256_16") == digest):
                 return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
+def recorded_valu(phase, source, workload):
+    """VALU instructions per step of a phase's kernels on `workload` from the
+    committed counter summaries (lines 'valu_record: ...'), or None when
+    none matches the current source."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for part in source.split("+"):
+        h.update(open(os.path.join(ROOT, part), "rb").read())
+    digest = h.hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("valu_record:"):
+                continue
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if (kv.get("phase") == phase and kv.get("workload") == workload
+                    and kv.get("source") == source and kv.get("sha256_16") == digest):
+                return float(kv["valu_insts"])
     return None
 
 
@@ -775,21 +780,27 @@ def bench_train(args, torch, nacc):
     render_roofline = {
         "bound": "hbm", "kernel": "render", "achieved": render_bps / 1e9, "peak": HBM_PEAK / 1e9,
         "unit": "GB/s", "frac": render_bps / HBM_PEAK,
-        "traffic": (recorded_traffic("render_mse_kernel", RENDER_SOURCES, w.name)
+        "traffic": (recorded_traffic("render_mse", RENDER_SOURCES, w.name)
                     if not forward_only else None)}
     if dominant == "march_count":
-        # the count pass is bound by its per-candidate arithmetic
+        # The count pass is bound by its arithmetic.  With the halo bits it
+        # looks up only part of the lattice, so its work is not a fixed
+        # number of operations per lattice candidate: `achieved` counts the
+        # VALU lane operations the phase's kernels executed per step
+        # (SQ_INSTS_VALU x 64 from the committed counter record of this
+        # workload and source; null when none matches), per phase time.
         cands = lattice_candidates(w, inp["rays_o"], inp["rays_d"])
-        ops = cands * OPS_PER_CANDIDATE[ops_key(w)]
-        ops_s = ops / (phase_avg["march_count"] * 1e-3)
-        # HBM bytes of the uniform-step count kernel, when counters of the
-        # current source are committed (the phase adds the scan's small kernels)
-        traffic = (recorded_traffic("count_uniform_kernel", MARCH_SOURCES, w.name)
-                   if getattr(w, "cone", 0.0) == 0.0 and getattr(w, "lookup", "aabb") == "aabb"
-                   else None)
-        roofline = {"bound": "alu", "kernel": "march_count", "achieved": ops_s / 1e12,
-                    "peak": ALU_PEAK / 1e12, "unit": "TOP/s", "frac": ops_s / ALU_PEAK,
-                    "traffic": traffic, "candidates": cands}
+        valu = recorded_valu("march_count", MARCH_SOURCES, w.name)
+        secs = phase_avg["march_count"] * 1e-3
+        ops_s = valu * 64 / secs if valu is not None else None
+        roofline = {"bound": "alu", "kernel": "march_count",
+                    "achieved": ops_s / 1e12 if ops_s is not None else None,
+                    "peak": ALU_PEAK / 1e12, "unit": "TOP/s",
+                    "frac": ops_s / ALU_PEAK if ops_s is not None else None,
+                    "traffic": recorded_traffic("march_count", MARCH_SOURCES, w.name),
+                    "measure": "VALU lane operations executed (SQ_INSTS_VALU x 64, committed "
+                               "counter record)",
+                    "candidates": cands, "candidates_per_s": cands / secs}
     elif dominant == "render":
         roofline = render_roofline
     else:

@@ -1246,12 +1246,28 @@ def bench_images(args, torch, nacc):
     f_depth = torch.empty(n_all, dtype=f32, device=dev)
     f_kept = torch.empty(n_all, dtype=i32, device=dev)
 
-    def fused(a=0, b=None):
+    # per workgroup of 64 rays: device wall clock at its start and its end
+    clocks = torch.zeros(2 * ((n_all + 63) // 64), dtype=torch.int64, device=dev)
+    clock_khz = lib.wall_clock_khz(dev.index or 0)
+
+    def fused(a=0, b=None, clk=None):
         """marching + field + render in one kernel, no samples written."""
         b = n_all if b is None else b
         lib.synth_render_fused(field.table, field.n_blobs, field.n_sets, None, rays_o[a:b],
                                rays_d[a:b], None, grid.bits, grid.desc, params, eps,
-                               f_color[a:b], f_opacity[a:b], f_depth[a:b], f_kept[a:b])
+                               f_color[a:b], f_opacity[a:b], f_depth[a:b], f_kept[a:b], skip, clk)
+
+    def image_done_ms():
+        """Completion of each image in the last launch with clocks, from the
+        start of its first workgroup (every image is a whole number of
+        64-ray groups here; a group shared by two images counts for both)."""
+        c = clocks.view(-1, 2).cpu().numpy()
+        t0 = int(c[:, 0].min())
+        out = []
+        for k in range(len(counts)):
+            g0, g1 = int(offs[k]) // 64, (int(offs[k + 1]) + 63) // 64
+            out.append((int(c[g0:g1, 1].max()) - t0) / clock_khz)
+        return out
 
     # warm-up (also fills the allocator's cache) and equality checks
     e_b, color_b = batched()
@@ -1288,16 +1304,17 @@ def bench_images(args, torch, nacc):
         lat_p += [start.elapsed_time(ev) for ev in done]
         ms_p.append(start.elapsed_time(done[-1]))
     # fused: all images in one launch, and one launch per image
-    ms_f, lat_f = [], []
+    ms_f, lat_f, lat_fb = [], [], []
     for _ in range(runs):
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record()
-        fused()
+        fused(clk=clocks)
         stop.record()
         torch.cuda.synchronize()
         ms_f.append(start.elapsed_time(stop))
+        lat_fb += image_done_ms()
         done = [torch.cuda.Event(enable_timing=True) for _ in counts]
         start.record()
         for k in range(len(counts)):
@@ -1352,7 +1369,11 @@ def bench_images(args, torch, nacc):
         "plain_ms": med_p,
         "batched_over_plain": med_p / med_f,
         "identical_to_plain": same_fused and same,
-        "latency_ms": {"batched": perc([med_f] * len(ms_f)),
+        # per-image completion inside the one launch (device wall clock at the
+        # end of each image's last workgroup, from the first workgroup's start)
+        "latency_ms": {"batched": perc(lat_fb),
+                       "batched_per_image_ms": [float(np.median(lat_fb[k::len(counts)]))
+                                                for k in range(len(counts))],
                        "plain": perc(lat_p),
                        "fused_per_image_launches": perc(lat_f)},
         "three_step_batched": {"ms": med_b, "samples_per_s": e_b / (med_b * 1e-3),

@@ -77,13 +77,20 @@ int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, 
  * in one kernel, without writing the samples out.  For fields that can be
  * evaluated inside the kernel only (this one).
  *   Arguments as in nacc_march_count / nacc_march_fill (rays_o, rays_d,
- *   grid_id nullable, grid_bits, grid, params) and nacc_synth_field_samples
- *   (table, n_blobs, n_sets, ray_set nullable); uniform steps only
- *   (params->cone must be 0, else NACC_ENOTSUP).  The skip field is not
- *   used (the sample set is the same).
+ *   grid_id nullable, grid_bits, grid_skip nullable, grid, params) and
+ *   nacc_synth_field_samples (table, n_blobs, n_sets, ray_set nullable);
+ *   uniform steps only (params->cone must be 0, else NACC_ENOTSUP).  With
+ *   a skip buffer the box lookup marches by the segments of its halo bits
+ *   (the sample set is the same); the other lookups ignore it.
  *   early_stop_eps  as in nacc_render_fwd (0 disables the cut).
  *   color float[n_rays][3], opacity, depth float[n_rays]: outputs as from
  *   nacc_render_fwd; kept int32[n_rays] (nullable): samples before the cut.
+ *   clocks  uint64[ceil(n_rays / 64)][2] (nullable): for each group of 64
+ *           consecutive rays (rendered by one workgroup), the device wall
+ *           clock (hipDeviceAttributeWallClockRate, kHz) when its workgroup
+ *           started and when the group's last ray was finished, so that a
+ *           caller rendering several images in one launch can tell when
+ *           each image was done.
  * The samples are those nacc_march_fill would write and the chunks those
  * nacc_render_fwd would read, so the outputs equal, bit for bit, marching,
  * then nacc_synth_field_samples, then nacc_render_fwd.  Marching stops at
@@ -93,9 +100,14 @@ int nacc_synth_field_points(const void* table, int32_t n_blobs, int32_t n_sets, 
  */
 int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, const int32_t* ray_set,
                             const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                            const uint32_t* grid_bits, const nacc_grid_desc* grid,
-                            const nacc_march_params* params, float early_stop_eps, float* color,
-                            float* opacity, float* depth, int32_t* kept, void* stream);
+                            const uint32_t* grid_bits, const uint8_t* grid_skip,
+                            const nacc_grid_desc* grid, const nacc_march_params* params,
+                            float early_stop_eps, float* color, float* opacity, float* depth,
+                            int32_t* kept, uint64_t* clocks, void* stream);
+
+/* Frequency (kHz) of the device wall clock the clocks output above counts,
+ * for device `device`; a negative status if the runtime cannot say. */
+int64_t nacc_wall_clock_khz(int32_t device);
 
 /*
  * The two field evaluations above as stages of a step plan (nacc_plan.h):

@@ -146,9 +146,10 @@ _SIGNATURES = {
     "nacc_plan_capture_step": (_INT, [_P]),
     "nacc_plan_launch": (_INT, [_P, _I32, _P]),
     "nacc_plan_autotune": (_INT, [_P, _I32, _P, ctypes.POINTER(Tuning), ctypes.POINTER(_F)]),
-    "nacc_synth_render_fused": (_INT, [_P, _I32, _I32, _P, _P, _P, _P, _I64, _P,
+    "nacc_wall_clock_khz": (_I64, [_I32]),
+    "nacc_synth_render_fused": (_INT, [_P, _I32, _I32, _P, _P, _P, _P, _I64, _P, _P,
                                        ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams), _F,
-                                       _P, _P, _P, _P, _P]),
+                                       _P, _P, _P, _P, _P, _P]),
     "nacc_probe_hbm": (_INT, [_I32, _P, _P, _I64, _I32, _P]),
 }
 
@@ -525,8 +526,18 @@ def synth_field_points(table, n_blobs, n_sets, points, point_set, sigmas, rgbs=N
         int(cells_per_set), n, _ptr(sigmas), _ptr(rgbs), _stream(stream)))
 
 
+def wall_clock_khz(device: int = 0) -> int:
+    """Frequency of the device wall clock that the fused kernel's clocks count."""
+    khz = int(lib.nacc_wall_clock_khz(device))
+    if khz <= 0:
+        raise NaccError("nacc_wall_clock_khz", khz if khz < 0 else NACC_EHIP,
+                        lib.nacc_last_error().decode())
+    return khz
+
+
 def synth_render_fused(table, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id, grid_bits, desc,
-                       params, early_stop_eps, color, opacity, depth, kept=None, stream=None):
+                       params, early_stop_eps, color, opacity, depth, kept=None, grid_skip=None,
+                       clocks=None, stream=None):
     n = rays_o.shape[0]
     _need(table, torch.float32, "table")
     _need(ray_set, torch.int32, "ray_set", n)
@@ -538,10 +549,13 @@ def synth_render_fused(table, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
     _need(opacity, torch.float32, "opacity", n)
     _need(depth, torch.float32, "depth", n)
     _need(kept, torch.int32, "kept", n)
+    _need(grid_skip, torch.uint8, "grid_skip", grid_skip_bytes(desc))
+    _need(clocks, torch.int64, "clocks", 2 * ((n + 63) // 64))
     _check("nacc_synth_render_fused", lib.nacc_synth_render_fused(
         _ptr(table), n_blobs, n_sets, _ptr(ray_set), _ptr(rays_o), _ptr(rays_d), _ptr(grid_id), n,
-        _ptr(grid_bits), ctypes.byref(desc), ctypes.byref(params), float(early_stop_eps),
-        _ptr(color), _ptr(opacity), _ptr(depth), _ptr(kept), _stream(stream)))
+        _ptr(grid_bits), _ptr(grid_skip), ctypes.byref(desc), ctypes.byref(params),
+        float(early_stop_eps), _ptr(color), _ptr(opacity), _ptr(depth), _ptr(kept), _ptr(clocks),
+        _stream(stream)))
 
 
 def render_attrs_fwd(packed_info, t_starts, t_ends, sigmas, attrs, early_stop_eps, alpha_thre,

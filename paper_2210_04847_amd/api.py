@@ -356,14 +356,15 @@ class BlobField:
 
 def render_fused(field: BlobField, rays_o, rays_d, grid: OccupancyGrid, near_plane=0.0,
                  far_plane=1e10, render_step_size=STEP_1024, early_stop_eps=1e-4, max_per_ray=0,
-                 grid_id=None, ray_set=None, return_kept=False):
+                 grid_id=None, ray_set=None, return_kept=False, skip_empty=True):
     """Inference in one kernel (Sec. 2.1 marching with early termination and
     Eq. 1, forward only) for a field the library evaluates itself: marches,
     evaluates `field` at the occupied samples and renders them without
     writing the samples out.  Returns (color [R, 3], opacity [R], depth [R])
     (and the samples before the cut per ray, with return_kept), equal bit
     for bit to ray_marching -> field.samples -> rendering.  Uniform steps
-    only."""
+    only.  With skip_empty the box lookup marches by the halo bits of the
+    grid's skip buffer (same samples)."""
     n = rays_o.shape[0]
     dev = rays_o.device
     color = torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -375,5 +376,5 @@ def render_fused(field: BlobField, rays_o, rays_d, grid: OccupancyGrid, near_pla
     rs = None if ray_set is None else ray_set.to(torch.int32).contiguous()
     _lib.synth_render_fused(field.table, field.n_blobs, field.n_sets, rs, rays_o.contiguous(),
                             rays_d.contiguous(), gid, grid.bits, grid.desc, params, early_stop_eps,
-                            color, opacity, depth, kept)
+                            color, opacity, depth, kept, grid.skip if skip_empty else None)
     return (color, opacity, depth, kept) if return_kept else (color, opacity, depth)

@@ -15,7 +15,11 @@
 // packed arrays, so colour, opacity and depth are bit for bit those of
 // marching + field + rendering as three steps.  Marching stops at the
 // early-termination cut, which the three-step form cannot do (it marches the
-// whole ray before any density is known).
+// whole ray before any density is known).  Through the box lookup with the
+// halo bits of a skip buffer, a ray is marched by segments as in the count
+// pass: 64 segments' halo bits tested at once, then only the candidates of
+// the live segments looked up, in t order, so the queued samples are the
+// same.
 #include <cmath>
 
 #include "blob_field.h"
@@ -37,14 +41,41 @@ constexpr int kFusedWaves = 4;
 constexpr int kFusedRays = 64;  // rays per workgroup: lane j of a wave clips its j-th ray
 constexpr int kRing = 256;      // candidate indices per wave: < 64 held + 128 appended
 
-template <int LOOKUP, bool PER_SET>
+// Appends the occupied candidates of one wave iteration (ballot m of the
+// candidates k, lanes in t order) to the ring, at most up to max_per_ray
+// samples; returns false when the cap ends the ray.
+__device__ __forceinline__ bool append_hits(uint64_t m, bool hit, int k, int head, int& queued, int& marched,
+                                            const StepK& p, int* __restrict__ ring) {
+    int n_new = __popcll(m);
+    bool more = true;
+    if (p.max_per_ray > 0 && marched + n_new >= p.max_per_ray) {
+        n_new = p.max_per_ray - marched;  // the first ones in t order
+        hit = hit && bits_below(m) < n_new;
+        more = false;
+    }
+    if (hit) ring[(head + queued + bits_below(m)) & (kRing - 1)] = k;
+    queued += n_new;
+    marched += n_new;
+    return more;
+}
+
+// Where the segment walk of a ray stands between chunks.
+struct SegWalk {
+    int block = 0;      // next block of 64 segments to test
+    int slot = 0;       // next entry of the current block's live list
+    int n_live = 0;     // entries of that list
+    bool last = false;  // the current block is the ray's last
+};
+
+template <int LOOKUP, bool PER_SET, bool SEG>
 __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span, const float* __restrict__ table,
                                                  int n_blobs, int n_sets, const int32_t* __restrict__ ray_set,
                                                  const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-                                                 const uint32_t* __restrict__ bits, const GridK& g, const StepK& p,
-                                                 float eps, int* __restrict__ ring, float* __restrict__ color,
-                                                 float* __restrict__ opacity, float* __restrict__ depth,
-                                                 int32_t* __restrict__ kept) {
+                                                 const uint32_t* __restrict__ bits,
+                                                 const uint32_t* __restrict__ halo, const GridK& g, const StepK& p,
+                                                 float eps, int* __restrict__ ring, uint8_t* __restrict__ list,
+                                                 float* __restrict__ color, float* __restrict__ opacity,
+                                                 float* __restrict__ depth, int32_t* __restrict__ kept) {
     const int lane = lane_id();
     const float* o = span.o;  // loaded lane-parallel with the wave's other rays
     const float* d = span.d;
@@ -65,11 +96,64 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
     int n_kept = -1;
     bool more = span.valid;
     int k0 = 0;
+    SegRay sg{0, 0u};
+    if (SEG && span.valid) sg = seg_ray(g, span, p);
+    SegWalk sw;
     while (true) {
         // march until a whole chunk is queued or the ray's candidates end,
-        // two chunks of candidates per iteration (both grid words loaded,
-        // both ballots taken, before either chunk is appended)
-        while (more && queued < kWave) {
+        // by segments: two iterations of live segments' candidates at a time
+        // (both grid words loaded before either is tested)
+        while (SEG && sg.log_g != 0 && more && queued < kWave) {
+            if (sw.slot >= sw.n_live) {  // the next block of segments
+                uint64_t vm;
+                const uint64_t lm = sw.last ? 0ull : live_segments(span, halo, g, p, sg, sw.block, vm);
+                if (sw.last || vm == 0ull) {
+                    more = false;
+                    break;
+                }
+                wave_lds_sync();  // the previous block's list has been read
+                if (((lm >> lane) & 1ull) != 0ull) list[bits_below(lm)] = static_cast<uint8_t>(lane);
+                wave_lds_sync();
+                sw.n_live = static_cast<int>(__popcll(lm));
+                sw.slot = 0;
+                sw.last = vm != ~0ull;
+                ++sw.block;
+                continue;
+            }
+            const int log_g = sg.log_g;
+            const int per_iter = kWave >> log_g;
+            int k[2];
+            float t0[2], t1[2];
+            bool alive[2];
+            uint64_t ms[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int slot = sw.slot + u * per_iter + (lane >> log_g);
+                const bool in = slot < sw.n_live;
+                const int seg = in ? static_cast<int>(list[slot]) : 0;
+                k[u] = (((sw.block - 1) * kWave + seg) << log_g) + (lane & ((1 << log_g) - 1));
+                t0[u] = t_near + static_cast<float>(k[u]) * p.dt;
+                t1[u] = t_near + static_cast<float>(k[u] + 1) * p.dt;
+                alive[u] = in && t0[u] < t_far;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float tm = (t0[u] + t1[u]) * 0.5f;
+                const Probe q =
+                    probe<LOOKUP>(g, span.word0, o[0] + d[0] * tm, o[1] + d[1] * tm, o[2] + d[2] * tm);
+                const uint32_t w = grid_word(grid_rsrc(bits, g), q.word);  // every lane: the index is clamped into the grid
+                ms[u] = ballot(alive[u] & (((w >> q.bit) & 1u) != 0u));
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!append_hits(ms[u], ((ms[u] >> lane) & 1ull) != 0ull, k[u], head, queued, marched, p, ring)) {
+                    more = false;
+                    break;
+                }
+            }
+            sw.slot += 2 * per_iter;
+        }
+        while (!(SEG && sg.log_g != 0) && more && queued < kWave) {
             float t0[2], t1[2];
             bool live[2];
             uint64_t ms[2];
@@ -98,18 +182,11 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
                     more = false;
                     break;
                 }
-                uint64_t m = ms[u];
-                bool hit = ((m >> lane) & 1ull) != 0ull;
-                int n_new = __popcll(m);
-                if (p.max_per_ray > 0 && marched + n_new >= p.max_per_ray) {
-                    n_new = p.max_per_ray - marched;  // the first ones in t order
-                    hit = hit && bits_below(m) < n_new;
+                if (!append_hits(ms[u], ((ms[u] >> lane) & 1ull) != 0ull, k0 + u * kWave + lane, head, queued,
+                                 marched, p, ring)) {
                     more = false;
+                    break;
                 }
-                if (hit) ring[(head + queued + bits_below(m)) & (kRing - 1)] = k0 + u * kWave + lane;
-                queued += n_new;
-                marched += n_new;
-                if (!more) break;
             }
             k0 += 2 * kWave;
         }
@@ -164,13 +241,18 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
     }
 }
 
-template <int LOOKUP, bool PER_SET>
+// clocks (nullable): the device wall clock when the workgroup started and
+// when its last wave finished, per workgroup of kFusedRays rays.
+template <int LOOKUP, bool PER_SET, bool SEG>
 __global__ __launch_bounds__(kFusedWaves * kWave) void fused_render_kernel(
     const float* __restrict__ table, int n_blobs, int n_sets, const int32_t* __restrict__ ray_set,
     const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
-    int64_t n_rays, const uint32_t* __restrict__ bits, GridK g, ClipK c, StepK p, float eps,
-    float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth, int32_t* __restrict__ kept) {
+    int64_t n_rays, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ halo, GridK g, ClipK c,
+    StepK p, float eps, float* __restrict__ color, float* __restrict__ opacity, float* __restrict__ depth,
+    int32_t* __restrict__ kept, uint64_t* __restrict__ clocks) {
     __shared__ int rings[kFusedWaves][kRing];
+    __shared__ uint8_t lists[kFusedWaves][SEG ? kWave : 1];
+    const uint64_t t_start = clocks != nullptr ? wall_clock64() : 0ull;
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kFusedRays;
     // this wave's rays are first + wave + j kFusedWaves; lane j clips ray j
@@ -183,22 +265,31 @@ __global__ __launch_bounds__(kFusedWaves * kWave) void fused_render_kernel(
         const int64_t r = first + i;
         if (r >= n_rays) break;
         const RaySpan span = read_span(spans, i / kFusedWaves);
-        render_ray_fused<LOOKUP, PER_SET>(r, span, table, n_blobs, n_sets, ray_set, rays_o, rays_d, bits, g, p, eps,
-                                          rings[wave], color, opacity, depth, kept);
+        render_ray_fused<LOOKUP, PER_SET, SEG>(r, span, table, n_blobs, n_sets, ray_set, rays_o, rays_d, bits, halo,
+                                               g, p, eps, rings[wave], lists[wave], color, opacity, depth, kept);
+    }
+    if (clocks != nullptr) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            clocks[2 * blockIdx.x] = t_start;
+            clocks[2 * blockIdx.x + 1] = wall_clock64();
+        }
     }
 }
 
-template <int LOOKUP>
-void launch_fused(bool per_set, unsigned nb, hipStream_t s, const float* table, int n_blobs, int n_sets,
-                  const int32_t* ray_set, const float* o, const float* d, const int32_t* gid, int64_t n,
-                  const uint32_t* bits, const GridK& g, const ClipK& c, const StepK& p, float eps, float* color,
-                  float* opacity, float* depth, int32_t* kept) {
+template <int LOOKUP, bool SEG>
+void launch_fused_seg(bool per_set, unsigned nb, hipStream_t s, const float* table, int n_blobs, int n_sets,
+                      const int32_t* ray_set, const float* o, const float* d, const int32_t* gid, int64_t n,
+                      const uint32_t* bits, const uint32_t* halo, const GridK& g, const ClipK& c, const StepK& p,
+                      float eps, float* color, float* opacity, float* depth, int32_t* kept, uint64_t* clocks) {
     if (per_set) {
-        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, true>), dim3(nb), dim3(kFusedWaves * kWave), 0, s, table,
-                           n_blobs, n_sets, ray_set, o, d, gid, n, bits, g, c, p, eps, color, opacity, depth, kept);
+        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, true, SEG>), dim3(nb), dim3(kFusedWaves * kWave), 0, s,
+                           table, n_blobs, n_sets, ray_set, o, d, gid, n, bits, halo, g, c, p, eps, color, opacity,
+                           depth, kept, clocks);
     } else {
-        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, false>), dim3(nb), dim3(kFusedWaves * kWave), 0, s, table,
-                           n_blobs, n_sets, ray_set, o, d, gid, n, bits, g, c, p, eps, color, opacity, depth, kept);
+        hipLaunchKernelGGL((fused_render_kernel<LOOKUP, false, SEG>), dim3(nb), dim3(kFusedWaves * kWave), 0, s,
+                           table, n_blobs, n_sets, ray_set, o, d, gid, n, bits, halo, g, c, p, eps, color, opacity,
+                           depth, kept, clocks);
     }
 }
 
@@ -206,11 +297,19 @@ void launch_fused(bool per_set, unsigned nb, hipStream_t s, const float* table, 
 
 extern "C" {
 
+int64_t nacc_wall_clock_khz(int32_t device) {
+    clear_error();
+    int khz = 0;
+    const hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
+    if (e != hipSuccess) return set_error(NACC_EHIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    return khz;
+}
+
 int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, const int32_t* ray_set,
                             const float* rays_o, const float* rays_d, const int32_t* grid_id, int64_t n_rays,
-                            const uint32_t* grid_bits, const nacc_grid_desc* grid, const nacc_march_params* params,
-                            float early_stop_eps, float* color, float* opacity, float* depth, int32_t* kept,
-                            void* stream) {
+                            const uint32_t* grid_bits, const uint8_t* grid_skip, const nacc_grid_desc* grid,
+                            const nacc_march_params* params, float early_stop_eps, float* color, float* opacity,
+                            float* depth, int32_t* kept, uint64_t* clocks, void* stream) {
     clear_error();
     int st = validate(rays_o, rays_d, n_rays, grid_bits, grid, params);
     if (st != NACC_OK) return st;
@@ -231,20 +330,31 @@ int nacc_synth_render_fused(const void* table, int32_t n_blobs, int32_t n_sets, 
     hipStream_t s = as_stream(stream);
     const float* tb = static_cast<const float*>(table);
     const bool per_set = ray_set != nullptr;
+    // the halo bits of the skip buffer (box lookup, res a multiple of 4)
+    const uint32_t* halo = grid_skip != nullptr && grid->res % 4 == 0 && grid->lookup == NACC_LOOKUP_AABB
+                               ? reinterpret_cast<const uint32_t*>(grid_skip + halo_offset(g.res, g.n_grids))
+                               : nullptr;
     switch (grid->lookup) {
         case NACC_LOOKUP_AABB:
-            launch_fused<NACC_LOOKUP_AABB>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
-                                           n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity, depth, kept);
+            if (halo != nullptr) {
+                launch_fused_seg<NACC_LOOKUP_AABB, true>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o,
+                                                         rays_d, grid_id, n_rays, grid_bits, halo, g, c, p,
+                                                         early_stop_eps, color, opacity, depth, kept, clocks);
+            } else {
+                launch_fused_seg<NACC_LOOKUP_AABB, false>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o,
+                                                          rays_d, grid_id, n_rays, grid_bits, nullptr, g, c, p,
+                                                          early_stop_eps, color, opacity, depth, kept, clocks);
+            }
             break;
         case NACC_LOOKUP_CASCADE:
-            launch_fused<NACC_LOOKUP_CASCADE>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d, grid_id,
-                                              n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity, depth,
-                                              kept);
+            launch_fused_seg<NACC_LOOKUP_CASCADE, false>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d,
+                                                         grid_id, n_rays, grid_bits, nullptr, g, c, p,
+                                                         early_stop_eps, color, opacity, depth, kept, clocks);
             break;
         default:
-            launch_fused<NACC_LOOKUP_CONTRACT>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o, rays_d,
-                                               grid_id, n_rays, grid_bits, g, c, p, early_stop_eps, color, opacity,
-                                               depth, kept);
+            launch_fused_seg<NACC_LOOKUP_CONTRACT, false>(per_set, nb, s, tb, n_blobs, n_sets, ray_set, rays_o,
+                                                          rays_d, grid_id, n_rays, grid_bits, nullptr, g, c, p,
+                                                          early_stop_eps, color, opacity, depth, kept, clocks);
             break;
     }
     return check_launch("fused render");

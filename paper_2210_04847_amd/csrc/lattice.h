@@ -224,6 +224,93 @@ __device__ __forceinline__ RaySpan read_span(const RaySpan& s, int lane) {
     return b;
 }
 
+// ---------------------------------------------------------------------------
+// Uniform steps through the box lookup with the halo bits of the skip
+// buffer.  A ray's candidates are grouped into segments of G consecutive
+// ones (segment j: candidates [j G, j G + G)); a wave tests 64 segments at
+// once, one halo bit each at the segment's centre, and then looks up one by
+// one only the candidates of the segments whose bit is set, 64 at a time
+// (64 / G segments per iteration, in segment order, so the ballots still
+// list the samples in t order).
+//
+// A clear bit proves its segment empty.  The segment's midpoints lie within
+// (G/2) dt of its centre in t, so their fine-cell coordinates
+// u_i = (x_i - lo_i) s_i differ from the centre's by less than
+// v (G/2) dt plus rounding, v = max_i s_i |d_i|.  G is the largest power of
+// two up to 32 that keeps this below kHaloReach cells; the cells of the
+// midpoints then lie within kHaloReach cells of the centre's cell (clamping
+// into the grid only brings coordinates closer), so within kHaloReach cells
+// of the centre's 2x2x2 halo cell on every axis, and a clear halo bit says
+// none of those cells is occupied.  Rays that would need G < 8 are marched
+// candidate by candidate.  The samples are exactly those of the plain
+// traversal.
+// ---------------------------------------------------------------------------
+constexpr int kMinSegmentLog2 = 3;  // segments of 8, 16 or 32 candidates
+
+struct SegRay {
+    int log_g;       // log2 of the candidates per segment; 0: no segments
+    uint32_t halo0;  // first halo word of the ray's grid
+};
+
+__device__ __forceinline__ SegRay seg_ray(const GridK& g, const RaySpan& span, const StepK& p) {
+    SegRay sg{0, 0u};
+    const float* o = span.o;
+    const float* d = span.d;
+    const float v = fmaxf(fmaxf(g.s[0] * fabsf(d[0]), g.s[1] * fabsf(d[1])), g.s[2] * fabsf(d[2]));
+    const float smax = fmaxf(fmaxf(g.s[0], g.s[1]), g.s[2]);
+    const float omax = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]));
+    const float dmax = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+    const float tmax = fmaxf(fabsf(span.t_near), fabsf(span.t_far));
+    // allowances in cells, each taken generously: the rounding of both
+    // positions (a few ulps of the largest coordinate the ray reaches), of
+    // the cell coordinates, and of the t values (a few ulps of t, times v)
+    const float slack_x = (omax + dmax * tmax + 1.0f) * 0x1p-20f;
+    const float slack = 2.0f * smax * slack_x + static_cast<float>(g.res) * 0x1p-17f + v * tmax * 0x1p-20f;
+    const float budget = static_cast<float>(kHaloReach) - slack;
+    int lg = 5;
+    while (lg >= kMinSegmentLog2 && !(v * ldexpf(p.dt, lg - 1) * (1.0f + 0x1p-10f) <= budget)) --lg;
+    if (lg >= kMinSegmentLog2) {
+        sg.log_g = lg;
+        sg.halo0 = span.grid * g.halo_words;
+    }
+    return sg;
+}
+
+// Halo bit of the cell holding point x (the box lookup's clamped cell
+// coordinates, halved).
+__device__ __forceinline__ bool halo_bit(__amdgpu_buffer_rsrc_t rs, const GridK& g, uint32_t halo0, float x0,
+                                         float x1, float x2) {
+    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
+    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
+    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
+    const uint32_t cell =
+        __umul24(j0 >> 1, g.halo_res2) + (__umul24(j1 >> 1, static_cast<uint32_t>(g.halo_res)) + (j2 >> 1));
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (halo0 + (cell >> 5)) << 2, 0, 0);
+    return ((w >> (cell & 31u)) & 1u) != 0u;
+}
+
+// Live-segment ballot of block b of a ray's segments (segment j = b 64 +
+// lane): its first candidate lies before t_far (ballot `vm`, returned too)
+// and the halo bit at its centre is set.
+__device__ __forceinline__ uint64_t live_segments(const RaySpan& span, const uint32_t* __restrict__ halo,
+                                                  const GridK& g, const StepK& p, const SegRay& sg, int b,
+                                                  uint64_t& vm) {
+    const int lane = lane_id();
+    const int log_g = sg.log_g;
+    const int k_first = (b * kWave + lane) << log_g;
+    // kMaxCandidates is a multiple of every G: a segment starting below it
+    // ends at or below it
+    const bool valid = k_first < kMaxCandidates && span.t_near + static_cast<float>(k_first) * p.dt < span.t_far;
+    vm = ballot(valid);
+    if (vm == 0ull) return 0ull;
+    const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
+    const float tc = span.t_near + static_cast<float>(k_first + (1 << (log_g - 1))) * p.dt;
+    const bool hb = halo_bit(hrs, g, sg.halo0, span.o[0] + span.d[0] * tc, span.o[1] + span.d[1] * tc,
+                             span.o[2] + span.d[2] * tc);
+    return vm & ballot(hb);
+}
+
 int validate(const float* rays_o, const float* rays_d, int64_t n_rays, const uint32_t* bits,
              const nacc_grid_desc* grid, const nacc_march_params* params) {
     NACC_REQUIRE(grid != nullptr && params != nullptr, NACC_EINVAL, "grid and params must be non-NULL");

@@ -73,12 +73,16 @@ def train4k():
     return nacc, w, inp, grid, field
 
 
+@pytest.mark.parametrize("skip", [True, False])
 @pytest.mark.parametrize("eps", [1e-4, 0.0, 0.05])
-def test_fused_equals_three_steps(train4k, eps):
+def test_fused_equals_three_steps(train4k, eps, skip):
+    """With the grid's skip buffer (marching by the segments of its halo
+    bits) and without."""
     nacc, w, inp, grid, field = train4k
     o, d = _cuda(inp["rays_o"]), _cuda(inp["rays_d"])
     ref = _three_step(nacc, field, grid, o, d, w.near, w.far, w.dt, eps)
-    fused = nacc.render_fused(field, o, d, grid, w.near, w.far, w.dt, eps, return_kept=True)
+    fused = nacc.render_fused(field, o, d, grid, w.near, w.far, w.dt, eps, return_kept=True,
+                              skip_empty=skip)
     torch.cuda.synchronize()
     _assert_same(fused, ref)
     counts = ref["packed"][:, 1]
@@ -175,8 +179,9 @@ def test_fused_max_per_ray_and_lookups():
     for cap in (37, 64, 100):
         ref = _three_step(nacc, field, grid, o, d, w.near, w.far, w.dt, 1e-4, max_per_ray=cap)
         assert int(ref["packed"][:, 1].max()) == cap
-        _assert_same(nacc.render_fused(field, o, d, grid, w.near, w.far, w.dt, 1e-4,
-                                       max_per_ray=cap, return_kept=True), ref)
+        for skip in (True, False):
+            _assert_same(nacc.render_fused(field, o, d, grid, w.near, w.far, w.dt, 1e-4,
+                                           max_per_ray=cap, return_kept=True, skip_empty=skip), ref)
     uw = synth.UNBOUNDED_WORKLOADS["unbounded_262k"]
     uin = synth.unbounded_inputs(uw, 1200, 32)
     uf = nacc.BlobField(uin["scene"])
@@ -195,6 +200,42 @@ def test_fused_max_per_ray_and_lookups():
     assert ref["ri"].numel() > 10000
     _assert_same(nacc.render_fused(uf, uo, ud, kg, kw.near, 200.0, 0.02, 1e-4, max_per_ray=1024,
                                    return_kept=True), ref)
+
+
+def test_fused_coarse_steps_and_workgroup_clocks(train4k):
+    """Steps too long for segments (each ray marched candidate by candidate
+    although the skip buffer is given), and the per-workgroup clocks: set
+    for every group of 64 rays, start before end, within the launch, and
+    the colours the same as without them."""
+    nacc, w, inp, grid, field = train4k
+    lib = nacc._lib
+    o, d = _cuda(inp["rays_o"]), _cuda(inp["rays_d"])
+    ref = _three_step(nacc, field, grid, o, d, w.near, w.far, 0.05, 1e-4)
+    _assert_same(nacc.render_fused(field, o, d, grid, w.near, w.far, 0.05, 1e-4, return_kept=True),
+                 ref)
+    n = o.shape[0]
+    groups = (n + 63) // 64
+    clocks = torch.zeros(2 * groups, dtype=torch.int64, device="cuda")
+    color = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    opacity = torch.empty(n, dtype=torch.float32, device="cuda")
+    depth = torch.empty(n, dtype=torch.float32, device="cuda")
+    kept = torch.empty(n, dtype=torch.int32, device="cuda")
+    params = lib.march_params(w.near, w.far, w.dt)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    lib.synth_render_fused(field.table, field.n_blobs, field.n_sets, None, o, d, None, grid.bits,
+                           grid.desc, params, 1e-4, color, opacity, depth, kept, grid.skip, clocks)
+    stop.record()
+    torch.cuda.synchronize()
+    want = _three_step(nacc, field, grid, o, d, w.near, w.far, w.dt, 1e-4)
+    _assert_same((color, opacity, depth, kept), want)
+    c = clocks.view(groups, 2).cpu().numpy()
+    assert (c > 0).all() and (c[:, 1] >= c[:, 0]).all()
+    khz = lib.wall_clock_khz(0)
+    assert khz > 0
+    span_ms = (int(c[:, 1].max()) - int(c[:, 0].min())) / khz
+    assert 0 < span_ms <= start.elapsed_time(stop) * 1.05 + 0.05
 
 
 def test_fused_frames_grid_ids_and_edge_cases():

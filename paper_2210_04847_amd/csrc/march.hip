@@ -969,20 +969,25 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_chunks_kernel(
 }
 
 // Per-ray counts from the chunk masks (capped at max_per_ray) and the
-// workgroup sums of the scan.
+// workgroup sums of the scan.  For the segment fill (nullable): the samples
+// of each ray before each chunk, and per ray the bits of the chunks holding
+// samples (sample_chunks may be live_chunks itself: each ray's word is read
+// before it is written).
 __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_rays, int n_masks, int max_per_ray,
                                                                     const uint64_t* __restrict__ masks,
                                                                     const int32_t* __restrict__ extra,
                                                                     int32_t* __restrict__ packed_info,
                                                                     int64_t* __restrict__ block_sums,
                                                                     int32_t* __restrict__ chunk_base,
-                                                                    const uint64_t* __restrict__ live_chunks) {
+                                                                    const uint64_t* live_chunks,
+                                                                    uint64_t* sample_chunks) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     int n = 0;
     if (r < n_rays) {
         // with a task list, the chunks left out of it hold no samples (their
         // masks were not written)
         const uint64_t listed = live_chunks != nullptr ? live_chunks[r] : ~0ull;
+        uint64_t holding = 0ull;
         int64_t total = 0;
         for (int j = 0; j < n_masks; ++j) {
             // samples of the ray before chunk j (for the segment fill)
@@ -990,8 +995,13 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
                 chunk_base[static_cast<int64_t>(j) * n_rays + r] =
                     static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
             }
-            if (((listed >> j) & 1ull) != 0ull) total += __popcll(masks[static_cast<int64_t>(j) * n_rays + r]);
+            if (((listed >> j) & 1ull) != 0ull) {
+                const uint64_t m = masks[static_cast<int64_t>(j) * n_rays + r];
+                total += __popcll(m);
+                if (m != 0ull) holding |= 1ull << j;
+            }
         }
+        if (sample_chunks != nullptr) sample_chunks[r] = holding;
         total += extra[r];
         if (max_per_ray > 0) total = min(total, static_cast<int64_t>(max_per_ray));
         n = static_cast<int>(min(total, static_cast<int64_t>(kMaxCandidates)));
@@ -1269,115 +1279,193 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     }
 }
 
-// Fill pass of the segment count: one lane per chunk queues its segments
-// that hold samples (and lie before the ray's limit); they are then written
-// one per lane from the stored t at their start, 8 recurrence steps each.
+// Fill pass of the segment count, ray-major with staged stores.  A wave
+// takes 64 consecutive rays and lists their (ray, chunk) tasks for the
+// chunks that hold samples (cone_counts_kernel leaves their bits per ray),
+// ray by ray, chunk by chunk, so the segments that hold samples, queued in
+// that order, are in the order of their samples in the output.  The queue
+// is written 64 segments at a time: one lane per segment runs its 8
+// recurrence steps from the stored t at its start and puts its samples
+// (t_start, t_end) into this wave's LDS slots in output order; then the
+// wave stores the slots, 64 consecutive positions at a time, with the ray
+// indices, so every store is coalesced (each segment's samples stored from
+// its own lane scatter 4-byte writes over as many cache lines as lanes).
+// A ray longer than the stored chunks is finished past them by its lane.
+constexpr int kFillSlots = kWave * kConeBatch;  // the samples of 64 segments at most
+
+// Position of the k-th set bit of v (k < popcount(v)).
+__device__ __forceinline__ int nth_set_bit(uint64_t v, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = static_cast<int>(__popcll(v & ((1ull << w) - 1ull)));
+        if (k >= c) {
+            k -= c;
+            v >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
 template <int LOOKUP>
-__global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
+__global__ __launch_bounds__(kTaskThreads) void fill_cone_rays_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
     int64_t n_rays, const uint32_t* __restrict__ bits, GridK g, StepK p, int n_masks,
     const float* __restrict__ chunk_t, const float* __restrict__ t_far_in, const uint64_t* __restrict__ masks,
-    const int32_t* __restrict__ chunk_base, const float* __restrict__ seg_t, const int32_t* __restrict__ packed_info,
-    int64_t capacity, float* __restrict__ t_starts, float* __restrict__ t_ends, int32_t* __restrict__ status,
-    const int32_t* __restrict__ task_list, const int64_t* __restrict__ task_total) {
+    const int32_t* __restrict__ chunk_base, const float* __restrict__ seg_t,
+    const uint64_t* __restrict__ sample_chunks, const int32_t* __restrict__ packed_info, int64_t capacity,
+    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends,
+    int32_t* __restrict__ status) {
     __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
+    __shared__ float s_t0[kTaskWaves][kFillSlots];
+    __shared__ float s_t1[kTaskWaves][kFillSlots];
+    __shared__ uint8_t s_entry[kTaskWaves][kFillSlots];  // the queue entry (of this round) a slot belongs to
+    __shared__ int64_t e_pos[kTaskWaves][kWave];         // output position of an entry's first sample
+    __shared__ int32_t e_slot[kTaskWaves][kWave];        // its first slot
+    __shared__ int32_t e_ray[kTaskWaves][kWave];
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
-    const int64_t first_idx = static_cast<int64_t>(blockIdx.x) * kTaskThreads + wave * kWave;
-    const int64_t idx = first_idx + lane;
-    bool in_range;
-    int64_t task = idx;
-    if (task_list != nullptr) {
-        in_range = idx < *task_total;
-        if (in_range) task = task_list[idx];
-    } else {
-        in_range = idx < static_cast<int64_t>(n_masks) * n_rays;
-    }
-    int j = 0;
-    int64_t r = 0;
-    float t = INFINITY;
-    uint64_t m = 0ull;
-    int limit = 0, base = 0;
+    // lane i: ray first + i
+    const int64_t ray = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kWave + lane;
+    int limit = 0;
     int64_t start = 0;
-    if (in_range) {
-        j = static_cast<int>(task / n_rays);
-        r = task - static_cast<int64_t>(j) * n_rays;
-        t = chunk_t[task];
-        if (t < INFINITY) {
-            m = masks[task];
-            limit = packed_info[2 * r + 1];
-            start = packed_info[2 * r];
-            base = chunk_base[task];
+    uint64_t nz = 0ull;
+    if (ray < n_rays) {
+        limit = packed_info[2 * ray + 1];
+        if (limit > 0) {
+            start = packed_info[2 * ray];
+            nz = sample_chunks[ray];
         }
     }
-    // the whole wave: no samples and no ray continuing past the stored chunks
-    if (ballot(m != 0ull || (j == n_masks - 1 && t < INFINITY)) == 0ull) return;
-    const float t_far = t < INFINITY ? t_far_in[r] : -INFINITY;
-    // segments holding samples that fall before the ray's limit
-    uint32_t todo = 0u;
-#pragma unroll
-    for (int s = 0; s < kSegsPerChunk; ++s) {
-        const bool holds = ((m >> (s * kConeBatch)) & 0xffull) != 0ull;
-        const int idx = base + static_cast<int>(__popcll(m & ((1ull << (s * kConeBatch)) - 1ull)));
-        if (holds && idx < limit) todo |= 1u << s;
-    }
-    const int n_items = __popc(todo);
-    const int before = wave_inclusive_sum(n_items) - n_items;
-    const int total = read_lane(before + n_items, kWave - 1);
-    {
-        int pos = before;
-#pragma unroll
-        for (int s = 0; s < kSegsPerChunk; ++s) {
-            if (((todo >> s) & 1u) != 0u) {
-                q_id[wave][pos] = static_cast<uint16_t>(lane | (s << kWaveLog2));
-                ++pos;
-            }
-        }
-    }
-    wave_lds_sync();
+    // a ray whose last stored chunk exists may go on past the stored chunks
+    const float t_last = limit > 0 ? chunk_t[static_cast<int64_t>(n_masks - 1) * n_rays + ray] : INFINITY;
+    const int n_tasks = static_cast<int>(__popcll(nz));
+    const int t_before = wave_inclusive_sum(n_tasks) - n_tasks;
+    const int t_total = read_lane(t_before + n_tasks, kWave - 1);
     bool overflow = false;
     const int start_lo = static_cast<int>(start), start_hi = static_cast<int>(start >> 32);
-    const int m_lo = static_cast<int>(m), m_hi = static_cast<int>(m >> 32);
-    for (int qb = 0; qb < total; qb += kWave) {
-        const int i = qb + lane;
-        const bool has = i < total;
-        const int id = has ? static_cast<int>(q_id[wave][i]) : 0;
-        const int src = id & (kWave - 1);
-        const int s = id >> kWaveLog2;
-        const float s_far = lane_value(t_far, src);
-        const int s_limit = lane_value(limit, src);
-        const int s_base = lane_value(base, src);
-        const int64_t s_start = (static_cast<int64_t>(lane_value(start_hi, src)) << 32) |
-                                static_cast<uint32_t>(lane_value(start_lo, src));
-        const uint64_t s_m = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(m_hi, src))) << 32) |
-                             static_cast<uint32_t>(lane_value(m_lo, src));
-        const int64_t s_task =
-            task_list != nullptr ? static_cast<int64_t>(lane_value(static_cast<int>(task), src)) : first_idx + src;
-        if (has) {
-            const float t0 = seg_t[s_task * kSegsPerChunk + s];
-            float tb[kConeBatch + 1];
-            const int n_valid = cone_steps(t0, s_far, p, tb);
-            const uint32_t hits = static_cast<uint32_t>(s_m >> (s * kConeBatch)) & 0xffu & ((1u << n_valid) - 1u);
-            int idx = s_base + static_cast<int>(__popcll(s_m & ((1ull << (s * kConeBatch)) - 1ull)));
+    const int nz_lo = static_cast<int>(nz), nz_hi = static_cast<int>(nz >> 32);
+    for (int tb0 = 0; tb0 < t_total; tb0 += kWave) {
+        // task i of the wave: the ray lane L whose tasks hold it, and its
+        // (i - first task of L)-th chunk holding samples
+        const int i = tb0 + lane;
+        int L = 0;
 #pragma unroll
-            for (int u = 0; u < kConeBatch; ++u) {
-                if (((hits >> u) & 1u) != 0u && idx < s_limit) {
-                    const int64_t pos = s_start + idx;
-                    if (pos >= 0 && pos < capacity) {
-                        t_starts[pos] = tb[u];
-                        t_ends[pos] = tb[u + 1];
-                    } else {
-                        overflow = true;
-                    }
-                    ++idx;
+        for (int step = kWave / 2; step >= 1; step >>= 1) {
+            const int probe_lane = L + step;  // < 64
+            if (lane_value(t_before, probe_lane) <= i) L = probe_lane;
+        }
+        const bool has_task = i < t_total;
+        const uint64_t l_nz = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(nz_hi, L))) << 32) |
+                              static_cast<uint32_t>(lane_value(nz_lo, L));
+        const int l_first = lane_value(t_before, L);
+        const int l_limit = lane_value(limit, L);
+        const int64_t l_start = (static_cast<int64_t>(lane_value(start_hi, L)) << 32) |
+                                static_cast<uint32_t>(lane_value(start_lo, L));
+        const int64_t r = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kWave + L;
+        uint64_t m = 0ull;
+        int base = 0;
+        int64_t task = 0;
+        float t_far = -INFINITY;
+        if (has_task) {
+            const int j = nth_set_bit(l_nz, i - l_first);
+            task = static_cast<int64_t>(j) * n_rays + r;
+            m = masks[task];
+            base = chunk_base[task];
+            t_far = t_far_in[r];
+        }
+        // segments holding samples that fall before the ray's limit
+        uint32_t todo = 0u;
+#pragma unroll
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            const bool holds = ((m >> (s * kConeBatch)) & 0xffull) != 0ull;
+            const int idx = base + static_cast<int>(__popcll(m & ((1ull << (s * kConeBatch)) - 1ull)));
+            if (holds && idx < l_limit) todo |= 1u << s;
+        }
+        const int n_items = __popc(todo);
+        const int before = wave_inclusive_sum(n_items) - n_items;
+        const int total = read_lane(before + n_items, kWave - 1);
+        {
+            int pos = before;
+#pragma unroll
+            for (int s = 0; s < kSegsPerChunk; ++s) {
+                if (((todo >> s) & 1u) != 0u) {
+                    q_id[wave][pos] = static_cast<uint16_t>(lane | (s << kWaveLog2));
+                    ++pos;
                 }
             }
         }
+        wave_lds_sync();
+        const int m_lo = static_cast<int>(m), m_hi = static_cast<int>(m >> 32);
+        const int task_lo = static_cast<int>(task), task_hi = static_cast<int>(task >> 32);
+        for (int qb = 0; qb < total; qb += kWave) {
+            const int q = qb + lane;
+            const bool has = q < total;
+            const int id = has ? static_cast<int>(q_id[wave][q]) : 0;
+            const int src = id & (kWave - 1);
+            const int s = id >> kWaveLog2;
+            // the queued segment's task, gathered from its lane (every lane
+            // takes part in the permutes)
+            const float s_far = lane_value(t_far, src);
+            const int s_limit = lane_value(l_limit, src);
+            const int s_base = lane_value(base, src);
+            const int s_ray = lane_value(static_cast<int>(r), src);
+            const int64_t s_start = (static_cast<int64_t>(lane_value(static_cast<int>(l_start >> 32), src)) << 32) |
+                                    static_cast<uint32_t>(lane_value(static_cast<int>(l_start), src));
+            const uint64_t s_m = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(m_hi, src))) << 32) |
+                                 static_cast<uint32_t>(lane_value(m_lo, src));
+            const int64_t s_task = (static_cast<int64_t>(lane_value(task_hi, src)) << 32) |
+                                   static_cast<uint32_t>(lane_value(task_lo, src));
+            float tb[kConeBatch + 1];
+            uint32_t hits = 0u;
+            int first = 0;  // the segment's first sample within its ray
+            if (has) {
+                const int n_valid = cone_steps(seg_t[s_task * kSegsPerChunk + s], s_far, p, tb);
+                hits = static_cast<uint32_t>(s_m >> (s * kConeBatch)) & 0xffu & ((1u << n_valid) - 1u);
+                first = s_base + static_cast<int>(__popcll(s_m & ((1ull << (s * kConeBatch)) - 1ull)));
+            }
+            const int n_out = has ? min(__popc(hits), max(s_limit - first, 0)) : 0;
+            const int slot0 = wave_inclusive_sum(n_out) - n_out;
+            const int n_slots = read_lane(slot0 + n_out, kWave - 1);
+            if (has) {
+                e_pos[wave][lane] = s_start + first;
+                e_slot[wave][lane] = slot0;
+                e_ray[wave][lane] = s_ray;
+                int k = 0;
+#pragma unroll
+                for (int u = 0; u < kConeBatch; ++u) {
+                    if (((hits >> u) & 1u) != 0u && k < n_out) {
+                        s_t0[wave][slot0 + k] = tb[u];
+                        s_t1[wave][slot0 + k] = tb[u + 1];
+                        s_entry[wave][slot0 + k] = static_cast<uint8_t>(lane);
+                        ++k;
+                    }
+                }
+            }
+            wave_lds_sync();
+            for (int k = lane; k < n_slots; k += kWave) {
+                const int e = s_entry[wave][k];
+                const int64_t pos = e_pos[wave][e] + (k - e_slot[wave][e]);
+                if (pos >= 0 && pos < capacity) {
+                    t_starts[pos] = s_t0[wave][k];
+                    t_ends[pos] = s_t1[wave][k];
+                    ray_indices[pos] = e_ray[wave][e];
+                } else {
+                    overflow = true;
+                }
+            }
+            wave_lds_sync();  // the queue and the slots are written again next round
+        }
     }
-    if (in_range && j == n_masks - 1 && t < INFINITY) {
-        // past the stored chunks: walk this chunk, then look the rest of the
-        // ray up again
-        int idx = base + static_cast<int>(__popcll(m));
+    if (t_last < INFINITY) {
+        // the last stored chunk: walk it, then look the rest of the ray up
+        // again (rays of more than n_masks chunks of candidates, rare)
+        const int64_t last = static_cast<int64_t>(n_masks - 1) * n_rays + ray;
+        const uint64_t m = masks[last];
+        int idx = chunk_base[last] + static_cast<int>(__popcll(m));
+        const float t_far = t_far_in[ray];
+        float t = t_last;
         bool ended = false;
         for (int s = 0; s < kSegsPerChunk && !ended; ++s) {
             float tb[kConeBatch + 1];
@@ -1389,11 +1477,11 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
             float o[3], d[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                o[c] = rays_o[3 * r + c];
-                d[c] = rays_d[3 * r + c];
+                o[c] = rays_o[3 * ray + c];
+                d[c] = rays_d[3 * ray + c];
             }
             uint32_t word0;
-            grid_of_ray<LOOKUP>(grid_id, r, g, word0);
+            grid_of_ray<LOOKUP>(grid_id, ray, g, word0);
             SkipRay sk{};
             float skip_end = -INFINITY;
             for (int k0 = n_masks * kWave; k0 < kMaxCandidates && idx < limit; k0 += kConeBatch) {
@@ -1409,6 +1497,7 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_segments_kernel(
                         if (pos >= 0 && pos < capacity) {
                             t_starts[pos] = tb[u];
                             t_ends[pos] = tb[u + 1];
+                            ray_indices[pos] = static_cast<int32_t>(ray);
                         } else {
                             overflow = true;
                         }
@@ -1667,7 +1756,7 @@ void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const floa
         }
         hipLaunchKernelGGL(cone_counts_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, n, cw->n_masks, p.max_per_ray,
                            cw->masks, cw->extra, packed, sums, SKIP ? cw->chunk_base : nullptr,
-                           listed ? cw->live_chunks : nullptr);
+                           listed ? cw->live_chunks : nullptr, SKIP ? cw->live_chunks : nullptr);
         return;
     }
     switch (tuning().march_waves_per_group) {
@@ -1685,13 +1774,14 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
                       const ClipK& c, const StepK& p, const int32_t* packed, int64_t capacity, int32_t* ri, float* ts,
                       float* te, int32_t* status, const uint64_t* masks, int n_masks) {
     if (cone) {
-        if (cw != nullptr && cw->n_masks > 0 && SKIP) {  // the segment count's masks and starts
-            const bool listed = cone_task_list<LOOKUP, SKIP>(*cw, n);
-            hipLaunchKernelGGL((fill_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
-                               dim3(kTaskThreads), 0, s, o, d, gid, n, bits, g, p, cw->n_masks, cw->chunk_t,
-                               cw->t_far, cw->masks, cw->chunk_base, cw->seg_t, packed, capacity, ts, te, status,
-                               listed ? cw->task_list : nullptr,
-                               listed ? cw->task_sums + num_blocks(n) * cw->n_masks : nullptr);
+        if (cw != nullptr && cw->n_masks > 0 && SKIP) {
+            // the segment count's masks, segment starts and chunks holding
+            // samples, ray-major (the ray indices written with the samples)
+            const unsigned blocks = static_cast<unsigned>((n + kTaskThreads - 1) / kTaskThreads);
+            hipLaunchKernelGGL((fill_cone_rays_kernel<LOOKUP>), dim3(blocks), dim3(kTaskThreads), 0, s, o, d, gid, n,
+                               bits, g, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->masks, cw->chunk_base,
+                               cw->seg_t, cw->live_chunks, packed, capacity, ri, ts, te, status);
+            return;
         } else if (cw != nullptr && cw->n_masks > 0) {  // replay the count pass's chunks, one lane per chunk
             hipLaunchKernelGGL((fill_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,

@@ -770,7 +770,11 @@ __device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffe
         x2 = ldexpf(x2, -l_hi);
         dev = ldexpf(k.v * h + k.smax * slack_x, -l_hi) + cell_slack;
     } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
-        const float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
+        // The hardware square root and reciprocal (within a few ulps) serve
+        // here: every quantity below is a bound that carries a margin far
+        // above their error (2^-18 relative on |x|, L and the motion factor;
+        // 2^-16 contracted units on the centre's position).
+        const float n = __builtin_amdgcn_sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
         // r_min bounds |x| from below over the segment; beyond radius r > 1
         // the contraction shrinks distances by at most (2 - 1/r)/r, and a
         // motion along the ray by at most (1 + 2|o|)/r^2: its radial part
@@ -779,11 +783,13 @@ __device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffe
         const float r_min = n * (1.0f - 0x1p-18f) - k.dnorm * h - 2.0f * slack_x;
         float lip = 1.0f, along = 1.0f;
         if (r_min > 1.0f) {
-            lip = ((2.0f - 1.0f / r_min) / r_min) * (1.0f + 0x1p-18f);
-            along = fminf(lip, ((1.0f + 2.0f * k.onorm) / (r_min * r_min)) * (1.0f + 0x1p-18f));
+            const float ir = __builtin_amdgcn_rcpf(r_min);
+            lip = ((2.0f - ir) * ir) * (1.0f + 0x1p-18f);
+            along = fminf(lip, ((1.0f + 2.0f * k.onorm) * (ir * ir)) * (1.0f + 0x1p-18f));
         }
         if (n > 1.0f) {
-            const float f = (2.0f - 1.0f / n) / n;
+            const float in = __builtin_amdgcn_rcpf(n);
+            const float f = (2.0f - in) * in;
             x0 = x0 * f;
             x1 = x1 * f;
             x2 = x2 * f;
@@ -990,16 +996,15 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
         uint64_t holding = 0ull;
         int64_t total = 0;
         for (int j = 0; j < n_masks; ++j) {
-            // samples of the ray before chunk j (for the segment fill)
-            if (chunk_base != nullptr) {
+            const uint64_t m = ((listed >> j) & 1ull) != 0ull ? masks[static_cast<int64_t>(j) * n_rays + r] : 0ull;
+            // samples of the ray before chunk j, for the segment fill, which
+            // reads it for the chunks holding samples and the last one
+            if (chunk_base != nullptr && (m != 0ull || j == n_masks - 1)) {
                 chunk_base[static_cast<int64_t>(j) * n_rays + r] =
                     static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
             }
-            if (((listed >> j) & 1ull) != 0ull) {
-                const uint64_t m = masks[static_cast<int64_t>(j) * n_rays + r];
-                total += __popcll(m);
-                if (m != 0ull) holding |= 1ull << j;
-            }
+            total += __popcll(m);
+            if (m != 0ull) holding |= 1ull << j;
         }
         if (sample_chunks != nullptr) sample_chunks[r] = holding;
         total += extra[r];

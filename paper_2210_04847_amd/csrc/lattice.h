@@ -36,6 +36,7 @@ struct GridK {
     uint32_t halo_res2;      // halo_res^2
     uint32_t halo_words;     // 32-bit words per grid of the halo bits
     uint32_t halo_bytes;     // bytes of all grids' halo bits
+    float contract_delta;    // contraction lookup: see probe
 };
 
 // The grids' words are read through a buffer resource: 32-bit byte offsets
@@ -132,19 +133,57 @@ __device__ __forceinline__ Probe probe(const GridK& g, uint32_t word0, float x0,
         x2 = ldexpf(x2, -q.level);
         grid = static_cast<uint32_t>(q.level);
         word0 = grid * g.words;
-    } else if (LOOKUP == NACC_LOOKUP_CONTRACT) {
-        float n = sqrtf((x0 * x0 + x1 * x1) + x2 * x2);
-        q.m = n;  // |x|, for the skip bound
-        if (n > 1.0f) {
-            float f = (2.0f - 1.0f / n) / n;
-            x0 = x0 * f;
-            x1 = x1 * f;
-            x2 = x2 * f;
-        }
     }
-    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x0 - g.lo[0]) * g.s[0], g.top)));
-    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x1 - g.lo[1]) * g.s[1], g.top)));
-    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell((x2 - g.lo[2]) * g.s[2], g.top)));
+    float u0, u1, u2;  // cell coordinates
+    if (LOOKUP == NACC_LOOKUP_CONTRACT) {
+        // The FP32 contract contracts x with a correctly rounded square root
+        // and divisions: n = |x|, f = (2 - 1/n) / n.  The cell is decided
+        // first from the hardware square root and reciprocal (a few ulps);
+        // it is the contract's cell wherever the fast cell coordinates lie
+        // farther than contract_delta from a cell boundary (an integer) and
+        // |x| is not near 1, because the two evaluations differ by less:
+        // with every hardware result within 2 ulps, the fast u is within
+        // s (48.8 + 2 |lo|) 2^-24 of the exact value and the contract's
+        // within s (22.4 + 2 |lo|) 2^-24 (|y| < 2 after contraction), and
+        // contract_delta is twice their sum.  Other lanes evaluate the
+        // contract itself.
+        const float n2 = (x0 * x0 + x1 * x1) + x2 * x2;
+        const float na = __builtin_amdgcn_sqrtf(n2);
+        q.m = na;  // |x|, for the skip bound (which allows 2^-18 relative)
+        bool exact = fabsf(na - 1.0f) <= 0x1p-20f;
+        if (na > 1.0f) {
+            const float ia = __builtin_amdgcn_rcpf(na);
+            const float fa = (2.0f - ia) * ia;
+            u0 = (x0 * fa - g.lo[0]) * g.s[0];
+            u1 = (x1 * fa - g.lo[1]) * g.s[1];
+            u2 = (x2 * fa - g.lo[2]) * g.s[2];
+            exact = exact || fabsf(u0 - rintf(u0)) <= g.contract_delta ||
+                    fabsf(u1 - rintf(u1)) <= g.contract_delta || fabsf(u2 - rintf(u2)) <= g.contract_delta;
+        } else {  // not contracted, as in the contract
+            u0 = (x0 - g.lo[0]) * g.s[0];
+            u1 = (x1 - g.lo[1]) * g.s[1];
+            u2 = (x2 - g.lo[2]) * g.s[2];
+        }
+        if (exact) {
+            const float n = sqrtf(n2);
+            if (n > 1.0f) {
+                const float f = (2.0f - 1.0f / n) / n;
+                x0 = x0 * f;
+                x1 = x1 * f;
+                x2 = x2 * f;
+            }
+            u0 = (x0 - g.lo[0]) * g.s[0];
+            u1 = (x1 - g.lo[1]) * g.s[1];
+            u2 = (x2 - g.lo[2]) * g.s[2];
+        }
+    } else {
+        u0 = (x0 - g.lo[0]) * g.s[0];
+        u1 = (x1 - g.lo[1]) * g.s[1];
+        u2 = (x2 - g.lo[2]) * g.s[2];
+    }
+    const uint32_t j0 = static_cast<uint32_t>(static_cast<int>(clamp_cell(u0, g.top)));
+    const uint32_t j1 = static_cast<uint32_t>(static_cast<int>(clamp_cell(u1, g.top)));
+    const uint32_t j2 = static_cast<uint32_t>(static_cast<int>(clamp_cell(u2, g.top)));
     // j < res <= 1024 and res^2 <= 2^20: every factor fits the 24-bit
     // multiplier, every product 32 bits
     const uint32_t res = static_cast<uint32_t>(g.res);
@@ -381,6 +420,12 @@ void make_constants(const nacc_grid_desc& grid, const nacc_march_params& params,
     g.halo_res2 = static_cast<uint32_t>(g.halo_res) * static_cast<uint32_t>(g.halo_res);
     g.halo_words = static_cast<uint32_t>(halo_words(grid.res));
     g.halo_bytes = static_cast<uint32_t>(static_cast<int64_t>(grid.n_grids) * g.halo_words * 4);
+    float smax = 0.0f, lmax = 0.0f;
+    for (int i = 0; i < 3; ++i) {
+        smax = std::fmax(smax, g.s[i]);
+        lmax = std::fmax(lmax, std::fabs(g.lo[i]));
+    }
+    g.contract_delta = static_cast<float>(2.0 * 0x1p-24 * smax * (72.0 + 4.0 * lmax));
     p.near_plane = params.near_plane;
     p.far_plane = params.far_plane;
     p.dt = params.dt;

@@ -278,6 +278,24 @@ def test_contraction_skip_sparse(p_occ, cone):
     assert want[1].size > 1000
 
 
+@pytest.mark.parametrize("cone", [0.0, 1.0 / 256])
+def test_contraction_fine_grid_cell_edges(cone):
+    """A 512^3 contracted-space grid: the lookup decides cells on a fast
+    contraction away from cell edges and on the FP32 contract near them
+    (within about 1e-3 cells here, so several in a thousand lookups take the
+    contract's path); every variant bit for bit against the oracle."""
+    res = 512
+    mask = synth.random_mask(res ** 3, 0.3, 19)
+    o, d = synth.rays_unbounded(1500, 19)
+    box = np.array([-2, -2, -2, 2, 2, 2], np.float32)
+    if cone:
+        want = compare(o, d, mask, res, box, 0.2, 1e4, 0.002, cone=cone, dt_max=1e10, lookup=2,
+                       max_per_ray=4096)
+    else:
+        want = compare(o, d, mask, res, box, 0.2, 12.0, 0.003, lookup=2)
+    assert want[1].size > 100000
+
+
 def test_contraction_lookup():
     res = 32
     mask = synth.random_mask(res ** 3, 0.3, 14)

@@ -803,6 +803,41 @@ __device__ __forceinline__ bool cone_segment_live(const GridK& g, __amdgpu_buffe
     return open | hb;
 }
 
+// The cone-step lattice from the near plane, shared by every ray that
+// starts there (rays from inside the clip box, or with no box at all, start
+// at the near plane): t at every 8th candidate, computed once on the host
+// in FP32 with the device's operations (each correctly rounded; the
+// median of three is the clamp), and passed by value.  The recurrence only
+// depends on t, so a chunk of any ray whose first t equals the table's
+// entry continues along the table; the starts and count passes then read
+// chunk and segment starts instead of walking them.  Left empty (n = 0) if
+// the steps stall within the table (t + step == t), which the walks handle.
+constexpr int kMaxMaskChunks = 64;  // one per lane of a wave
+constexpr int kTableStride = kWave / kConeBatch;  // table entries per chunk
+struct ConeTable {
+    float t[kMaxMaskChunks * kTableStride + 1];
+    int n;  // entries: n_masks 8 + 1, or 0
+};
+
+ConeTable cone_table(const StepK& p, int n_masks) {
+    ConeTable tab;
+    tab.n = 0;
+    float t = p.near_plane;
+    if (n_masks <= 0 || !std::isfinite(t)) return tab;
+    const int n = n_masks * kTableStride + 1;
+    for (int i = 0; i < n; ++i) {
+        tab.t[i] = t;
+        for (int u = 0; u < kConeBatch && i + 1 < n; ++u) {
+            const float step = std::fmin(std::fmax(t * p.cone, p.dt), p.dt_max);
+            const float t1 = t + step;
+            if (!(t1 > t)) return tab;  // stalls: no table
+            t = t1;
+        }
+    }
+    tab.n = n;
+    return tab;
+}
+
 // Chunk-parallel cone marching.  The recurrence itself is cheap (four FP32
 // operations per candidate) but serial; the grid lookups are not.  A
 // pre-pass walks each ray's recurrence once, one lane per ray, and records
@@ -823,7 +858,7 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
     const float* __restrict__ rays_o, const float* __restrict__ rays_d, const int32_t* __restrict__ grid_id,
     int64_t n_rays, GridK g, ClipK c, StepK p, int n_masks, float* __restrict__ chunk_t,
     float* __restrict__ t_far_out, int32_t* __restrict__ extra, const uint32_t* __restrict__ halo,
-    uint64_t* __restrict__ live_chunks, int64_t* __restrict__ task_sums) {
+    uint64_t* __restrict__ live_chunks, int64_t* __restrict__ task_sums, ConeTable tab) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kRaysPerBlock + threadIdx.x;
     uint64_t listed = 0ull;  // CULL: chunks with candidates that may hold samples
     if (r < n_rays) {
@@ -843,12 +878,15 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
         const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
         float t = t_near;
+        const bool tabled = tab.n > 0 && t_near == tab.t[0];  // starts at the near plane
         for (int j = 0; j < n_masks; ++j) {
             live = live && t < t_far;  // the chunk's first candidate exists
             const float ta = t;
             const bool has = live;
-            if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
-                // the wave's rays have all ended
+            if (__builtin_amdgcn_ballot_w64(live && !tabled) == 0ull) {
+                // the wave's live rays all follow the table (or have all
+                // ended): the next chunk's start, past the ray's end too
+                if (tabled) t = tab.t[kTableStride * (j + 1)];
             } else if (p.no_stall) {
                 // every step advances, so the candidates inside the ray are a
                 // prefix: the steps are taken without tests (past the ray's
@@ -1130,7 +1168,7 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     int64_t n_rays, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ halo, GridK g, StepK p,
     int n_masks, const float* __restrict__ chunk_t, const float* __restrict__ t_far_in,
     uint64_t* __restrict__ masks, int32_t* __restrict__ extra, float* __restrict__ seg_t,
-    const int32_t* __restrict__ task_list, const int64_t* __restrict__ task_total) {
+    const int32_t* __restrict__ task_list, const int64_t* __restrict__ task_total, ConeTable tab) {
     __shared__ float q_t[kTaskWaves][kSegQueue];
     __shared__ uint16_t q_id[kTaskWaves][kSegQueue];
     __shared__ uint64_t q_mask[kTaskWaves][kWave];
@@ -1181,7 +1219,19 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     float st[kSegsPerChunk];
     uint32_t live = 0u;
     bool alive = active;
-    if (p.no_stall) {
+    // a chunk that starts on the near-plane lattice (not the last stored
+    // one, whose end the continuation needs) reads its segment starts
+    const bool tabled = tab.n > 0 && active && j < n_masks - 1 && t == tab.t[kTableStride * j];
+    if (ballot(active && !tabled) == 0ull) {
+#pragma unroll
+        for (int s = 0; s < kSegsPerChunk; ++s) {
+            const float ta = tabled ? tab.t[kTableStride * j + s] : t;
+            const float tb = tabled ? tab.t[kTableStride * j + s + 1] : t;
+            st[s] = ta;
+            const bool any = active && ta < t_far;
+            live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, tb) & any) << s;
+        }
+    } else if (p.no_stall) {
         // every step advances: a segment holds candidates inside the ray iff
         // its first t lies before t_far; its extent is taken past the ray's
         // end (a larger interval only weakens the test)
@@ -1602,8 +1652,6 @@ int64_t candidate_bound(const nacc_grid_desc& grid, const nacc_march_params& p) 
     return std::min<int64_t>(kMaxCandidates, k + 2);
 }
 
-constexpr int kMaxMaskChunks = 64;  // one per lane of a wave
-
 // Workspace of the marching calls: the per-workgroup sums of the scan, then
 // n_masks 64-bit occupancy masks per ray, one per chunk of 64 candidates,
 // written by the count pass and replayed by the fill pass.  n_masks covers
@@ -1736,24 +1784,25 @@ void launch_count_impl(const ConeWork* cw, int64_t nb, hipStream_t s, const floa
                        const ClipK& c, const StepK& p, int32_t* packed, int64_t* sums, uint64_t* masks, int n_masks) {
     if (cw != nullptr) {  // cone steps
         const bool listed = cone_task_list<LOOKUP, SKIP>(*cw, n);
+        const ConeTable tab = cone_table(p, cw->n_masks);
         if (listed) {
             hipLaunchKernelGGL((cone_starts_kernel<LOOKUP, true>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
                                g, c, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->extra, halo_of(skip, g),
-                               cw->live_chunks, cw->task_sums);
+                               cw->live_chunks, cw->task_sums, tab);
             const int64_t n_sums = nb * cw->n_masks;
             scan_exclusive(cw->task_sums, n_sums, cw->task_sums + n_sums, cw->task_sums + n_sums + 1, s);
             hipLaunchKernelGGL(task_list_kernel, dim3(nb), dim3(kRaysPerBlock), 0, s, cw->task_sums, n,
                                cw->n_masks, cw->live_chunks, cw->task_list);
         } else {
             hipLaunchKernelGGL((cone_starts_kernel<LOOKUP, false>), dim3(nb), dim3(kRaysPerBlock), 0, s, o, d, gid, n,
-                               g, c, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->extra, nullptr, nullptr, nullptr);
+                               g, c, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->extra, nullptr, nullptr, nullptr, tab);
         }
         if (cw->n_masks > 0 && SKIP) {  // segments through the halo bits
             hipLaunchKernelGGL((count_cone_segments_kernel<LOOKUP>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, halo_of(skip, g), g, p, cw->n_masks,
                                cw->chunk_t, cw->t_far, cw->masks, cw->extra, cw->seg_t,
                                listed ? cw->task_list : nullptr,
-                               listed ? cw->task_sums + nb * cw->n_masks : nullptr);
+                               listed ? cw->task_sums + nb * cw->n_masks : nullptr, tab);
         } else if (cw->n_masks > 0) {
             hipLaunchKernelGGL((count_cone_chunks_kernel<LOOKUP, false>), dim3(task_blocks(cw->n_masks, n)),
                                dim3(kTaskThreads), 0, s, o, d, gid, n, bits, skip, g, p, cw->n_masks, cw->chunk_t,

@@ -490,10 +490,10 @@ __global__ __launch_bounds__(256) void zero_sums_kernel(int64_t* __restrict__ su
     if (i < n) sums[i] = 0;
 }
 
-// Writes the samples of one ray from the per-chunk occupancy masks stored by
-// the count pass (the first n_masks chunks), so the grid is not traversed a
-// second time; a ray whose samples continue past those chunks is traversed
-// from there on.
+// The fill pass writes the samples of a ray from the per-chunk occupancy
+// masks stored by the count pass (the first n_masks chunks), so the grid is
+// not traversed a second time; a ray whose samples continue past those
+// chunks is traversed from there on.
 // The samples of the stored chunks of one ray (lane j of `mine` holds
 // chunk j's mask), up to `limit`; only the chunks holding samples are
 // visited, in order.  Returns the number written (or, CHECKED, taken).
@@ -540,31 +540,7 @@ __device__ __forceinline__ int fill_chunks(int64_t r, float t_near, float dt, in
     return written;
 }
 
-template <int LOOKUP, bool SKIP>
-__device__ __forceinline__ void fill_ray_from_masks(
-    int64_t r, const RaySpan& span, const float* __restrict__ rays_o, const float* __restrict__ rays_d,
-    const uint32_t* __restrict__ bits, const uint8_t* __restrict__ skip,
-    const GridK& g, const StepK& p, int64_t start, int limit, int64_t capacity,
-    int32_t* __restrict__ ray_indices, float* __restrict__ t_starts, float* __restrict__ t_ends, bool& overflow,
-    const uint64_t* __restrict__ masks, int n_masks) {
-    const int lane = lane_id();
-    const float t_near = span.t_near;
-    const uint64_t mine = lane < n_masks ? masks[lane] : 0ull;  // one load: lane j holds chunk j
-    // the loop is bound by its scalar bookkeeping: a ray whose samples fit
-    // the outputs takes it without per-sample range checks
-    int written;
-    if (start >= 0 && start + limit <= capacity) {
-        written = fill_chunks<false>(r, t_near, p.dt, start, limit, capacity, ray_indices, t_starts, t_ends,
-                                     overflow, mine);
-    } else {
-        written = fill_chunks<true>(r, t_near, p.dt, start, limit, capacity, ray_indices, t_starts, t_ends,
-                                    overflow, mine);
-    }
-    if (written < limit) {
-        march_ray_uniform<LOOKUP, true, SKIP>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit, capacity,
-                                              ray_indices, t_starts, t_ends, overflow, nullptr, 0, n_masks, written);
-    }
-}
+constexpr int kFillBatch = 8;  // rays per wave whose loads the fill issues together
 
 template <int LOOKUP, bool SKIP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
@@ -582,6 +558,70 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
         spans = ray_span<LOOKUP>(mine, rays_o, rays_d, grid_id, g, c, p);
     }
     bool overflow = false;
+    // the box lookup's count pass leaves the plain traversal's masks also
+    // when it marched by segments
+    constexpr bool kFillSkip = SKIP && !kSegments<LOOKUP, SKIP>;
+    if (masks != nullptr) {
+        // kFillBatch rays at a time: their ranges and masks are all loaded
+        // before any of their samples is stored.  A wave waits on its loads
+        // only after its earlier stores have completed too (one counter
+        // covers both), so loading ray by ray would put a store round trip
+        // between consecutive rays.
+        for (int i0 = wave; i0 < per; i0 += WAVES * kFillBatch) {
+            int my_start = 0, my_limit = 0;  // lane b: ray i0 + b WAVES
+            {
+                const int ib = i0 + lane_id() * WAVES;
+                const int64_t rb = first + ib;
+                if (lane_id() < kFillBatch && ib < per && rb < n_rays) {
+                    my_start = packed_info[2 * rb];
+                    my_limit = packed_info[2 * rb + 1];
+                }
+            }
+            uint64_t mk[kFillBatch];
+#pragma unroll
+            for (int b = 0; b < kFillBatch; ++b) {
+                const int i = i0 + b * WAVES;
+                const int64_t r = first + i;
+                mk[b] = i < per && r < n_rays && lane_id() < n_masks ? masks[r * n_masks + lane_id()] : 0ull;
+            }
+            // every loaded value is read here, before the batch's first
+            // store, so the wait for the loads is not a wait for stores
+            int lim[kFillBatch], beg[kFillBatch];
+            uint64_t any = 0ull;
+#pragma unroll
+            for (int b = 0; b < kFillBatch; ++b) {
+                lim[b] = read_lane(my_limit, b);
+                beg[b] = read_lane(my_start, b);
+                any |= ballot(mk[b] != 0ull) | static_cast<uint64_t>(lim[b]);
+            }
+            if (any == 0ull) continue;  // no ray of the batch has samples
+#pragma unroll
+            for (int b = 0; b < kFillBatch; ++b) {
+                const int i = i0 + b * WAVES;
+                const int64_t r = first + i;
+                if (i >= per || r >= n_rays) break;
+                const int limit = lim[b];
+                if (limit == 0) continue;
+                const int64_t start = beg[b];
+                const RaySpan span = read_span(spans, i / WAVES);
+                int written;
+                if (start >= 0 && start + limit <= capacity) {
+                    written = fill_chunks<false>(r, span.t_near, p.dt, start, limit, capacity, ray_indices,
+                                                 t_starts, t_ends, overflow, mk[b]);
+                } else {
+                    written = fill_chunks<true>(r, span.t_near, p.dt, start, limit, capacity, ray_indices,
+                                                t_starts, t_ends, overflow, mk[b]);
+                }
+                if (written < limit) {  // samples past the stored chunks: traverse from there
+                    march_ray_uniform<LOOKUP, true, kFillSkip>(r, span, rays_o, rays_d, bits, skip, g, p, start,
+                                                               limit, capacity, ray_indices, t_starts, t_ends,
+                                                               overflow, nullptr, 0, n_masks, written);
+                }
+            }
+        }
+        if (overflow && status != nullptr) *status = NACC_ECAPACITY;
+        return;
+    }
     for (int i = wave; i < per; i += WAVES) {
         const int64_t r = first + i;
         if (r >= n_rays) break;
@@ -589,14 +629,7 @@ __global__ __launch_bounds__(WAVES * kWave) void fill_uniform_kernel(
         const int limit = uniform<int>(packed_info[2 * r + 1]);
         if (limit == 0) continue;
         const RaySpan span = read_span(spans, i / WAVES);
-        // the box lookup's count pass leaves the plain traversal's masks also
-        // when it marched by segments
-        constexpr bool kFillSkip = SKIP && !kSegments<LOOKUP, SKIP>;
-        if (masks != nullptr) {
-            fill_ray_from_masks<LOOKUP, kFillSkip>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit,
-                                                   capacity, ray_indices, t_starts, t_ends, overflow,
-                                                   masks + r * n_masks, n_masks);
-        } else if constexpr (kSegments<LOOKUP, SKIP>) {
+        if constexpr (kSegments<LOOKUP, SKIP>) {
             // no stored masks: the segment count pass finds the samples with
             // fewer lookups; its ballots are written here directly
             march_ray_uniform<LOOKUP, true, false>(r, span, rays_o, rays_d, bits, skip, g, p, start, limit,

@@ -1253,13 +1253,16 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
     uint32_t live = 0u;
     bool alive = active;
     // a chunk that starts on the near-plane lattice (not the last stored
-    // one, whose end the continuation needs) reads its segment starts
-    const bool tabled = tab.n > 0 && active && j < n_masks - 1 && t == tab.t[kTableStride * j];
+    // one, whose end the continuation needs) reads its segment starts; the
+    // wave's tasks are chunk-major, so they nearly always share one chunk
+    // index, whose entries are then read with scalar loads
+    const int j0 = uniform<int>(j);
+    const bool tabled = tab.n > 0 && active && j == j0 && j0 < n_masks - 1 && t == tab.t[kTableStride * j0];
     if (ballot(active && !tabled) == 0ull) {
 #pragma unroll
         for (int s = 0; s < kSegsPerChunk; ++s) {
-            const float ta = tabled ? tab.t[kTableStride * j + s] : t;
-            const float tb = tabled ? tab.t[kTableStride * j + s + 1] : t;
+            const float ta = tabled ? tab.t[kTableStride * j0 + s] : t;
+            const float tb = tabled ? tab.t[kTableStride * j0 + s + 1] : t;
             st[s] = ta;
             const bool any = active && ta < t_far;
             live |= static_cast<uint32_t>(cone_segment_live<LOOKUP>(g, hrs, grid, o, d, k, ta, tb) & any) << s;

@@ -1066,16 +1066,29 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_counts_kernel(int64_t n_ra
         const uint64_t listed = live_chunks != nullptr ? live_chunks[r] : ~0ull;
         uint64_t holding = 0ull;
         int64_t total = 0;
-        for (int j = 0; j < n_masks; ++j) {
-            const uint64_t m = ((listed >> j) & 1ull) != 0ull ? masks[static_cast<int64_t>(j) * n_rays + r] : 0ull;
-            // samples of the ray before chunk j, for the segment fill, which
-            // reads it for the chunks holding samples and the last one
-            if (chunk_base != nullptr && (m != 0ull || j == n_masks - 1)) {
-                chunk_base[static_cast<int64_t>(j) * n_rays + r] =
-                    static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
+        // eight chunks' masks loaded together, then taken in order
+        constexpr int kGroup = 8;
+        for (int j0 = 0; j0 < n_masks; j0 += kGroup) {
+            uint64_t mg[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int j = j0 + u;
+                mg[u] = j < n_masks && ((listed >> j) & 1ull) != 0ull ? masks[static_cast<int64_t>(j) * n_rays + r]
+                                                                       : 0ull;
             }
-            total += __popcll(m);
-            if (m != 0ull) holding |= 1ull << j;
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int j = j0 + u;
+                const uint64_t m = mg[u];
+                // samples of the ray before chunk j, for the segment fill,
+                // which reads it for the chunks holding samples and the last
+                if (chunk_base != nullptr && j < n_masks && (m != 0ull || j == n_masks - 1)) {
+                    chunk_base[static_cast<int64_t>(j) * n_rays + r] =
+                        static_cast<int32_t>(min(total, static_cast<int64_t>(kMaxCandidates)));
+                }
+                total += __popcll(m);
+                if (m != 0ull) holding |= 1ull << j;
+            }
         }
         if (sample_chunks != nullptr) sample_chunks[r] = holding;
         total += extra[r];

@@ -1503,12 +1503,33 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_rays_kernel(
         wave_lds_sync();
         const int m_lo = static_cast<int>(m), m_hi = static_cast<int>(m >> 32);
         const int task_lo = static_cast<int>(task), task_hi = static_cast<int>(task >> 32);
+        // the stored starts of every round's segments (round k: queue entry
+        // 64 k + lane; at most 8 rounds), all loaded before the first round
+        // stores anything: one counter tracks a wave's loads and stores, so
+        // a load issued after stores is waited for together with them
+        float t_seg[kSegsPerChunk];
+#pragma unroll
+        for (int k = 0; k < kSegsPerChunk; ++k) {
+            t_seg[k] = 0.0f;
+            if (k * kWave < total) {
+                const int q = k * kWave + lane;
+                const bool has = q < total;
+                const int id = has ? static_cast<int>(q_id[wave][q]) : 0;
+                const int src = id & (kWave - 1);
+                const int64_t s_task = (static_cast<int64_t>(lane_value(task_hi, src)) << 32) |
+                                       static_cast<uint32_t>(lane_value(task_lo, src));
+                if (has) t_seg[k] = seg_t[s_task * kSegsPerChunk + (id >> kWaveLog2)];
+            }
+        }
         for (int qb = 0; qb < total; qb += kWave) {
             const int q = qb + lane;
             const bool has = q < total;
             const int id = has ? static_cast<int>(q_id[wave][q]) : 0;
             const int src = id & (kWave - 1);
             const int s = id >> kWaveLog2;
+            const float seg_t0 = t_seg[0];
+#pragma unroll
+            for (int k = 0; k + 1 < kSegsPerChunk; ++k) t_seg[k] = t_seg[k + 1];  // the next round's first
             // the queued segment's task, gathered from its lane (every lane
             // takes part in the permutes)
             const float s_far = lane_value(t_far, src);
@@ -1519,13 +1540,11 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_rays_kernel(
                                     static_cast<uint32_t>(lane_value(static_cast<int>(l_start), src));
             const uint64_t s_m = (static_cast<uint64_t>(static_cast<uint32_t>(lane_value(m_hi, src))) << 32) |
                                  static_cast<uint32_t>(lane_value(m_lo, src));
-            const int64_t s_task = (static_cast<int64_t>(lane_value(task_hi, src)) << 32) |
-                                   static_cast<uint32_t>(lane_value(task_lo, src));
             float tb[kConeBatch + 1];
             uint32_t hits = 0u;
             int first = 0;  // the segment's first sample within its ray
             if (has) {
-                const int n_valid = cone_steps(seg_t[s_task * kSegsPerChunk + s], s_far, p, tb);
+                const int n_valid = cone_steps(seg_t0, s_far, p, tb);
                 hits = static_cast<uint32_t>(s_m >> (s * kConeBatch)) & 0xffu & ((1u << n_valid) - 1u);
                 first = s_base + static_cast<int>(__popcll(s_m & ((1ull << (s * kConeBatch)) - 1ull)));
             }

@@ -912,7 +912,31 @@ __global__ __launch_bounds__(kRaysPerBlock) void cone_starts_kernel(
             const_cast<uint32_t*>(halo), 0, static_cast<int>(g.halo_bytes), kBufferWord3);
         float t = t_near;
         const bool tabled = tab.n > 0 && t_near == tab.t[0];  // starts at the near plane
-        for (int j = 0; j < n_masks; ++j) {
+        const bool all_tabled = __builtin_amdgcn_ballot_w64(live && !tabled) == 0ull;
+        if (all_tabled) {
+            // every live ray of the wave follows the table: eight chunks at
+            // a time, so that their culling tests' loads are in flight
+            // together
+            for (int j0 = 0; j0 < n_masks; j0 += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = j0 + u;
+                    if (j < n_masks) {
+                        const float ta = tab.t[kTableStride * j];
+                        const bool has = live && ta < t_far;
+                        float start = has ? ta : INFINITY;
+                        if (CULL && has && j < n_masks - 1 &&
+                            !cone_segment_live<LOOKUP>(g, hrs, word0 / g.words, o, d, k, ta,
+                                                       tab.t[kTableStride * (j + 1)])) {
+                            start = __builtin_nanf("");
+                        }
+                        if (CULL && start < INFINITY) listed |= 1ull << j;
+                        chunk_t[static_cast<int64_t>(j) * n_rays + r] = start;
+                    }
+                }
+            }
+        }
+        for (int j = 0; j < (all_tabled ? 0 : n_masks); ++j) {
             live = live && t < t_far;  // the chunk's first candidate exists
             const float ta = t;
             const bool has = live;

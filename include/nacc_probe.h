@@ -1,5 +1,6 @@
 /*
- * nacc_probe.h -- HBM bandwidth probes for measurement.
+ * nacc_probe.h -- probes for measurement: HBM bandwidth, and the hardware
+ * square root and reciprocal.
  *
  * NOT part of the method.  The rendering and marching kernels are bound by
  * HBM bandwidth or by vector ALU issue; to state how far each sits from the
@@ -44,6 +45,18 @@ enum {
  */
 int nacc_probe_hbm(int32_t kind, const void* src, void* dst, int64_t n_bytes,
                    int32_t blocks, void* stream);
+
+/*
+ * The hardware square root and reciprocal (v_sqrt_f32, v_rcp_f32) of n
+ * floats: sqrt_out[i] and rcp_out[i] for x[i] (device arrays of n floats;
+ * n >= 0).  The contraction lookup decides most cells on these instructions
+ * and relies on their results lying within 2 ulps of the correctly rounded
+ * ones (the error bound behind its fall-back margin); this call lets that
+ * be measured on the device at hand.
+ * Errors: NACC_EINVAL for bad arguments, NACC_EHIP if the launch fails.
+ */
+int nacc_probe_fast_sqrt_rcp(const float* x, int64_t n, float* sqrt_out,
+                             float* rcp_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -151,6 +151,7 @@ _SIGNATURES = {
                                        ctypes.POINTER(GridDesc), ctypes.POINTER(MarchParams), _F,
                                        _P, _P, _P, _P, _P, _P]),
     "nacc_probe_hbm": (_INT, [_I32, _P, _P, _I64, _I32, _P]),
+    "nacc_probe_fast_sqrt_rcp": (_INT, [_P, _I64, _P, _P, _P]),
 }
 
 # Symbols declared in the headers under include/.
@@ -805,3 +806,13 @@ def probe_hbm(kind, src, dst, n_bytes, blocks, stream=None):
         raise ValueError("dst is smaller than n_bytes")
     _check("nacc_probe_hbm", lib.nacc_probe_hbm(int(kind), _ptr(src), _ptr(dst), int(n_bytes),
                                                 int(blocks), _stream(stream)))
+
+
+def probe_fast_sqrt_rcp(x, sqrt_out, rcp_out, stream=None):
+    """The hardware square root and reciprocal of x (float32 device tensors)."""
+    n = x.numel()
+    _need(x, torch.float32, "x")
+    _need(sqrt_out, torch.float32, "sqrt_out", n)
+    _need(rcp_out, torch.float32, "rcp_out", n)
+    _check("nacc_probe_fast_sqrt_rcp", lib.nacc_probe_fast_sqrt_rcp(
+        _ptr(x), n, _ptr(sqrt_out), _ptr(rcp_out), _stream(stream)))

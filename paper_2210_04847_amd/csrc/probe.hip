@@ -1,5 +1,6 @@
-// Streaming HBM probes (nacc_probe.h): read-only, write-only and copy
-// kernels over 16-byte vectors, four vectors in flight per lane.
+// Probes (nacc_probe.h): streaming HBM read-only, write-only and copy
+// kernels over 16-byte vectors, four vectors in flight per lane; the
+// hardware square root and reciprocal of given inputs.
 #include "common.h"
 #include "nacc_probe.h"
 
@@ -54,7 +55,28 @@ __global__ void __launch_bounds__(kProbeThreads) probe_copy_kernel(const uint4* 
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+__global__ void __launch_bounds__(kProbeThreads) probe_sqrt_rcp_kernel(const float* __restrict__ x, int64_t n,
+                                                                       float* __restrict__ s, float* __restrict__ r) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kProbeThreads + threadIdx.x;
+    if (i < n) {
+        s[i] = __builtin_amdgcn_sqrtf(x[i]);
+        r[i] = __builtin_amdgcn_rcpf(x[i]);
+    }
+}
+
 }  // namespace
+
+extern "C" int nacc_probe_fast_sqrt_rcp(const float* x, int64_t n, float* sqrt_out, float* rcp_out, void* stream) {
+    clear_error();
+    NACC_REQUIRE(n >= 0 && n <= INT32_MAX, NACC_EINVAL, "n = %lld out of [0, 2^31 - 1]",
+                 static_cast<long long>(n));
+    NACC_REQUIRE(n == 0 || (x != nullptr && sqrt_out != nullptr && rcp_out != nullptr), NACC_EINVAL,
+                 "x, sqrt_out and rcp_out must be non-NULL");
+    if (n == 0) return NACC_OK;
+    hipLaunchKernelGGL(probe_sqrt_rcp_kernel, dim3(static_cast<unsigned>((n + kProbeThreads - 1) / kProbeThreads)),
+                       dim3(kProbeThreads), 0, as_stream(stream), x, n, sqrt_out, rcp_out);
+    return check_launch("probe sqrt rcp");
+}
 
 extern "C" int nacc_probe_hbm(int32_t kind, const void* src, void* dst, int64_t n_bytes, int32_t blocks,
                               void* stream) {

@@ -39,24 +39,89 @@ struct Sample {
     float t0, t1, sigma, r, g, b;
 };
 
-__device__ __forceinline__ Sample load_sample(bool valid, int64_t s, const float* __restrict__ ts,
-                                              const float* __restrict__ te, const float* __restrict__ sig,
-                                              const float* __restrict__ rgb) {
-    Sample x{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (valid) {
-        x.t0 = ts[s];
-        x.t1 = te[s];
-        x.sigma = sig[s];
-        const float3 c = reinterpret_cast<const float3*>(rgb)[s];
-        x.r = c.x;
-        x.g = c.y;
-        x.b = c.z;
-    }
+// A ray's samples are consecutive in every packed array, so a span of them
+// is read and written through buffer resources: a resource covers `count`
+// samples from `first`, sample i of the span sits at the byte offset 4 i
+// (12 i for colours), so each lane's offset is a constant of the kernel and
+// no address is formed per access, and the hardware range check reads 0
+// for every lane past the span and drops its stores.  Spans cover at most
+// 64 K samples (one resource per chunk past the first K), so every offset
+// stays far inside 32 bits however long the ray.  The last word of a
+// resource selects 32-bit untyped data.  Only 32-bit buffer accesses are
+// used (a colour is three of them at neighbouring offsets): this compiler's
+// 64- and 96-bit buffer-load builtins can come out as a 32-bit load whose
+// other words are lost.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const float* base, int64_t first, int count, int width) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base) + first * width, 0, count * width * 4,
+                                             kRawBufferWord3);
+}
+
+struct SampleSpan {
+    __amdgpu_buffer_rsrc_t ts, te, sig, rgb;
+};
+
+__device__ __forceinline__ SampleSpan sample_span(const float* ts, const float* te, const float* sig,
+                                                  const float* rgb, int64_t first, int count) {
+    return SampleSpan{span_rsrc(ts, first, count, 1), span_rsrc(te, first, count, 1),
+                      span_rsrc(sig, first, count, 1), span_rsrc(rgb, first, count, 3)};
+}
+
+// Byte offsets of the calling lane's sample in a span: 4 i in the 32-bit
+// arrays, 12 i in the colours.  Chunk c of a span adds the constants 256 c
+// and 768 c, which the compiler places in the instructions' immediate
+// offsets; the lane's part is made opaque (an empty asm statement that
+// claims to change it, no instruction) so that the sums are not hoisted out
+// of the ray loop into registers of their own.
+struct LaneOffset {
+    uint32_t o4, o12;
+};
+
+__device__ __forceinline__ LaneOffset lane_offset() {
+    uint32_t o4 = static_cast<uint32_t>(lane_id()) * 4u, o12 = static_cast<uint32_t>(lane_id()) * 12u;
+    asm volatile("" : "+v"(o4), "+v"(o12));
+    return LaneOffset{o4, o12};
+}
+
+__device__ __forceinline__ LaneOffset chunk_offset(const LaneOffset& l, int c) {
+    return LaneOffset{l.o4 + static_cast<uint32_t>(c) * 256u, l.o12 + static_cast<uint32_t>(c) * 768u};
+}
+
+// The sample at offset o of the span (zeros past its end).
+__device__ __forceinline__ Sample load_span(const SampleSpan& sp, const LaneOffset& o) {
+    Sample x;
+    x.t0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.ts, o.o4, 0, 0));
+    x.t1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.te, o.o4, 0, 0));
+    x.sigma = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.sig, o.o4, 0, 0));
+    x.r = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.rgb, o.o12, 0, 0));
+    x.g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.rgb, o.o12 + 4u, 0, 0));
+    x.b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp.rgb, o.o12 + 8u, 0, 0));
     return x;
 }
 
-__device__ __forceinline__ void store_rgb(float* __restrict__ out, int64_t s, float r, float g, float b) {
-    reinterpret_cast<float3*>(out)[s] = make_float3(r, g, b);
+// The first samples of a ray (the first chunk of the next ray, or the K
+// register-cached chunks), at most `cap`.
+__device__ __forceinline__ SampleSpan head_span(const float* ts, const float* te, const float* sig, const float* rgb,
+                                                int64_t start, int n, int cap) {
+    return sample_span(ts, te, sig, rgb, start, min(n, cap));
+}
+
+// Where a span's gradients go.
+struct GradSpan {
+    __amdgpu_buffer_rsrc_t sig, rgb;
+};
+
+__device__ __forceinline__ GradSpan grad_span(float* g_sigmas, float* g_rgbs, int64_t first, int count) {
+    return GradSpan{span_rsrc(g_sigmas, first, count, 1), span_rsrc(g_rgbs, first, count, 3)};
+}
+
+__device__ __forceinline__ void store_grads(const GradSpan& d, const LaneOffset& o, float gs, float gr, float gg,
+                                            float gb) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, gs), d.sig, o.o4, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, gr), d.rgb, o.o12, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, gg), d.rgb, o.o12 + 4u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, gb), d.rgb, o.o12 + 8u, 0, 0);
 }
 
 __device__ __forceinline__ Trans chunk_transmittance(const Sample& x, double carry) {
@@ -84,7 +149,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         const int i = c + lane;
         const bool valid = i < n;
         const int64_t s = start + i;
-        const Sample x = load_sample(valid, s, ts, te, sig, rgb);
+        const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(n - c, kWave)), lane_offset());
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         const bool keep = valid && lane < keep_n;
@@ -156,19 +221,13 @@ __device__ __forceinline__ float vdot(const RayGrad& q, const GradInput& x) {
 // gets.  Lanes at or past the cut get zeros.
 template <bool NO_AD>
 __device__ __forceinline__ float chunk_grads(const RayGrad& q, const GradInput& x, float w, float t_next, bool keep,
-                                             bool valid, int64_t s, float above, float* __restrict__ g_sigmas,
-                                             float* __restrict__ g_rgbs) {
+                                             const GradSpan& dst, const LaneOffset& o, float above) {
     const float v = vdot<NO_AD>(q, x);
     const float wv = keep ? w * v : 0.0f;
     const float incl = wave_inclusive_suffix(wv);
     const float suffix = above + shift_down_one(incl);
-    if (keep) {
-        g_sigmas[s] = x.delta * __builtin_fmaf(t_next, v, -suffix);
-        store_rgb(g_rgbs, s, w * q.gr, w * q.gg, w * q.gb);
-    } else if (valid) {
-        g_sigmas[s] = 0.0f;
-        store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
-    }
+    const float gs = x.delta * __builtin_fmaf(t_next, v, -suffix);
+    store_grads(dst, o, keep ? gs : 0.0f, keep ? w * q.gr : 0.0f, keep ? w * q.gg : 0.0f, keep ? w * q.gb : 0.0f);
     return above + read_lane(incl, 0);
 }
 
@@ -193,16 +252,18 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
                                             double& prefix_hi, float acc[3], float& acc_a, float& acc_d,
                                             const Sample& chunk0 = Sample{}) {
     const int lane = lane_id();
+    const LaneOffset lo = lane_offset();
+    // chunks past the ray's end are neither loaded nor read
     Sample x[K];
+    const SampleSpan head = head_span(ts, te, sig, rgb, start, n, K * kWave);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        const int i = c * kWave + lane;
+        if (c * kWave >= n) continue;
         if (PRELOADED && c == 0) {
             x[0] = chunk0;  // loaded while the previous ray was finished
         } else {
-            x[c] = load_sample(i < n, start + i, ts, te, sig, rgb);
+            x[c] = load_span(head, chunk_offset(lo, c));
         }
-        cache.x[c] = grad_input(x[c]);
     }
     double carry = 0.0, carry_prev = 0.0;
     kept = n;
@@ -213,7 +274,9 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
     for (int c = 0; c < K; ++c) {
         cache.w[c] = 0.0f;
         cache.t_next[c] = 0.0f;
-        if (stopped || c * kWave >= n) continue;
+        if (c * kWave >= n) continue;
+        cache.x[c] = grad_input(x[c]);
+        if (stopped) continue;
         if (lane == c) cache.carries = carry;
         const int i = c * kWave + lane;
         const bool valid = i < n;
@@ -244,7 +307,7 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         if (lane == c / kWave) cache.carries = carry;
         const int i = c + lane;
         const bool valid = i < n;
-        const Sample x = load_sample(valid, start + i, ts, te, sig, rgb);
+        const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(n - c, kWave)), lo);
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep(valid, t.t_in, eps);
         if (ACCUM) {
@@ -278,6 +341,7 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
                                              const RayCache<K>& cache, const RayGrad& q, float* __restrict__ g_sigmas,
                                              float* __restrict__ g_rgbs) {
     const int lane = lane_id();
+    const LaneOffset lo = lane_offset();
     const int cached_end = K * kWave;
     const int c_hi = kept > 0 ? ((kept - 1) / kWave) * kWave : -kWave;
     float above = 0.0f;
@@ -285,8 +349,8 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
     for (int c = c_hi; c >= cached_end; c -= kWave) {
         const int i = c + lane;
         const bool keep = i < kept;
-        const int64_t s = start + i;
-        const Sample x = load_sample(keep, s, ts, te, sig, rgb);
+        // samples past the cut read as zeros, as in the forward pass's sums
+        const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(kept - c, kWave)), lo);
         const float tau = x.sigma * (x.t1 - x.t0);
         const float chunk_tau = wave_sum(tau);
         // the forward pass's own carry (so T is bit for bit the forward T)
@@ -297,25 +361,22 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
         const Trans t = chunk_transmittance(x, p_start);
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         const float t_next = t.t_next;
-        above = chunk_grads<NO_AD>(q, grad_input(x), w, t_next, keep, i < n, s, above, g_sigmas, g_rgbs);
+        above = chunk_grads<NO_AD>(q, grad_input(x), w, t_next, keep,
+                                   grad_span(g_sigmas, g_rgbs, start + c, min(n - c, kWave)), lo, above);
         p_end = p_start;
     }
+    const GradSpan head = grad_span(g_sigmas, g_rgbs, start, min(n, cached_end));
 #pragma unroll
     for (int c = K - 1; c >= 0; --c) {
         if (c * kWave >= n) continue;
         const int i = c * kWave + lane;
-        above = chunk_grads<NO_AD>(q, cache.x[c], cache.w[c], cache.t_next[c], i < kept, i < n, start + i, above,
-                                   g_sigmas, g_rgbs);
+        above = chunk_grads<NO_AD>(q, cache.x[c], cache.w[c], cache.t_next[c], i < kept, head, chunk_offset(lo, c),
+                                   above);
     }
     // streamed chunks past the cut: zeros, no loads (stored last, so no wait
     // on memory above waits for them)
     for (int c = max(c_hi + kWave, cached_end); c < n; c += kWave) {
-        const int i = c + lane;
-        if (i < n) {
-            const int64_t s = start + i;
-            g_sigmas[s] = 0.0f;
-            store_rgb(g_rgbs, s, 0.0f, 0.0f, 0.0f);
-        }
+        store_grads(grad_span(g_sigmas, g_rgbs, start + c, min(n - c, kWave)), lo, 0.0f, 0.0f, 0.0f, 0.0f);
     }
 }
 
@@ -374,7 +435,7 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
     Sample pre{};
     if (PREFETCH && r < n_rays) {
         ray_range(packed_info, r, n_samples, start, n);
-        pre = load_sample(lane < n, start + lane, ts, te, sig, rgb);
+        pre = load_span(head_span(ts, te, sig, rgb, start, n, kWave), lane_offset());
     }
     for (; r < n_rays; r += stride) {
         if (!PREFETCH) ray_range(packed_info, r, n_samples, start, n);
@@ -405,7 +466,7 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
         q.ga = 0.0f;
         q.gd = 0.0f;
         wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
-        if (PREFETCH) pre = load_sample(lane < n_next, start_next + lane, ts, te, sig, rgb);
+        if (PREFETCH) pre = load_span(head_span(ts, te, sig, rgb, start_next, n_next, kWave), lane_offset());
         if (n > 0) ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
         // stored after the backward: a store before it would make the
         // backward's first wait on memory also wait for the store
@@ -478,7 +539,7 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
             int64_t s_j;
             int n_j;
             ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j, n_j);
-            pre = load_sample(lane < n_j, s_j + lane, ts, te, sig, rgb);
+            pre = load_span(head_span(ts, te, sig, rgb, s_j, n_j, kWave), lane_offset());
         }
         while (todo != 0ull) {
             const int i = static_cast<int>(__builtin_ctzll(todo));
@@ -514,7 +575,7 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
                 int n_j;
                 ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j,
                           n_j);
-                pre = load_sample(lane < n_j, s_j + lane, ts, te, sig, rgb);
+                pre = load_span(head_span(ts, te, sig, rgb, s_j, n_j, kWave), lane_offset());
             }
             ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
             // stored after the backward: a store before it would make the

@@ -20,17 +20,18 @@ constexpr float kLog2e = 1.4426950408889634f;
 // e^-x for x >= 0 on the hardware exp2 (relative error a few ulp).
 __device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-x * kLog2e); }
 
-// alpha = 1 - e^-tau without cancellation: for tau <= 1/4 the alternating
-// series tau (1 - tau/2 (1 - tau/3 (... (1 - tau/6)))) (truncation below
-// tau^6 / 5040 < 5e-8 relative), above it 1 - e^-tau directly (e^-tau <=
-// 0.78, so the subtraction loses at most a few ulp).
+// alpha = 1 - e^-tau without cancellation: for tau <= 1/4, tau times the
+// Taylor series of (1 - e^-tau) / tau = sum_k (-tau)^k / (k + 1)! through
+// k = 5, in Horner form with fused multiply-adds (truncation below
+// tau^6 / 5040 < 5e-8 relative, rounding a few ulp); above it 1 - e^-tau
+// directly (e^-tau <= 0.78, so the subtraction loses at most a few ulp).
 __device__ __forceinline__ float alpha_of(float tau) {
     if (tau <= 0.25f) {
-        float p = 1.0f - tau * (1.0f / 6.0f);
-        p = 1.0f - tau * (1.0f / 5.0f) * p;
-        p = 1.0f - tau * 0.25f * p;
-        p = 1.0f - tau * (1.0f / 3.0f) * p;
-        p = 1.0f - tau * 0.5f * p;
+        float p = __builtin_fmaf(tau, -1.0f / 720.0f, 1.0f / 120.0f);
+        p = __builtin_fmaf(p, tau, -1.0f / 24.0f);
+        p = __builtin_fmaf(p, tau, 1.0f / 6.0f);
+        p = __builtin_fmaf(p, tau, -0.5f);
+        p = __builtin_fmaf(p, tau, 1.0f);
         return tau * p;
     }
     return 1.0f - exp_neg(tau);

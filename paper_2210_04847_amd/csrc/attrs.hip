@@ -273,8 +273,8 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
                     if (c + lane < n) weights[start + c + lane] = 0.0f;
                 }
             }
-            total_a = wave_sum(acc_a);
-            acc_d = wave_sum(acc_d);
+            total_a = wave_sum1(acc_a);
+            acc_d = wave_sum1(acc_d);
             if (lane == 0) {
                 if (opacity != nullptr) opacity[r] = total_a;
                 if (depth != nullptr) depth[r] = acc_d;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kAttrThreads) void attrs_fwd_kernel(
 #pragma unroll
         for (int k = 0; k < kBlock; ++k) {
             if (k < cb) {
-                float v = wave_sum(acc[k]);
+                float v = wave_sum1(acc[k]);
                 if (background != nullptr) v += background[c0 + k] * (1.0f - total_a);
                 if (lane == 0) out[r * n_ch + c0 + k] = v;
             }

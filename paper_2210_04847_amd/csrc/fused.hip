@@ -226,11 +226,8 @@ __device__ __forceinline__ void render_ray_fused(int64_t r, const RaySpan& span,
         }
         rendered += n_chunk;
     }
-    acc_r = wave_sum(acc_r);
-    acc_g = wave_sum(acc_g);
-    acc_b = wave_sum(acc_b);
-    acc_a = wave_sum(acc_a);
-    acc_d = wave_sum(acc_d);
+    wave_sum4(acc_r, acc_g, acc_b, acc_a);
+    acc_d = wave_sum1(acc_d);
     if (lane == 0) {
         color[3 * r] = acc_r;
         color[3 * r + 1] = acc_g;

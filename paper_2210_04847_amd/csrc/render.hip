@@ -151,8 +151,8 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
         const int64_t s = start + i;
         const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(n - c, kWave)), lane_offset());
         const Trans t = chunk_transmittance(x, carry);
-        const int keep_n = chunk_keep(valid, t.t_in, eps);
-        const bool keep = valid && lane < keep_n;
+        const int keep_n = chunk_keep_n(n - c, t.t_in, eps);
+        const bool keep = lane < min(keep_n, n - c);
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         acc_r = __builtin_fmaf(w, x.r, acc_r);
         acc_g = __builtin_fmaf(w, x.g, acc_g);
@@ -172,11 +172,8 @@ __global__ __launch_bounds__(kRenderThreads) void render_fwd_kernel(
             if (c + lane < n) weights[start + c + lane] = 0.0f;
         }
     }
-    acc_r = wave_sum(acc_r);
-    acc_g = wave_sum(acc_g);
-    acc_b = wave_sum(acc_b);
-    acc_a = wave_sum(acc_a);
-    acc_d = wave_sum(acc_d);
+    wave_sum4(acc_r, acc_g, acc_b, acc_a);
+    acc_d = wave_sum1(acc_d);
     if (lane == 0) {
         color[3 * r] = acc_r;
         color[3 * r + 1] = acc_g;
@@ -278,11 +275,10 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         cache.x[c] = grad_input(x[c]);
         if (stopped) continue;
         if (lane == c) cache.carries = carry;
-        const int i = c * kWave + lane;
-        const bool valid = i < n;
+        const int n_valid = n - c * kWave;
         const Trans t = chunk_transmittance(x[c], carry);
-        const int keep_n = chunk_keep(valid, t.t_in, eps);
-        const bool keep = valid && lane < keep_n;
+        const int keep_n = chunk_keep_n(n_valid, t.t_in, eps);
+        const bool keep = lane < min(keep_n, n_valid);
         const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
         cache.w[c] = w;
         cache.t_next[c] = t.t_next;
@@ -305,13 +301,11 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
     }
     for (int c = K * kWave; !stopped && c < n; c += kWave) {
         if (lane == c / kWave) cache.carries = carry;
-        const int i = c + lane;
-        const bool valid = i < n;
         const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(n - c, kWave)), lo);
         const Trans t = chunk_transmittance(x, carry);
-        const int keep_n = chunk_keep(valid, t.t_in, eps);
+        const int keep_n = chunk_keep_n(n - c, t.t_in, eps);
         if (ACCUM) {
-            const bool keep = valid && lane < keep_n;
+            const bool keep = lane < min(keep_n, n - c);
             const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
             acc[0] = __builtin_fmaf(w, x.r, acc[0]);
             acc[1] = __builtin_fmaf(w, x.g, acc[1]);
@@ -411,12 +405,13 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
 // Fused forward + MSE + backward.  The forward gives the colour, the loss
 // gradient g_C = 2 (C - target) / (3 n_rays) follows, then the backward runs
 // on the cached chunks.  Rays are walked grid-stride (one ray per wave at
-// the largest grid); each wave leaves one partial sum of the loss.  At
-// least 7 waves per SIMD (at most 72 VGPRs): with K = 4 cached chunks the
-// compiler would otherwise take 74 and fit only 6, and the kernel is as
-// much bound by its VALU issue as by memory, so the extra wave pays.
+// the largest grid); each wave leaves one partial sum of the loss.  8 waves
+// per SIMD (at most 64 VGPRs) wherever that needs no spill (7 with K = 4
+// and the prefetch): the kernel is bound by its VALU issue as much as by
+// memory, so every extra wave pays.
 template <int K, bool PREFETCH>
-__global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(7))) void render_mse_kernel(
+__global__ __launch_bounds__(kRenderThreads)
+__attribute__((amdgpu_waves_per_eu(K == 4 && PREFETCH ? 7 : 8))) void render_mse_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
     const float* __restrict__ target, float inv_count2, float* __restrict__ color, float* __restrict__ opacity,
@@ -453,11 +448,9 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
         float acc_a = 0.0f, acc_d = 0.0f;
         ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
                                        pre);
-        const float cr = wave_sum(acc[0]);
-        const float cg = wave_sum(acc[1]);
-        const float cb = wave_sum(acc[2]);
-        acc_a = wave_sum(acc_a);
-        acc_d = wave_sum(acc_d);
+        wave_sum4(acc[0], acc[1], acc[2], acc_a);
+        acc_d = wave_sum1(acc_d);
+        const float cr = acc[0], cg = acc[1], cb = acc[2];
         const float er = cr - tr, eg = cg - tg, eb = cb - tb;
         RayGrad q;
         q.gr = uniform<float>(er * inv_count2);
@@ -489,8 +482,11 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
 
 // The fused loss kernel for launches with fewer waves than rays (each wave
 // takes several rays): rays without samples are finished lane-parallel.
+// Occupancy as in render_mse_kernel: 8 waves per SIMD, 7 or 6 where more
+// registers are live (K = 3 with the prefetch, K = 4).
 template <int K, bool PREFETCH>
-__global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(7))) void render_mse_grouped_kernel(
+__global__ __launch_bounds__(kRenderThreads)
+__attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 7 : 8)))) void render_mse_grouped_kernel(
     const int32_t* __restrict__ packed_info, int64_t n_rays, int64_t n_samples, const float* __restrict__ ts,
     const float* __restrict__ te, const float* __restrict__ sig, const float* __restrict__ rgb, float eps,
     const float* __restrict__ target, float inv_count2, float* __restrict__ color, float* __restrict__ opacity,
@@ -557,11 +553,9 @@ __global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(
             float acc_a = 0.0f, acc_d = 0.0f;
             ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
                                            pre);
-            const float cr = wave_sum(acc[0]);
-            const float cg = wave_sum(acc[1]);
-            const float cb = wave_sum(acc[2]);
-            acc_a = wave_sum(acc_a);
-            acc_d = wave_sum(acc_d);
+            wave_sum4(acc[0], acc[1], acc[2], acc_a);
+            acc_d = wave_sum1(acc_d);
+            const float cr = acc[0], cg = acc[1], cb = acc[2];
             const float er = cr - tr, eg = cg - tg, eb = cb - tb;
             RayGrad q;
             q.gr = uniform<float>(er * inv_count2);

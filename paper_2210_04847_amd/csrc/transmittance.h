@@ -69,11 +69,62 @@ __device__ __forceinline__ Trans transmittance_of(float tau, double carry) {
     return t;
 }
 
+// Sums over the 64 lanes of a ray's accumulators (colour, opacity, depth,
+// attribute channels) in one fixed association, the same for every value
+// whatever its slot, so that every rendering kernel produces the same bits:
+// lanes i and i + 32 are added (i < 32), then of those i and i + 16
+// (i < 16), then the 16 partial sums by the row scan's tree (lane 15 of the
+// row).  gfx950's lane swaps (v_permlane32_swap: the upper half of the
+// first register with the lower half of the second; v_permlane16_swap: the
+// odd rows of the first with the even rows of the second) place the halves
+// of two values side by side, so that one addition folds both: four values
+// cost the folds of one.
+__device__ __forceinline__ uint32_t as_bits(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ float as_float(uint32_t x) { return __builtin_bit_cast(float, x); }
+
+// Tree sum of each row of 16 lanes, in its lane 15.
+__device__ __forceinline__ float row_tree(float x) {
+    x = x + dpp<kRowShr1>(x);
+    x = x + dpp<kRowShr2>(x);
+    x = x + dpp<kRowShr4>(x);
+    x = x + dpp<kRowShr8>(x);
+    return x;
+}
+
+__device__ __forceinline__ void wave_sum4(float& a, float& b, float& c, float& d) {
+    const auto ab = __builtin_amdgcn_permlane32_swap(as_bits(a), as_bits(b), false, false);
+    const float s1 = as_float(ab[0]) + as_float(ab[1]);  // lanes < 32: a, else b
+    const auto cd = __builtin_amdgcn_permlane32_swap(as_bits(c), as_bits(d), false, false);
+    const float s2 = as_float(cd[0]) + as_float(cd[1]);  // lanes < 32: c, else d
+    const auto q = __builtin_amdgcn_permlane16_swap(as_bits(s1), as_bits(s2), false, false);
+    const float t = row_tree(as_float(q[0]) + as_float(q[1]));  // rows: a, c, b, d
+    a = read_lane(t, 15);
+    c = read_lane(t, 31);
+    b = read_lane(t, 47);
+    d = read_lane(t, 63);
+}
+
+__device__ __forceinline__ float wave_sum1(float x) {
+    const auto h = __builtin_amdgcn_permlane32_swap(as_bits(x), as_bits(x), false, false);
+    const float y = as_float(h[0]) + as_float(h[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(as_bits(y), as_bits(y), false, false);
+    return read_lane(row_tree(as_float(q[0]) + as_float(q[1])), 15);
+}
+
 // Number of leading lanes kept in this chunk: the first valid lane with
 // T < eps and every lane after it are cut (64 = no cut here).
 __device__ __forceinline__ int chunk_keep(bool valid, float t_in, float eps) {
     if (!(eps > 0.0f)) return kWave;
     const uint64_t m = ballot(valid && t_in < eps);
+    return m == 0 ? kWave : static_cast<int>(__builtin_ctzll(m));
+}
+
+// The same for a chunk whose first n_valid > 0 lanes hold samples (n_valid
+// wave-uniform): the valid lanes' mask is formed in scalar registers.
+__device__ __forceinline__ int chunk_keep_n(int n_valid, float t_in, float eps) {
+    if (!(eps > 0.0f)) return kWave;
+    const uint64_t valid = n_valid >= kWave ? ~0ull : (1ull << n_valid) - 1ull;
+    const uint64_t m = ballot(t_in < eps) & valid;
     return m == 0 ? kWave : static_cast<int>(__builtin_ctzll(m));
 }
 

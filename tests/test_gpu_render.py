@@ -184,6 +184,81 @@ def test_render_deterministic():
     assert_bit_exact(outs[0][1], outs[1][1], "g_rgbs repeat")
 
 
+def _span_edge_inputs():
+    """Rays at every edge of the rendering kernels' spans: 64-sample chunks,
+    the register-cached chunks (1 to 4 of them), the 64 chunks whose carries
+    the backward keeps (past 4,096 samples it walks the prefix down), and
+    rays cut on the first sample of a chunk (the first cached, first
+    streamed and first uncarried chunk), which leaves that chunk empty."""
+    rng = np.random.default_rng(31)
+    counts = [0, 1, 2, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 320, 4095, 4096, 4097,
+              4160, 5000, 0, 300, 400, 4200]
+    cut_at = {22: 64, 23: 256, 24: 4096}  # ray index -> sample whose T falls below 1e-4
+    dt = np.float32(0.004)
+    ts, te, sg, cl = [], [], [], []
+    for r, n in enumerate(counts):
+        k = np.arange(n, dtype=np.float32)
+        t0 = np.float32(0.5) + k * dt
+        ts.append(t0)
+        te.append(t0 + dt)
+        # small densities: T stays well above 1e-4 over 5,000 samples
+        s = rng.uniform(0.0, 0.02, n).astype(np.float32)
+        if r in cut_at:
+            c = cut_at[r]
+            s[:c] = 0.0
+            s[c - 1] = np.float32(30.0) / dt  # tau = 30: T = e^-30 from sample c on
+        sg.append(s)
+        cl.append(rng.uniform(0.0, 1.0, (n, 3)).astype(np.float32))
+    cnt = np.array(counts, np.int64)
+    packed = np.stack([np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt], 1).astype(np.int32)
+    return packed, np.concatenate(ts), np.concatenate(te), np.concatenate(sg), np.concatenate(cl)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_span_edges_and_very_long_rays(eps):
+    """Forward and backward against the oracle and the fused loss kernel
+    against them bit for bit, under every number of register-cached chunks."""
+    lib = _nacc()._lib
+    packed, ts, te, sg, cl = _span_edge_inputs()
+    n, e = packed.shape[0], ts.size
+    p_d, ts_d, te_d, sg_d, cl_d = _cuda(packed, ts, te, sg, cl)
+    tgt = synth.targets(n, 41)
+    (tg_d,) = _cuda(tgt)
+    before = lib.get_tuning()
+    try:
+        for k in (1, 2, 3, 4):
+            lib.set_tuning(**dict(before, render_cached_chunks=k))
+            color = torch.empty((n, 3), device="cuda")
+            opacity = torch.empty(n, device="cuda")
+            depth = torch.empty(n, device="cuda")
+            lib.render_fwd(p_d, ts_d, te_d, sg_d, cl_d, eps, color, opacity, depth)
+            torch.cuda.synchronize()
+            got = dict(color=color.cpu().numpy(), opacity=opacity.cpu().numpy(), depth=depth.cpu().numpy())
+            if k == 1:
+                check_forward(got, packed, ts, te, sg, cl, eps)
+            gc = (color - tg_d) * float(np.float32(2.0 / (3 * n)))
+            g_sig = torch.full((e,), np.nan, device="cuda")
+            g_rgb = torch.full((e, 3), np.nan, device="cuda")
+            lib.render_bwd(p_d, ts_d, te_d, sg_d, cl_d, eps, gc, None, None, g_sig, g_rgb)
+            torch.cuda.synchronize()
+            check_backward(g_sig.cpu().numpy(), g_rgb.cpu().numpy(), packed, ts, te, sg, cl,
+                           gc.cpu().numpy().astype(np.float64), None, None, eps)
+            c2, o2, d2 = torch.empty_like(color), torch.empty_like(opacity), torch.empty_like(depth)
+            gs2 = torch.full_like(g_sig, np.nan)
+            gr2 = torch.full_like(g_rgb, np.nan)
+            loss = torch.empty(1, device="cuda")
+            ws = torch.empty(lib.render_mse_workspace_size(n), dtype=torch.uint8, device="cuda")
+            for blocks in (1, 4096):  # waves taking several rays, and one ray per wave
+                lib.set_tuning(**dict(before, render_cached_chunks=k, render_mse_max_blocks=blocks))
+                lib.render_fwd_bwd_mse(p_d, ts_d, te_d, sg_d, cl_d, eps, tg_d, c2, o2, d2, gs2, gr2, loss, ws)
+                torch.cuda.synchronize()
+                for a, b, name in ((c2, color, "colour"), (o2, opacity, "opacity"), (d2, depth, "depth"),
+                                   (gs2, g_sig, "g_sigmas"), (gr2, g_rgb, "g_rgbs")):
+                    assert_bit_exact(a.cpu().numpy(), b.cpu().numpy(), f"fused {name}, K={k}, {blocks} blocks")
+    finally:
+        lib.set_tuning(**before)
+
+
 # seeds 141, 186 and 210 found samples whose colour-gradient dot product
 # cancels across channels to ~3e-5 of its terms: kept as regression cases
 @pytest.mark.parametrize("seed", list(range(64)) + [141, 186, 210])

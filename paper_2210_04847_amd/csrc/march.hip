@@ -1408,7 +1408,7 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
 }
 
 // Fill pass of the segment count, ray-major with staged stores.  A wave
-// takes 64 consecutive rays and lists their (ray, chunk) tasks for the
+// takes kFillRays consecutive rays and lists their (ray, chunk) tasks for the
 // chunks that hold samples (cone_counts_kernel leaves their bits per ray),
 // ray by ray, chunk by chunk, so the segments that hold samples, queued in
 // that order, are in the order of their samples in the output.  The queue
@@ -1420,6 +1420,11 @@ __global__ __launch_bounds__(kTaskThreads) void count_cone_segments_kernel(
 // its own lane scatter 4-byte writes over as many cache lines as lanes).
 // A ray longer than the stored chunks is finished past them by its lane.
 constexpr int kFillSlots = kWave * kConeBatch;  // the samples of 64 segments at most
+// Rays per wave: their tasks still spread over all 64 lanes, and more,
+// shorter waves hide the latency of each round's permutes, LDS round trips
+// and stores better (contraction lookup: 111 -> 94 us at 262,144 rays; 8
+// rays per wave lose again).
+constexpr int kFillRays = 16;
 
 // Position of the k-th set bit of v (k < popcount(v)).
 __device__ __forceinline__ int nth_set_bit(uint64_t v, int k) {
@@ -1455,11 +1460,11 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_rays_kernel(
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
     // lane i: ray first + i
-    const int64_t ray = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kWave + lane;
+    const int64_t ray = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kFillRays + lane;
     int limit = 0;
     int64_t start = 0;
     uint64_t nz = 0ull;
-    if (ray < n_rays) {
+    if (lane < kFillRays && ray < n_rays) {
         limit = packed_info[2 * ray + 1];
         if (limit > 0) {
             start = packed_info[2 * ray];
@@ -1491,7 +1496,7 @@ __global__ __launch_bounds__(kTaskThreads) void fill_cone_rays_kernel(
         const int l_limit = lane_value(limit, L);
         const int64_t l_start = (static_cast<int64_t>(lane_value(start_hi, L)) << 32) |
                                 static_cast<uint32_t>(lane_value(start_lo, L));
-        const int64_t r = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kWave + L;
+        const int64_t r = (static_cast<int64_t>(blockIdx.x) * kTaskWaves + wave) * kFillRays + L;
         uint64_t m = 0ull;
         int base = 0;
         int64_t task = 0;
@@ -1923,7 +1928,8 @@ void launch_fill_impl(bool cone, const ConeWork* cw, int64_t nb, hipStream_t s, 
         if (cw != nullptr && cw->n_masks > 0 && SKIP) {
             // the segment count's masks, segment starts and chunks holding
             // samples, ray-major (the ray indices written with the samples)
-            const unsigned blocks = static_cast<unsigned>((n + kTaskThreads - 1) / kTaskThreads);
+            const int64_t per_block = static_cast<int64_t>(kTaskWaves) * kFillRays;
+            const unsigned blocks = static_cast<unsigned>((n + per_block - 1) / per_block);
             hipLaunchKernelGGL((fill_cone_rays_kernel<LOOKUP>), dim3(blocks), dim3(kTaskThreads), 0, s, o, d, gid, n,
                                bits, g, p, cw->n_masks, cw->chunk_t, cw->t_far, cw->masks, cw->chunk_base,
                                cw->seg_t, cw->live_chunks, packed, capacity, ri, ts, te, status);

@@ -504,11 +504,12 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
     for (int64_t rb = r0; rb < n_rays; rb += stride * kWave) {
         const int64_t my_r = rb + static_cast<int64_t>(lane) * stride;
         const bool mine = my_r < n_rays;
-        int my_n = 0;
+        int my_n = 0, my_start = 0;
         if (mine) {
             const int s0 = packed_info[2 * my_r], c0 = packed_info[2 * my_r + 1];
             const bool ok = s0 >= 0 && c0 >= 0 && static_cast<int64_t>(s0) + c0 <= n_samples;
             my_n = ok ? c0 : 0;
+            my_start = ok ? s0 : 0;
         }
         if (ballot(mine && my_n == 0) != 0ull) {
             double sq = 0.0;
@@ -529,21 +530,19 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
         // PREFETCH: a ray's first chunk is loaded during the previous ray's
         // backward pass
         Sample pre{};
-        // (the lanes' ranges are read again with scalar loads below, so that
-        // no vector register holds them through the rendering)
+        // (a ray's range is taken from its lane's registers, not loaded
+        // again: no memory round trip before its samples are requested)
         if (PREFETCH && todo != 0ull) {
-            int64_t s_j;
-            int n_j;
-            ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j, n_j);
-            pre = load_span(head_span(ts, te, sig, rgb, s_j, n_j, kWave), lane_offset());
+            const int j = static_cast<int>(__builtin_ctzll(todo));
+            pre = load_span(head_span(ts, te, sig, rgb, read_lane(my_start, j), read_lane(my_n, j), kWave),
+                            lane_offset());
         }
         while (todo != 0ull) {
             const int i = static_cast<int>(__builtin_ctzll(todo));
             todo &= todo - 1ull;
             const int64_t r = rb + static_cast<int64_t>(i) * stride;
-            int64_t start;
-            int n;
-            ray_range(packed_info, r, n_samples, start, n);
+            const int64_t start = read_lane(my_start, i);
+            const int n = read_lane(my_n, i);
             // the target's address is wave-uniform: scalar loads
             const float tr = target[3 * r], tg = target[3 * r + 1], tb = target[3 * r + 2];
             RayCache<K> cache;
@@ -565,11 +564,9 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
             q.gd = 0.0f;
             wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
             if (PREFETCH && todo != 0ull) {
-                int64_t s_j;
-                int n_j;
-                ray_range(packed_info, rb + static_cast<int64_t>(__builtin_ctzll(todo)) * stride, n_samples, s_j,
-                          n_j);
-                pre = load_span(head_span(ts, te, sig, rgb, s_j, n_j, kWave), lane_offset());
+                const int j = static_cast<int>(__builtin_ctzll(todo));
+                pre = load_span(head_span(ts, te, sig, rgb, read_lane(my_start, j), read_lane(my_n, j), kWave),
+                                lane_offset());
             }
             ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
             // stored after the backward: a store before it would make the

@@ -2,7 +2,8 @@
 // Sec. 2.2 "Differentiable Rendering"; early termination from Sec. 2.1).
 //
 // One wavefront per ray.  The ray's samples are read in chunks of 64, one per
-// lane, with coalesced loads of the packed arrays.  Inside a chunk the
+// lane, with coalesced loads of the packed arrays through buffer resources
+// that span the ray's samples (SampleSpan below).  Inside a chunk the
 // exclusive transmittance comes from a DPP prefix sum of tau = sigma * delta
 // over the 64 lanes; the running prefix across chunks is carried in FP64.
 // The same routine (chunk_transmittance) produces T in the forward, the
@@ -407,8 +408,8 @@ __global__ __launch_bounds__(kRenderThreads) void render_bwd_kernel(
 // on the cached chunks.  Rays are walked grid-stride (one ray per wave at
 // the largest grid); each wave leaves one partial sum of the loss.  8 waves
 // per SIMD (at most 64 VGPRs) wherever that needs no spill (7 with K = 4
-// and the prefetch): the kernel is bound by its VALU issue as much as by
-// memory, so every extra wave pays.
+// and the prefetch); with the buffer addressing 8 waves run no faster than
+// 7, and no slower.
 template <int K, bool PREFETCH>
 __global__ __launch_bounds__(kRenderThreads)
 __attribute__((amdgpu_waves_per_eu(K == 4 && PREFETCH ? 7 : 8))) void render_mse_kernel(

@@ -362,7 +362,7 @@ RENDER_OPS = 30
 
 # VALU lane operations per second: the 157.3 TFLOP/s FP32 vector figure with
 # an FMA counted as one operation, 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.
-# Single-issue, unpacked code (this build compiles without packed FP32) is
+# Single-issue, unpacked code (the library compiles without packed FP32) is
 # held near half of it, 16 lanes per SIMD per clock; the counters show the
 # count kernels issuing slightly above that half, so only the full figure is
 # a ceiling.
@@ -1391,7 +1391,7 @@ def bench_images(args, torch, nacc):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs on one GPU "
               "(rays shard across GPUs without communication except the grid update; see the "
               "design notes)", file=sys.stderr)
         sys.exit(2)

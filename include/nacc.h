@@ -76,7 +76,7 @@ enum {
     NACC_ESHAPE = -2,    /* sizes inconsistent with each other */
     NACC_ECAPACITY = -3, /* an output would not fit its buffer or int32 */
     NACC_EHIP = -4,      /* the HIP runtime reported an error */
-    NACC_ENOTSUP = -5    /* a valid request this build does not support */
+    NACC_ENOTSUP = -5    /* a valid request the library does not support */
 };
 
 /* Grid lookup modes. */

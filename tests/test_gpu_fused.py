@@ -91,6 +91,32 @@ def test_fused_equals_three_steps(train4k, eps, skip):
         assert int((ref["kept"] < counts).sum()) > 100  # the cut stops many rays early
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_fused_random_scenes_equal_three_steps(seed):
+    """Random blob scenes, grid resolutions and thresholds, ray counts (the
+    64-ray workgroup edges), step sizes, cut thresholds, caps and skip
+    settings: the fused kernel gives the three-step form's bits on every ray."""
+    nacc = _nacc()
+    rng = np.random.default_rng(5000 + seed)
+    scene = synth.blob_scene(int(rng.integers(1, 40)), 6000 + seed, peak=float(rng.choice([5.0, 50.0, 500.0])))
+    res = int(rng.choice([16, 32, 64, 128]))
+    grid = nacc.OccupancyGrid(tuple(BOX[:3]) + tuple(BOX[3:]), res)
+    grid.set_occupancy(_cuda(synth.initial_occupancy(scene, res, BOX)), float(rng.choice([1e-3, 0.01, 1.0])))
+    field = nacc.BlobField(scene)
+    n = int(rng.choice([1, 63, 64, 65, 700, 3000]))
+    o, d = synth.rays_toward_origin(n, 7000 + seed, jitter_std=float(rng.choice([0.1, 1.0])))
+    o, d = _cuda(o), _cuda(d)
+    dt = float(np.float32(3 ** 0.5 * 3 / float(rng.choice([256, 1024, 4096]))))
+    eps = float(rng.choice([0.0, 1e-4, 1e-2]))
+    cap = int(rng.choice([0, 0, 50, 300]))
+    skip = bool(rng.integers(0, 2))
+    ref = _three_step(nacc, field, grid, o, d, 0.0, 1e10, dt, eps, max_per_ray=cap)
+    fused = nacc.render_fused(field, o, d, grid, 0.0, 1e10, dt, eps, max_per_ray=cap, return_kept=True,
+                              skip_empty=skip)
+    torch.cuda.synchronize()
+    _assert_same(fused, ref)
+
+
 def test_fused_matches_oracle_render_of_its_samples(train4k):
     """Against the oracle's FP64 render of the marched samples at the field
     values the field kernel gives them (the render tolerances)."""

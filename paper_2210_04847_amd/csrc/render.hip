@@ -243,12 +243,21 @@ struct RayCache {
     double carries;  // lane j: FP64 tau prefix at the start of chunk j (j < 64)
 };
 
-template <int K, bool ACCUM, bool PRELOADED = false>
+// The first S chunks past the register-cached ones can be kept in LDS: per
+// chunk and lane what the backward reads of a sample (interval length,
+// colour, w_i and T_{i+1}, 6 floats; the midpoint's term is +0 in the loss
+// kernels), so that their backward pass neither reloads them from memory nor
+// forms T again.  Each lane reads back only its own slots, in the wave's own
+// order of LDS accesses.
+constexpr int kStashFloats = 6;
+constexpr int kStashChunks = 3;  // 18 KiB of LDS per workgroup of 4 waves: 8 workgroups per CU
+
+template <int K, bool ACCUM, bool PRELOADED = false, int S = 0>
 __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* __restrict__ ts,
                                             const float* __restrict__ te, const float* __restrict__ sig,
                                             const float* __restrict__ rgb, float eps, RayCache<K>& cache, int& kept,
                                             double& prefix_hi, float acc[3], float& acc_a, float& acc_d,
-                                            const Sample& chunk0 = Sample{}) {
+                                            const Sample& chunk0 = Sample{}, float* stash = nullptr) {
     const int lane = lane_id();
     const LaneOffset lo = lane_offset();
     // chunks past the ray's end are neither loaded nor read
@@ -305,14 +314,26 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
         const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(n - c, kWave)), lo);
         const Trans t = chunk_transmittance(x, carry);
         const int keep_n = chunk_keep_n(n - c, t.t_in, eps);
-        if (ACCUM) {
+        if (ACCUM || S > 0) {
             const bool keep = lane < min(keep_n, n - c);
             const float w = keep ? t.t_in * alpha_of(t.tau) : 0.0f;
-            acc[0] = __builtin_fmaf(w, x.r, acc[0]);
-            acc[1] = __builtin_fmaf(w, x.g, acc[1]);
-            acc[2] = __builtin_fmaf(w, x.b, acc[2]);
-            acc_a += w;
-            acc_d = __builtin_fmaf(w, (x.t0 + x.t1) * 0.5f, acc_d);
+            if (ACCUM) {
+                acc[0] = __builtin_fmaf(w, x.r, acc[0]);
+                acc[1] = __builtin_fmaf(w, x.g, acc[1]);
+                acc[2] = __builtin_fmaf(w, x.b, acc[2]);
+                acc_a += w;
+                acc_d = __builtin_fmaf(w, (x.t0 + x.t1) * 0.5f, acc_d);
+            }
+            const int slot = c / kWave - K;
+            if (S > 0 && slot < S) {
+                float* st = stash + slot * kStashFloats * kWave + lane;
+                st[0] = x.t1 - x.t0;
+                st[kWave] = x.r;
+                st[2 * kWave] = x.g;
+                st[3 * kWave] = x.b;
+                st[4 * kWave] = w;
+                st[5 * kWave] = t.t_next;
+            }
         }
         if (keep_n < kWave) {
             kept = c + keep_n;
@@ -329,12 +350,13 @@ __device__ __forceinline__ void ray_forward(int64_t start, int n, const float* _
 // Backward pass of one ray: chunks from the last kept one down to the first.
 // Streamed chunks rebuild T from the FP64 prefix at their end (walked down
 // from prefix_hi); cached chunks reuse w and T_{i+1} from the forward pass.
-template <int K, bool NO_AD>
+template <int K, bool NO_AD, int S = 0>
 __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, double prefix_hi,
                                              const float* __restrict__ ts, const float* __restrict__ te,
                                              const float* __restrict__ sig, const float* __restrict__ rgb,
                                              const RayCache<K>& cache, const RayGrad& q, float* __restrict__ g_sigmas,
-                                             float* __restrict__ g_rgbs) {
+                                             float* __restrict__ g_rgbs, const float* stash = nullptr) {
+    static_assert(S == 0 || NO_AD, "the stash leaves out the midpoint");
     const int lane = lane_id();
     const LaneOffset lo = lane_offset();
     const int cached_end = K * kWave;
@@ -344,6 +366,14 @@ __device__ __forceinline__ void ray_backward(int64_t start, int n, int kept, dou
     for (int c = c_hi; c >= cached_end; c -= kWave) {
         const int i = c + lane;
         const bool keep = i < kept;
+        const int slot = c / kWave - K;
+        if (S > 0 && slot < S) {  // the forward's values, from LDS (chunk < 64: p_end is not needed below)
+            const float* st = stash + slot * kStashFloats * kWave + lane;
+            const GradInput gx{st[0], 0.0f, st[kWave], st[2 * kWave], st[3 * kWave]};
+            above = chunk_grads<NO_AD>(q, gx, st[4 * kWave], st[5 * kWave], keep,
+                                       grad_span(g_sigmas, g_rgbs, start + c, min(n - c, kWave)), lo, above);
+            continue;
+        }
         // samples past the cut read as zeros, as in the forward pass's sums
         const Sample x = load_span(sample_span(ts, te, sig, rgb, start + c, min(kept - c, kWave)), lo);
         const float tau = x.sigma * (x.t1 - x.t0);
@@ -420,6 +450,8 @@ __attribute__((amdgpu_waves_per_eu(K == 4 && PREFETCH ? 7 : 8))) void render_mse
     double* __restrict__ loss_partial) {
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    __shared__ float stash_all[kRaysPerRenderBlock * kStashChunks * kStashFloats * kWave];
+    float* stash = stash_all + wave * kStashChunks * kStashFloats * kWave;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
     double wave_total = 0.0;
     // PREFETCH: the next ray's range is read when a ray starts and its first
@@ -447,8 +479,8 @@ __attribute__((amdgpu_waves_per_eu(K == 4 && PREFETCH ? 7 : 8))) void render_mse
         double prefix_hi;
         float acc[3] = {0.0f, 0.0f, 0.0f};
         float acc_a = 0.0f, acc_d = 0.0f;
-        ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
-                                       pre);
+        ray_forward<K, true, PREFETCH, kStashChunks>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc,
+                                                     acc_a, acc_d, pre, stash);
         wave_sum4(acc[0], acc[1], acc[2], acc_a);
         acc_d = wave_sum1(acc_d);
         const float cr = acc[0], cg = acc[1], cb = acc[2];
@@ -461,7 +493,10 @@ __attribute__((amdgpu_waves_per_eu(K == 4 && PREFETCH ? 7 : 8))) void render_mse
         q.gd = 0.0f;
         wave_total += static_cast<double>(er) * er + static_cast<double>(eg) * eg + static_cast<double>(eb) * eb;
         if (PREFETCH) pre = load_span(head_span(ts, te, sig, rgb, start_next, n_next, kWave), lane_offset());
-        if (n > 0) ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+        if (n > 0) {
+            ray_backward<K, true, kStashChunks>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas,
+                                                g_rgbs, stash);
+        }
         // stored after the backward: a store before it would make the
         // backward's first wait on memory also wait for the store
         if (lane == 0) {
@@ -495,6 +530,8 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
     double* __restrict__ loss_partial) {
     const int lane = lane_id();
     const int wave = uniform<int>(static_cast<int>(threadIdx.x) / kWave);
+    __shared__ float stash_all[kRaysPerRenderBlock * kStashChunks * kStashFloats * kWave];
+    float* stash = stash_all + wave * kStashChunks * kStashFloats * kWave;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kRaysPerRenderBlock;
     const int64_t r0 = xcd_grouped<16>(blockIdx.x, gridDim.x) * kRaysPerRenderBlock + wave;
     double wave_total = 0.0;  // squared errors of the wave's rays
@@ -551,8 +588,8 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
             double prefix_hi;
             float acc[3] = {0.0f, 0.0f, 0.0f};
             float acc_a = 0.0f, acc_d = 0.0f;
-            ray_forward<K, true, PREFETCH>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi, acc, acc_a, acc_d,
-                                           pre);
+            ray_forward<K, true, PREFETCH, kStashChunks>(start, n, ts, te, sig, rgb, eps, cache, kept, prefix_hi,
+                                                         acc, acc_a, acc_d, pre, stash);
             wave_sum4(acc[0], acc[1], acc[2], acc_a);
             acc_d = wave_sum1(acc_d);
             const float cr = acc[0], cg = acc[1], cb = acc[2];
@@ -569,7 +606,8 @@ __attribute__((amdgpu_waves_per_eu(K + PREFETCH >= 5 ? 6 : (K + PREFETCH >= 4 ? 
                 pre = load_span(head_span(ts, te, sig, rgb, read_lane(my_start, j), read_lane(my_n, j), kWave),
                                 lane_offset());
             }
-            ray_backward<K, true>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas, g_rgbs);
+            ray_backward<K, true, kStashChunks>(start, n, kept, prefix_hi, ts, te, sig, rgb, cache, q, g_sigmas,
+                                                g_rgbs, stash);
             // stored after the backward: a store before it would make the
             // backward's first wait on memory also wait for the store
             if (lane == 0) {
